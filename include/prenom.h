@@ -1,0 +1,241 @@
+/*
+ * prenom.h -- C ABI of the MI355X (gfx950) per-object NeRF training step of
+ * PRENOM (arXiv 2503.01582, Sec. III-B "Online Object Mapping").
+ *
+ * One training iteration of one object NeRF is
+ *
+ *   prenom_sample      prior-based probabilistic ray sampling   Sec. III-B, Eq. (4)-(6)
+ *   prenom_render_fwd  hash encoding + MLP + volume rendering   Sec. III-B, Eq. (7)
+ *                      + losses                                 Eq. (8)-(9)
+ *   prenom_render_bwd  the adjoint of render_fwd (parameter gradients)
+ *   prenom_adam_step   Adam on every parameter                  Sec. III-B, last paragraph
+ *
+ * Conventions for every call
+ *   - Array arguments are DEVICE pointers owned by the caller.  The library
+ *     never allocates, frees or synchronises inside these calls; each call only
+ *     enqueues kernels on `stream` (a hipStream_t; NULL = the null stream) and
+ *     returns.  Structs are passed by HOST pointer and read before return.
+ *   - Arguments are validated on the host before anything is launched; on any
+ *     error status nothing is enqueued.  Launch failures return
+ *     PRENOM_ERR_HIP.  prenom_last_error() gives a message for the calling
+ *     thread's last non-OK status.  No call aborts or exits.
+ *   - Layouts are row-major and densely packed.  FP32 unless stated.
+ *   - Thread safety: calls on different streams with disjoint outputs and
+ *     workspaces may run concurrently.
+ */
+#ifndef PRENOM_H
+#define PRENOM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PRENOM_MAX_LEVELS 32
+#define PRENOM_N_OUT 4 /* head outputs: density logit + 3 colour logits */
+
+typedef enum prenom_status {
+    PRENOM_OK = 0,
+    PRENOM_ERR_INVALID_ARG = 1, /* NULL where required, out-of-range scalar */
+    PRENOM_ERR_SHAPE = 2,       /* sizes inconsistent with each other       */
+    PRENOM_ERR_UNSUPPORTED = 3, /* architecture not compiled into the lib   */
+    PRENOM_ERR_WORKSPACE = 4,   /* workspace smaller than required          */
+    PRENOM_ERR_HIP = 5          /* a HIP launch failed                      */
+} prenom_status;
+
+/* Per-ray flags written by prenom_sample. */
+enum {
+    PRENOM_FLAG_MISS = 1,    /* ray does not meet the object box: no samples  */
+    PRENOM_FLAG_ESCAPED = 2, /* prior mass below epsilon: uniform draws       */
+    PRENOM_FLAG_UNIFORM = 4  /* no prior used (uniform mode or no prior grid) */
+};
+
+/* Architecture alpha (Sec. III and III-A): a multi-resolution hash grid with
+ * n_levels levels of 2^log2_table entries of n_features features each, and a
+ * bias-free MLP: mlp_hidden ReLU layers of width mlp_width, then a linear
+ * 4-output head (density = exp(o0), colour = sigmoid(o1..3)).
+ * resolution[l] is the lattice resolution N_l of level l (the caller computes
+ * floor(N_min * b^l)).  A level is stored 1:1 when (N_l+1)^3 <= 2^log2_table,
+ * and through the XOR-of-primes spatial hash otherwise.
+ * Supported: n_features = 2; n_levels in {8, 16}; mlp_width = 64;
+ * mlp_hidden in {1, 2}; log2_table in [10, 24]; 2 <= N_l < 2^20. */
+typedef struct prenom_arch {
+    int32_t n_levels;
+    int32_t log2_table;
+    int32_t n_features;
+    int32_t resolution[PRENOM_MAX_LEVELS];
+    int32_t mlp_width;
+    int32_t mlp_hidden;
+} prenom_arch;
+
+/* One object's NeRF.  Four device arrays of prenom_param_count(&arch) floats:
+ * parameters, their gradients (accumulated with += by prenom_render_bwd,
+ * zeroed by prenom_adam_step after use; the caller zeroes them once at
+ * allocation), and Adam's first and second moments.
+ * Parameter layout: hash tables [L][T][F], then W_1 [W][L*F],
+ * W_2..W_D [W][W], W_out [4][W]. */
+typedef struct prenom_model {
+    prenom_arch arch;
+    float* params;
+    float* grads;
+    float* adam_m;
+    float* adam_v;
+} prenom_model;
+
+int64_t prenom_param_count(const prenom_arch* arch);       /* -1 if invalid */
+int64_t prenom_table_param_count(const prenom_arch* arch); /* L * T * F   */
+
+/* ------------------------------------------------------------------------
+ * prenom_sample -- Sec. III-B "Probabilistic Ray Sampling", Eq. (4)-(6).
+ *
+ * Each world ray (rays_o, rays_d: [n_rays][3], unit direction) is moved into
+ * the object frame with world_to_obj (row-major 3x4 affine onto NOCS [0,1]^3),
+ * clipped to the unit box and [near_t, far_t].  n_coarse points at the bin
+ * midpoints give sigma_i = F(x_i) (trilinear, vertex-aligned: F[i] at
+ * i/(R-1)), delta_i = bin length in NOCS units, the termination mass of
+ * Eq. (5) and the CDF of Eq. (6).  n_fine stratified draws
+ * u_k = (k + xi_k)/n_fine (xi: [n_rays][n_fine], each in (0,1)) are inverted:
+ * bin b_k = first i with CDF_{i+1} >= u_k, linear inside the bin.  A ray whose
+ * total mass 1 - exp(-sum sigma delta) is below eps escapes to the uniform
+ * draws t_k = t_n + u_k (t_f - t_n) (Sec. III-B, escape rule).  The whole
+ * decision chain runs in FP64, so bins do not depend on FP32 rounding.
+ *
+ * Outputs (S = n_fine + (include_coarse ? n_coarse : 0)):
+ *   ray_obj [n_rays][6]  object-frame origin and direction (FP32)
+ *   t       [n_rays][S]  sorted sample distances (world units along the ray)
+ *   dt      [n_rays][S]  delta_j = (t_{j+1} - t_j) |d_obj|, last: (t_f - t_S-1)|d_obj|
+ *   bins    [n_rays][n_fine]  int32 CDF bin of each draw, -1 when uniform
+ *   flags   [n_rays]     uint8 PRENOM_FLAG_*; missed rays get t = dt = 0
+ * prior: device [R][R][R] (x fastest), R >= 2, or NULL (uniform draws).
+ * n_coarse in [1, 256] unless uniform_only; n_fine in [1, 256].
+ * ---------------------------------------------------------------------- */
+typedef struct prenom_sample_cfg {
+    int32_t n_coarse;
+    int32_t n_fine;
+    int32_t include_coarse; /* also render the n_coarse midpoints (sorted merge) */
+    int32_t uniform_only;   /* ignore the prior: stratified uniform draws        */
+    float eps;              /* escape threshold                                  */
+    float near_t, far_t;
+    float world_to_obj[12];
+    const float* prior;
+    int32_t prior_res;
+} prenom_sample_cfg;
+
+prenom_status prenom_sample(const prenom_sample_cfg* cfg, const float* rays_o, const float* rays_d,
+                            const float* xi, int64_t n_rays, float* ray_obj, float* t, float* dt,
+                            int32_t* bins, uint8_t* flags, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Rendering configuration.  loss_mode 0: mean squared errors,
+ *   L = 1/(3n) sum_k |C^_k - C_k|^2 + lambda_d/n sum_{mask} (D^_k - D_k)^2
+ *       + lambda_sigma/n sum_{!mask} sum_j sigma_kj
+ * loss_mode 1: the norms of Eq. (8) combined by Eq. (9),
+ *   L = sum_k |C^_k - C_k|_2 + lambda_d sum_{mask} |D^_k - D_k|
+ *       + lambda_sigma sum_{!mask} sum_j |sigma_kj|
+ * where C_k is tgt_rgb (for background rays: the background colour, the
+ * random colour of Eq. (8)).
+ * ---------------------------------------------------------------------- */
+typedef struct prenom_render_cfg {
+    int32_t n_samples; /* S, 1..256 */
+    int32_t loss_mode;
+    float lambda_d;
+    float lambda_sigma;
+} prenom_render_cfg;
+
+/* Bytes of device workspace render_fwd/render_bwd need for this batch. */
+size_t prenom_workspace_size(const prenom_arch* arch, int64_t n_rays, int32_t n_samples);
+
+/* ------------------------------------------------------------------------
+ * prenom_render_fwd -- Sec. III-B "Volume Rendering", Eq. (7)-(9).
+ *
+ * Sample positions x_j = clamp(fmaf(t_j, d, o), 0, 1) (o, d from ray_obj) are
+ * hash-encoded (Mueller et al. 2022, used in Sec. III-B "Object-level
+ * NeRFs"), fed through the MLP, and composited:
+ *   alpha_j = 1 - exp(-sigma_j delta_j), T_j = exp(-sum_{i<j} sigma_i delta_i),
+ *   rgb = sum_j T_j alpha_j c_j + T_S bg, depth = sum_j T_j alpha_j t_j,
+ *   opacity = sum_j T_j alpha_j.
+ * Missed rays (flags & MISS) give rgb = bg, depth = opacity = 0.
+ * Inputs: ray_obj [n][6], t, dt [n][S], flags [n] as from prenom_sample;
+ *   bg [n][3] or NULL (black); targets tgt_rgb [n][3], tgt_depth [n],
+ *   mask [n] (uint8, 1 = object ray) may all be NULL (no loss).
+ * Outputs: rgb [n][3], depth [n], opacity [n]; loss [1] (device scalar, or
+ *   NULL); sample_out [n][S][4] = (sigma, r, g, b) per sample, or NULL.
+ * workspace: >= prenom_workspace_size bytes, 256-byte aligned.  It carries
+ *   the per-sample features and per-ray results that prenom_render_bwd reads:
+ *   pass the same workspace and unchanged inputs to the matching bwd call.
+ * ---------------------------------------------------------------------- */
+prenom_status prenom_render_fwd(const prenom_model* model, const prenom_render_cfg* cfg,
+                                const float* ray_obj, const float* t, const float* dt,
+                                const uint8_t* flags, int64_t n_rays, const float* bg,
+                                const float* tgt_rgb, const float* tgt_depth, const uint8_t* mask,
+                                float* rgb, float* depth, float* opacity, float* loss,
+                                float* sample_out, void* workspace, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * prenom_render_bwd -- gradient of the rendering path (Sec. III-B, last
+ * paragraph: the loss of Eq. (9) is back-propagated to the NeRF parameters).
+ * Adds dL/dparams to model->grads.  With d_rgb [n][3] (and optionally
+ * d_depth [n]) given, the gradient is that of sum(d_rgb*rgb + d_depth*depth)
+ * (vector-Jacobian product for an outer autograd); with d_rgb == NULL it is
+ * the gradient of the fused loss of render_fwd (targets required).
+ * Must follow render_fwd on the same stream with the same workspace and
+ * inputs.  Table gradients are accumulated with FP32 atomics: summation order,
+ * hence the last bits, may differ between runs.
+ * ---------------------------------------------------------------------- */
+prenom_status prenom_render_bwd(const prenom_model* model, const prenom_render_cfg* cfg,
+                                const float* ray_obj, const float* t, const float* dt,
+                                const uint8_t* flags, int64_t n_rays, const float* bg,
+                                const float* tgt_rgb, const float* tgt_depth, const uint8_t* mask,
+                                const float* d_rgb, const float* d_depth, void* workspace,
+                                size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * prenom_adam_step -- Adam (Sec. III-B, last paragraph) on every parameter:
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *   p -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps)
+ * then zeroes the gradients.  step >= 1 is the 1-based iteration count.
+ * ---------------------------------------------------------------------- */
+typedef struct prenom_adam_cfg {
+    float lr, beta1, beta2, eps;
+    int64_t step;
+} prenom_adam_cfg;
+
+prenom_status prenom_adam_step(const prenom_model* model, const prenom_adam_cfg* cfg, void* stream);
+
+/* ------------------------------------------------------------------------
+ * prenom_encode -- the hash encoding alone (Sec. III-B "Object-level NeRFs"):
+ * pos [n][3] in [0,1]^3 -> features [L][n][F] (level-major); corner_idx
+ * [L][n][8] (int32 table row of each cell corner, corner e = (e&1, e>>1&1,
+ * e>>2&1)) or NULL.  table: [L][T][F].
+ * ---------------------------------------------------------------------- */
+prenom_status prenom_encode(const prenom_arch* arch, const float* table, const float* pos, int64_t n,
+                            float* features, int32_t* corner_idx, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Kernel timing (instrumentation, not part of the method).  Between
+ * prenom_profile_begin() and prenom_profile_end(), every kernel the library
+ * launches is bracketed by a pair of HIP events on its stream.
+ * prenom_profile_end waits for those events and returns, per kernel name,
+ * the number of launches and their summed duration in milliseconds
+ * (up to `capacity` entries; *n_kernels receives the number written).
+ * The events are created on first use and reused; nothing else allocates.
+ * ---------------------------------------------------------------------- */
+typedef struct prenom_kernel_time {
+    char name[48];
+    int64_t launches;
+    double total_ms;
+} prenom_kernel_time;
+
+prenom_status prenom_profile_begin(void);
+prenom_status prenom_profile_end(prenom_kernel_time* out, int32_t capacity, int32_t* n_kernels);
+
+const char* prenom_status_string(prenom_status s);
+const char* prenom_last_error(void);
+const char* prenom_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PRENOM_H */

@@ -103,7 +103,7 @@ static double orc_prior_at(const float* F, int R, const double x_in[3])
     double f[3];
     for (int a = 0; a < 3; ++a) {
         double x = x_in[a];
-        if (x < 0.0) x = 0.0;
+        if (!(x >= 0.0)) x = 0.0; /* also maps NaN to 0 */
         if (x > 1.0) x = 1.0;
         const double g = x * (double)(R - 1);
         int i = (int)floor(g);
@@ -234,7 +234,7 @@ void orc_sample(const orc_sample_cfg* c, const float* rays_o, const float* rays_
                     double x[3];
                     for (int a = 0; a < 3; ++a) {
                         x[a] = fma(m[i], d[a], o[a]);
-                        if (x[a] < 0.0) x[a] = 0.0;
+                        if (!(x[a] >= 0.0)) x[a] = 0.0;
                         if (x[a] > 1.0) x[a] = 1.0;
                     }
                     const double sig = orc_prior_at(c->prior, c->prior_res, x);
@@ -260,7 +260,7 @@ void orc_sample(const orc_sample_cfg* c, const float* rays_o, const float* rays_
                     br[k] = -1;
                 } else {
                     int b = 0;
-                    while (C[b + 1] < u) ++b; /* terminates: C[Nc] = 1 > u */
+                    while (b + 1 < Nc && C[b + 1] < u) ++b; /* C[Nc] = 1 > u for xi in (0,1) */
                     const double lo = C[b], hi = C[b + 1];
                     tf_k[k] = tn + delta * ((double)b + (u - lo) / (hi - lo));
                     br[k] = b;

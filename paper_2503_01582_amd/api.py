@@ -1,0 +1,255 @@
+"""Python binding of the C ABI (include/prenom.h), one function per entry point
+with the same name.  PyTorch supplies device memory and the current stream;
+every step of the computation runs in libprenom's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream() -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: Optional[torch.Tensor], dtype, name: str):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def make_arch(arch) -> L.PrenomArch:
+    """arch: object with n_levels, log2_table, n_features, resolutions, width, hidden."""
+    a = L.PrenomArch()
+    a.n_levels = arch.n_levels
+    a.log2_table = arch.log2_table
+    a.n_features = arch.n_features
+    for i, r in enumerate(arch.resolutions):
+        a.resolution[i] = int(r)
+    a.mlp_width = arch.width
+    a.mlp_hidden = arch.hidden
+    return a
+
+
+def prenom_param_count(arch) -> int:
+    return int(L.lib().prenom_param_count(C.byref(make_arch(arch))))
+
+
+def prenom_table_param_count(arch) -> int:
+    return int(L.lib().prenom_table_param_count(C.byref(make_arch(arch))))
+
+
+def prenom_workspace_size(arch, n_rays: int, n_samples: int) -> int:
+    return int(L.lib().prenom_workspace_size(C.byref(make_arch(arch)), n_rays, n_samples))
+
+
+class Model:
+    """One object NeRF on the device: parameters, gradients and Adam moments."""
+
+    def __init__(self, arch, params, device="cuda"):
+        self.arch = arch
+        n = prenom_param_count(arch)
+        if n < 0:
+            raise ValueError("invalid architecture")
+        p = torch.as_tensor(np.asarray(params, np.float32) if not torch.is_tensor(params) else params)
+        if p.numel() != n:
+            raise ValueError(f"expected {n} parameters, got {p.numel()}")
+        self.params = p.to(device=device, dtype=torch.float32).contiguous().clone()
+        self.grads = torch.zeros_like(self.params)
+        self.adam_m = torch.zeros_like(self.params)
+        self.adam_v = torch.zeros_like(self.params)
+        self.step = 0
+        self._c_arch = make_arch(arch)
+
+    def c_struct(self, grads: Optional[torch.Tensor] = None) -> L.PrenomModel:
+        m = L.PrenomModel()
+        m.arch = self._c_arch
+        m.params = self.params.data_ptr()
+        m.grads = (grads if grads is not None else self.grads).data_ptr()
+        m.adam_m = self.adam_m.data_ptr()
+        m.adam_v = self.adam_v.data_ptr()
+        return m
+
+    @property
+    def n_table(self) -> int:
+        return self.arch.n_table_params
+
+
+@dataclass
+class SampleOut:
+    ray_obj: torch.Tensor
+    t: torch.Tensor
+    dt: torch.Tensor
+    bins: torch.Tensor
+    flags: torch.Tensor
+
+    @property
+    def n_samples(self) -> int:
+        return self.t.shape[1]
+
+
+def alloc_sample_out(n_rays: int, n_fine: int, n_samples: int, device="cuda") -> SampleOut:
+    f = dict(device=device)
+    return SampleOut(ray_obj=torch.empty((n_rays, 6), dtype=torch.float32, **f),
+                     t=torch.empty((n_rays, n_samples), dtype=torch.float32, **f),
+                     dt=torch.empty((n_rays, n_samples), dtype=torch.float32, **f),
+                     bins=torch.empty((n_rays, n_fine), dtype=torch.int32, **f),
+                     flags=torch.empty((n_rays,), dtype=torch.uint8, **f))
+
+
+def sample_cfg(spec, world_to_obj, prior: Optional[torch.Tensor]) -> L.PrenomSampleCfg:
+    c = L.PrenomSampleCfg()
+    c.n_coarse = spec.n_coarse
+    c.n_fine = spec.n_fine
+    c.include_coarse = int(spec.include_coarse)
+    c.uniform_only = int(spec.uniform_only)
+    c.eps = spec.eps
+    c.near_t = spec.near
+    c.far_t = spec.far
+    A = np.asarray(world_to_obj, np.float32).reshape(12)
+    for i in range(12):
+        c.world_to_obj[i] = float(A[i])
+    if prior is not None:
+        _dev(prior, torch.float32, "prior")
+        c.prior = prior.data_ptr()
+        c.prior_res = prior.shape[0]
+    else:
+        c.prior = None
+        c.prior_res = 0
+    return c
+
+
+def prenom_sample(spec, rays_o: torch.Tensor, rays_d: torch.Tensor, xi: torch.Tensor, world_to_obj,
+                  prior: Optional[torch.Tensor] = None, out: Optional[SampleOut] = None) -> SampleOut:
+    _dev(rays_o, torch.float32, "rays_o")
+    _dev(rays_d, torch.float32, "rays_d")
+    _dev(xi, torch.float32, "xi")
+    n = rays_o.shape[0]
+    if rays_d.shape != (n, 3) or rays_o.shape != (n, 3) or xi.shape != (n, spec.n_fine):
+        raise ValueError("rays_o, rays_d must be [n, 3] and xi [n, n_fine]")
+    if out is None:
+        out = alloc_sample_out(n, spec.n_fine, spec.n_samples, rays_o.device)
+    cfg = sample_cfg(spec, world_to_obj, prior)
+    st = L.lib().prenom_sample(C.byref(cfg), _ptr(rays_o), _ptr(rays_d), _ptr(xi), n,
+                               _ptr(out.ray_obj), _ptr(out.t), _ptr(out.dt), _ptr(out.bins),
+                               _ptr(out.flags), _stream())
+    L.check(st, "prenom_sample")
+    return out
+
+
+def render_cfg(n_samples: int, loss) -> L.PrenomRenderCfg:
+    c = L.PrenomRenderCfg()
+    c.n_samples = n_samples
+    c.loss_mode = loss.loss_mode if loss is not None else 0
+    c.lambda_d = loss.lambda_d if loss is not None else 0.0
+    c.lambda_sigma = loss.lambda_sigma if loss is not None else 0.0
+    return c
+
+
+class Workspace:
+    """Device scratch for render_fwd/render_bwd, grown on demand."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.buf: Optional[torch.Tensor] = None
+
+    def get(self, arch, n_rays: int, n_samples: int) -> torch.Tensor:
+        need = prenom_workspace_size(arch, n_rays, n_samples)
+        if self.buf is None or self.buf.numel() < need:
+            self.buf = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+def prenom_render_fwd(model: Model, samp: SampleOut, loss_spec, ws: torch.Tensor, *, bg=None,
+                      tgt_rgb=None, tgt_depth=None, mask=None, want_loss=True, sample_out=None,
+                      out=None):
+    n, S = samp.t.shape
+    dev = samp.t.device
+    if out is None:
+        out = dict(rgb=torch.empty((n, 3), dtype=torch.float32, device=dev),
+                   depth=torch.empty((n,), dtype=torch.float32, device=dev),
+                   opacity=torch.empty((n,), dtype=torch.float32, device=dev),
+                   loss=torch.zeros((1,), dtype=torch.float32, device=dev))
+    _dev(bg, torch.float32, "bg")
+    _dev(tgt_rgb, torch.float32, "tgt_rgb")
+    _dev(tgt_depth, torch.float32, "tgt_depth")
+    _dev(mask, torch.uint8, "mask")
+    _dev(sample_out, torch.float32, "sample_out")
+    cfg = render_cfg(S, loss_spec)
+    mc = model.c_struct()
+    st = L.lib().prenom_render_fwd(
+        C.byref(mc), C.byref(cfg), _ptr(samp.ray_obj), _ptr(samp.t), _ptr(samp.dt), _ptr(samp.flags), n,
+        _ptr(bg), _ptr(tgt_rgb), _ptr(tgt_depth), _ptr(mask), _ptr(out["rgb"]), _ptr(out["depth"]),
+        _ptr(out["opacity"]), _ptr(out["loss"]) if (want_loss and tgt_rgb is not None) else None,
+        _ptr(sample_out), _ptr(ws), ws.numel(), _stream())
+    L.check(st, "prenom_render_fwd")
+    return out
+
+
+def prenom_render_bwd(model: Model, samp: SampleOut, loss_spec, ws: torch.Tensor, *, bg=None,
+                      tgt_rgb=None, tgt_depth=None, mask=None, d_rgb=None, d_depth=None,
+                      grads: Optional[torch.Tensor] = None):
+    n, S = samp.t.shape
+    _dev(d_rgb, torch.float32, "d_rgb")
+    _dev(d_depth, torch.float32, "d_depth")
+    cfg = render_cfg(S, loss_spec)
+    mc = model.c_struct(grads)
+    st = L.lib().prenom_render_bwd(
+        C.byref(mc), C.byref(cfg), _ptr(samp.ray_obj), _ptr(samp.t), _ptr(samp.dt), _ptr(samp.flags), n,
+        _ptr(bg), _ptr(tgt_rgb), _ptr(tgt_depth), _ptr(mask), _ptr(d_rgb), _ptr(d_depth), _ptr(ws),
+        ws.numel(), _stream())
+    L.check(st, "prenom_render_bwd")
+
+
+def prenom_adam_step(model: Model, *, lr=1e-2, beta1=0.9, beta2=0.99, eps=1e-15, step=None):
+    if step is None:
+        model.step += 1
+        step = model.step
+    c = L.PrenomAdamCfg()
+    c.lr, c.beta1, c.beta2, c.eps, c.step = lr, beta1, beta2, eps, step
+    mc = model.c_struct()
+    L.check(L.lib().prenom_adam_step(C.byref(mc), C.byref(c), _stream()), "prenom_adam_step")
+
+
+def prenom_encode(arch, table: torch.Tensor, pos: torch.Tensor, with_corners=False):
+    _dev(table, torch.float32, "table")
+    _dev(pos, torch.float32, "pos")
+    n = pos.shape[0]
+    feats = torch.empty((arch.n_levels, n, arch.n_features), dtype=torch.float32, device=pos.device)
+    idx = torch.empty((arch.n_levels, n, 8), dtype=torch.int32, device=pos.device) if with_corners else None
+    a = make_arch(arch)
+    st = L.lib().prenom_encode(C.byref(a), _ptr(table), _ptr(pos), n, _ptr(feats), _ptr(idx), _stream())
+    L.check(st, "prenom_encode")
+    return (feats, idx) if with_corners else feats
+
+
+def prenom_profile_begin():
+    L.check(L.lib().prenom_profile_begin(), "prenom_profile_begin")
+
+
+def prenom_profile_end(capacity: int = 64) -> dict:
+    """{kernel name: (launches, total milliseconds)} since profile_begin."""
+    arr = (L.PrenomKernelTime * capacity)()
+    n = C.c_int32(0)
+    L.check(L.lib().prenom_profile_end(arr, capacity, C.byref(n)), "prenom_profile_end")
+    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(n.value)}
+
+
+def version() -> str:
+    return L.lib().prenom_version().decode()

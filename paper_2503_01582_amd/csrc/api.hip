@@ -1,0 +1,462 @@
+// C ABI of libprenom: argument validation, workspace layout and the launch
+// sequence of each call.  Host code only; every kernel lives in its own unit.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "common.h"
+
+namespace {
+
+using namespace prenom;
+
+thread_local char g_last_error[512] = "";
+
+prenom_status fail(prenom_status st, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+prenom_status hip_status(hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return PRENOM_OK;
+    return fail(PRENOM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define PRENOM_TRY_HIP(expr, what)                          \
+    do {                                                    \
+        const prenom_status st_ = hip_status((expr), what); \
+        if (st_ != PRENOM_OK) return st_;                   \
+    } while (0)
+
+// ---------------------------------------------------------------- kernel timing
+struct ProfRecord {
+    const char* name;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRecord> g_prof_records;
+std::vector<hipEvent_t> g_event_pool;
+size_t g_pool_used = 0;
+
+hipEvent_t pool_event()
+{
+    if (g_pool_used == g_event_pool.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        g_event_pool.push_back(e);
+    }
+    return g_event_pool[g_pool_used++];
+}
+
+// Runs one launcher; brackets it with events when timing is on.
+template <class F>
+hipError_t timed(const char* name, hipStream_t s, F&& launch)
+{
+    hipEvent_t a = nullptr, b = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        if (g_prof_on) {
+            a = pool_event();
+            b = pool_event();
+        }
+    }
+    if (a && b) hipEventRecord(a, s);
+    const hipError_t e = launch();
+    if (a && b) {
+        hipEventRecord(b, s);
+        std::lock_guard<std::mutex> lk(g_prof_mu);
+        g_prof_records.push_back({name, a, b});
+    }
+    return e;
+}
+
+#define PRENOM_LAUNCH(name, stream, expr) PRENOM_TRY_HIP(timed(name, stream, [&] { return (expr); }), name)
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
+
+// Shape rules an architecture must satisfy (independent of what is compiled).
+prenom_status check_arch(const prenom_arch* a)
+{
+    if (!a) return fail(PRENOM_ERR_INVALID_ARG, "arch is NULL");
+    if (a->n_levels < 1 || a->n_levels > PRENOM_MAX_LEVELS)
+        return fail(PRENOM_ERR_INVALID_ARG, "n_levels %d outside [1, %d]", a->n_levels, PRENOM_MAX_LEVELS);
+    if (a->log2_table < 10 || a->log2_table > 24)
+        return fail(PRENOM_ERR_INVALID_ARG, "log2_table %d outside [10, 24]", a->log2_table);
+    if (a->n_features != 2) return fail(PRENOM_ERR_UNSUPPORTED, "n_features %d (only 2)", a->n_features);
+    for (int l = 0; l < a->n_levels; ++l)
+        if (a->resolution[l] < 2 || a->resolution[l] >= (1 << 20))
+            return fail(PRENOM_ERR_INVALID_ARG, "resolution[%d] = %d outside [2, 2^20)", l, a->resolution[l]);
+    if (a->mlp_width < 16 || a->mlp_width % 16 || a->mlp_hidden < 1 || a->mlp_hidden > 4)
+        return fail(PRENOM_ERR_INVALID_ARG, "mlp %d x %d", a->mlp_width, a->mlp_hidden);
+    return PRENOM_OK;
+}
+
+prenom_status check_supported(const prenom_arch* a)
+{
+    const prenom_status st = check_arch(a);
+    if (st != PRENOM_OK) return st;
+    const MlpShape m{a->n_levels * a->n_features, a->mlp_width, a->mlp_hidden};
+    if (!mlp_supported(m))
+        return fail(PRENOM_ERR_UNSUPPORTED, "MLP in=%d width=%d hidden=%d is not compiled into this library",
+                    m.in_dim, m.width, m.hidden);
+    return PRENOM_OK;
+}
+
+int64_t table_params(const prenom_arch* a) { return ((int64_t)a->n_levels << a->log2_table) * a->n_features; }
+
+int64_t mlp_params(const prenom_arch* a)
+{
+    const int64_t in = (int64_t)a->n_levels * a->n_features, W = a->mlp_width;
+    return W * in + (int64_t)(a->mlp_hidden - 1) * W * W + (int64_t)PRENOM_N_OUT * W;
+}
+
+GridInfo grid_info(const prenom_arch* a)
+{
+    GridInfo g{};
+    g.n_levels = a->n_levels;
+    g.log2_table = a->log2_table;
+    g.dense_mask = 0;
+    const int64_t T = (int64_t)1 << a->log2_table;
+    for (int l = 0; l < a->n_levels; ++l) {
+        g.res[l] = a->resolution[l];
+        const int64_t side = (int64_t)a->resolution[l] + 1;
+        if (side * side * side <= T) g.dense_mask |= 1u << l;
+    }
+    return g;
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct WsLayout {
+    size_t y, sc, dout, dy, ray_state, loss_partial, mlp_partial, total;
+    int n_loss_blocks, n_mlp_slots;
+};
+
+WsLayout ws_layout(const prenom_arch* a, int64_t n_rays, int32_t S)
+{
+    WsLayout w{};
+    const size_t n_s = (size_t)n_rays * (size_t)S, L = (size_t)a->n_levels;
+    size_t off = 0;
+    w.y = off;
+    off = align_up(off + L * n_s * 2 * sizeof(float));
+    w.sc = off;
+    off = align_up(off + n_s * 4 * sizeof(float));
+    w.dout = off;
+    off = align_up(off + n_s * 4 * sizeof(float));
+    w.dy = off;
+    off = align_up(off + L * n_s * 2 * sizeof(float));
+    w.ray_state = off;
+    off = align_up(off + (size_t)n_rays * 8 * sizeof(float));
+    w.n_loss_blocks = composite_loss_blocks(n_rays);
+    w.loss_partial = off;
+    off = align_up(off + (size_t)(w.n_loss_blocks > 0 ? w.n_loss_blocks : 1) * sizeof(double));
+    w.n_mlp_slots = mlp_bwd_waves((int64_t)n_s);
+    w.mlp_partial = off;
+    off = align_up(off + (size_t)w.n_mlp_slots * (size_t)mlp_params(a) * sizeof(float));
+    w.total = off;
+    return w;
+}
+
+template <typename T>
+T* at(void* base, size_t off)
+{
+    return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+prenom_status check_model(const prenom_model* m, bool need_grads)
+{
+    if (!m) return fail(PRENOM_ERR_INVALID_ARG, "model is NULL");
+    const prenom_status st = check_supported(&m->arch);
+    if (st != PRENOM_OK) return st;
+    if (!m->params || !aligned(m->params, 16)) return fail(PRENOM_ERR_INVALID_ARG, "params NULL or not 16-byte aligned");
+    if (need_grads && (!m->grads || !aligned(m->grads, 16)))
+        return fail(PRENOM_ERR_INVALID_ARG, "grads NULL or not 16-byte aligned");
+    return PRENOM_OK;
+}
+
+prenom_status check_render(const prenom_model* model, const prenom_render_cfg* cfg, const float* ray_obj,
+                           const float* t, const float* dt, const uint8_t* flags, int64_t n_rays, void* ws,
+                           size_t ws_bytes, bool need_grads)
+{
+    prenom_status st = check_model(model, need_grads);
+    if (st != PRENOM_OK) return st;
+    if (!cfg) return fail(PRENOM_ERR_INVALID_ARG, "cfg is NULL");
+    if (cfg->n_samples < 1 || cfg->n_samples > 256)
+        return fail(PRENOM_ERR_SHAPE, "n_samples %d outside [1, 256]", cfg->n_samples);
+    if (cfg->loss_mode != 0 && cfg->loss_mode != 1) return fail(PRENOM_ERR_INVALID_ARG, "loss_mode %d", cfg->loss_mode);
+    if (!(cfg->lambda_d >= 0.0f) || !(cfg->lambda_sigma >= 0.0f))
+        return fail(PRENOM_ERR_INVALID_ARG, "negative or NaN loss weight");
+    if (n_rays < 0) return fail(PRENOM_ERR_SHAPE, "n_rays < 0");
+    if ((double)n_rays * cfg->n_samples >= 2147483648.0) return fail(PRENOM_ERR_SHAPE, "n_rays * n_samples >= 2^31");
+    if (n_rays > 0 && (!ray_obj || !t || !dt || !flags))
+        return fail(PRENOM_ERR_INVALID_ARG, "ray_obj, t, dt and flags are required");
+    const WsLayout w = ws_layout(&model->arch, n_rays, cfg->n_samples);
+    if (!ws || !aligned(ws, kAlign)) return fail(PRENOM_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
+    if (ws_bytes < w.total)
+        return fail(PRENOM_ERR_WORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, w.total);
+    return PRENOM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t prenom_param_count(const prenom_arch* arch)
+{
+    if (check_arch(arch) != PRENOM_OK) return -1;
+    return table_params(arch) + mlp_params(arch);
+}
+
+int64_t prenom_table_param_count(const prenom_arch* arch)
+{
+    if (check_arch(arch) != PRENOM_OK) return -1;
+    return table_params(arch);
+}
+
+size_t prenom_workspace_size(const prenom_arch* arch, int64_t n_rays, int32_t n_samples)
+{
+    if (check_arch(arch) != PRENOM_OK || n_rays < 0 || n_samples < 1) return 0;
+    return ws_layout(arch, n_rays, n_samples).total;
+}
+
+prenom_status prenom_sample(const prenom_sample_cfg* cfg, const float* rays_o, const float* rays_d, const float* xi,
+                            int64_t n_rays, float* ray_obj, float* t, float* dt, int32_t* bins, uint8_t* flags,
+                            void* stream)
+{
+    if (!cfg) return fail(PRENOM_ERR_INVALID_ARG, "cfg is NULL");
+    if (n_rays < 0) return fail(PRENOM_ERR_SHAPE, "n_rays < 0");
+    if (cfg->n_fine < 1 || cfg->n_fine > 256) return fail(PRENOM_ERR_SHAPE, "n_fine %d outside [1, 256]", cfg->n_fine);
+    const bool use_prior = !cfg->uniform_only && cfg->prior != nullptr;
+    if (cfg->n_coarse < 0 || cfg->n_coarse > 256) return fail(PRENOM_ERR_SHAPE, "n_coarse %d outside [0, 256]", cfg->n_coarse);
+    if ((use_prior || cfg->include_coarse) && cfg->n_coarse < 1)
+        return fail(PRENOM_ERR_SHAPE, "n_coarse must be >= 1 with a prior or include_coarse");
+    if (use_prior && cfg->prior_res < 2) return fail(PRENOM_ERR_SHAPE, "prior_res %d < 2", cfg->prior_res);
+    if (!(cfg->eps >= 0.0f)) return fail(PRENOM_ERR_INVALID_ARG, "eps must be >= 0");
+    if (!(cfg->near_t <= cfg->far_t)) return fail(PRENOM_ERR_INVALID_ARG, "near_t > far_t");
+    for (int i = 0; i < 12; ++i)
+        if (!std::isfinite(cfg->world_to_obj[i])) return fail(PRENOM_ERR_INVALID_ARG, "world_to_obj not finite");
+    if (n_rays > 0 && (!rays_o || !rays_d || !xi || !ray_obj || !t || !dt || !bins || !flags))
+        return fail(PRENOM_ERR_INVALID_ARG, "NULL array argument");
+    SampleArgs a{};
+    a.n_coarse = cfg->n_coarse;
+    a.n_fine = cfg->n_fine;
+    a.include_coarse = cfg->include_coarse ? 1 : 0;
+    a.use_prior = use_prior ? 1 : 0;
+    a.eps = (double)cfg->eps;
+    a.near_t = (double)cfg->near_t;
+    a.far_t = (double)cfg->far_t;
+    for (int i = 0; i < 12; ++i) a.A[i] = (double)cfg->world_to_obj[i];
+    a.prior = cfg->prior;
+    a.R = cfg->prior_res;
+    a.rays_o = rays_o;
+    a.rays_d = rays_d;
+    a.xi = xi;
+    a.n = n_rays;
+    a.ray_obj = ray_obj;
+    a.t = t;
+    a.dt = dt;
+    a.bins = bins;
+    a.flags = flags;
+    PRENOM_LAUNCH("k_sample", (hipStream_t)stream, launch_sample(a, (hipStream_t)stream));
+    return PRENOM_OK;
+}
+
+prenom_status prenom_render_fwd(const prenom_model* model, const prenom_render_cfg* cfg, const float* ray_obj,
+                                const float* t, const float* dt, const uint8_t* flags, int64_t n_rays, const float* bg,
+                                const float* tgt_rgb, const float* tgt_depth, const uint8_t* mask, float* rgb,
+                                float* depth, float* opacity, float* loss, float* sample_out, void* workspace,
+                                size_t ws_bytes, void* stream)
+{
+    prenom_status st = check_render(model, cfg, ray_obj, t, dt, flags, n_rays, workspace, ws_bytes, false);
+    if (st != PRENOM_OK) return st;
+    if (n_rays > 0 && (!rgb || !depth || !opacity)) return fail(PRENOM_ERR_INVALID_ARG, "rgb, depth, opacity required");
+    if (loss && !tgt_rgb && n_rays > 0) return fail(PRENOM_ERR_INVALID_ARG, "loss requested without tgt_rgb");
+    hipStream_t s = (hipStream_t)stream;
+    const prenom_arch* a = &model->arch;
+    const WsLayout w = ws_layout(a, n_rays, cfg->n_samples);
+    const int64_t n_s = n_rays * cfg->n_samples;
+    const GridInfo g = grid_info(a);
+    float* y = at<float>(workspace, w.y);
+    float* sc = at<float>(workspace, w.sc);
+    PRENOM_LAUNCH("k_encode_fwd", s, launch_encode_samples(g, model->params, ray_obj, t, n_rays, cfg->n_samples, y, s));
+    const MlpShape m{a->n_levels * a->n_features, a->mlp_width, a->mlp_hidden};
+    PRENOM_LAUNCH("k_mlp_fwd", s, launch_mlp_fwd(m, model->params + table_params(a), y, n_s, sc, s));
+    CompositeArgs c{};
+    c.n_rays = n_rays;
+    c.S = cfg->n_samples;
+    c.loss_mode = cfg->loss_mode;
+    c.lambda_d = cfg->lambda_d;
+    c.lambda_sigma = cfg->lambda_sigma;
+    c.sc = sc;
+    c.t = t;
+    c.dt = dt;
+    c.flags = flags;
+    c.bg = bg;
+    c.tgt_rgb = tgt_rgb;
+    c.tgt_depth = tgt_depth;
+    c.mask = mask;
+    c.rgb = rgb;
+    c.depth = depth;
+    c.opacity = opacity;
+    c.ray_state = at<float>(workspace, w.ray_state);
+    c.loss_partial = loss ? at<double>(workspace, w.loss_partial) : nullptr;
+    PRENOM_LAUNCH("k_composite_fwd", s, launch_composite_fwd(c, s));
+    if (loss) PRENOM_LAUNCH("k_loss_finalize", s, launch_loss_finalize(c.loss_partial, w.n_loss_blocks, loss, s));
+    if (sample_out && n_s > 0)
+        PRENOM_TRY_HIP(hipMemcpyAsync(sample_out, sc, (size_t)n_s * 4 * sizeof(float), hipMemcpyDeviceToDevice, s),
+                       "copy sample_out");
+    return PRENOM_OK;
+}
+
+prenom_status prenom_render_bwd(const prenom_model* model, const prenom_render_cfg* cfg, const float* ray_obj,
+                                const float* t, const float* dt, const uint8_t* flags, int64_t n_rays, const float* bg,
+                                const float* tgt_rgb, const float* tgt_depth, const uint8_t* mask, const float* d_rgb,
+                                const float* d_depth, void* workspace, size_t ws_bytes, void* stream)
+{
+    prenom_status st = check_render(model, cfg, ray_obj, t, dt, flags, n_rays, workspace, ws_bytes, true);
+    if (st != PRENOM_OK) return st;
+    if (!d_rgb && !tgt_rgb && n_rays > 0)
+        return fail(PRENOM_ERR_INVALID_ARG, "either d_rgb or the loss targets are required");
+    hipStream_t s = (hipStream_t)stream;
+    const prenom_arch* a = &model->arch;
+    const WsLayout w = ws_layout(a, n_rays, cfg->n_samples);
+    const int64_t n_s = n_rays * cfg->n_samples;
+    CompositeArgs c{};
+    c.n_rays = n_rays;
+    c.S = cfg->n_samples;
+    c.loss_mode = cfg->loss_mode;
+    c.lambda_d = cfg->lambda_d;
+    c.lambda_sigma = cfg->lambda_sigma;
+    c.sc = at<float>(workspace, w.sc);
+    c.t = t;
+    c.dt = dt;
+    c.flags = flags;
+    c.bg = bg;
+    c.tgt_rgb = tgt_rgb;
+    c.tgt_depth = tgt_depth;
+    c.mask = mask;
+    c.ray_state = at<float>(workspace, w.ray_state);
+    c.d_rgb = d_rgb;
+    c.d_depth = d_depth;
+    c.dout = at<float>(workspace, w.dout);
+    PRENOM_LAUNCH("k_composite_bwd", s, launch_composite_bwd(c, s));
+    const MlpShape m{a->n_levels * a->n_features, a->mlp_width, a->mlp_hidden};
+    float* partial = at<float>(workspace, w.mlp_partial);
+    float* dy = at<float>(workspace, w.dy);
+    PRENOM_LAUNCH("k_mlp_bwd", s,
+                  launch_mlp_bwd(m, model->params + table_params(a), at<float>(workspace, w.y), c.dout, n_s, dy,
+                                 partial, s));
+    if (n_s > 0)
+        PRENOM_LAUNCH("k_reduce_partials", s,
+                      launch_reduce_partials(partial, w.n_mlp_slots, mlp_params(a), model->grads + table_params(a), s));
+    PRENOM_LAUNCH("k_encode_bwd", s,
+                  launch_encode_bwd(grid_info(a), ray_obj, t, n_rays, cfg->n_samples, dy, model->grads, s));
+    return PRENOM_OK;
+}
+
+prenom_status prenom_adam_step(const prenom_model* model, const prenom_adam_cfg* cfg, void* stream)
+{
+    prenom_status st = check_model(model, true);
+    if (st != PRENOM_OK) return st;
+    if (!cfg) return fail(PRENOM_ERR_INVALID_ARG, "cfg is NULL");
+    if (cfg->step < 1) return fail(PRENOM_ERR_INVALID_ARG, "step must be >= 1");
+    if (!model->adam_m || !model->adam_v || !aligned(model->adam_m, 16) || !aligned(model->adam_v, 16))
+        return fail(PRENOM_ERR_INVALID_ARG, "adam moments NULL or not 16-byte aligned");
+    if (!(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f && cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f && cfg->lr >= 0.0f &&
+          cfg->eps >= 0.0f))
+        return fail(PRENOM_ERR_INVALID_ARG, "Adam hyper-parameters out of range");
+    AdamArgs a{};
+    a.p = model->params;
+    a.g = model->grads;
+    a.m = model->adam_m;
+    a.v = model->adam_v;
+    a.n = table_params(&model->arch) + mlp_params(&model->arch);
+    a.lr = cfg->lr;
+    a.beta1 = cfg->beta1;
+    a.beta2 = cfg->beta2;
+    a.eps = cfg->eps;
+    a.inv_c1 = (float)(1.0 / (1.0 - std::pow((double)cfg->beta1, (double)cfg->step)));
+    a.inv_c2 = (float)(1.0 / (1.0 - std::pow((double)cfg->beta2, (double)cfg->step)));
+    PRENOM_LAUNCH("k_adam", (hipStream_t)stream, launch_adam(a, (hipStream_t)stream));
+    return PRENOM_OK;
+}
+
+prenom_status prenom_encode(const prenom_arch* arch, const float* table, const float* pos, int64_t n, float* features,
+                            int32_t* corner_idx, void* stream)
+{
+    prenom_status st = check_arch(arch);
+    if (st != PRENOM_OK) return st;
+    if (n < 0 || n >= (int64_t)1 << 31) return fail(PRENOM_ERR_SHAPE, "n outside [0, 2^31)");
+    if (n > 0 && (!table || !pos || !features)) return fail(PRENOM_ERR_INVALID_ARG, "NULL array argument");
+    if (table && !aligned(table, 8)) return fail(PRENOM_ERR_INVALID_ARG, "table not 8-byte aligned");
+    if (features && !aligned(features, 8)) return fail(PRENOM_ERR_INVALID_ARG, "features not 8-byte aligned");
+    PRENOM_LAUNCH("k_encode_points", (hipStream_t)stream,
+                  launch_encode_points(grid_info(arch), table, pos, n, features, corner_idx, (hipStream_t)stream));
+    return PRENOM_OK;
+}
+
+prenom_status prenom_profile_begin(void)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = true;
+    g_prof_records.clear();
+    g_pool_used = 0;
+    return PRENOM_OK;
+}
+
+prenom_status prenom_profile_end(prenom_kernel_time* out, int32_t capacity, int32_t* n_kernels)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = false;
+    int32_t n = 0;
+    for (const ProfRecord& r : g_prof_records) {
+        PRENOM_TRY_HIP(hipEventSynchronize(r.b), "hipEventSynchronize");
+        float ms = 0.0f;
+        PRENOM_TRY_HIP(hipEventElapsedTime(&ms, r.a, r.b), "hipEventElapsedTime");
+        int32_t k = 0;
+        while (k < n && std::strncmp(out[k].name, r.name, sizeof(out[k].name)) != 0) ++k;
+        if (k == n) {
+            if (!out || n >= capacity) continue;
+            std::memset(out[k].name, 0, sizeof(out[k].name));
+            std::strncpy(out[k].name, r.name, sizeof(out[k].name) - 1);
+            out[k].launches = 0;
+            out[k].total_ms = 0.0;
+            ++n;
+        }
+        out[k].launches += 1;
+        out[k].total_ms += (double)ms;
+    }
+    g_prof_records.clear();
+    g_pool_used = 0;
+    if (n_kernels) *n_kernels = n;
+    return PRENOM_OK;
+}
+
+const char* prenom_status_string(prenom_status s)
+{
+    switch (s) {
+        case PRENOM_OK: return "ok";
+        case PRENOM_ERR_INVALID_ARG: return "invalid argument";
+        case PRENOM_ERR_SHAPE: return "inconsistent shape";
+        case PRENOM_ERR_UNSUPPORTED: return "unsupported architecture";
+        case PRENOM_ERR_WORKSPACE: return "workspace too small";
+        case PRENOM_ERR_HIP: return "HIP error";
+    }
+    return "unknown status";
+}
+
+const char* prenom_last_error(void) { return g_last_error; }
+
+const char* prenom_version(void) { return "prenom-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,479 @@
+// The shallow MLP of the object NeRF (Sec. III-B "Object-level NeRFs" and
+// "Volume Rendering"): encoded position -> D bias-free ReLU layers of width W
+// -> 4 linear outputs; density = exp(o0), colour = sigmoid(o1..3).
+//
+// Both passes run on the matrix cores with v_mfma_f32_16x16x4_f32, in the
+// transposed form H^T = W X^T: a 16-sample tile is the N (column) dimension,
+// neurons are rows.  Operand layouts of the 16x16x4 instruction (lane l,
+// q = l/16, j = l%16):  A[i][k] at lane i + 16k, B[k][n] at lane n + 16k,
+// D[i][n] at lane n + 16*(i/4), register i%4.  With that layout the output
+// registers of one layer are directly the B operand of the next: register r of
+// output tile ti holds neuron 16 ti + 4 q + r of sample j, so K-step (ti, r)
+// of the next layer covers those neurons and the weight fragment is permuted
+// to match.  Weights are permuted once per block into LDS "fragments" of 64
+// floats (one value per lane), read conflict-free.
+//
+// Backward: the adjoint runs the same chain with W^T fragments; the weight
+// gradient dW = delta h^T contracts over samples, so delta and h of the tile
+// go through a per-wave LDS transpose and are accumulated in registers for all
+// tiles the wave processes; each wave finally writes one partial dW, and a
+// reduction kernel sums the partials in FP64 into the gradient buffer.
+#include "common.h"
+
+namespace prenom {
+namespace {
+
+__device__ __forceinline__ floatx4 mfma4(float a, float b, floatx4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ floatx4 relu4(floatx4 v)
+{
+    floatx4 r;
+    r[0] = fmaxf(v[0], 0.0f);
+    r[1] = fmaxf(v[1], 0.0f);
+    r[2] = fmaxf(v[2], 0.0f);
+    r[3] = fmaxf(v[3], 0.0f);
+    return r;
+}
+
+__device__ __forceinline__ floatx4 mask_pos(floatx4 g, floatx4 h)
+{
+    floatx4 r;
+    r[0] = h[0] > 0.0f ? g[0] : 0.0f;
+    r[1] = h[1] > 0.0f ? g[1] : 0.0f;
+    r[2] = h[2] > 0.0f ? g[2] : 0.0f;
+    r[3] = h[3] > 0.0f ? g[3] : 0.0f;
+    return r;
+}
+
+// Orders one wave's LDS writes before its later LDS reads (and reads before
+// later overwrites): a wave's LDS operations execute in program order, so
+// only compiler reordering has to be prevented.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ float sigmoidf_(float z) { return 1.0f / (1.0f + __expf(-z)); }
+
+template <int IN, int W, int D>
+struct Net {
+    static constexpr int KT1 = IN / 4;          // K-steps of layer 1
+    static constexpr int OT = W / 16;           // 16-row tiles of a hidden layer
+    static constexpr int KTH = W / 4;           // K-steps over a hidden layer
+    static constexpr int IT = (IN + 15) / 16;   // 16-row tiles of the input
+    // forward fragments
+    static constexpr int F1 = 0;                         // [OT][KT1]
+    static constexpr int FH = F1 + OT * KT1;             // [D-1][OT][KTH]
+    static constexpr int FO = FH + (D - 1) * OT * KTH;   // [KTH]
+    static constexpr int N_FWD = FO + KTH;
+    // backward fragments
+    static constexpr int BO = N_FWD;                     // [OT]
+    static constexpr int BH = BO + OT;                   // [D-1][OT][KTH]
+    static constexpr int B1 = BH + (D - 1) * OT * KTH;   // [IT][KTH]
+    static constexpr int N_ALL = B1 + IT * KTH;
+    // parameter offsets (row-major layers)
+    static constexpr int OFF_W1 = 0;
+    static constexpr int OFF_H = W * IN;                 // + (k-1)*W*W
+    static constexpr int OFF_OUT = W * IN + (D - 1) * W * W;
+    static constexpr int N_PARAMS = OFF_OUT + 4 * W;
+    static_assert(IN % 4 == 0 && W % 16 == 0 && D >= 1, "shape");
+};
+
+// Builds the weight fragments of one block in LDS.
+template <int IN, int W, int D>
+__device__ void load_fragments(const float* __restrict__ w, float* __restrict__ frag, int n_frag)
+{
+    using N = Net<IN, W, D>;
+    for (int idx = threadIdx.x; idx < n_frag * 64; idx += blockDim.x) {
+        const int f = idx >> 6, l = idx & 63, q = l >> 4, j = l & 15;
+        float v = 0.0f;
+        if (f < N::FH) {  // W1[16 to + j][4 kk + q]
+            const int to = f / N::KT1, kk = f % N::KT1;
+            v = w[N::OFF_W1 + (16 * to + j) * IN + 4 * kk + q];
+        } else if (f < N::FO) {  // Wk[16 to + j][16 ti + 4 q + r]
+            const int g = f - N::FH, k = g / (N::OT * N::KTH), rem = g % (N::OT * N::KTH);
+            const int to = rem / N::KTH, ks = rem % N::KTH, ti = ks >> 2, r = ks & 3;
+            v = w[N::OFF_H + k * W * W + (16 * to + j) * W + 16 * ti + 4 * q + r];
+        } else if (f < N::N_FWD) {  // Wout[j][16 ti + 4 q + r], rows >= 4 zero
+            const int ks = f - N::FO, ti = ks >> 2, r = ks & 3;
+            v = j < 4 ? w[N::OFF_OUT + j * W + 16 * ti + 4 * q + r] : 0.0f;
+        } else if (f < N::BH) {  // Wout^T: A[i=j][k=q] = Wout[q][16 to + j]
+            const int to = f - N::BO;
+            v = w[N::OFF_OUT + q * W + 16 * to + j];
+        } else if (f < N::B1) {  // Wk^T: Wk[16 ti + 4 q + r][16 to + j]
+            const int g = f - N::BH, k = g / (N::OT * N::KTH), rem = g % (N::OT * N::KTH);
+            const int to = rem / N::KTH, ks = rem % N::KTH, ti = ks >> 2, r = ks & 3;
+            v = w[N::OFF_H + k * W * W + (16 * ti + 4 * q + r) * W + 16 * to + j];
+        } else {  // W1^T: W1[16 ti + 4 q + r][16 to + j], cols >= IN zero
+            const int g = f - N::B1, to = g / N::KTH, ks = g % N::KTH, ti = ks >> 2, r = ks & 3;
+            const int col = 16 * to + j;
+            v = col < IN ? w[N::OFF_W1 + (16 * ti + 4 * q + r) * IN + col] : 0.0f;
+        }
+        frag[idx] = v;
+    }
+}
+
+// Layer-1 B operand of K-step kk: feature 4 kk + q of sample s, from the
+// level-major feature array y [L][n][2].
+template <int KT1>
+__device__ __forceinline__ void load_inputs(const float* __restrict__ y, int64_t n_s, int64_t s, bool valid,
+                                            int q, float (&yb)[KT1])
+{
+#pragma unroll
+    for (int kk = 0; kk < KT1; ++kk) {
+        const int level = 2 * kk + (q >> 1), comp = q & 1;
+        yb[kk] = valid ? y[((int64_t)level * n_s + s) * 2 + comp] : 0.0f;
+    }
+}
+
+// Forward through the hidden layers and the head; hs[k] = output of layer k.
+template <int IN, int W, int D>
+__device__ __forceinline__ void mlp_chain(const float* __restrict__ frag, int lane,
+                                          const float (&yb)[Net<IN, W, D>::KT1],
+                                          floatx4 (&hs)[D][Net<IN, W, D>::OT], floatx4& o)
+{
+    using N = Net<IN, W, D>;
+#pragma unroll
+    for (int to = 0; to < N::OT; ++to) {
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int kk = 0; kk < N::KT1; ++kk) acc = mfma4(frag[(N::F1 + to * N::KT1 + kk) * 64 + lane], yb[kk], acc);
+        hs[0][to] = relu4(acc);
+    }
+#pragma unroll
+    for (int k = 1; k < D; ++k) {
+#pragma unroll
+        for (int to = 0; to < N::OT; ++to) {
+            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int ks = 0; ks < N::KTH; ++ks)
+                acc = mfma4(frag[(N::FH + ((k - 1) * N::OT + to) * N::KTH + ks) * 64 + lane], hs[k - 1][ks >> 2][ks & 3],
+                            acc);
+            hs[k][to] = relu4(acc);
+        }
+    }
+    o = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ks = 0; ks < N::KTH; ++ks) o = mfma4(frag[(N::FO + ks) * 64 + lane], hs[D - 1][ks >> 2][ks & 3], o);
+}
+
+template <int IN, int W, int D>
+__global__ __launch_bounds__(256) void k_mlp_fwd(const float* __restrict__ w, const float* __restrict__ y,
+                                                 int64_t n_s, float4* __restrict__ sc)
+{
+    using N = Net<IN, W, D>;
+    __shared__ float frag[N::N_FWD * 64];
+    load_fragments<IN, W, D>(w, frag, N::N_FWD);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, q = lane >> 4, j = lane & 15;
+    const int64_t n_tiles = (n_s + 15) / 16;
+    const int64_t wave0 = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x / 64);
+    for (int64_t tile = wave0; tile < n_tiles; tile += n_waves) {
+        const int64_t s = tile * 16 + j;
+        const bool valid = s < n_s;
+        float yb[N::KT1];
+        load_inputs<N::KT1>(y, n_s, s, valid, q, yb);
+        floatx4 hs[D][N::OT];
+        floatx4 o;
+        mlp_chain<IN, W, D>(frag, lane, yb, hs, o);
+        if (q == 0 && valid) sc[s] = make_float4(__expf(o[0]), sigmoidf_(o[1]), sigmoidf_(o[2]), sigmoidf_(o[3]));
+    }
+}
+
+constexpr int kBwdWaves = 8;     // waves per block of the backward kernel
+constexpr int kBwdMaxBlocks = 256;
+constexpr int kStagePad = 4;
+
+template <int IN, int W, int D>
+struct BwdLds {
+    static constexpr int IP = 16 * Net<IN, W, D>::IT;           // input dim padded to 16
+    static constexpr int HW = (W > IP ? W : IP) + kStagePad;    // H row pitch
+    static constexpr int DW = W + kStagePad;                    // Delta row pitch
+    static constexpr int PER_WAVE = 16 * (HW + DW);
+};
+
+// Stage the tile's delta (D layout, out tiles) and h (D layout) for the
+// dW = delta h^T contraction over the 16 samples.
+template <int OTILES, int ITILES, int DP, int HP>
+__device__ __forceinline__ void stage_dw(float* __restrict__ sD, float* __restrict__ sH,
+                                         const floatx4 (&delta)[OTILES], const floatx4 (&h)[ITILES], int q, int j)
+{
+#pragma unroll
+    for (int to = 0; to < OTILES; ++to)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sD[j * DP + 16 * to + 4 * q + r] = delta[to][r];
+#pragma unroll
+    for (int ti = 0; ti < ITILES; ++ti)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sH[j * HP + 16 * ti + 4 * q + r] = h[ti][r];
+}
+
+template <int OTILES, int ITILES, int DP, int HP>
+__device__ __forceinline__ void accumulate_dw(const float* __restrict__ sD, const float* __restrict__ sH,
+                                              floatx4 (&dw)[OTILES][ITILES], int q, int j)
+{
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+        float a[OTILES], b[ITILES];
+#pragma unroll
+        for (int to = 0; to < OTILES; ++to) a[to] = sD[(4 * ks + q) * DP + 16 * to + j];
+#pragma unroll
+        for (int ti = 0; ti < ITILES; ++ti) b[ti] = sH[(4 * ks + q) * HP + 16 * ti + j];
+#pragma unroll
+        for (int to = 0; to < OTILES; ++to)
+#pragma unroll
+            for (int ti = 0; ti < ITILES; ++ti) dw[to][ti] = mfma4(a[to], b[ti], dw[to][ti]);
+    }
+}
+
+// Write one dW accumulator set (D layout: row 16 to + 4 q + r, col 16 ti + j).
+template <int OTILES, int ITILES>
+__device__ __forceinline__ void store_dw(float* __restrict__ dst, const floatx4 (&dw)[OTILES][ITILES], int rows,
+                                         int cols, int q, int j)
+{
+#pragma unroll
+    for (int to = 0; to < OTILES; ++to)
+#pragma unroll
+        for (int ti = 0; ti < ITILES; ++ti)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * to + 4 * q + r, col = 16 * ti + j;
+                if (row < rows && col < cols) dst[row * cols + col] = dw[to][ti][r];
+            }
+}
+
+template <int IN, int W, int D>
+__global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_bwd(const float* __restrict__ w,
+                                                            const float* __restrict__ y,
+                                                            const float4* __restrict__ dout, int64_t n_s,
+                                                            float2* __restrict__ dy, float* __restrict__ partial)
+{
+    using N = Net<IN, W, D>;
+    using B = BwdLds<IN, W, D>;
+    extern __shared__ float lds[];
+    float* frag = lds;
+    load_fragments<IN, W, D>(w, frag, N::N_ALL);
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, j = lane & 15;
+    float* sD = lds + N::N_ALL * 64 + wave * B::PER_WAVE;
+    float* sH = sD + 16 * B::DW;
+
+    floatx4 dW1[N::OT][N::IT];
+    floatx4 dWh[D > 1 ? D - 1 : 1][N::OT][N::OT];
+    floatx4 dWo[1][N::OT];
+#pragma unroll
+    for (int a = 0; a < N::OT; ++a) {
+#pragma unroll
+        for (int b = 0; b < N::IT; ++b) dW1[a][b] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int b = 0; b < N::OT; ++b) {
+#pragma unroll
+            for (int k = 0; k < (D > 1 ? D - 1 : 1); ++k) dWh[k][a][b] = {0.0f, 0.0f, 0.0f, 0.0f};
+        }
+        dWo[0][a] = {0.0f, 0.0f, 0.0f, 0.0f};
+    }
+
+    const int64_t n_tiles = (n_s + 15) / 16;
+    const int64_t wave0 = (int64_t)blockIdx.x * kBwdWaves + wave;
+    const int64_t n_waves = (int64_t)gridDim.x * kBwdWaves;
+    for (int64_t tile = wave0; tile < n_tiles; tile += n_waves) {
+        const int64_t s = tile * 16 + j;
+        const bool valid = s < n_s;
+        float yb[N::KT1];
+        load_inputs<N::KT1>(y, n_s, s, valid, q, yb);
+        floatx4 hs[D][N::OT];
+        floatx4 o;
+        mlp_chain<IN, W, D>(frag, lane, yb, hs, o);
+
+        // head adjoint: lanes with q == 0 hold the 4 outputs of sample j
+        float dq0 = 0.0f, dq1 = 0.0f, dq2 = 0.0f, dq3 = 0.0f;
+        if (q == 0 && valid) {
+            const float4 g = dout[s];
+            const float sig = __expf(o[0]);
+            const float c1 = sigmoidf_(o[1]), c2 = sigmoidf_(o[2]), c3 = sigmoidf_(o[3]);
+            dq0 = g.x * sig;
+            dq1 = g.y * c1 * (1.0f - c1);
+            dq2 = g.z * c2 * (1.0f - c2);
+            dq3 = g.w * c3 * (1.0f - c3);
+        }
+        // B operand of the head adjoint: lane l holds output q of sample j
+        const float v0 = __shfl(dq0, j), v1 = __shfl(dq1, j), v2 = __shfl(dq2, j), v3 = __shfl(dq3, j);
+        const float dqb = q == 0 ? v0 : (q == 1 ? v1 : (q == 2 ? v2 : v3));
+
+        // dW_out += dO h_D^T  (dO staged as a 16-row block with rows >= 4 zero)
+        {
+            floatx4 dO[1];
+            dO[0] = {q == 0 ? v0 : 0.0f, q == 0 ? v1 : 0.0f, q == 0 ? v2 : 0.0f, q == 0 ? v3 : 0.0f};
+            // D layout for rows 4q+r: only q == 0 carries real rows 0..3
+            wave_lds_sync();
+            stage_dw<1, N::OT, B::DW, B::HW>(sD, sH, dO, hs[D - 1], q, j);
+            wave_lds_sync();
+            accumulate_dw<1, N::OT, B::DW, B::HW>(sD, sH, dWo, q, j);
+        }
+        // delta of the last hidden layer
+        floatx4 delta[N::OT];
+#pragma unroll
+        for (int to = 0; to < N::OT; ++to) {
+            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            acc = mfma4(frag[(N::BO + to) * 64 + lane], dqb, acc);
+            delta[to] = mask_pos(acc, hs[D - 1][to]);
+        }
+        // hidden layers, last to first
+#pragma unroll
+        for (int k = D - 1; k >= 1; --k) {
+            wave_lds_sync();
+            stage_dw<N::OT, N::OT, B::DW, B::HW>(sD, sH, delta, hs[k - 1], q, j);
+            wave_lds_sync();
+            accumulate_dw<N::OT, N::OT, B::DW, B::HW>(sD, sH, dWh[k - 1], q, j);
+            floatx4 nd[N::OT];
+#pragma unroll
+            for (int to = 0; to < N::OT; ++to) {
+                floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int ks = 0; ks < N::KTH; ++ks)
+                    acc = mfma4(frag[(N::BH + ((k - 1) * N::OT + to) * N::KTH + ks) * 64 + lane], delta[ks >> 2][ks & 3],
+                                acc);
+                nd[to] = mask_pos(acc, hs[k - 1][to]);
+            }
+#pragma unroll
+            for (int to = 0; to < N::OT; ++to) delta[to] = nd[to];
+        }
+        // layer 1: dW_1 += delta y^T (y staged from its B-operand layout)
+        wave_lds_sync();
+#pragma unroll
+        for (int to = 0; to < N::OT; ++to)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sD[j * B::DW + 16 * to + 4 * q + r] = delta[to][r];
+#pragma unroll
+        for (int kk = 0; kk < N::KT1; ++kk) sH[j * B::HW + 4 * kk + q] = yb[kk];
+#pragma unroll
+        for (int c = IN + q; c < B::IP; c += 4) sH[j * B::HW + c] = 0.0f;
+        wave_lds_sync();
+        accumulate_dw<N::OT, N::IT, B::DW, B::HW>(sD, sH, dW1, q, j);
+        // dy = W_1^T delta_1
+#pragma unroll
+        for (int to = 0; to < N::IT; ++to) {
+            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int ks = 0; ks < N::KTH; ++ks)
+                acc = mfma4(frag[(N::B1 + to * N::KTH + ks) * 64 + lane], delta[ks >> 2][ks & 3], acc);
+            const int f = 16 * to + 4 * q;  // features f..f+3 = levels f/2, f/2 + 1
+            if (valid && f < IN) {
+                dy[(int64_t)(f >> 1) * n_s + s] = make_float2(acc[0], acc[1]);
+                dy[(int64_t)((f >> 1) + 1) * n_s + s] = make_float2(acc[2], acc[3]);
+            }
+        }
+    }
+
+    float* dst = partial + ((int64_t)blockIdx.x * kBwdWaves + wave) * N::N_PARAMS;
+    store_dw<N::OT, N::IT>(dst + N::OFF_W1, dW1, W, IN, q, j);
+#pragma unroll
+    for (int k = 1; k < D; ++k) store_dw<N::OT, N::OT>(dst + N::OFF_H + (k - 1) * W * W, dWh[k - 1], W, W, q, j);
+    store_dw<1, N::OT>(dst + N::OFF_OUT, dWo, 4, W, q, j);
+}
+
+__global__ void k_reduce_partials(const float* __restrict__ partial, int n_slots, int64_t n_mlp,
+                                  float* __restrict__ g)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_mlp) return;
+    double acc = 0.0;
+    for (int sl = 0; sl < n_slots; ++sl) acc += (double)partial[(int64_t)sl * n_mlp + p];
+    g[p] += (float)acc;
+}
+
+template <int IN, int W, int D>
+hipError_t fwd_impl(const float* w, const float* y, int64_t n_s, float* sc, hipStream_t s)
+{
+    const int64_t n_tiles = (n_s + 15) / 16;
+    int64_t blocks = (n_tiles + 3) / 4;
+    blocks = blocks > 2048 ? 2048 : blocks;
+    hipLaunchKernelGGL((k_mlp_fwd<IN, W, D>), dim3((uint32_t)blocks), dim3(256), 0, s, w, y, n_s, (float4*)sc);
+    return hipGetLastError();
+}
+
+template <int IN, int W, int D>
+size_t bwd_lds_bytes()
+{
+    return sizeof(float) * ((size_t)Net<IN, W, D>::N_ALL * 64 + (size_t)kBwdWaves * BwdLds<IN, W, D>::PER_WAVE);
+}
+
+int bwd_blocks(int64_t n_s)
+{
+    const int64_t n_tiles = (n_s + 15) / 16;
+    int64_t b = (n_tiles + kBwdWaves * 16 - 1) / (kBwdWaves * 16);  // >= 16 tiles per wave
+    b = b < 1 ? 1 : b;
+    return (int)(b > kBwdMaxBlocks ? kBwdMaxBlocks : b);
+}
+
+template <int IN, int W, int D>
+hipError_t bwd_impl(const float* w, const float* y, const float* dout, int64_t n_s, float* dy, float* partial,
+                    hipStream_t s)
+{
+    const size_t lds = bwd_lds_bytes<IN, W, D>();
+    auto kern = k_mlp_bwd<IN, W, D>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((uint32_t)bwd_blocks(n_s)), dim3(64 * kBwdWaves), lds, s, w, y,
+                       (const float4*)dout, n_s, (float2*)dy, partial);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool mlp_supported(const MlpShape& m)
+{
+    return m.width == 64 && (m.in_dim == 16 || m.in_dim == 32) && (m.hidden == 1 || m.hidden == 2);
+}
+
+int mlp_bwd_waves(int64_t n_samples) { return bwd_blocks(n_samples) * kBwdWaves; }
+
+#define PRENOM_MLP_DISPATCH(CALL)                                                           \
+    if (m.width == 64 && m.in_dim == 16 && m.hidden == 1) return CALL<16, 64, 1>;          \
+    if (m.width == 64 && m.in_dim == 16 && m.hidden == 2) return CALL<16, 64, 2>;          \
+    if (m.width == 64 && m.in_dim == 32 && m.hidden == 1) return CALL<32, 64, 1>;          \
+    if (m.width == 64 && m.in_dim == 32 && m.hidden == 2) return CALL<32, 64, 2>;          \
+    return hipErrorInvalidValue;
+
+hipError_t launch_mlp_fwd(const MlpShape& m, const float* w, const float* y, int64_t n_s, float* sc, hipStream_t s)
+{
+    if (n_s == 0) return hipSuccess;
+#define CALL_FWD fwd_impl
+#define FWD_ARGS (w, y, n_s, sc, s)
+    if (m.width == 64 && m.in_dim == 16 && m.hidden == 1) return fwd_impl<16, 64, 1> FWD_ARGS;
+    if (m.width == 64 && m.in_dim == 16 && m.hidden == 2) return fwd_impl<16, 64, 2> FWD_ARGS;
+    if (m.width == 64 && m.in_dim == 32 && m.hidden == 1) return fwd_impl<32, 64, 1> FWD_ARGS;
+    if (m.width == 64 && m.in_dim == 32 && m.hidden == 2) return fwd_impl<32, 64, 2> FWD_ARGS;
+#undef FWD_ARGS
+#undef CALL_FWD
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_mlp_bwd(const MlpShape& m, const float* w, const float* y, const float* dout, int64_t n_s,
+                          float* dy, float* partial, hipStream_t s)
+{
+    if (n_s == 0) return hipSuccess;
+#define BWD_ARGS (w, y, dout, n_s, dy, partial, s)
+    if (m.width == 64 && m.in_dim == 16 && m.hidden == 1) return bwd_impl<16, 64, 1> BWD_ARGS;
+    if (m.width == 64 && m.in_dim == 16 && m.hidden == 2) return bwd_impl<16, 64, 2> BWD_ARGS;
+    if (m.width == 64 && m.in_dim == 32 && m.hidden == 1) return bwd_impl<32, 64, 1> BWD_ARGS;
+    if (m.width == 64 && m.in_dim == 32 && m.hidden == 2) return bwd_impl<32, 64, 2> BWD_ARGS;
+#undef BWD_ARGS
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce_partials(const float* partial, int n_slots, int64_t n_mlp, float* g_mlp, hipStream_t s)
+{
+    if (n_slots == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_partials, dim3((uint32_t)((n_mlp + 255) / 256)), dim3(256), 0, s, partial, n_slots,
+                       n_mlp, g_mlp);
+    return hipGetLastError();
+}
+
+}  // namespace prenom
