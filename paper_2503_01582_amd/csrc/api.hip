@@ -83,6 +83,16 @@ hipError_t timed(const char* name, hipStream_t s, F&& launch)
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
 
+// Compute units of the current device (persistent grids size to it).
+int device_cus()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+        return 256;
+    return cus;
+}
+
 // Shape rules an architecture must satisfy (independent of what is compiled).
 prenom_status check_arch(const prenom_arch* a)
 {
@@ -138,8 +148,10 @@ constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct WsLayout {
-    size_t y, sc, dout, dy, ray_state, loss_partial, mlp_partial, total;
+    size_t y, sc, dout, dy, ray_state, loss_partial, mlp_partial;
+    size_t counts, block_max, tile_exp, tile_total, tile_start, chunk_start, work_counter, keys, vals, total;
     int n_loss_blocks, n_mlp_slots;
+    ScatterPlan plan;
 };
 
 WsLayout ws_layout(const prenom_arch* a, int64_t n_rays, int32_t S)
@@ -163,6 +175,26 @@ WsLayout ws_layout(const prenom_arch* a, int64_t n_rays, int32_t S)
     w.n_mlp_slots = mlp_bwd_waves((int64_t)n_s);
     w.mlp_partial = off;
     off = align_up(off + (size_t)w.n_mlp_slots * (size_t)mlp_params(a) * sizeof(float));
+    w.plan = scatter_plan(grid_info(a), (int64_t)n_s);
+    const size_t nt = (size_t)w.plan.n_tiles;
+    w.counts = off;
+    off = align_up(off + nt * (size_t)w.plan.n_blocks * sizeof(uint32_t));
+    w.block_max = off;
+    off = align_up(off + (size_t)a->n_levels * (size_t)w.plan.n_blocks * sizeof(float));
+    w.tile_exp = off;
+    off = align_up(off + nt * sizeof(int32_t));
+    w.tile_total = off;
+    off = align_up(off + nt * sizeof(uint64_t));
+    w.tile_start = off;
+    off = align_up(off + (nt + 1) * sizeof(uint64_t));
+    w.chunk_start = off;
+    off = align_up(off + (nt + 1) * sizeof(uint64_t));
+    w.work_counter = off;
+    off = align_up(off + sizeof(uint64_t));
+    w.keys = off;
+    off = align_up(off + (size_t)w.plan.max_records * sizeof(uint16_t));
+    w.vals = off;
+    off = align_up(off + (size_t)w.plan.max_records * 2 * sizeof(float));
     w.total = off;
     return w;
 }
@@ -197,7 +229,7 @@ prenom_status check_render(const prenom_model* model, const prenom_render_cfg* c
     if (!(cfg->lambda_d >= 0.0f) || !(cfg->lambda_sigma >= 0.0f))
         return fail(PRENOM_ERR_INVALID_ARG, "negative or NaN loss weight");
     if (n_rays < 0) return fail(PRENOM_ERR_SHAPE, "n_rays < 0");
-    if ((double)n_rays * cfg->n_samples >= 2147483648.0) return fail(PRENOM_ERR_SHAPE, "n_rays * n_samples >= 2^31");
+    if ((double)n_rays * cfg->n_samples > 536870912.0) return fail(PRENOM_ERR_SHAPE, "n_rays * n_samples > 2^29");
     if (n_rays > 0 && (!ray_obj || !t || !dt || !flags))
         return fail(PRENOM_ERR_INVALID_ARG, "ray_obj, t, dt and flags are required");
     const WsLayout w = ws_layout(&model->arch, n_rays, cfg->n_samples);
@@ -359,8 +391,34 @@ prenom_status prenom_render_bwd(const prenom_model* model, const prenom_render_c
     if (n_s > 0)
         PRENOM_LAUNCH("k_reduce_partials", s,
                       launch_reduce_partials(partial, w.n_mlp_slots, mlp_params(a), model->grads + table_params(a), s));
-    PRENOM_LAUNCH("k_encode_bwd", s,
-                  launch_encode_bwd(grid_info(a), ray_obj, t, n_rays, cfg->n_samples, dy, model->grads, s));
+    ScatterArgs sa{};
+    sa.grid = grid_info(a);
+    sa.n_s = n_s;
+    sa.S = cfg->n_samples;
+    sa.n_blocks = w.plan.n_blocks;
+    sa.n_tiles = w.plan.n_tiles;
+    sa.reduce_blocks = device_cus();
+    sa.tiles_max = 1;
+    for (int l = 0; l < PRENOM_MAX_LEVELS; ++l) {
+        sa.tiles_max = l < a->n_levels && w.plan.tiles[l] > sa.tiles_max ? w.plan.tiles[l] : sa.tiles_max;
+        sa.tiles[l] = w.plan.tiles[l];
+        sa.tile_base[l] = w.plan.tile_base[l];
+        sa.level_rows[l] = w.plan.level_rows[l];
+    }
+    sa.ray_obj = ray_obj;
+    sa.t = t;
+    sa.dy = reinterpret_cast<const float2*>(dy);
+    sa.g_table = model->grads;
+    sa.counts = at<uint32_t>(workspace, w.counts);
+    sa.block_max = at<float>(workspace, w.block_max);
+    sa.tile_exp = at<int32_t>(workspace, w.tile_exp);
+    sa.tile_total = at<uint64_t>(workspace, w.tile_total);
+    sa.tile_start = at<uint64_t>(workspace, w.tile_start);
+    sa.chunk_start = at<uint64_t>(workspace, w.chunk_start);
+    sa.work_counter = at<unsigned long long>(workspace, w.work_counter);
+    sa.keys = at<uint16_t>(workspace, w.keys);
+    sa.vals = at<float2>(workspace, w.vals);
+    PRENOM_LAUNCH("k_encode_bwd", s, launch_scatter(sa, s));
     return PRENOM_OK;
 }
 

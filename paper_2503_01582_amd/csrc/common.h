@@ -43,10 +43,36 @@ __device__ __forceinline__ void lattice_cell(float x, int N, uint32_t& c, float&
     f = (float)(g - (double)ci);
 }
 
+// The 8 cell corners of x on level l: table rows and trilinear weights
+// (corner e = (e & 1, e >> 1 & 1, e >> 2 & 1)).  Used by the forward encoding
+// and by both passes of the scatter, so all of them agree bit for bit.
+struct Corners {
+    uint32_t row[8];
+    float w[8];
+};
+
 // Sample position in the object frame: clamp(fmaf(t, d, o), 0, 1).
 __device__ __forceinline__ float sample_coord(float t, float d, float o)
 {
     return fminf(fmaxf(fmaf(t, d, o), 0.0f), 1.0f);
+}
+
+__device__ __forceinline__ void level_corners(const GridInfo& g, int l, float x0, float x1, float x2, Corners& c)
+{
+    const int N = g.res[l];
+    const bool dense = (g.dense_mask >> l) & 1u;
+    const uint32_t side = (uint32_t)N + 1u;
+    uint32_t cx, cy, cz;
+    float fx, fy, fz;
+    lattice_cell(x0, N, cx, fx);
+    lattice_cell(x1, N, cy, fy);
+    lattice_cell(x2, N, cz, fz);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const uint32_t ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
+        c.row[e] = corner_row(dense, side, (uint32_t)g.log2_table, cx + ex, cy + ey, cz + ez);
+        c.w[e] = (ex ? fx : 1.0f - fx) * (ey ? fy : 1.0f - fy) * (ez ? fz : 1.0f - fz);
+    }
 }
 
 // ------------------------------------------------------------------ launches
@@ -78,9 +104,42 @@ hipError_t launch_encode_points(const GridInfo& g, const float* table, const flo
 hipError_t launch_encode_samples(const GridInfo& g, const float* table, const float* ray_obj,
                                  const float* t, int64_t n_rays, int32_t S, float* y, hipStream_t s);
 
-// Scatter-add of feature gradients dy [L][n_s][2] into the table gradient.
-hipError_t launch_encode_bwd(const GridInfo& g, const float* ray_obj, const float* t, int64_t n_rays,
-                             int32_t S, const float* dy, float* g_table, hipStream_t s);
+// Bucketed scatter-add of the feature gradients into the table gradient.
+struct ScatterPlan {
+    int32_t n_blocks;  // sample blocks per level
+    int32_t n_tiles;   // table tiles over all levels
+    int32_t tiles[PRENOM_MAX_LEVELS];
+    int32_t tile_base[PRENOM_MAX_LEVELS];
+    int64_t level_rows[PRENOM_MAX_LEVELS];
+    int64_t max_records;  // n_s * L * 8
+};
+ScatterPlan scatter_plan(const GridInfo& g, int64_t n_s);
+int scatter_max_tiles_per_level();
+
+struct ScatterArgs {
+    GridInfo grid;
+    int64_t n_s;
+    int32_t S;
+    int32_t n_blocks, n_tiles, reduce_blocks;
+    int32_t tiles_max;  // max tiles of one level
+    int32_t tiles[PRENOM_MAX_LEVELS];
+    int32_t tile_base[PRENOM_MAX_LEVELS];
+    int64_t level_rows[PRENOM_MAX_LEVELS];
+    const float* ray_obj;
+    const float* t;
+    const float2* dy;
+    float* g_table;
+    uint32_t* counts;       // [n_tiles][n_blocks]
+    float* block_max;       // [L][n_blocks] max |dy| per sample block
+    int32_t* tile_exp;      // [n_tiles] fixed-point exponent
+    uint64_t* tile_total;   // [n_tiles]
+    uint64_t* tile_start;   // [n_tiles + 1]
+    uint64_t* chunk_start;  // [n_tiles + 1]
+    unsigned long long* work_counter;
+    uint16_t* keys;         // [max_records]
+    float2* vals;           // [max_records]
+};
+hipError_t launch_scatter(const ScatterArgs& a, hipStream_t s);
 
 // MLP: forward writes (sigma, r, g, b) per sample; backward recomputes the
 // activations, writes dy and per-wave partial weight gradients.
@@ -88,7 +147,7 @@ struct MlpShape {
     int32_t in_dim, width, hidden;
 };
 bool mlp_supported(const MlpShape& m);
-int mlp_bwd_waves(int64_t n_samples);  // partial-gradient slots the bwd writes
+int mlp_bwd_waves(int64_t n_samples);  // partial-gradient slots (one per block) the bwd writes
 hipError_t launch_mlp_fwd(const MlpShape& m, const float* w, const float* y, int64_t n_s, float* sc,
                           hipStream_t s);
 hipError_t launch_mlp_bwd(const MlpShape& m, const float* w, const float* y, const float* dout,

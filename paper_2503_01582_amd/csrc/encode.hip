@@ -1,42 +1,17 @@
-// Multi-resolution hash encoding, forward and backward (Sec. III-B
-// "Object-level NeRFs": sample positions are normalised and encoded with the
-// hash grid of Mueller et al. 2022 before the MLP).
+// Multi-resolution hash encoding, forward (Sec. III-B "Object-level NeRFs":
+// sample positions are normalised and encoded with the hash grid of Mueller
+// et al. 2022 before the MLP).  The backward lives in scatter.hip.
 //
-// Layout: tables [L][T][2] (one float2 per row), features y and their
-// gradients dy level-major [L][n_samples][2], so a wavefront of one level
-// reads and writes 64 consecutive float2 (512 contiguous bytes).
-// The launch grid is (sample blocks, levels): one thread per (sample, level),
-// 8 float2 gathers (forward) or 16 FP32 atomic adds (backward) each.
+// Layout: tables [L][T][2] (one float2 per row), features y level-major
+// [L][n_samples][2], so a wavefront of one level writes 64 consecutive float2
+// (512 contiguous bytes).  The launch grid is (sample blocks, levels): one
+// thread per (sample, level), 8 float2 gathers each.
 #include "common.h"
 
 namespace prenom {
 namespace {
 
 constexpr int kEncBlock = 256;
-
-struct Corners {
-    uint32_t row[8];
-    float w[8];
-};
-
-__device__ __forceinline__ void level_corners(const GridInfo& g, int l, float x0, float x1, float x2,
-                                              Corners& c)
-{
-    const int N = g.res[l];
-    const bool dense = (g.dense_mask >> l) & 1u;
-    const uint32_t side = (uint32_t)N + 1u;
-    uint32_t cx, cy, cz;
-    float fx, fy, fz;
-    lattice_cell(x0, N, cx, fx);
-    lattice_cell(x1, N, cy, fy);
-    lattice_cell(x2, N, cz, fz);
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const uint32_t ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
-        c.row[e] = corner_row(dense, side, (uint32_t)g.log2_table, cx + ex, cy + ey, cz + ez);
-        c.w[e] = (ex ? fx : 1.0f - fx) * (ey ? fy : 1.0f - fy) * (ez ? fz : 1.0f - fz);
-    }
-}
 
 __device__ __forceinline__ float2 gather_blend(const float2* __restrict__ level_table, const Corners& c)
 {
@@ -91,31 +66,6 @@ __global__ __launch_bounds__(kEncBlock) void k_encode_points(GridInfo g, const f
     }
 }
 
-__global__ __launch_bounds__(kEncBlock) void k_encode_bwd(GridInfo g, const float* __restrict__ ray_obj,
-                                                          const float* __restrict__ t, int64_t n_s,
-                                                          int32_t S, const float2* __restrict__ dy,
-                                                          float* __restrict__ g_table)
-{
-    const int64_t s = (int64_t)blockIdx.x * kEncBlock + threadIdx.x;
-    const int l = blockIdx.y;
-    if (s >= n_s) return;
-    const float2 d = dy[(int64_t)l * n_s + s];
-    if (d.x == 0.0f && d.y == 0.0f) return;
-    const int64_t ray = s / S;
-    const float* ro = ray_obj + 6 * ray;
-    const float ts = t[s];
-    Corners c;
-    level_corners(g, l, sample_coord(ts, ro[3], ro[0]), sample_coord(ts, ro[4], ro[1]),
-                  sample_coord(ts, ro[5], ro[2]), c);
-    float* lt = g_table + (((int64_t)l << g.log2_table) << 1);
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        float* row = lt + 2 * (int64_t)c.row[e];
-        atomicAdd(row, c.w[e] * d.x);
-        atomicAdd(row + 1, c.w[e] * d.y);
-    }
-}
-
 dim3 enc_grid(int64_t n, int L) { return dim3((uint32_t)((n + kEncBlock - 1) / kEncBlock), (uint32_t)L); }
 
 }  // namespace
@@ -136,16 +86,6 @@ hipError_t launch_encode_points(const GridInfo& g, const float* table, const flo
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_encode_points, enc_grid(n, g.n_levels), dim3(kEncBlock), 0, s, g,
                        (const float2*)table, pos, n, (float2*)features, corner_idx);
-    return hipGetLastError();
-}
-
-hipError_t launch_encode_bwd(const GridInfo& g, const float* ray_obj, const float* t, int64_t n_rays,
-                             int32_t S, const float* dy, float* g_table, hipStream_t s)
-{
-    const int64_t n_s = n_rays * S;
-    if (n_s == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_encode_bwd, enc_grid(n_s, g.n_levels), dim3(kEncBlock), 0, s, g, ray_obj, t, n_s,
-                       S, (const float2*)dy, g_table);
     return hipGetLastError();
 }
 

@@ -16,8 +16,9 @@
 // Backward: the adjoint runs the same chain with W^T fragments; the weight
 // gradient dW = delta h^T contracts over samples, so delta and h of the tile
 // go through a per-wave LDS transpose and are accumulated in registers for all
-// tiles the wave processes; each wave finally writes one partial dW, and a
-// reduction kernel sums the partials in FP64 into the gradient buffer.
+// tiles the wave processes; the waves of a block then merge their dW in LDS
+// (in wave order), each block writes one partial, and a reduction kernel sums
+// the partials in FP64 into the gradient buffer.
 #include "common.h"
 
 namespace prenom {
@@ -232,10 +233,11 @@ __device__ __forceinline__ void accumulate_dw(const float* __restrict__ sD, cons
     }
 }
 
-// Write one dW accumulator set (D layout: row 16 to + 4 q + r, col 16 ti + j).
+// Add (or, for the first wave, store) one dW accumulator set into the
+// block's LDS reduction buffer (D layout: row 16 to + 4 q + r, col 16 ti + j).
 template <int OTILES, int ITILES>
-__device__ __forceinline__ void store_dw(float* __restrict__ dst, const floatx4 (&dw)[OTILES][ITILES], int rows,
-                                         int cols, int q, int j)
+__device__ __forceinline__ void merge_dw(float* __restrict__ dst, const floatx4 (&dw)[OTILES][ITILES], int rows,
+                                         int cols, int q, int j, bool first)
 {
 #pragma unroll
     for (int to = 0; to < OTILES; ++to)
@@ -244,7 +246,10 @@ __device__ __forceinline__ void store_dw(float* __restrict__ dst, const floatx4 
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = 16 * to + 4 * q + r, col = 16 * ti + j;
-                if (row < rows && col < cols) dst[row * cols + col] = dw[to][ti][r];
+                if (row < rows && col < cols) {
+                    float* p = dst + row * cols + col;
+                    *p = first ? dw[to][ti][r] : *p + dw[to][ti][r];
+                }
             }
 }
 
@@ -371,11 +376,23 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_bwd(const float* __restr
         }
     }
 
-    float* dst = partial + ((int64_t)blockIdx.x * kBwdWaves + wave) * N::N_PARAMS;
-    store_dw<N::OT, N::IT>(dst + N::OFF_W1, dW1, W, IN, q, j);
+    // block reduction of the 8 waves' dW (in wave order, so it is
+    // deterministic), in the staging area, then one partial per block
+    static_assert(N::N_PARAMS <= kBwdWaves * B::PER_WAVE, "reduction buffer");
+    float* red = lds + N::N_ALL * 64;
+    __syncthreads();
+    for (int w = 0; w < kBwdWaves; ++w) {
+        if (wave == w) {
+            merge_dw<N::OT, N::IT>(red + N::OFF_W1, dW1, W, IN, q, j, w == 0);
 #pragma unroll
-    for (int k = 1; k < D; ++k) store_dw<N::OT, N::OT>(dst + N::OFF_H + (k - 1) * W * W, dWh[k - 1], W, W, q, j);
-    store_dw<1, N::OT>(dst + N::OFF_OUT, dWo, 4, W, q, j);
+            for (int k = 1; k < D; ++k)
+                merge_dw<N::OT, N::OT>(red + N::OFF_H + (k - 1) * W * W, dWh[k - 1], W, W, q, j, w == 0);
+            merge_dw<1, N::OT>(red + N::OFF_OUT, dWo, 4, W, q, j, w == 0);
+        }
+        __syncthreads();
+    }
+    float* dst = partial + (int64_t)blockIdx.x * N::N_PARAMS;
+    for (int p = threadIdx.x; p < N::N_PARAMS; p += blockDim.x) dst[p] = red[p];
 }
 
 __global__ void k_reduce_partials(const float* __restrict__ partial, int n_slots, int64_t n_mlp,
@@ -432,7 +449,7 @@ bool mlp_supported(const MlpShape& m)
     return m.width == 64 && (m.in_dim == 16 || m.in_dim == 32) && (m.hidden == 1 || m.hidden == 2);
 }
 
-int mlp_bwd_waves(int64_t n_samples) { return bwd_blocks(n_samples) * kBwdWaves; }
+int mlp_bwd_waves(int64_t n_samples) { return bwd_blocks(n_samples); }
 
 #define PRENOM_MLP_DISPATCH(CALL)                                                           \
     if (m.width == 64 && m.in_dim == 16 && m.hidden == 1) return CALL<16, 64, 1>;          \
