@@ -83,6 +83,9 @@ def main():
     ap.add_argument("--rays", type=int, default=65536)
     ap.add_argument("--cpu-rays", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, copy 1 GiB device-to-device once (a kernel of known "
+                         "traffic for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); nothing here uses a "
@@ -127,6 +130,12 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kt = api.prenom_profile_end()
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("bench: copied 1 GiB device-to-device for counter calibration")
     ms = ev0.elapsed_time(ev1)
     ms_per_step = ms / args.steps
     value = args.rays * args.steps / (ms / 1e3)

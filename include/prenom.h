@@ -45,6 +45,9 @@ typedef enum prenom_status {
     PRENOM_ERR_HIP = 5          /* a HIP launch failed                      */
 } prenom_status;
 
+/* Element types of the reduced-precision forms. */
+typedef enum prenom_dtype { PRENOM_F32 = 0, PRENOM_BF16 = 1, PRENOM_F16 = 2 } prenom_dtype;
+
 /* Per-ray flags written by prenom_sample. */
 enum {
     PRENOM_FLAG_MISS = 1,    /* ray does not meet the object box: no samples  */
@@ -59,6 +62,10 @@ enum {
  * resolution[l] is the lattice resolution N_l of level l (the caller computes
  * floor(N_min * b^l)).  A level is stored 1:1 when (N_l+1)^3 <= 2^log2_table,
  * and through the XOR-of-primes spatial hash otherwise.
+ * mlp_dtype: element type of the MLP matrix products (PRENOM_F32, or
+ * PRENOM_BF16 / PRENOM_F16 operands with FP32 accumulation; weights stay FP32
+ * masters).  table_dtype: PRENOM_F32, or PRENOM_F16 when the forward gathers
+ * read the FP16 copy model->table_lp (gradients accumulate in FP32 always).
  * Supported: n_features = 2; n_levels in {8, 16}; mlp_width = 64;
  * mlp_hidden in {1, 2}; log2_table in [10, 24]; 2 <= N_l < 2^20. */
 typedef struct prenom_arch {
@@ -68,6 +75,8 @@ typedef struct prenom_arch {
     int32_t resolution[PRENOM_MAX_LEVELS];
     int32_t mlp_width;
     int32_t mlp_hidden;
+    int32_t mlp_dtype;
+    int32_t table_dtype;
 } prenom_arch;
 
 /* One object's NeRF.  Four device arrays of prenom_param_count(&arch) floats:
@@ -75,13 +84,25 @@ typedef struct prenom_arch {
  * zeroed by prenom_adam_step after use; the caller zeroes them once at
  * allocation), and Adam's first and second moments.
  * Parameter layout: hash tables [L][T][F], then W_1 [W][L*F],
- * W_2..W_D [W][W], W_out [4][W]. */
+ * W_2..W_D [W][W], W_out [4][W].
+ * table_lp: FP16 copy of the tables ([L][T][F] halves), required when
+ *   arch.table_dtype == PRENOM_F16; prenom_adam_step keeps it in step with the
+ *   masters and prenom_refresh_lowp (re)writes it.
+ * loss_scale: device scalar multiplying the upstream gradient inside
+ *   render_bwd (NULL = 1).  scaler_state: device int32[2] = {non-finite
+ *   gradient seen, finite steps since the scale last changed}, required with
+ *   loss_scale, zeroed by the caller once.  With them prenom_adam_step
+ *   unscales the gradient, skips the update when any entry is not finite and
+ *   halves the scale, and doubles it after growth_interval finite steps. */
 typedef struct prenom_model {
     prenom_arch arch;
     float* params;
     float* grads;
     float* adam_m;
     float* adam_v;
+    void* table_lp;
+    float* loss_scale;
+    int32_t* scaler_state;
 } prenom_model;
 
 int64_t prenom_param_count(const prenom_arch* arch);       /* -1 if invalid */
@@ -142,6 +163,10 @@ typedef struct prenom_render_cfg {
     int32_t loss_mode;
     float lambda_d;
     float lambda_sigma;
+    int32_t recompute; /* 0: render_bwd reads what render_fwd stored in the workspace
+                          (per-sample features, head outputs, per-ray results);
+                          1: render_bwd recomputes them, so the workspace need not
+                          survive between the two calls (activations are not kept) */
 } prenom_render_cfg;
 
 /* Bytes of device workspace render_fwd/render_bwd need for this batch. */
@@ -162,9 +187,10 @@ size_t prenom_workspace_size(const prenom_arch* arch, int64_t n_rays, int32_t n_
  *   mask [n] (uint8, 1 = object ray) may all be NULL (no loss).
  * Outputs: rgb [n][3], depth [n], opacity [n]; loss [1] (device scalar, or
  *   NULL); sample_out [n][S][4] = (sigma, r, g, b) per sample, or NULL.
- * workspace: >= prenom_workspace_size bytes, 256-byte aligned.  It carries
- *   the per-sample features and per-ray results that prenom_render_bwd reads:
- *   pass the same workspace and unchanged inputs to the matching bwd call.
+ * workspace: >= prenom_workspace_size bytes, 256-byte aligned.  Unless
+ *   cfg->recompute is set, it carries the per-sample features and per-ray
+ *   results that prenom_render_bwd reads: pass the same workspace and
+ *   unchanged inputs to the matching bwd call.
  * ---------------------------------------------------------------------- */
 prenom_status prenom_render_fwd(const prenom_model* model, const prenom_render_cfg* cfg,
                                 const float* ray_obj, const float* t, const float* dt,
@@ -176,20 +202,24 @@ prenom_status prenom_render_fwd(const prenom_model* model, const prenom_render_c
 /* ------------------------------------------------------------------------
  * prenom_render_bwd -- gradient of the rendering path (Sec. III-B, last
  * paragraph: the loss of Eq. (9) is back-propagated to the NeRF parameters).
- * Adds dL/dparams to model->grads.  With d_rgb [n][3] (and optionally
- * d_depth [n]) given, the gradient is that of sum(d_rgb*rgb + d_depth*depth)
- * (vector-Jacobian product for an outer autograd); with d_rgb == NULL it is
- * the gradient of the fused loss of render_fwd (targets required).
- * Must follow render_fwd on the same stream with the same workspace and
- * inputs.  Table gradients are accumulated with FP32 atomics: summation order,
- * hence the last bits, may differ between runs.
+ * Adds dL/dparams to model->grads.  With d_rgb [n][3] given (d_depth [n]
+ * and d_opacity [n] optional), the gradient is that of
+ * sum(d_rgb*rgb + d_depth*depth + d_opacity*opacity), the vector-Jacobian
+ * product an outer autograd needs; with d_rgb == NULL it is the gradient of
+ * the fused loss of render_fwd (targets required).
+ * Without cfg->recompute it must follow render_fwd on the same stream with the
+ * same workspace and inputs; with it, only the inputs must match.
+ * The table gradient is accumulated per 2^13-row tile in 64-bit fixed point
+ * (order independent); tiles that receive more than 2^21 contributions are
+ * split and their partial sums added with FP32 atomics, so only those may
+ * differ in the last bits between runs.
  * ---------------------------------------------------------------------- */
 prenom_status prenom_render_bwd(const prenom_model* model, const prenom_render_cfg* cfg,
                                 const float* ray_obj, const float* t, const float* dt,
                                 const uint8_t* flags, int64_t n_rays, const float* bg,
                                 const float* tgt_rgb, const float* tgt_depth, const uint8_t* mask,
-                                const float* d_rgb, const float* d_depth, void* workspace,
-                                size_t ws_bytes, void* stream);
+                                const float* d_rgb, const float* d_depth, const float* d_opacity,
+                                void* workspace, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * prenom_adam_step -- Adam (Sec. III-B, last paragraph) on every parameter:
@@ -200,9 +230,13 @@ prenom_status prenom_render_bwd(const prenom_model* model, const prenom_render_c
 typedef struct prenom_adam_cfg {
     float lr, beta1, beta2, eps;
     int64_t step;
+    int32_t growth_interval; /* loss scaling: finite steps before the scale doubles (0 = never) */
 } prenom_adam_cfg;
 
 prenom_status prenom_adam_step(const prenom_model* model, const prenom_adam_cfg* cfg, void* stream);
+
+/* Rewrites model->table_lp (FP16) from the FP32 tables, rounding to nearest. */
+prenom_status prenom_refresh_lowp(const prenom_model* model, void* stream);
 
 /* ------------------------------------------------------------------------
  * prenom_encode -- the hash encoding alone (Sec. III-B "Object-level NeRFs"):

@@ -84,7 +84,8 @@ def lib():
                                      C.c_int64, _f32p, _f32p, _f32p, _u8p, _f64p, _f64p, _f64p,
                                      _f64p, _f64p, _f64p, C.POINTER(C.c_uint64)]
         L.orc_render_bwd.argtypes = [C.POINTER(OrcRenderCfg), _f32p, _f32p, _f32p, _f32p, _u8p,
-                                     C.c_int64, _f32p, _f32p, _f32p, _u8p, _f32p, _f32p, _f64p]
+                                     C.c_int64, _f32p, _f32p, _f32p, _u8p, _f32p, _f32p, _f32p,
+                                     _f64p]
         L.orc_adam.argtypes = [C.c_int64, _f32p, _f32p, _f32p, _f32p, C.c_double, C.c_double,
                                C.c_double, C.c_double, C.c_int64, _f64p, _f64p, _f64p]
         L.orc_positions.argtypes = [_f32p, _f32p, C.c_int64, C.c_int32, _f32p]
@@ -286,9 +287,10 @@ def render_fwd(arch, params, ray_obj, t, dt, flags, *, bg=None, tgt_rgb=None, tg
 
 
 def render_bwd(arch, params, ray_obj, t, dt, flags, *, bg=None, tgt_rgb=None, tgt_depth=None,
-               mask=None, d_rgb=None, d_depth=None, loss_mode=0, lambda_d=0.0, lambda_sigma=0.0):
+               mask=None, d_rgb=None, d_depth=None, d_opacity=None, loss_mode=0, lambda_d=0.0,
+               lambda_sigma=0.0):
     """Parameter gradient [n_params] (FP64) of the fused loss, or of
-    sum(d_rgb * rgb) + sum(d_depth * depth) when d_rgb is given."""
+    sum(d_rgb * rgb + d_depth * depth + d_opacity * opacity) when d_rgb is given."""
     params = _f32(params)
     ray_obj = _f32(ray_obj).reshape(-1, 6)
     n = ray_obj.shape[0]
@@ -297,13 +299,13 @@ def render_bwd(arch, params, ray_obj, t, dt, flags, *, bg=None, tgt_rgb=None, tg
     dt = _f32(dt).reshape(n, S)
     flags = _u8(flags)
     bg, tgt_rgb, tgt_depth, mask = _f32(bg), _f32(tgt_rgb), _f32(tgt_depth), _u8(mask)
-    d_rgb, d_depth = _f32(d_rgb), _f32(d_depth)
+    d_rgb, d_depth, d_opacity = _f32(d_rgb), _f32(d_depth), _f32(d_opacity)
     cfg = _render_cfg(arch, S, loss_mode, lambda_d, lambda_sigma)
     grads = np.zeros(params.shape[0], np.float64)
     lib().orc_render_bwd(C.byref(cfg), _p(params, _f32p), _p(ray_obj, _f32p), _p(t, _f32p),
                          _p(dt, _f32p), _p(flags, _u8p), n, _p(bg, _f32p), _p(tgt_rgb, _f32p),
                          _p(tgt_depth, _f32p), _p(mask, _u8p), _p(d_rgb, _f32p),
-                         _p(d_depth, _f32p), _p(grads, _f64p))
+                         _p(d_depth, _f32p), _p(d_opacity, _f32p), _p(grads, _f64p))
     return grads
 
 

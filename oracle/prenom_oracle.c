@@ -729,12 +729,13 @@ void orc_render_fwd(const orc_render_cfg* c, const float* params, const float* r
 }
 
 /* Backward of the rendering path; gradients are ADDED to grads [n_params].
- * Upstream gradients d_rgb [n][3] / d_depth [n] replace the loss gradient
- * when d_rgb is not NULL (the density term then contributes nothing). */
+ * Upstream gradients d_rgb [n][3] / d_depth [n] / d_opacity [n] replace the
+ * loss gradient when d_rgb is not NULL (the density term then contributes
+ * nothing). */
 void orc_render_bwd(const orc_render_cfg* c, const float* params, const float* ray_obj, const float* t,
                     const float* dt, const uint8_t* flags, int64_t n, const float* bg,
                     const float* tgt_rgb, const float* tgt_depth, const uint8_t* mask,
-                    const float* d_rgb, const float* d_depth, double* grads)
+                    const float* d_rgb, const float* d_depth, const float* d_opacity, double* grads)
 {
     const orc_arch* a = &c->arch;
     const int S = c->n_samples;
@@ -771,17 +772,18 @@ void orc_render_bwd(const orc_render_cfg* c, const float* params, const float* r
                     for (int k = 0; k < 3; ++k) bgc[k] = (double)bg[3 * r + k];
                 double C[3], D, A;
                 orc_ray_forward(c, params, &mv, ray_obj + 6 * r, t + r * S, dt + r * S, bgc, &s, C, &D, &A);
-                double gC[3], gD, extra = 0.0;
+                double gC[3], gD, gA = 0.0, extra = 0.0;
                 if (d_rgb) {
                     for (int k = 0; k < 3; ++k) gC[k] = (double)d_rgb[3 * r + k];
                     gD = d_depth ? (double)d_depth[r] : 0.0;
+                    gA = d_opacity ? (double)d_opacity[r] : 0.0;
                 } else {
                     double sigma_sum = 0.0;
                     for (int j = 0; j < S; ++j) sigma_sum += s.sigma[j];
                     orc_ray_loss(c, n, C, D, tgt_rgb + 3 * r, tgt_depth ? tgt_depth[r] : 0.0f,
                                  mask ? mask[r] != 0 : 1, sigma_sum, gC, &gD, &extra);
                 }
-                orc_composite_ray_bwd(S, s.rgb, s.tt, s.dtt, bgc, s.w, s.T, gC, gD, 0.0, dsig, drgb);
+                orc_composite_ray_bwd(S, s.rgb, s.tt, s.dtt, bgc, s.w, s.T, gC, gD, gA, dsig, drgb);
                 for (int j = 0; j < S; ++j) {
                     dsig[j] += extra;
                     /* head: sigma = exp(o0), c = sigmoid(o_k) */

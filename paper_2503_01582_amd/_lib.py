@@ -9,6 +9,7 @@ import ctypes as C
 import os
 
 MAX_LEVELS = 32
+F32, BF16, F16 = 0, 1, 2
 N_OUT = 4
 FLAG_MISS, FLAG_ESCAPED, FLAG_UNIFORM = 1, 2, 4
 
@@ -21,12 +22,13 @@ STATUS = {0: "PRENOM_OK", 1: "PRENOM_ERR_INVALID_ARG", 2: "PRENOM_ERR_SHAPE",
 class PrenomArch(C.Structure):
     _fields_ = [("n_levels", C.c_int32), ("log2_table", C.c_int32), ("n_features", C.c_int32),
                 ("resolution", C.c_int32 * MAX_LEVELS), ("mlp_width", C.c_int32),
-                ("mlp_hidden", C.c_int32)]
+                ("mlp_hidden", C.c_int32), ("mlp_dtype", C.c_int32), ("table_dtype", C.c_int32)]
 
 
 class PrenomModel(C.Structure):
     _fields_ = [("arch", PrenomArch), ("params", C.c_void_p), ("grads", C.c_void_p),
-                ("adam_m", C.c_void_p), ("adam_v", C.c_void_p)]
+                ("adam_m", C.c_void_p), ("adam_v", C.c_void_p), ("table_lp", C.c_void_p),
+                ("loss_scale", C.c_void_p), ("scaler_state", C.c_void_p)]
 
 
 class PrenomSampleCfg(C.Structure):
@@ -38,12 +40,12 @@ class PrenomSampleCfg(C.Structure):
 
 class PrenomRenderCfg(C.Structure):
     _fields_ = [("n_samples", C.c_int32), ("loss_mode", C.c_int32), ("lambda_d", C.c_float),
-                ("lambda_sigma", C.c_float)]
+                ("lambda_sigma", C.c_float), ("recompute", C.c_int32)]
 
 
 class PrenomAdamCfg(C.Structure):
     _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
-                ("step", C.c_int64)]
+                ("step", C.c_int64), ("growth_interval", C.c_int32)]
 
 
 class PrenomKernelTime(C.Structure):
@@ -81,9 +83,11 @@ def lib():
         L.prenom_render_bwd.restype = C.c_int
         L.prenom_render_bwd.argtypes = [C.POINTER(PrenomModel), C.POINTER(PrenomRenderCfg),
                                         _vp, _vp, _vp, _vp, C.c_int64, _vp, _vp, _vp, _vp,
-                                        _vp, _vp, _vp, C.c_size_t, _vp]
+                                        _vp, _vp, _vp, _vp, C.c_size_t, _vp]
         L.prenom_adam_step.restype = C.c_int
         L.prenom_adam_step.argtypes = [C.POINTER(PrenomModel), C.POINTER(PrenomAdamCfg), _vp]
+        L.prenom_refresh_lowp.restype = C.c_int
+        L.prenom_refresh_lowp.argtypes = [C.POINTER(PrenomModel), _vp]
         L.prenom_encode.restype = C.c_int
         L.prenom_encode.argtypes = [C.POINTER(PrenomArch), _vp, _vp, C.c_int64, _vp, _vp, _vp]
         L.prenom_profile_begin.restype = C.c_int

@@ -44,6 +44,8 @@ def make_arch(arch) -> L.PrenomArch:
         a.resolution[i] = int(r)
     a.mlp_width = arch.width
     a.mlp_hidden = arch.hidden
+    a.mlp_dtype = {"fp32": L.F32, "bf16": L.BF16, "fp16": L.F16}[getattr(arch, "mlp_dtype", "fp32")]
+    a.table_dtype = {"fp32": L.F32, "fp16": L.F16}[getattr(arch, "table_dtype", "fp32")]
     return a
 
 
@@ -60,9 +62,11 @@ def prenom_workspace_size(arch, n_rays: int, n_samples: int) -> int:
 
 
 class Model:
-    """One object NeRF on the device: parameters, gradients and Adam moments."""
+    """One object NeRF on the device: parameters, gradients and Adam moments,
+    plus the FP16 table copy and the loss-scaling state of the
+    reduced-precision form (arch.table_dtype == "fp16", loss_scale given)."""
 
-    def __init__(self, arch, params, device="cuda"):
+    def __init__(self, arch, params, device="cuda", loss_scale=None):
         self.arch = arch
         n = prenom_param_count(arch)
         if n < 0:
@@ -76,6 +80,16 @@ class Model:
         self.adam_v = torch.zeros_like(self.params)
         self.step = 0
         self._c_arch = make_arch(arch)
+        self.table_lp = None
+        if self._c_arch.table_dtype == L.F16:
+            self.table_lp = torch.empty(arch.n_table_params, dtype=torch.float16, device=device)
+        self.loss_scale = None
+        self.scaler_state = None
+        if loss_scale is not None:
+            self.loss_scale = torch.full((1,), float(loss_scale), dtype=torch.float32, device=device)
+            self.scaler_state = torch.zeros(2, dtype=torch.int32, device=device)
+        if self.table_lp is not None:
+            prenom_refresh_lowp(self)
 
     def c_struct(self, grads: Optional[torch.Tensor] = None) -> L.PrenomModel:
         m = L.PrenomModel()
@@ -84,6 +98,9 @@ class Model:
         m.grads = (grads if grads is not None else self.grads).data_ptr()
         m.adam_m = self.adam_m.data_ptr()
         m.adam_v = self.adam_v.data_ptr()
+        m.table_lp = None if self.table_lp is None else self.table_lp.data_ptr()
+        m.loss_scale = None if self.loss_scale is None else self.loss_scale.data_ptr()
+        m.scaler_state = None if self.scaler_state is None else self.scaler_state.data_ptr()
         return m
 
     @property
@@ -153,9 +170,10 @@ def prenom_sample(spec, rays_o: torch.Tensor, rays_d: torch.Tensor, xi: torch.Te
     return out
 
 
-def render_cfg(n_samples: int, loss) -> L.PrenomRenderCfg:
+def render_cfg(n_samples: int, loss, recompute: bool = False) -> L.PrenomRenderCfg:
     c = L.PrenomRenderCfg()
     c.n_samples = n_samples
+    c.recompute = int(recompute)
     c.loss_mode = loss.loss_mode if loss is not None else 0
     c.lambda_d = loss.lambda_d if loss is not None else 0.0
     c.lambda_sigma = loss.lambda_sigma if loss is not None else 0.0
@@ -204,25 +222,33 @@ def prenom_render_fwd(model: Model, samp: SampleOut, loss_spec, ws: torch.Tensor
 
 def prenom_render_bwd(model: Model, samp: SampleOut, loss_spec, ws: torch.Tensor, *, bg=None,
                       tgt_rgb=None, tgt_depth=None, mask=None, d_rgb=None, d_depth=None,
-                      grads: Optional[torch.Tensor] = None):
+                      d_opacity=None, grads: Optional[torch.Tensor] = None, recompute=False):
     n, S = samp.t.shape
     _dev(d_rgb, torch.float32, "d_rgb")
     _dev(d_depth, torch.float32, "d_depth")
-    cfg = render_cfg(S, loss_spec)
+    _dev(d_opacity, torch.float32, "d_opacity")
+    cfg = render_cfg(S, loss_spec, recompute)
     mc = model.c_struct(grads)
     st = L.lib().prenom_render_bwd(
         C.byref(mc), C.byref(cfg), _ptr(samp.ray_obj), _ptr(samp.t), _ptr(samp.dt), _ptr(samp.flags), n,
-        _ptr(bg), _ptr(tgt_rgb), _ptr(tgt_depth), _ptr(mask), _ptr(d_rgb), _ptr(d_depth), _ptr(ws),
-        ws.numel(), _stream())
+        _ptr(bg), _ptr(tgt_rgb), _ptr(tgt_depth), _ptr(mask), _ptr(d_rgb), _ptr(d_depth),
+        _ptr(d_opacity), _ptr(ws), ws.numel(), _stream())
     L.check(st, "prenom_render_bwd")
 
 
-def prenom_adam_step(model: Model, *, lr=1e-2, beta1=0.9, beta2=0.99, eps=1e-15, step=None):
+def prenom_refresh_lowp(model: Model):
+    mc = model.c_struct()
+    L.check(L.lib().prenom_refresh_lowp(C.byref(mc), _stream()), "prenom_refresh_lowp")
+
+
+def prenom_adam_step(model: Model, *, lr=1e-2, beta1=0.9, beta2=0.99, eps=1e-15, step=None,
+                     growth_interval=2000):
     if step is None:
         model.step += 1
         step = model.step
     c = L.PrenomAdamCfg()
     c.lr, c.beta1, c.beta2, c.eps, c.step = lr, beta1, beta2, eps, step
+    c.growth_interval = growth_interval
     mc = model.c_struct()
     L.check(L.lib().prenom_adam_step(C.byref(mc), C.byref(c), _stream()), "prenom_adam_step")
 

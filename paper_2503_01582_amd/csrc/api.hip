@@ -107,14 +107,35 @@ prenom_status check_arch(const prenom_arch* a)
             return fail(PRENOM_ERR_INVALID_ARG, "resolution[%d] = %d outside [2, 2^20)", l, a->resolution[l]);
     if (a->mlp_width < 16 || a->mlp_width % 16 || a->mlp_hidden < 1 || a->mlp_hidden > 4)
         return fail(PRENOM_ERR_INVALID_ARG, "mlp %d x %d", a->mlp_width, a->mlp_hidden);
+    if (a->mlp_dtype != PRENOM_F32 && a->mlp_dtype != PRENOM_BF16 && a->mlp_dtype != PRENOM_F16)
+        return fail(PRENOM_ERR_INVALID_ARG, "mlp_dtype %d", a->mlp_dtype);
+    if (a->table_dtype != PRENOM_F32 && a->table_dtype != PRENOM_F16)
+        return fail(PRENOM_ERR_INVALID_ARG, "table_dtype %d (FP32 or FP16)", a->table_dtype);
     return PRENOM_OK;
+}
+
+MlpShape mlp_shape(const prenom_arch* a)
+{
+    return MlpShape{a->n_levels * a->n_features, a->mlp_width, a->mlp_hidden, a->mlp_dtype};
+}
+
+hipError_t mlp_fwd_any(const MlpShape& m, const float* w, const float* y, int64_t n_s, float* sc, hipStream_t s)
+{
+    return m.dtype == PRENOM_F32 ? launch_mlp_fwd(m, w, y, n_s, sc, s) : launch_mlp_fwd_lp(m, w, y, n_s, sc, s);
+}
+
+hipError_t mlp_bwd_any(const MlpShape& m, const float* w, const float* y, const float* dout, int64_t n_s, float* dy,
+                       float* partial, hipStream_t s)
+{
+    return m.dtype == PRENOM_F32 ? launch_mlp_bwd(m, w, y, dout, n_s, dy, partial, s)
+                                 : launch_mlp_bwd_lp(m, w, y, dout, n_s, dy, partial, s);
 }
 
 prenom_status check_supported(const prenom_arch* a)
 {
     const prenom_status st = check_arch(a);
     if (st != PRENOM_OK) return st;
-    const MlpShape m{a->n_levels * a->n_features, a->mlp_width, a->mlp_hidden};
+    const MlpShape m = mlp_shape(a);
     if (!mlp_supported(m))
         return fail(PRENOM_ERR_UNSUPPORTED, "MLP in=%d width=%d hidden=%d is not compiled into this library",
                     m.in_dim, m.width, m.hidden);
@@ -213,6 +234,9 @@ prenom_status check_model(const prenom_model* m, bool need_grads)
     if (!m->params || !aligned(m->params, 16)) return fail(PRENOM_ERR_INVALID_ARG, "params NULL or not 16-byte aligned");
     if (need_grads && (!m->grads || !aligned(m->grads, 16)))
         return fail(PRENOM_ERR_INVALID_ARG, "grads NULL or not 16-byte aligned");
+    if (m->arch.table_dtype == PRENOM_F16 && (!m->table_lp || !aligned(m->table_lp, 8)))
+        return fail(PRENOM_ERR_INVALID_ARG, "table_dtype FP16 needs an 8-byte aligned table_lp");
+    if (m->loss_scale && !m->scaler_state) return fail(PRENOM_ERR_INVALID_ARG, "loss_scale needs scaler_state");
     return PRENOM_OK;
 }
 
@@ -226,6 +250,7 @@ prenom_status check_render(const prenom_model* model, const prenom_render_cfg* c
     if (cfg->n_samples < 1 || cfg->n_samples > 256)
         return fail(PRENOM_ERR_SHAPE, "n_samples %d outside [1, 256]", cfg->n_samples);
     if (cfg->loss_mode != 0 && cfg->loss_mode != 1) return fail(PRENOM_ERR_INVALID_ARG, "loss_mode %d", cfg->loss_mode);
+    if (cfg->recompute != 0 && cfg->recompute != 1) return fail(PRENOM_ERR_INVALID_ARG, "recompute %d", cfg->recompute);
     if (!(cfg->lambda_d >= 0.0f) || !(cfg->lambda_sigma >= 0.0f))
         return fail(PRENOM_ERR_INVALID_ARG, "negative or NaN loss weight");
     if (n_rays < 0) return fail(PRENOM_ERR_SHAPE, "n_rays < 0");
@@ -320,9 +345,11 @@ prenom_status prenom_render_fwd(const prenom_model* model, const prenom_render_c
     const GridInfo g = grid_info(a);
     float* y = at<float>(workspace, w.y);
     float* sc = at<float>(workspace, w.sc);
-    PRENOM_LAUNCH("k_encode_fwd", s, launch_encode_samples(g, model->params, ray_obj, t, n_rays, cfg->n_samples, y, s));
-    const MlpShape m{a->n_levels * a->n_features, a->mlp_width, a->mlp_hidden};
-    PRENOM_LAUNCH("k_mlp_fwd", s, launch_mlp_fwd(m, model->params + table_params(a), y, n_s, sc, s));
+    const void* tlp = a->table_dtype == PRENOM_F16 ? model->table_lp : nullptr;
+    PRENOM_LAUNCH("k_encode_fwd", s,
+                  launch_encode_samples(g, model->params, tlp, ray_obj, t, n_rays, cfg->n_samples, y, s));
+    const MlpShape m = mlp_shape(a);
+    PRENOM_LAUNCH("k_mlp_fwd", s, mlp_fwd_any(m, model->params + table_params(a), y, n_s, sc, s));
     CompositeArgs c{};
     c.n_rays = n_rays;
     c.S = cfg->n_samples;
@@ -353,7 +380,8 @@ prenom_status prenom_render_fwd(const prenom_model* model, const prenom_render_c
 prenom_status prenom_render_bwd(const prenom_model* model, const prenom_render_cfg* cfg, const float* ray_obj,
                                 const float* t, const float* dt, const uint8_t* flags, int64_t n_rays, const float* bg,
                                 const float* tgt_rgb, const float* tgt_depth, const uint8_t* mask, const float* d_rgb,
-                                const float* d_depth, void* workspace, size_t ws_bytes, void* stream)
+                                const float* d_depth, const float* d_opacity, void* workspace, size_t ws_bytes,
+                                void* stream)
 {
     prenom_status st = check_render(model, cfg, ray_obj, t, dt, flags, n_rays, workspace, ws_bytes, true);
     if (st != PRENOM_OK) return st;
@@ -363,6 +391,26 @@ prenom_status prenom_render_bwd(const prenom_model* model, const prenom_render_c
     const prenom_arch* a = &model->arch;
     const WsLayout w = ws_layout(a, n_rays, cfg->n_samples);
     const int64_t n_s = n_rays * cfg->n_samples;
+    const MlpShape m = mlp_shape(a);
+    if (cfg->recompute) {
+        // rebuild the features, head outputs and per-ray results render_fwd would have left
+        float* y = at<float>(workspace, w.y);
+        const void* tlp = a->table_dtype == PRENOM_F16 ? model->table_lp : nullptr;
+        PRENOM_LAUNCH("k_encode_fwd", s, launch_encode_samples(grid_info(a), model->params, tlp, ray_obj, t, n_rays,
+                                                               cfg->n_samples, y, s));
+        PRENOM_LAUNCH("k_mlp_fwd", s, mlp_fwd_any(m, model->params + table_params(a), y, n_s,
+                                                  at<float>(workspace, w.sc), s));
+        CompositeArgs f{};
+        f.n_rays = n_rays;
+        f.S = cfg->n_samples;
+        f.sc = at<float>(workspace, w.sc);
+        f.t = t;
+        f.dt = dt;
+        f.flags = flags;
+        f.bg = bg;
+        f.ray_state = at<float>(workspace, w.ray_state);
+        PRENOM_LAUNCH("k_composite_fwd", s, launch_composite_fwd(f, s));
+    }
     CompositeArgs c{};
     c.n_rays = n_rays;
     c.S = cfg->n_samples;
@@ -380,14 +428,15 @@ prenom_status prenom_render_bwd(const prenom_model* model, const prenom_render_c
     c.ray_state = at<float>(workspace, w.ray_state);
     c.d_rgb = d_rgb;
     c.d_depth = d_depth;
+    c.d_opacity = d_opacity;
+    c.loss_scale = model->loss_scale;
     c.dout = at<float>(workspace, w.dout);
     PRENOM_LAUNCH("k_composite_bwd", s, launch_composite_bwd(c, s));
-    const MlpShape m{a->n_levels * a->n_features, a->mlp_width, a->mlp_hidden};
     float* partial = at<float>(workspace, w.mlp_partial);
     float* dy = at<float>(workspace, w.dy);
     PRENOM_LAUNCH("k_mlp_bwd", s,
-                  launch_mlp_bwd(m, model->params + table_params(a), at<float>(workspace, w.y), c.dout, n_s, dy,
-                                 partial, s));
+                  mlp_bwd_any(m, model->params + table_params(a), at<float>(workspace, w.y), c.dout, n_s, dy,
+                              partial, s));
     if (n_s > 0)
         PRENOM_LAUNCH("k_reduce_partials", s,
                       launch_reduce_partials(partial, w.n_mlp_slots, mlp_params(a), model->grads + table_params(a), s));
@@ -428,6 +477,7 @@ prenom_status prenom_adam_step(const prenom_model* model, const prenom_adam_cfg*
     if (st != PRENOM_OK) return st;
     if (!cfg) return fail(PRENOM_ERR_INVALID_ARG, "cfg is NULL");
     if (cfg->step < 1) return fail(PRENOM_ERR_INVALID_ARG, "step must be >= 1");
+    if (cfg->growth_interval < 0) return fail(PRENOM_ERR_INVALID_ARG, "growth_interval < 0");
     if (!model->adam_m || !model->adam_v || !aligned(model->adam_m, 16) || !aligned(model->adam_v, 16))
         return fail(PRENOM_ERR_INVALID_ARG, "adam moments NULL or not 16-byte aligned");
     if (!(cfg->beta1 >= 0.0f && cfg->beta1 < 1.0f && cfg->beta2 >= 0.0f && cfg->beta2 < 1.0f && cfg->lr >= 0.0f &&
@@ -445,7 +495,22 @@ prenom_status prenom_adam_step(const prenom_model* model, const prenom_adam_cfg*
     a.eps = cfg->eps;
     a.inv_c1 = (float)(1.0 / (1.0 - std::pow((double)cfg->beta1, (double)cfg->step)));
     a.inv_c2 = (float)(1.0 / (1.0 - std::pow((double)cfg->beta2, (double)cfg->step)));
+    a.table_f16 = model->arch.table_dtype == PRENOM_F16 ? model->table_lp : nullptr;
+    a.n_table = table_params(&model->arch);
+    a.loss_scale = model->loss_scale;
+    a.scaler_state = model->scaler_state;
+    a.growth_interval = cfg->growth_interval;
     PRENOM_LAUNCH("k_adam", (hipStream_t)stream, launch_adam(a, (hipStream_t)stream));
+    return PRENOM_OK;
+}
+
+prenom_status prenom_refresh_lowp(const prenom_model* model, void* stream)
+{
+    prenom_status st = check_model(model, false);
+    if (st != PRENOM_OK) return st;
+    if (model->arch.table_dtype != PRENOM_F16) return PRENOM_OK;
+    PRENOM_LAUNCH("k_to_f16", (hipStream_t)stream,
+                  launch_to_f16(model->params, model->table_lp, table_params(&model->arch), (hipStream_t)stream));
     return PRENOM_OK;
 }
 

@@ -100,9 +100,11 @@ hipError_t launch_sample(const SampleArgs& a, hipStream_t s);
 hipError_t launch_encode_points(const GridInfo& g, const float* table, const float* pos, int64_t n,
                                 float* features, int32_t* corner_idx, hipStream_t s);
 
-// Encoding of the rendered samples (positions from rays and t).
-hipError_t launch_encode_samples(const GridInfo& g, const float* table, const float* ray_obj,
-                                 const float* t, int64_t n_rays, int32_t S, float* y, hipStream_t s);
+// Encoding of the rendered samples (positions from rays and t); reads the
+// FP16 table copy when table_f16 is not null, the FP32 tables otherwise.
+hipError_t launch_encode_samples(const GridInfo& g, const float* table, const void* table_f16,
+                                 const float* ray_obj, const float* t, int64_t n_rays, int32_t S, float* y,
+                                 hipStream_t s);
 
 // Bucketed scatter-add of the feature gradients into the table gradient.
 struct ScatterPlan {
@@ -144,7 +146,7 @@ hipError_t launch_scatter(const ScatterArgs& a, hipStream_t s);
 // MLP: forward writes (sigma, r, g, b) per sample; backward recomputes the
 // activations, writes dy and per-wave partial weight gradients.
 struct MlpShape {
-    int32_t in_dim, width, hidden;
+    int32_t in_dim, width, hidden, dtype;
 };
 bool mlp_supported(const MlpShape& m);
 int mlp_bwd_waves(int64_t n_samples);  // partial-gradient slots (one per block) the bwd writes
@@ -152,6 +154,10 @@ hipError_t launch_mlp_fwd(const MlpShape& m, const float* w, const float* y, int
                           hipStream_t s);
 hipError_t launch_mlp_bwd(const MlpShape& m, const float* w, const float* y, const float* dout,
                           int64_t n_s, float* dy, float* partial, hipStream_t s);
+hipError_t launch_mlp_fwd_lp(const MlpShape& m, const float* w, const float* y, int64_t n_s, float* sc,
+                             hipStream_t s);
+hipError_t launch_mlp_bwd_lp(const MlpShape& m, const float* w, const float* y, const float* dout, int64_t n_s,
+                             float* dy, float* partial, hipStream_t s);
 hipError_t launch_reduce_partials(const float* partial, int n_slots, int64_t n_mlp, float* g_mlp,
                                   hipStream_t s);
 
@@ -169,13 +175,15 @@ struct CompositeArgs {
     const float* tgt_rgb; // [n][3] or null
     const float* tgt_depth;
     const uint8_t* mask;
-    float* rgb;
+    float* rgb;           // fwd outputs, or null (then only ray_state is written)
     float* depth;
     float* opacity;
     float* ray_state;     // [n][8]: rgb(3), depth, T_S, sigma sum, -, -
     double* loss_partial; // [blocks]
     const float* d_rgb;   // bwd only
     const float* d_depth;
+    const float* d_opacity;
+    const float* loss_scale;  // bwd: device scalar multiplying the upstream gradient, or null
     float* dout;          // bwd: [n_s][4] (dsigma, dr, dg, db)
 };
 int composite_loss_blocks(int64_t n_rays);
@@ -190,7 +198,13 @@ struct AdamArgs {
     float* v;
     int64_t n;
     float lr, beta1, beta2, eps, inv_c1, inv_c2;
+    void* table_f16;         // FP16 copy of the first n_table entries, or null
+    int64_t n_table;
+    float* loss_scale;       // null: plain Adam
+    int32_t* scaler_state;   // [2] non-finite flag, finite steps since the last scale change
+    int32_t growth_interval;
 };
 hipError_t launch_adam(const AdamArgs& a, hipStream_t s);
+hipError_t launch_to_f16(const float* src, void* dst, int64_t n, hipStream_t s);
 
 }  // namespace prenom

@@ -110,9 +110,11 @@ __global__ __launch_bounds__(64 * kRaysPerBlock) void k_composite_fwd(CompositeA
         }
         for (int k = 0; k < 3; ++k) C[k] += T_S * bg[k];
         if (lane == 0) {
-            for (int k = 0; k < 3; ++k) a.rgb[3 * r + k] = C[k];
-            a.depth[r] = Dh;
-            a.opacity[r] = A;
+            if (a.rgb) {
+                for (int k = 0; k < 3; ++k) a.rgb[3 * r + k] = C[k];
+                a.depth[r] = Dh;
+                a.opacity[r] = A;
+            }
             float* st = a.ray_state + 8 * r;
             st[0] = C[0];
             st[1] = C[1];
@@ -177,10 +179,11 @@ __global__ __launch_bounds__(64 * kRaysPerBlock) void k_composite_bwd(CompositeA
     const float Dh = st[3], T_S = st[4];
 
     // upstream gradients of this ray: dL/dC, dL/dD and the per-sample density term
-    float gC[3], gD = 0.0f, extra = 0.0f;
+    float gC[3], gD = 0.0f, gA = 0.0f, extra = 0.0f;
     if (a.d_rgb) {
         for (int k = 0; k < 3; ++k) gC[k] = a.d_rgb[3 * r + k];
         gD = a.d_depth ? a.d_depth[r] : 0.0f;
+        gA = a.d_opacity ? a.d_opacity[r] : 0.0f;
     } else {
         const RayTargets tg = load_targets(a, r);
         const float n = (float)a.n_rays;
@@ -200,6 +203,15 @@ __global__ __launch_bounds__(64 * kRaysPerBlock) void k_composite_bwd(CompositeA
             else
                 extra = a.lambda_sigma;
         }
+    }
+    if (a.loss_scale) {  // loss scaling: every downstream gradient is scaled
+        const float sc = *a.loss_scale;
+        gC[0] *= sc;
+        gC[1] *= sc;
+        gC[2] *= sc;
+        gD *= sc;
+        gA *= sc;
+        extra *= sc;
     }
     float bg_term = 0.0f;
     if (a.bg) bg_term = T_S * (gC[0] * a.bg[3 * r] + gC[1] * a.bg[3 * r + 1] + gC[2] * a.bg[3 * r + 2]);
@@ -230,7 +242,7 @@ __global__ __launch_bounds__(64 * kRaysPerBlock) void k_composite_bwd(CompositeA
         const float Tj = expf(-excl);
         const float Tj1 = expf(-(excl + tau));
         const float w = Tj * (-expm1f(-tau));
-        const float aj = gC[0] * v.y + gC[1] * v.z + gC[2] * v.w + gD * tj;
+        const float aj = gC[0] * v.y + gC[1] * v.z + gC[2] * v.w + gD * tj + gA;
         const float wa = valid ? w * aj : 0.0f;
         const float suffix = wave_excl_suffix(wa, lane) + suffix_carry;
         const float dsig = dtj * (Tj1 * aj - suffix - bg_term) + extra;

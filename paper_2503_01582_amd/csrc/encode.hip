@@ -13,21 +13,30 @@ namespace {
 
 constexpr int kEncBlock = 256;
 
-__device__ __forceinline__ float2 gather_blend(const float2* __restrict__ level_table, const Corners& c)
+typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float2 to_f2(float2 v) { return v; }
+__device__ __forceinline__ float2 to_f2(half2_t v) { return make_float2((float)v[0], (float)v[1]); }
+
+// Table rows are float2 (FP32 tables) or two halves (the FP16 copy).
+template <typename Row>
+__device__ __forceinline__ float2 gather_blend(const Row* __restrict__ level_table, const Corners& c)
 {
-    float2 v[8];
+    Row v[8];
 #pragma unroll
     for (int e = 0; e < 8; ++e) v[e] = level_table[c.row[e]];  // issue all 8 loads first
     float2 acc = make_float2(0.0f, 0.0f);
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-        acc.x = fmaf(c.w[e], v[e].x, acc.x);
-        acc.y = fmaf(c.w[e], v[e].y, acc.y);
+        const float2 f = to_f2(v[e]);
+        acc.x = fmaf(c.w[e], f.x, acc.x);
+        acc.y = fmaf(c.w[e], f.y, acc.y);
     }
     return acc;
 }
 
-__global__ __launch_bounds__(kEncBlock) void k_encode_samples(GridInfo g, const float2* __restrict__ table,
+template <typename Row>
+__global__ __launch_bounds__(kEncBlock) void k_encode_samples(GridInfo g, const Row* __restrict__ table,
                                                               const float* __restrict__ ray_obj,
                                                               const float* __restrict__ t, int64_t n_s,
                                                               int32_t S, float2* __restrict__ y)
@@ -41,7 +50,7 @@ __global__ __launch_bounds__(kEncBlock) void k_encode_samples(GridInfo g, const 
     Corners c;
     level_corners(g, l, sample_coord(ts, ro[3], ro[0]), sample_coord(ts, ro[4], ro[1]),
                   sample_coord(ts, ro[5], ro[2]), c);
-    const float2* lt = table + ((int64_t)l << g.log2_table);
+    const Row* lt = table + ((int64_t)l << g.log2_table);
     y[(int64_t)l * n_s + s] = gather_blend(lt, c);
 }
 
@@ -70,13 +79,18 @@ dim3 enc_grid(int64_t n, int L) { return dim3((uint32_t)((n + kEncBlock - 1) / k
 
 }  // namespace
 
-hipError_t launch_encode_samples(const GridInfo& g, const float* table, const float* ray_obj, const float* t,
-                                 int64_t n_rays, int32_t S, float* y, hipStream_t s)
+hipError_t launch_encode_samples(const GridInfo& g, const float* table, const void* table_f16,
+                                 const float* ray_obj, const float* t, int64_t n_rays, int32_t S, float* y,
+                                 hipStream_t s)
 {
     const int64_t n_s = n_rays * S;
     if (n_s == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_encode_samples, enc_grid(n_s, g.n_levels), dim3(kEncBlock), 0, s, g,
-                       (const float2*)table, ray_obj, t, n_s, S, (float2*)y);
+    if (table_f16)
+        hipLaunchKernelGGL(k_encode_samples<half2_t>, enc_grid(n_s, g.n_levels), dim3(kEncBlock), 0, s, g,
+                           (const half2_t*)table_f16, ray_obj, t, n_s, S, (float2*)y);
+    else
+        hipLaunchKernelGGL(k_encode_samples<float2>, enc_grid(n_s, g.n_levels), dim3(kEncBlock), 0, s, g,
+                           (const float2*)table, ray_obj, t, n_s, S, (float2*)y);
     return hipGetLastError();
 }
 

@@ -1,0 +1,407 @@
+// Reduced-precision form of the object-NeRF MLP: BF16 or FP16 operands on
+// v_mfma_f32_16x16x16_{bf16,f16} with FP32 accumulation.  The FP32 master
+// weights are converted once per block into LDS fragments; activations,
+// deltas and every gradient stay FP32 in registers and are rounded only when
+// they become an MFMA operand.
+//
+// Operand layouts of the 16x16x16 instruction (lane l, q = l/16, j = l%16):
+// A[i][k] holds k = 4q..4q+3 of row i = j in lane l; B[k][n] holds
+// k = 4q..4q+3 of column n = j; D[i][n] sits at lane n + 16*(i/4), register
+// i%4.  So the four output registers of a 16-neuron tile are exactly the B
+// operand of the next layer over that tile (k = 4q + r), with no permutation;
+// weight fragments hold W[16 to + j][16 ti + 4q .. 4q+3].
+//
+// The weight gradient contracts over the 16 samples of a tile with one MFMA
+// per (out tile, in tile), after the same per-wave LDS transpose as the FP32
+// form; the 8 waves of a block merge their dW in LDS and write one partial.
+#include "mlp_common.h"
+
+namespace prenom {
+namespace {
+
+typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+
+struct Bf16Op {
+    using vec = short4_t;
+    static __device__ __forceinline__ short cvt(float x) { return __builtin_bit_cast(short, (__bf16)x); }
+    static __device__ __forceinline__ floatx4 mma(vec a, vec b, floatx4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+    }
+};
+
+struct F16Op {
+    using vec = half4_t;
+    static __device__ __forceinline__ _Float16 cvt(float x) { return (_Float16)x; }
+    static __device__ __forceinline__ floatx4 mma(vec a, vec b, floatx4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+    }
+};
+
+template <class P>
+__device__ __forceinline__ typename P::vec pack(float a, float b, float c, float d)
+{
+    typename P::vec v;
+    v[0] = P::cvt(a);
+    v[1] = P::cvt(b);
+    v[2] = P::cvt(c);
+    v[3] = P::cvt(d);
+    return v;
+}
+
+template <class P>
+__device__ __forceinline__ typename P::vec pack(floatx4 x)
+{
+    return pack<P>(x[0], x[1], x[2], x[3]);
+}
+
+template <int IN, int W, int D>
+struct NetLp {
+    static constexpr int KB1 = IN / 16;       // 16-feature K-blocks of layer 1
+    static constexpr int OT = W / 16;         // 16-neuron tiles of a hidden layer
+    static constexpr int IT = (IN + 15) / 16; // 16-feature tiles of the input
+    static constexpr int F1 = 0;                        // [OT][KB1]
+    static constexpr int FH = F1 + OT * KB1;            // [D-1][OT][OT]
+    static constexpr int FO = FH + (D - 1) * OT * OT;   // [OT]
+    static constexpr int N_FWD = FO + OT;
+    static constexpr int BO = N_FWD;                    // [OT]
+    static constexpr int BH = BO + OT;                  // [D-1][OT][OT]
+    static constexpr int B1 = BH + (D - 1) * OT * OT;   // [IT][OT]
+    static constexpr int N_ALL = B1 + IT * OT;
+    static constexpr int OFF_W1 = 0;
+    static constexpr int OFF_H = W * IN;
+    static constexpr int OFF_OUT = W * IN + (D - 1) * W * W;
+    static constexpr int N_PARAMS = OFF_OUT + 4 * W;
+    static_assert(IN % 16 == 0 && W % 16 == 0 && D >= 1, "shape");
+};
+
+// Weight fragments: fragment f, lane l holds 4 consecutive K values.
+template <int IN, int W, int D, class P>
+__device__ void load_fragments_lp(const float* __restrict__ w, typename P::vec* __restrict__ frag, int n_frag)
+{
+    using N = NetLp<IN, W, D>;
+    for (int idx = threadIdx.x; idx < n_frag * 64; idx += blockDim.x) {
+        const int f = idx >> 6, l = idx & 63, q = l >> 4, j = l & 15;
+        float v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            float x;
+            if (f < N::FH) {  // W1[16 to + j][16 m + 4 q + r]
+                const int to = f / N::KB1, m = f % N::KB1;
+                x = w[N::OFF_W1 + (16 * to + j) * IN + 16 * m + 4 * q + r];
+            } else if (f < N::FO) {  // Wk[16 to + j][16 ti + 4 q + r]
+                const int g = f - N::FH, k = g / (N::OT * N::OT), rem = g % (N::OT * N::OT);
+                const int to = rem / N::OT, ti = rem % N::OT;
+                x = w[N::OFF_H + k * W * W + (16 * to + j) * W + 16 * ti + 4 * q + r];
+            } else if (f < N::N_FWD) {  // Wout[j][16 ti + 4 q + r], rows >= 4 zero
+                const int ti = f - N::FO;
+                x = j < 4 ? w[N::OFF_OUT + j * W + 16 * ti + 4 * q + r] : 0.0f;
+            } else if (f < N::BH) {  // Wout^T over the 4 outputs: k = 4 q + r < 4
+                const int to = f - N::BO;
+                x = q == 0 ? w[N::OFF_OUT + r * W + 16 * to + j] : 0.0f;
+            } else if (f < N::B1) {  // Wk^T: Wk[16 ti + 4 q + r][16 to + j]
+                const int g = f - N::BH, k = g / (N::OT * N::OT), rem = g % (N::OT * N::OT);
+                const int to = rem / N::OT, ti = rem % N::OT;
+                x = w[N::OFF_H + k * W * W + (16 * ti + 4 * q + r) * W + 16 * to + j];
+            } else {  // W1^T: W1[16 ti + 4 q + r][16 to + j], columns >= IN zero
+                const int g = f - N::B1, to = g / N::OT, ti = g % N::OT, col = 16 * to + j;
+                x = col < IN ? w[N::OFF_W1 + (16 * ti + 4 * q + r) * IN + col] : 0.0f;
+            }
+            v[r] = x;
+        }
+        frag[idx] = pack<P>(v[0], v[1], v[2], v[3]);
+    }
+}
+
+// Layer-1 inputs of one lane: features 16 m + 4 q + r of sample s (levels
+// 8 m + 2 q and 8 m + 2 q + 1 of the level-major feature array).
+template <int KB1>
+__device__ __forceinline__ void load_inputs_lp(const float2* __restrict__ y, int64_t n_s, int64_t s, bool valid, int q,
+                                               floatx4 (&yf)[KB1])
+{
+#pragma unroll
+    for (int m = 0; m < KB1; ++m) {
+        float2 a = make_float2(0.0f, 0.0f), b = make_float2(0.0f, 0.0f);
+        if (valid) {
+            a = y[(int64_t)(8 * m + 2 * q) * n_s + s];
+            b = y[(int64_t)(8 * m + 2 * q + 1) * n_s + s];
+        }
+        yf[m] = {a.x, a.y, b.x, b.y};
+    }
+}
+
+template <int IN, int W, int D, class P>
+__device__ __forceinline__ void chain_lp(const typename P::vec* __restrict__ frag, int lane,
+                                         const floatx4 (&yf)[NetLp<IN, W, D>::KB1],
+                                         floatx4 (&hs)[D][NetLp<IN, W, D>::OT], floatx4& o)
+{
+    using N = NetLp<IN, W, D>;
+#pragma unroll
+    for (int to = 0; to < N::OT; ++to) {
+        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int m = 0; m < N::KB1; ++m) acc = P::mma(frag[(N::F1 + to * N::KB1 + m) * 64 + lane], pack<P>(yf[m]), acc);
+        hs[0][to] = relu4(acc);
+    }
+#pragma unroll
+    for (int k = 1; k < D; ++k) {
+#pragma unroll
+        for (int to = 0; to < N::OT; ++to) {
+            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int ti = 0; ti < N::OT; ++ti)
+                acc = P::mma(frag[(N::FH + ((k - 1) * N::OT + to) * N::OT + ti) * 64 + lane], pack<P>(hs[k - 1][ti]), acc);
+            hs[k][to] = relu4(acc);
+        }
+    }
+    o = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ti = 0; ti < N::OT; ++ti) o = P::mma(frag[(N::FO + ti) * 64 + lane], pack<P>(hs[D - 1][ti]), o);
+}
+
+template <int IN, int W, int D, class P>
+__global__ __launch_bounds__(256) void k_mlp_fwd_lp(const float* __restrict__ w, const float2* __restrict__ y,
+                                                    int64_t n_s, float4* __restrict__ sc)
+{
+    using N = NetLp<IN, W, D>;
+    __shared__ typename P::vec frag[N::N_FWD * 64];
+    load_fragments_lp<IN, W, D, P>(w, frag, N::N_FWD);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, q = lane >> 4, j = lane & 15;
+    const int64_t n_tiles = (n_s + 15) / 16;
+    const int64_t wave0 = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x / 64);
+    for (int64_t tile = wave0; tile < n_tiles; tile += n_waves) {
+        const int64_t s = tile * 16 + j;
+        const bool valid = s < n_s;
+        floatx4 yf[N::KB1];
+        load_inputs_lp<N::KB1>(y, n_s, s, valid, q, yf);
+        floatx4 hs[D][N::OT];
+        floatx4 o;
+        chain_lp<IN, W, D, P>(frag, lane, yf, hs, o);
+        if (q == 0 && valid) sc[s] = make_float4(__expf(o[0]), sigmoidf_(o[1]), sigmoidf_(o[2]), sigmoidf_(o[3]));
+    }
+}
+
+template <int IN, int W, int D>
+struct BwdLdsLp {
+    static constexpr int IP = 16 * NetLp<IN, W, D>::IT;
+    static constexpr int HW = (W > IP ? W : IP) + kStagePad;
+    static constexpr int DW = W + kStagePad;
+    static constexpr int PER_WAVE = 16 * (HW + DW);  // floats
+};
+
+template <int OTILES, int ITILES, int DP, int HP, class P>
+__device__ __forceinline__ void accumulate_dw_lp(const float* __restrict__ sD, const float* __restrict__ sH,
+                                                 floatx4 (&dw)[OTILES][ITILES], int q, int j)
+{
+    typename P::vec a[OTILES], b[ITILES];
+#pragma unroll
+    for (int to = 0; to < OTILES; ++to)
+        a[to] = pack<P>(sD[(4 * q) * DP + 16 * to + j], sD[(4 * q + 1) * DP + 16 * to + j],
+                        sD[(4 * q + 2) * DP + 16 * to + j], sD[(4 * q + 3) * DP + 16 * to + j]);
+#pragma unroll
+    for (int ti = 0; ti < ITILES; ++ti)
+        b[ti] = pack<P>(sH[(4 * q) * HP + 16 * ti + j], sH[(4 * q + 1) * HP + 16 * ti + j],
+                        sH[(4 * q + 2) * HP + 16 * ti + j], sH[(4 * q + 3) * HP + 16 * ti + j]);
+#pragma unroll
+    for (int to = 0; to < OTILES; ++to)
+#pragma unroll
+        for (int ti = 0; ti < ITILES; ++ti) dw[to][ti] = P::mma(a[to], b[ti], dw[to][ti]);
+}
+
+template <int IN, int W, int D, class P>
+__global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_bwd_lp(const float* __restrict__ w,
+                                                               const float2* __restrict__ y,
+                                                               const float4* __restrict__ dout, int64_t n_s,
+                                                               float2* __restrict__ dy, float* __restrict__ partial)
+{
+    using N = NetLp<IN, W, D>;
+    using B = BwdLdsLp<IN, W, D>;
+    extern __shared__ __align__(16) unsigned char smem_lp[];
+    typename P::vec* frag = reinterpret_cast<typename P::vec*>(smem_lp);
+    float* stage = reinterpret_cast<float*>(smem_lp + sizeof(typename P::vec) * N::N_ALL * 64);
+    load_fragments_lp<IN, W, D, P>(w, frag, N::N_ALL);
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, j = lane & 15;
+    float* sD = stage + wave * B::PER_WAVE;
+    float* sH = sD + 16 * B::DW;
+
+    floatx4 dW1[N::OT][N::IT];
+    floatx4 dWh[D > 1 ? D - 1 : 1][N::OT][N::OT];
+    floatx4 dWo[1][N::OT];
+#pragma unroll
+    for (int a = 0; a < N::OT; ++a) {
+#pragma unroll
+        for (int b = 0; b < N::IT; ++b) dW1[a][b] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int b = 0; b < N::OT; ++b)
+#pragma unroll
+            for (int k = 0; k < (D > 1 ? D - 1 : 1); ++k) dWh[k][a][b] = {0.0f, 0.0f, 0.0f, 0.0f};
+        dWo[0][a] = {0.0f, 0.0f, 0.0f, 0.0f};
+    }
+
+    const int64_t n_tiles = (n_s + 15) / 16;
+    const int64_t wave0 = (int64_t)blockIdx.x * kBwdWaves + wave;
+    const int64_t n_waves = (int64_t)gridDim.x * kBwdWaves;
+    for (int64_t tile = wave0; tile < n_tiles; tile += n_waves) {
+        const int64_t s = tile * 16 + j;
+        const bool valid = s < n_s;
+        floatx4 yf[N::KB1];
+        load_inputs_lp<N::KB1>(y, n_s, s, valid, q, yf);
+        floatx4 hs[D][N::OT];
+        floatx4 o;
+        chain_lp<IN, W, D, P>(frag, lane, yf, hs, o);
+
+        // head adjoint in the output tile's own layout (rows 4q + r; only q == 0 is real)
+        floatx4 dO[1] = {{0.0f, 0.0f, 0.0f, 0.0f}};
+        if (q == 0 && valid) {
+            const float4 g = dout[s];
+            const float c1 = sigmoidf_(o[1]), c2 = sigmoidf_(o[2]), c3 = sigmoidf_(o[3]);
+            dO[0] = {g.x * __expf(o[0]), g.y * c1 * (1.0f - c1), g.z * c2 * (1.0f - c2), g.w * c3 * (1.0f - c3)};
+        }
+        wave_lds_sync();
+        stage_dw<1, N::OT, B::DW, B::HW>(sD, sH, dO, hs[D - 1], q, j);
+        wave_lds_sync();
+        accumulate_dw_lp<1, N::OT, B::DW, B::HW, P>(sD, sH, dWo, q, j);
+
+        floatx4 delta[N::OT];
+        const typename P::vec dOp = pack<P>(dO[0]);
+#pragma unroll
+        for (int to = 0; to < N::OT; ++to) {
+            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            acc = P::mma(frag[(N::BO + to) * 64 + lane], dOp, acc);
+            delta[to] = mask_pos(acc, hs[D - 1][to]);
+        }
+#pragma unroll
+        for (int k = D - 1; k >= 1; --k) {
+            wave_lds_sync();
+            stage_dw<N::OT, N::OT, B::DW, B::HW>(sD, sH, delta, hs[k - 1], q, j);
+            wave_lds_sync();
+            accumulate_dw_lp<N::OT, N::OT, B::DW, B::HW, P>(sD, sH, dWh[k - 1], q, j);
+            typename P::vec dp[N::OT];
+#pragma unroll
+            for (int ti = 0; ti < N::OT; ++ti) dp[ti] = pack<P>(delta[ti]);
+#pragma unroll
+            for (int to = 0; to < N::OT; ++to) {
+                floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int ti = 0; ti < N::OT; ++ti)
+                    acc = P::mma(frag[(N::BH + ((k - 1) * N::OT + to) * N::OT + ti) * 64 + lane], dp[ti], acc);
+                delta[to] = mask_pos(acc, hs[k - 1][to]);
+            }
+        }
+        // layer 1: stage delta and the inputs (features 16 m + 4 q + r of sample j)
+        wave_lds_sync();
+#pragma unroll
+        for (int to = 0; to < N::OT; ++to)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sD[j * B::DW + 16 * to + 4 * q + r] = delta[to][r];
+#pragma unroll
+        for (int m = 0; m < N::KB1; ++m)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sH[j * B::HW + 16 * m + 4 * q + r] = yf[m][r];
+        wave_lds_sync();
+        accumulate_dw_lp<N::OT, N::IT, B::DW, B::HW, P>(sD, sH, dW1, q, j);
+        typename P::vec dp[N::OT];
+#pragma unroll
+        for (int ti = 0; ti < N::OT; ++ti) dp[ti] = pack<P>(delta[ti]);
+#pragma unroll
+        for (int to = 0; to < N::IT; ++to) {
+            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int ti = 0; ti < N::OT; ++ti) acc = P::mma(frag[(N::B1 + to * N::OT + ti) * 64 + lane], dp[ti], acc);
+            const int f = 16 * to + 4 * q;  // features f..f+3 = levels f/2 and f/2 + 1
+            if (valid && f < IN) {
+                dy[(int64_t)(f >> 1) * n_s + s] = make_float2(acc[0], acc[1]);
+                dy[(int64_t)((f >> 1) + 1) * n_s + s] = make_float2(acc[2], acc[3]);
+            }
+        }
+    }
+
+    static_assert(N::N_PARAMS <= kBwdWaves * B::PER_WAVE, "reduction buffer");
+    float* red = stage;
+    __syncthreads();
+    for (int wv = 0; wv < kBwdWaves; ++wv) {
+        if (wave == wv) {
+            merge_dw<N::OT, N::IT>(red + N::OFF_W1, dW1, W, IN, q, j, wv == 0);
+#pragma unroll
+            for (int k = 1; k < D; ++k)
+                merge_dw<N::OT, N::OT>(red + N::OFF_H + (k - 1) * W * W, dWh[k - 1], W, W, q, j, wv == 0);
+            merge_dw<1, N::OT>(red + N::OFF_OUT, dWo, 4, W, q, j, wv == 0);
+        }
+        __syncthreads();
+    }
+    float* dst = partial + (int64_t)blockIdx.x * N::N_PARAMS;
+    for (int p = threadIdx.x; p < N::N_PARAMS; p += blockDim.x) dst[p] = red[p];
+}
+
+template <int IN, int W, int D, class P>
+hipError_t fwd_lp(const float* w, const float* y, int64_t n_s, float* sc, hipStream_t s)
+{
+    const int64_t n_tiles = (n_s + 15) / 16;
+    int64_t blocks = (n_tiles + 3) / 4;
+    blocks = blocks > 2048 ? 2048 : blocks;
+    hipLaunchKernelGGL((k_mlp_fwd_lp<IN, W, D, P>), dim3((uint32_t)blocks), dim3(256), 0, s, w, (const float2*)y,
+                       n_s, (float4*)sc);
+    return hipGetLastError();
+}
+
+template <int IN, int W, int D, class P>
+hipError_t bwd_lp(const float* w, const float* y, const float* dout, int64_t n_s, float* dy, float* partial,
+                  hipStream_t s)
+{
+    using N = NetLp<IN, W, D>;
+    const size_t lds = sizeof(typename P::vec) * (size_t)N::N_ALL * 64 +
+                       sizeof(float) * (size_t)kBwdWaves * BwdLdsLp<IN, W, D>::PER_WAVE;
+    auto kern = k_mlp_bwd_lp<IN, W, D, P>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((uint32_t)bwd_blocks(n_s)), dim3(64 * kBwdWaves), lds, s, w, (const float2*)y,
+                       (const float4*)dout, n_s, (float2*)dy, partial);
+    return hipGetLastError();
+}
+
+template <class P>
+hipError_t fwd_dispatch(const MlpShape& m, const float* w, const float* y, int64_t n_s, float* sc, hipStream_t s)
+{
+    if (m.width == 64 && m.in_dim == 16 && m.hidden == 1) return fwd_lp<16, 64, 1, P>(w, y, n_s, sc, s);
+    if (m.width == 64 && m.in_dim == 16 && m.hidden == 2) return fwd_lp<16, 64, 2, P>(w, y, n_s, sc, s);
+    if (m.width == 64 && m.in_dim == 32 && m.hidden == 1) return fwd_lp<32, 64, 1, P>(w, y, n_s, sc, s);
+    if (m.width == 64 && m.in_dim == 32 && m.hidden == 2) return fwd_lp<32, 64, 2, P>(w, y, n_s, sc, s);
+    return hipErrorInvalidValue;
+}
+
+template <class P>
+hipError_t bwd_dispatch(const MlpShape& m, const float* w, const float* y, const float* dout, int64_t n_s, float* dy,
+                        float* partial, hipStream_t s)
+{
+    if (m.width == 64 && m.in_dim == 16 && m.hidden == 1) return bwd_lp<16, 64, 1, P>(w, y, dout, n_s, dy, partial, s);
+    if (m.width == 64 && m.in_dim == 16 && m.hidden == 2) return bwd_lp<16, 64, 2, P>(w, y, dout, n_s, dy, partial, s);
+    if (m.width == 64 && m.in_dim == 32 && m.hidden == 1) return bwd_lp<32, 64, 1, P>(w, y, dout, n_s, dy, partial, s);
+    if (m.width == 64 && m.in_dim == 32 && m.hidden == 2) return bwd_lp<32, 64, 2, P>(w, y, dout, n_s, dy, partial, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_mlp_fwd_lp(const MlpShape& m, const float* w, const float* y, int64_t n_s, float* sc, hipStream_t s)
+{
+    if (n_s == 0) return hipSuccess;
+    if (m.dtype == PRENOM_BF16) return fwd_dispatch<Bf16Op>(m, w, y, n_s, sc, s);
+    if (m.dtype == PRENOM_F16) return fwd_dispatch<F16Op>(m, w, y, n_s, sc, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_mlp_bwd_lp(const MlpShape& m, const float* w, const float* y, const float* dout, int64_t n_s,
+                             float* dy, float* partial, hipStream_t s)
+{
+    if (n_s == 0) return hipSuccess;
+    if (m.dtype == PRENOM_BF16) return bwd_dispatch<Bf16Op>(m, w, y, dout, n_s, dy, partial, s);
+    if (m.dtype == PRENOM_F16) return bwd_dispatch<F16Op>(m, w, y, dout, n_s, dy, partial, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace prenom

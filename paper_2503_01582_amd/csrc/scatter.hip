@@ -45,6 +45,33 @@ constexpr int kReduceThreads = 1024;
 constexpr int kReduceUnroll = 8;  // records in flight per thread
 constexpr int64_t kChunk = (int64_t)1 << 21;  // records per reduce work item
 
+// Levels with at most this many tiles have most lanes of a wave in the same
+// tile; their histogram atomics are combined per wave first.
+constexpr int kAggregateTiles = 16;
+
+// Adds 1 to hist[tile] for every active lane and returns the lane's rank
+// among the additions to that tile.  Lanes of the wave that share a tile are
+// combined into one LDS atomic issued by their first lane (same-address
+// atomics of one instruction would otherwise serialise).
+__device__ __forceinline__ uint32_t wave_aggregated_add(uint32_t* hist, uint32_t tile)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint64_t remaining = __ballot(1);
+    uint32_t rank = 0;
+    while (remaining) {
+        const int leader = __ffsll((unsigned long long)remaining) - 1;
+        const uint32_t lt = __shfl(tile, leader);
+        const uint64_t mask = __ballot(tile == lt);
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&hist[lt], (uint32_t)__popcll(mask));
+        base = __shfl(base, leader);
+        if (tile == lt) rank = base + (uint32_t)__popcll(mask & lane_lt);
+        remaining &= ~mask;
+    }
+    return rank;
+}
+
 // Feature gradient and corners of one (sample, level); false when dy == 0
 // (the sample contributes nothing and is skipped by count and place alike).
 __device__ __forceinline__ bool load_contrib(const ScatterArgs& a, int l, int64_t s, float2& d, Corners& c)
@@ -74,8 +101,13 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_count(ScatterArgs a)
         Corners c;
         if (!load_contrib(a, l, s, d, c)) continue;
         m = fmaxf(m, fmaxf(fabsf(d.x), fabsf(d.y)));
+        if (nt <= kAggregateTiles) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) atomicAdd(&hist[c.row[e] >> kTileBits], 1u);
+            for (int e = 0; e < 8; ++e) wave_aggregated_add(hist, c.row[e] >> kTileBits);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) atomicAdd(&hist[c.row[e] >> kTileBits], 1u);
+        }
     }
 #pragma unroll
     for (int dd = 32; dd >= 1; dd >>= 1) m = fmaxf(m, __shfl_xor(m, dd));
@@ -204,8 +236,13 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
         float2 d;
         Corners c;
         if (s >= a.n_s || !load_contrib(a, l, s, d, c)) continue;
+        if (nt <= kAggregateTiles) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) rank[k][e] = atomicAdd(&hist[c.row[e] >> kTileBits], 1u);
+            for (int e = 0; e < 8; ++e) rank[k][e] = wave_aggregated_add(hist, c.row[e] >> kTileBits);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) rank[k][e] = atomicAdd(&hist[c.row[e] >> kTileBits], 1u);
+        }
     }
     __syncthreads();
     // block-local segments: exclusive scan of hist (serial over <= 1024 tiles by one wave)
@@ -259,7 +296,7 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
 
 __global__ __launch_bounds__(kReduceThreads) void k_scatter_reduce(ScatterArgs a)
 {
-    __shared__ unsigned long long acc[2 * kTileRows];  // fixed point, [row][feature]
+    __shared__ unsigned long long acc[2 * kTileRows];  // fixed point: feature 0 rows, then feature 1 rows
     __shared__ int64_t s_chunk;
     const uint64_t n_chunks = a.chunk_start[a.n_tiles];
     for (;;) {
@@ -288,7 +325,10 @@ __global__ __launch_bounds__(kReduceThreads) void k_scatter_reduce(ScatterArgs a
         const uint64_t r_end = min(r_begin + (uint64_t)kChunk, a.tile_start[tile + 1]);
         const bool owner = (a.chunk_start[tile + 1] - a.chunk_start[tile]) == 1;
         const int ex = a.tile_exp[tile];
-        for (int i = threadIdx.x; i < 2 * n_rows; i += kReduceThreads) acc[i] = 0ull;
+        for (int i = threadIdx.x; i < n_rows; i += kReduceThreads) {
+            acc[i] = 0ull;
+            acc[kTileRows + i] = 0ull;
+        }
         __syncthreads();
         // kReduceUnroll independent, coalesced record loads in flight per thread
         for (uint64_t r0 = r_begin; r0 < r_end; r0 += (uint64_t)kReduceThreads * kReduceUnroll) {
@@ -305,14 +345,14 @@ __global__ __launch_bounds__(kReduceThreads) void k_scatter_reduce(ScatterArgs a
             for (int u = 0; u < kReduceUnroll; ++u) {
                 const long long qx = (long long)rintf(ldexpf(v[u].x, ex));
                 const long long qy = (long long)rintf(ldexpf(v[u].y, ex));
-                if (qx != 0) atomicAdd(&acc[2 * key[u]], (unsigned long long)qx);
-                if (qy != 0) atomicAdd(&acc[2 * key[u] + 1], (unsigned long long)qy);
+                if (qx != 0) atomicAdd(&acc[key[u]], (unsigned long long)qx);
+                if (qy != 0) atomicAdd(&acc[kTileRows + key[u]], (unsigned long long)qy);
             }
         }
         __syncthreads();
         float2* g = reinterpret_cast<float2*>(a.g_table) + ((int64_t)l << a.grid.log2_table) + row0;
         for (int i = threadIdx.x; i < n_rows; i += kReduceThreads) {
-            const long long sx = (long long)acc[2 * i], sy = (long long)acc[2 * i + 1];
+            const long long sx = (long long)acc[i], sy = (long long)acc[kTileRows + i];
             if (sx == 0 && sy == 0) continue;
             const float2 v = make_float2((float)ldexp((double)sx, -ex), (float)ldexp((double)sy, -ex));
             if (owner) {

@@ -43,11 +43,11 @@ def to_device(batch, device="cuda") -> DeviceBatch:
 
 class Trainer:
     def __init__(self, arch, params, sample_spec, loss_spec, lr=1e-2, beta1=0.9, beta2=0.99,
-                 eps=1e-15, device="cuda"):
-        self.model = api.Model(arch, params, device)
+                 eps=1e-15, device="cuda", loss_scale=None, growth_interval=2000):
+        self.model = api.Model(arch, params, device, loss_scale=loss_scale)
         self.sample_spec = sample_spec
         self.loss_spec = loss_spec
-        self.adam = dict(lr=lr, beta1=beta1, beta2=beta2, eps=eps)
+        self.adam = dict(lr=lr, beta1=beta1, beta2=beta2, eps=eps, growth_interval=growth_interval)
         self.ws = api.Workspace(device)
         self._samp: Optional[api.SampleOut] = None
         self._out = None
@@ -86,3 +86,30 @@ class Trainer:
         self.backward(b, samp)
         api.prenom_adam_step(self.model, **self.adam)
         return out
+
+
+class AutogradTrainer(Trainer):
+    """The same iteration with the loss written in torch on top of
+    PrenomRender: colour MSE over all rays plus lambda_d * depth MSE over
+    object rays (the mean-squared form of Eq. (8)-(9)), then Adam."""
+
+    def __init__(self, *a, recompute=False, **k):
+        super().__init__(*a, **k)
+        self.recompute = recompute
+        self.model.params.requires_grad_(True)
+
+    def step(self, b: DeviceBatch):
+        from .autograd import render
+        samp = self.sample(b)
+        rgb, depth, _ = render(self.model, samp, b.bg, self.recompute)
+        n = b.n_rays
+        loss = ((rgb - b.tgt_rgb) ** 2).sum() / (3 * n)
+        if self.loss_spec.lambda_d > 0:
+            m = b.mask.float()
+            loss = loss + self.loss_spec.lambda_d * (m * (depth - b.tgt_depth) ** 2).sum() / n
+        self.model.params.grad = None
+        loss.backward()
+        with torch.no_grad():
+            self.model.grads.add_(self.model.params.grad)
+        api.prenom_adam_step(self.model, **self.adam)
+        return dict(rgb=rgb.detach(), depth=depth.detach(), loss=loss.detach().reshape(1))

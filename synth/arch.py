@@ -34,6 +34,8 @@ class Arch:
     width: int = 64
     hidden: int = 2
     resolutions: Tuple[int, ...] = field(default=())
+    mlp_dtype: str = "fp32"     # "fp32" | "bf16" | "fp16"
+    table_dtype: str = "fp32"   # "fp32" | "fp16" (an FP16 copy read by the forward gathers)
 
     def __post_init__(self):
         if not self.resolutions:
