@@ -1,15 +1,25 @@
 """Training-step throughput of the per-object NeRF step on one MI355X.
 
-Workload (prior-based sampling): 65536 rays per step drawn from 16 cameras at
-640x480 around a random 3-ellipsoid object, 16 coarse + 48 inverse-CDF
-samples per ray (64 rendered), hash grid 16 levels x 2^19 x 2 features, MLP
-64 x 2 hidden, FP32, mean-squared colour loss, Adam.  A step is
-prenom_sample + prenom_render_fwd (fused loss) + prenom_render_bwd +
-prenom_adam_step on resident inputs.
+Workloads (--workload):
+  prior   (default) one object, prior-based sampling: 65536 rays per step
+          drawn from 16 cameras at 640x480 around a random 3-ellipsoid
+          object, 16 coarse + 48 inverse-CDF samples per ray (64 rendered),
+          hash grid 16 levels x 2^19 x 2 features, MLP 64 x 2 hidden, FP32,
+          mean-squared colour loss, Adam.  A step is prenom_sample +
+          prenom_render_fwd (fused loss) + prenom_render_bwd +
+          prenom_adam_step on resident inputs.
+  batch24 24 objects trained together (own scene, prior, pose, log-uniform
+          ray count in [1k, 64k], architecture drawn from L {8,12,16},
+          T 2^14..2^19, W {32,64}, D {1,2}), FP32, one launch per phase,
+          the step captured in a HIP graph, MLP tiles from the autotuner;
+          also timed: the same objects as 24 single-object steps in turn.
+  batch48 48 objects, 2^20 rays in all, MLP in BF16 (--mlp-dtype) on the
+          matrix cores with FP32 accumulation, FP16 table copy, dynamic loss
+          scaling from 2^12; otherwise as batch24.
 
 Prints one JSON line: rays/s, the roofline position of the dominant kernel
-(per-kernel HIP-event timing inside the timed region) and the FP64 CPU oracle
-timed on a bounded sample of the same workload.
+(per-kernel HIP-event timing) and, for the prior workload, the FP64 CPU
+oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -26,29 +36,66 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix
+LOWP_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 / FP16 matrix
+METRIC = "training rays/s (fwd+bwd) vs plain FP32 at equal PSNR; % HBM/MFMA roofline"
 
 
 def algorithmic_work(arch, n_rays, S, n_fine):
-    """Per-launch algorithmic bytes (HBM-bound kernels) or FLOPs (MLP) of one
-    step's kernels.  Counting rule: every value the kernel must read or write
-    once, each hash-grid corner access as one 8-byte (2 x FP32) row, FP32
-    everywhere."""
+    """Algorithmic bytes (HBM-bound kernels) or FLOPs (MLP) of one step's
+    kernels for one object.  Counting rule: every value the kernel must read
+    or write once, each hash-grid corner access as one table row (2 x FP32,
+    or 2 x FP16 when the forward reads the FP16 copy)."""
     n_s = n_rays * S
     L = arch.n_levels
     in_dim, W, D = arch.in_dim, arch.width, arch.hidden
     macs = W * in_dim + (D - 1) * W * W + 4 * W
-    per_level = 8 * 8 + 8            # 8 corner rows + the feature pair (read or write)
+    row_fwd = 4 if getattr(arch, "table_dtype", "fp32") == "fp16" else 8
     pos = 4 + 24.0 / S               # t, plus the ray's origin/direction shared by S samples
     return {
         "k_sample": ("hbm", n_rays * (24 + 4 * n_fine + 8 * S + 4 * n_fine + 1 + 24)),
-        "k_encode_fwd": ("hbm", n_s * (pos + L * per_level)),
+        "k_encode_fwd": ("hbm", n_s * (pos + L * (8 * row_fwd + 8))),
         "k_mlp_fwd": ("mfma", n_s * 2.0 * macs),
         "k_composite_fwd": ("hbm", n_s * 24 + n_rays * (12 + 4 + 4 + 32 + 12 + 4 + 1)),
         "k_composite_bwd": ("hbm", n_s * 40 + n_rays * (32 + 12 + 4 + 1)),
         "k_mlp_bwd": ("mfma", n_s * 6.0 * macs),
-        "k_encode_bwd": ("hbm", n_s * (pos + L * per_level)),
-        "k_adam": ("hbm", arch.n_params * 32),
+        "k_encode_bwd": ("hbm", n_s * (pos + L * (8 * 8 + 8))),
+        "k_adam": ("hbm", arch.n_params * (32 + (2 if getattr(arch, "table_dtype", "fp32") == "fp16" else 0))),
     }
+
+
+def summed_work(items):
+    """Sum of algorithmic_work over (arch, n_rays, S, n_fine) items."""
+    tot = {}
+    for it in items:
+        for k, (bound, amount) in algorithmic_work(*it).items():
+            tot[k] = (bound, tot.get(k, (bound, 0.0))[1] + amount)
+    return tot
+
+
+def kernel_table(kt, steps, ms_per_step, work, mlp_peak, log):
+    """Per kernel: time per step, share of the step and, where its
+    algorithmic work is known, achieved rate vs the MI355X peak."""
+    kern = {}
+    for name, (n, tot) in sorted(kt.items(), key=lambda kv: -kv[1][1]):
+        per_step = tot / steps
+        entry = dict(avg_ms=tot / n, ms_per_step=per_step, launches_per_step=n / steps, share=per_step / ms_per_step)
+        if name in work:
+            bound, amount = work[name]
+            if bound == "hbm":
+                entry.update(bound="hbm", achieved=amount / (per_step * 1e-3) / 1e9, unit="GB/s", peak=HBM_PEAK_GBS)
+            else:
+                entry.update(bound="mfma", achieved=amount / (per_step * 1e-3) / 1e12, unit="TFLOP/s", peak=mlp_peak)
+            entry["frac"] = entry["achieved"] / entry["peak"]
+        kern[name] = entry
+        log(f"  {name:18s} {per_step * 1e3:9.1f} us/step ({n / steps:.0f} launches)  {100 * entry['share']:5.1f}%  "
+            + (f"{entry['achieved']:8.1f} {entry['unit']} ({100 * entry['frac']:.1f}% of peak)"
+               if "frac" in entry else ""))
+    dom = max((k for k in kern if "frac" in kern[k]), key=lambda k: kern[k]["ms_per_step"])
+    d = kern[dom]
+    roofline = dict(kernel=dom, bound=d["bound"], achieved=round(d["achieved"], 2), peak=d["peak"],
+                    unit=d["unit"], frac=round(d["frac"], 4), traffic=None)
+    kern = {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()} for k, v in kern.items()}
+    return kern, roofline
 
 
 def cpu_baseline(batch, params, n_sample_rays):
@@ -75,14 +122,184 @@ def cpu_baseline(batch, params, n_sample_rays):
                        f"FP64, {dt:.1f} s")
 
 
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed_loop(step, steps):
+    """Runs `steps` steps between two events on the current stream; returns ms."""
+    import torch
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1)
+
+
+def copy_calibration():
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log("bench: copied 1 GiB device-to-device for counter calibration")
+
+
+def run_prior(args):
+    import torch
+    from paper_2503_01582_amd import api
+    from paper_2503_01582_amd.trainer import Trainer, to_device
+    from synth.params import init_params
+    from synth.workloads import prior_batch, prior_world
+
+    log("bench: building the synthetic scene and batch")
+    world = prior_world(seed=1)
+    batch = prior_batch(world, args.rays, step=0)
+    arch = batch.arch
+    params = init_params(arch, 0)
+    tr = Trainer(arch, params, batch.sample, batch.loss)
+    db = to_device(batch)
+    S = batch.sample.n_samples
+    log(f"bench: {args.warmup} warm-up steps")
+    for _ in range(args.warmup):
+        tr.step(db)
+    torch.cuda.synchronize()
+    log(f"bench: {args.steps} timed steps")
+    api.prenom_profile_begin()
+    t0 = time.perf_counter()
+    ms = timed_loop(lambda: tr.step(db), args.steps)
+    wall = time.perf_counter() - t0
+    kt = api.prenom_profile_end()
+    if args.copy_calibration:
+        copy_calibration()
+    ms_per_step = ms / args.steps
+    value = args.rays * args.steps / (ms / 1e3)
+    log(f"bench: {ms_per_step:.3f} ms/step ({wall / args.steps * 1e3:.3f} ms wall), "
+        f"loss {float(tr._out['loss'].item()):.4e}")
+    kern, roofline = kernel_table(kt, args.steps, ms_per_step, algorithmic_work(arch, args.rays, S, batch.sample.n_fine),
+                                  FP32_MFMA_PEAK_TFLOPS, log)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"bench: CPU oracle on {args.cpu_rays} rays")
+        cpu = cpu_baseline(batch, params, args.cpu_rays)
+    config = dict(workload="prior-sampled object NeRF training step", n_rays=args.rays,
+                  samples_per_ray=S, n_coarse=batch.sample.n_coarse, n_fine=batch.sample.n_fine,
+                  hash_levels=arch.n_levels, log2_table=arch.log2_table, mlp_width=arch.width,
+                  mlp_hidden=arch.hidden, samples_per_s=round(value * S, 1))
+    return value, ms_per_step, "fp32", config, roofline, kern, cpu, {}
+
+
+def run_batch(args, n_objects, total_rays, mlp_dtype, table_dtype, seed):
+    import dataclasses
+    import torch
+    from paper_2503_01582_amd import api, autotune
+    from paper_2503_01582_amd.batch import BatchObject, BatchTrainer
+    from paper_2503_01582_amd.trainer import Trainer
+    from synth.multi import multi_batch, multi_objects
+    from synth.params import init_params
+    from synth.workloads import PRIOR_SAMPLE, LossSpec
+
+    log(f"bench: building {n_objects} objects")
+    objs = multi_objects(seed, n_objects, total_rays=total_rays, mlp_dtype=mlp_dtype, table_dtype=table_dtype)
+    n_rays = sum(o.n_rays for o in objs)
+    S = PRIOR_SAMPLE.n_samples
+    b = multi_batch(objs, step=0)
+    params = [init_params(o.arch, i) for i, o in enumerate(objs)]
+    priors = [torch.as_tensor(o.prior).cuda() for o in objs]
+    bobjs = [BatchObject(o.arch, o.n_rays, p, o.world_to_obj) for o, p in zip(objs, priors)]
+    tiles = autotune.tiles_for([o.arch for o in objs])
+    if len(tiles) < len({(o.arch.in_dim, o.arch.width, o.arch.hidden) for o in objs}) and not args.no_tune:
+        log("bench: tuning MLP tile shapes (no cached entry for every shape)")
+        tiles = autotune.tune([o.arch for o in objs], log=log)
+    loss = LossSpec()
+    lowp = mlp_dtype != "fp32"
+    tr = BatchTrainer(bobjs, params, PRIOR_SAMPLE, loss, tiles=tiles, loss_scale=4096.0 if lowp else None)
+    tr.load(b)
+    log(f"bench: {n_rays} rays over {n_objects} objects, {len(tr.model.params) / 1e6:.1f} M parameters; "
+        f"{args.warmup} eager warm-up steps")
+    for _ in range(args.warmup):
+        tr.step()
+    torch.cuda.synchronize()
+    # per-kernel times from eager steps (events cannot live inside the graph)
+    api.prenom_profile_begin()
+    prof_steps = max(3, min(args.steps, 10))
+    ms_eager = timed_loop(tr.step, prof_steps)
+    kt = api.prenom_profile_end()
+    tr.capture()
+    for _ in range(3):
+        tr.replay()
+    log(f"bench: {args.steps} timed graph replays")
+    t0 = time.perf_counter()
+    ms = timed_loop(tr.replay, args.steps)
+    wall = time.perf_counter() - t0
+    if args.copy_calibration:
+        copy_calibration()
+    ms_per_step = ms / args.steps
+    value = n_rays * args.steps / (ms / 1e3)
+    log(f"bench: {ms_per_step:.3f} ms/step replayed ({wall / args.steps * 1e3:.3f} ms wall), "
+        f"{ms_eager / prof_steps:.3f} ms/step eager; mean loss {float(tr.out['loss'].mean().item()):.4e}")
+    work = summed_work([(o.arch, o.n_rays, S, PRIOR_SAMPLE.n_fine) for o in objs])
+    kern, roofline = kernel_table(kt, prof_steps, ms_eager / prof_steps, work,
+                                  LOWP_MFMA_PEAK_TFLOPS if lowp else FP32_MFMA_PEAK_TFLOPS, log)
+    extra = dict(eager_ms_per_step=round(ms_eager / prof_steps, 4))
+    if not args.no_sequential:
+        # the same objects and rays as single-object steps, one after another on one stream
+        log("bench: the same objects as single-object steps in turn")
+        del tr
+        torch.cuda.empty_cache()
+        from paper_2503_01582_amd.trainer import DeviceBatch
+        trainers, dbs = [], []
+        for i, o in enumerate(objs):
+            if o.n_rays == 0:
+                continue
+            sl = b.slice(i)
+            t = Trainer(o.arch, params[i], PRIOR_SAMPLE, loss, loss_scale=4096.0 if lowp else None)
+            dev = lambda a, dt=torch.float32: torch.as_tensor(np.ascontiguousarray(a)).to("cuda", dt)
+            dbs.append(DeviceBatch(rays_o=dev(b.rays_o[sl]), rays_d=dev(b.rays_d[sl]), xi=dev(b.xi[sl]),
+                                   tgt_rgb=dev(b.tgt_rgb[sl]), tgt_depth=dev(b.tgt_depth[sl]),
+                                   mask=dev(b.mask[sl], torch.uint8), world_to_obj=o.world_to_obj,
+                                   prior=priors[i], bg=None))
+            trainers.append(t)
+
+        def seq_step():
+            for t, d in zip(trainers, dbs):
+                t.step(d)
+        for _ in range(max(2, args.warmup // 2)):
+            seq_step()
+        seq_steps = max(3, args.steps // 2)
+        ms_seq = timed_loop(seq_step, seq_steps) / seq_steps
+        extra.update(sequential_ms_per_step=round(ms_seq, 4), sequential_rays_per_s=round(n_rays / (ms_seq / 1e3), 1),
+                     speedup_vs_sequential=round(ms_seq / ms_per_step, 3))
+        log(f"bench: sequential single-object steps {ms_seq:.3f} ms/step -> batched speed-up "
+            f"{ms_seq / ms_per_step:.2f}x")
+    arch_mix = {}
+    for o in objs:
+        k = f"L{o.arch.n_levels} T2^{o.arch.log2_table} W{o.arch.width} D{o.arch.hidden}"
+        arch_mix[k] = arch_mix.get(k, 0) + 1
+    config = dict(workload=f"{n_objects} objects trained together, graph-captured step", n_objects=n_objects,
+                  n_rays=n_rays, samples_per_ray=S, mlp_dtype=mlp_dtype, table_dtype=table_dtype,
+                  loss_scale_init=4096.0 if lowp else None, tiles=tiles, architectures=arch_mix,
+                  samples_per_s=round(value * S, 1))
+    return value, ms_per_step, mlp_dtype if lowp else "fp32", config, roofline, kern, None, extra
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--rays", type=int, default=65536)
+    ap.add_argument("--workload", choices=("prior", "batch24", "batch48"), default="prior")
+    ap.add_argument("--mlp-dtype", choices=("bf16", "fp16"), default="bf16", help="batch48 only")
+    ap.add_argument("--rays", type=int, default=65536, help="prior workload only")
     ap.add_argument("--cpu-rays", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-sequential", action="store_true", help="batch workloads: skip the sequential comparison")
+    ap.add_argument("--no-tune", action="store_true", help="batch workloads: library default tiles if none cached")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy 1 GiB device-to-device once (a kernel of known "
                          "traffic for scaling hardware byte counters)")
@@ -91,99 +308,20 @@ def main():
         print(f"bench.py measures one GPU only (asked for {args.gpus}); nothing here uses a "
               "second GPU", file=sys.stderr)
         sys.exit(2)
-
     import torch
-    from paper_2503_01582_amd import api
-    from paper_2503_01582_amd.trainer import Trainer, to_device
-    from synth.params import init_params
-    from synth.workloads import prior_batch, prior_world
-
-    def log(*a):
-        print(*a, file=sys.stderr, flush=True)
-
-    log("bench: building the synthetic scene and batch")
-    world = prior_world(seed=1)
-    batch = prior_batch(world, args.rays, step=0)
-    arch = batch.arch
-    params = init_params(arch, 0)
     torch.cuda.set_device(0)
-    tr = Trainer(arch, params, batch.sample, batch.loss)
-    db = to_device(batch)
-    S = batch.sample.n_samples
-
-    log(f"bench: {args.warmup} warm-up steps")
-    for _ in range(args.warmup):
-        tr.step(db)
-    torch.cuda.synchronize()
-
-    log(f"bench: {args.steps} timed steps")
-    stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    api.prenom_profile_begin()
-    ev0.record(stream)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        out = tr.step(db)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kt = api.prenom_profile_end()
-    if args.copy_calibration:
-        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        log("bench: copied 1 GiB device-to-device for counter calibration")
-    ms = ev0.elapsed_time(ev1)
-    ms_per_step = ms / args.steps
-    value = args.rays * args.steps / (ms / 1e3)
-    loss = float(out["loss"].item())
-    log(f"bench: {ms_per_step:.3f} ms/step ({wall / args.steps * 1e3:.3f} ms wall), loss {loss:.4e}")
-
-    work = algorithmic_work(arch, args.rays, S, batch.sample.n_fine)
-    kern = {}
-    for name, (n, tot) in sorted(kt.items(), key=lambda kv: -kv[1][1]):
-        avg = tot / n
-        entry = dict(avg_ms=avg, share=tot / ms)
-        if name in work:
-            bound, amount = work[name]
-            if bound == "hbm":
-                entry.update(bound="hbm", achieved=amount / (avg * 1e-3) / 1e9, unit="GB/s",
-                             peak=HBM_PEAK_GBS)
-            else:
-                entry.update(bound="mfma", achieved=amount / (avg * 1e-3) / 1e12, unit="TFLOP/s",
-                             peak=FP32_MFMA_PEAK_TFLOPS)
-            entry["frac"] = entry["achieved"] / entry["peak"]
-        kern[name] = entry
-        log(f"  {name:18s} {avg * 1e3:9.1f} us/launch  {100 * tot / ms:5.1f}%  "
-            + (f"{entry['achieved']:8.1f} {entry['unit']} ({100 * entry['frac']:.1f}% of peak)"
-               if "frac" in entry else ""))
-    dom = max((k for k in kern if "frac" in kern[k]), key=lambda k: kern[k]["avg_ms"])
-    d = kern[dom]
-    roofline = dict(kernel=dom, bound=d["bound"], achieved=round(d["achieved"], 2), peak=d["peak"],
-                    unit=d["unit"], frac=round(d["frac"], 4), traffic=None)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        log(f"bench: CPU oracle on {args.cpu_rays} rays")
-        cpu = cpu_baseline(batch, params, args.cpu_rays)
-
-    line = dict(
-        metric="training rays/s (fwd+bwd) vs plain FP32 at equal PSNR; % HBM/MFMA roofline",
-        value=round(value, 1), unit="rays/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
-        ms_per_step=round(ms_per_step, 4), higher_is_better=True, scaling="weak", vs_baseline=None,
-        dtype="fp32", data="synthetic",
-        config=dict(workload="prior-sampled object NeRF training step", n_rays=args.rays,
-                    samples_per_ray=S, n_coarse=batch.sample.n_coarse, n_fine=batch.sample.n_fine,
-                    hash_levels=arch.n_levels, log2_table=arch.log2_table, mlp_width=arch.width,
-                    mlp_hidden=arch.hidden, samples_per_s=round(value * S, 1)),
-        roofline=roofline,
-        kernels={k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
-                 for k, v in kern.items()},
-        cpu_baseline=cpu,
-    )
+    if args.workload == "prior":
+        res = run_prior(args)
+    elif args.workload == "batch24":
+        res = run_batch(args, 24, None, "fp32", "fp32", seed=4)
+    else:
+        res = run_batch(args, 48, 1 << 20, args.mlp_dtype, "fp16", seed=5)
+    value, ms_per_step, dtype, config, roofline, kern, cpu, extra = res
+    line = dict(metric=METRIC, value=round(value, 1), unit="rays/s", n_gpus=1, steps=args.steps,
+                warmup=args.warmup, ms_per_step=round(ms_per_step, 4), higher_is_better=True, scaling="weak",
+                vs_baseline=None, dtype=dtype, data="synthetic", config=config, roofline=roofline,
+                kernels=kern, cpu_baseline=cpu)
+    line.update(extra)
     print(json.dumps(line), flush=True)
 
 

@@ -66,7 +66,7 @@ enum {
  * PRENOM_BF16 / PRENOM_F16 operands with FP32 accumulation; weights stay FP32
  * masters).  table_dtype: PRENOM_F32, or PRENOM_F16 when the forward gathers
  * read the FP16 copy model->table_lp (gradients accumulate in FP32 always).
- * Supported: n_features = 2; n_levels in {8, 16}; mlp_width = 64;
+ * Supported: n_features = 2; n_levels in {8, 12, 16}; mlp_width in {32, 64};
  * mlp_hidden in {1, 2}; log2_table in [10, 24]; 2 <= N_l < 2^20. */
 typedef struct prenom_arch {
     int32_t n_levels;
@@ -246,6 +246,119 @@ prenom_status prenom_refresh_lowp(const prenom_model* model, void* stream);
  * ---------------------------------------------------------------------- */
 prenom_status prenom_encode(const prenom_arch* arch, const float* table, const float* pos, int64_t n,
                             float* features, int32_t* corner_idx, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Batched training of many objects (Fig. 1 and Sec. IV-A: every object NeRF
+ * of the map trains concurrently, each with its own category architecture
+ * alpha, prior and pose).  Where the method gives each object its own host
+ * thread, a batch runs the step of all its objects with one launch per
+ * phase (the MLP: one launch per distinct MLP shape), so objects with few
+ * rays share the GPU with large ones.  The arithmetic of every object is that
+ * of the single-object calls above, with the loss of each object averaged
+ * over its own rays; the optimisation of each object is independent.
+ *
+ * Rays of the batch are the objects' rays in object order: object i owns
+ * rays [sum_{j<i} n_rays_j, sum_{j<=i} n_rays_j) of every per-ray array.
+ * Parameters of the batch are one device array per kind (params, grads,
+ * adam_m, adam_v) of prenom_batch_param_count floats; object i's parameters
+ * (layout as in prenom_model) start at prenom_batch_param_offset(i), a
+ * multiple of 64 floats.
+ * ---------------------------------------------------------------------- */
+
+/* Per-object part of a batch. */
+typedef struct prenom_object {
+    prenom_arch arch;
+    int64_t n_rays;          /* rays of this object in the batch (>= 0)              */
+    const float* prior;      /* device [R^3] prior grid of prenom_sample, or NULL:   */
+    int32_t prior_res;       /*   uniform sampling for this object                   */
+    float world_to_obj[12];  /* row-major 3x4 world -> NOCS affine, as in prenom_sample */
+} prenom_object;
+
+/* Tile shape of the batched MLP launches for one MLP shape (chosen by an
+ * autotuner; shapes without an entry use defaults).  fwd_tiles: 16-sample
+ * tiles per forward block, a multiple of 4 in [4, 4096]; bwd_tiles: per
+ * backward block (each writes one partial weight gradient), a multiple of 8
+ * in [8, 65536]. */
+typedef struct prenom_mlp_tiles {
+    int32_t in_dim, width, hidden, dtype;
+    int32_t fwd_tiles, bwd_tiles;
+} prenom_mlp_tiles;
+
+/* A batch: host arrays `objects` and `tiles` are read during each call.
+ * params_lp: device FP16 copy of the whole parameter array, required when an
+ *   object has table_dtype PRENOM_F16 (prenom_batch_adam_step keeps it in step).
+ * loss_scale / scaler_state: as in prenom_model, shared by the batch (a
+ *   non-finite gradient anywhere skips the update of every object).
+ * step: device int64 Adam step counter or NULL.  With it the bias corrections
+ *   use *step + 1 and the counter advances on the device after each applied
+ *   update, so a captured step graph can be replayed without host arguments
+ *   (the caller zeroes it once). */
+typedef struct prenom_batch {
+    int32_t n_objects;
+    const prenom_object* objects;
+    int32_t n_tiles;
+    const prenom_mlp_tiles* tiles;
+    float* params;
+    float* grads;
+    float* adam_m;
+    float* adam_v;
+    void* params_lp;
+    float* loss_scale;
+    int32_t* scaler_state;
+    int64_t* step;
+} prenom_batch;
+
+#define PRENOM_MAX_OBJECTS 4096
+
+/* Floats of each parameter array of the batch, and object i's first one
+ * (-1 on invalid input). */
+int64_t prenom_batch_param_count(const prenom_object* objects, int32_t n_objects);
+int64_t prenom_batch_param_offset(const prenom_object* objects, int32_t n_objects, int32_t i);
+
+/* Workspace bytes of the batched calls for n_samples samples per ray (0 on
+ * invalid input).  The workspace holds the batch's device descriptors and
+ * every intermediate of the step. */
+size_t prenom_batch_workspace_size(const prenom_batch* batch, int32_t n_samples);
+
+/* Writes the batch's device descriptors into the workspace (copies from host
+ * memory, then waits for `stream`).  Every other batched call checks that the
+ * workspace was prepared for the same objects, tile shapes and n_samples and
+ * fails with PRENOM_ERR_WORKSPACE otherwise.  Call it again whenever the
+ * objects change (new ray counts, priors or poses). */
+prenom_status prenom_batch_prepare(const prenom_batch* batch, int32_t n_samples, void* workspace, size_t ws_bytes,
+                                   void* stream);
+
+/* prenom_sample for every object at once: cfg's sampling counts, eps and
+ * near/far apply to all objects; its prior, prior_res and world_to_obj are
+ * ignored (each object supplies its own; uniform_only forces uniform draws
+ * for all).  Arrays as in prenom_sample over all rays of the batch. */
+prenom_status prenom_batch_sample(const prenom_batch* batch, const prenom_sample_cfg* cfg, const float* rays_o,
+                                  const float* rays_d, const float* xi, float* ray_obj, float* t, float* dt,
+                                  int32_t* bins, uint8_t* flags, void* workspace, size_t ws_bytes, void* stream);
+
+/* prenom_render_fwd for every object at once.  loss: device float[n_objects]
+ * (object i's loss of Eq. (8)/(9), averaged over its rays) or NULL. */
+prenom_status prenom_batch_render_fwd(const prenom_batch* batch, const prenom_render_cfg* cfg, const float* ray_obj,
+                                      const float* t, const float* dt, const uint8_t* flags, const float* bg,
+                                      const float* tgt_rgb, const float* tgt_depth, const uint8_t* mask, float* rgb,
+                                      float* depth, float* opacity, float* loss, void* workspace, size_t ws_bytes,
+                                      void* stream);
+
+/* prenom_render_bwd for every object at once: accumulates every object's
+ * gradient of its own loss (or of the upstream d_rgb / d_depth / d_opacity)
+ * into batch->grads. */
+prenom_status prenom_batch_render_bwd(const prenom_batch* batch, const prenom_render_cfg* cfg, const float* ray_obj,
+                                      const float* t, const float* dt, const uint8_t* flags, const float* bg,
+                                      const float* tgt_rgb, const float* tgt_depth, const uint8_t* mask,
+                                      const float* d_rgb, const float* d_depth, const float* d_opacity,
+                                      void* workspace, size_t ws_bytes, void* stream);
+
+/* prenom_adam_step over the whole parameter array of the batch (one launch).
+ * With batch->step set, cfg->step is ignored. */
+prenom_status prenom_batch_adam_step(const prenom_batch* batch, const prenom_adam_cfg* cfg, void* stream);
+
+/* Rewrites batch->params_lp (FP16, every parameter) from batch->params. */
+prenom_status prenom_batch_refresh_lowp(const prenom_batch* batch, void* stream);
 
 /* ------------------------------------------------------------------------
  * Kernel timing (instrumentation, not part of the method).  Between

@@ -48,6 +48,23 @@ class PrenomAdamCfg(C.Structure):
                 ("step", C.c_int64), ("growth_interval", C.c_int32)]
 
 
+class PrenomObject(C.Structure):
+    _fields_ = [("arch", PrenomArch), ("n_rays", C.c_int64), ("prior", C.c_void_p),
+                ("prior_res", C.c_int32), ("world_to_obj", C.c_float * 12)]
+
+
+class PrenomMlpTiles(C.Structure):
+    _fields_ = [("in_dim", C.c_int32), ("width", C.c_int32), ("hidden", C.c_int32), ("dtype", C.c_int32),
+                ("fwd_tiles", C.c_int32), ("bwd_tiles", C.c_int32)]
+
+
+class PrenomBatch(C.Structure):
+    _fields_ = [("n_objects", C.c_int32), ("objects", C.POINTER(PrenomObject)), ("n_tiles", C.c_int32),
+                ("tiles", C.POINTER(PrenomMlpTiles)), ("params", C.c_void_p), ("grads", C.c_void_p),
+                ("adam_m", C.c_void_p), ("adam_v", C.c_void_p), ("params_lp", C.c_void_p),
+                ("loss_scale", C.c_void_p), ("scaler_state", C.c_void_p), ("step", C.c_void_p)]
+
+
 class PrenomKernelTime(C.Structure):
     _fields_ = [("name", C.c_char * 48), ("launches", C.c_int64), ("total_ms", C.c_double)]
 
@@ -90,6 +107,28 @@ def lib():
         L.prenom_refresh_lowp.argtypes = [C.POINTER(PrenomModel), _vp]
         L.prenom_encode.restype = C.c_int
         L.prenom_encode.argtypes = [C.POINTER(PrenomArch), _vp, _vp, C.c_int64, _vp, _vp, _vp]
+        PB = C.POINTER(PrenomBatch)
+        L.prenom_batch_param_count.restype = C.c_int64
+        L.prenom_batch_param_count.argtypes = [C.POINTER(PrenomObject), C.c_int32]
+        L.prenom_batch_param_offset.restype = C.c_int64
+        L.prenom_batch_param_offset.argtypes = [C.POINTER(PrenomObject), C.c_int32, C.c_int32]
+        L.prenom_batch_workspace_size.restype = C.c_size_t
+        L.prenom_batch_workspace_size.argtypes = [PB, C.c_int32]
+        L.prenom_batch_prepare.restype = C.c_int
+        L.prenom_batch_prepare.argtypes = [PB, C.c_int32, _vp, C.c_size_t, _vp]
+        L.prenom_batch_sample.restype = C.c_int
+        L.prenom_batch_sample.argtypes = [PB, C.POINTER(PrenomSampleCfg), _vp, _vp, _vp, _vp, _vp, _vp,
+                                          _vp, _vp, _vp, C.c_size_t, _vp]
+        L.prenom_batch_render_fwd.restype = C.c_int
+        L.prenom_batch_render_fwd.argtypes = [PB, C.POINTER(PrenomRenderCfg), _vp, _vp, _vp, _vp, _vp, _vp,
+                                              _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp]
+        L.prenom_batch_render_bwd.restype = C.c_int
+        L.prenom_batch_render_bwd.argtypes = [PB, C.POINTER(PrenomRenderCfg), _vp, _vp, _vp, _vp, _vp, _vp,
+                                              _vp, _vp, _vp, _vp, _vp, _vp, C.c_size_t, _vp]
+        L.prenom_batch_adam_step.restype = C.c_int
+        L.prenom_batch_adam_step.argtypes = [PB, C.POINTER(PrenomAdamCfg), _vp]
+        L.prenom_batch_refresh_lowp.restype = C.c_int
+        L.prenom_batch_refresh_lowp.argtypes = [PB, _vp]
         L.prenom_profile_begin.restype = C.c_int
         L.prenom_profile_begin.argtypes = []
         L.prenom_profile_end.restype = C.c_int

@@ -47,6 +47,17 @@ __global__ __launch_bounds__(kAdamBlock) void k_adam(AdamArgs a)
     const int64_t n4 = a.n >> 2;
     const int64_t stride = (int64_t)gridDim.x * kAdamBlock;
     const bool skip = a.loss_scale && a.scaler_state[0] != 0;
+    if (a.step_dev) {  // bias corrections of step *step_dev + 1, once per block
+        __shared__ float s_c[2];
+        if (threadIdx.x == 0) {
+            const double k = (double)(*a.step_dev + 1);
+            s_c[0] = (float)(1.0 / (1.0 - pow((double)a.beta1, k)));
+            s_c[1] = (float)(1.0 / (1.0 - pow((double)a.beta2, k)));
+        }
+        __syncthreads();
+        a.inv_c1 = s_c[0];
+        a.inv_c2 = s_c[1];
+    }
     const float inv_scale = a.loss_scale ? 1.0f / *a.loss_scale : 1.0f;
     for (int64_t i = (int64_t)blockIdx.x * kAdamBlock + threadIdx.x; i < n4; i += stride) {
         float4* g4 = reinterpret_cast<float4*>(a.g) + i;
@@ -74,16 +85,23 @@ __global__ __launch_bounds__(kAdamBlock) void k_adam(AdamArgs a)
     // tail (n not a multiple of 4; never inside the tables): the first threads of block 0
     if (blockIdx.x == 0 && threadIdx.x < (a.n & 3)) {
         const int64_t i = (n4 << 2) + threadIdx.x;
-        if (skip)
+        if (skip) {
             a.g[i] = 0.0f;
-        else
+        } else {
             adam_one(a.p[i], a.g[i], a.m[i], a.v[i], a, inv_scale);
+            if (a.table_f16 && i < a.n_table) reinterpret_cast<_Float16*>(a.table_f16)[i] = (_Float16)a.p[i];
+        }
     }
 }
 
-__global__ void k_scale_update(float* scale, int32_t* state, int32_t growth_interval)
+// After the update: advance the device step counter unless the step was
+// skipped, then adjust the loss scale.
+__global__ void k_finish_step(float* scale, int32_t* state, int32_t growth_interval, int64_t* step)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const bool skipped = scale && state[0] != 0;
+    if (step && !skipped) *step += 1;
+    if (!scale) return;
     int32_t good = state[1];
     if (state[0]) {
         *scale *= 0.5f;
@@ -125,8 +143,9 @@ hipError_t launch_adam(const AdamArgs& a, hipStream_t s)
     }
     hipLaunchKernelGGL(k_adam, grid, dim3(kAdamBlock), 0, s, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (a.loss_scale) {
-        hipLaunchKernelGGL(k_scale_update, dim3(1), dim3(64), 0, s, a.loss_scale, a.scaler_state, a.growth_interval);
+    if (a.loss_scale || a.step_dev) {
+        hipLaunchKernelGGL(k_finish_step, dim3(1), dim3(64), 0, s, a.loss_scale, a.scaler_state, a.growth_interval,
+                           a.step_dev);
         e = hipGetLastError();
     }
     return e;

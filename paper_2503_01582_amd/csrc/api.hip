@@ -7,36 +7,15 @@
 #include <mutex>
 #include <vector>
 
+#include "api_util.h"
 #include "common.h"
 
+namespace prenom {
+namespace host {
+
 namespace {
-
-using namespace prenom;
-
 thread_local char g_last_error[512] = "";
 
-prenom_status fail(prenom_status st, const char* fmt, ...)
-{
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
-    va_end(ap);
-    return st;
-}
-
-prenom_status hip_status(hipError_t e, const char* what)
-{
-    if (e == hipSuccess) return PRENOM_OK;
-    return fail(PRENOM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
-}
-
-#define PRENOM_TRY_HIP(expr, what)                          \
-    do {                                                    \
-        const prenom_status st_ = hip_status((expr), what); \
-        if (st_ != PRENOM_OK) return st_;                   \
-    } while (0)
-
-// ---------------------------------------------------------------- kernel timing
 struct ProfRecord {
     const char* name;
     hipEvent_t a, b;
@@ -56,32 +35,39 @@ hipEvent_t pool_event()
     }
     return g_event_pool[g_pool_used++];
 }
+}  // namespace
 
-// Runs one launcher; brackets it with events when timing is on.
-template <class F>
-hipError_t timed(const char* name, hipStream_t s, F&& launch)
+prenom_status fail(prenom_status st, const char* fmt, ...)
 {
-    hipEvent_t a = nullptr, b = nullptr;
-    {
-        std::lock_guard<std::mutex> lk(g_prof_mu);
-        if (g_prof_on) {
-            a = pool_event();
-            b = pool_event();
-        }
-    }
-    if (a && b) hipEventRecord(a, s);
-    const hipError_t e = launch();
-    if (a && b) {
-        hipEventRecord(b, s);
-        std::lock_guard<std::mutex> lk(g_prof_mu);
-        g_prof_records.push_back({name, a, b});
-    }
-    return e;
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+    return st;
 }
 
-#define PRENOM_LAUNCH(name, stream, expr) PRENOM_TRY_HIP(timed(name, stream, [&] { return (expr); }), name)
+prenom_status hip_status(hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return PRENOM_OK;
+    return fail(PRENOM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
 
-bool aligned(const void* p, size_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
+const char* last_error() { return g_last_error; }
+
+bool prof_events(hipEvent_t* a, hipEvent_t* b)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on) return false;
+    *a = pool_event();
+    *b = pool_event();
+    return *a && *b;
+}
+
+void prof_record(const char* name, hipEvent_t a, hipEvent_t b)
+{
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_records.push_back({name, a, b});
+}
 
 // Compute units of the current device (persistent grids size to it).
 int device_cus()
@@ -165,14 +151,49 @@ GridInfo grid_info(const prenom_arch* a)
     return g;
 }
 
-constexpr size_t kAlign = 256;
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+prenom_status check_sample_cfg(const prenom_sample_cfg* cfg, bool need_prior_fields)
+{
+    if (!cfg) return fail(PRENOM_ERR_INVALID_ARG, "cfg is NULL");
+    if (cfg->n_fine < 1 || cfg->n_fine > 256) return fail(PRENOM_ERR_SHAPE, "n_fine %d outside [1, 256]", cfg->n_fine);
+    if (cfg->n_coarse < 0 || cfg->n_coarse > 256) return fail(PRENOM_ERR_SHAPE, "n_coarse %d outside [0, 256]", cfg->n_coarse);
+    const bool use_prior = need_prior_fields ? (!cfg->uniform_only && cfg->prior != nullptr) : !cfg->uniform_only;
+    if ((use_prior || cfg->include_coarse) && cfg->n_coarse < 1)
+        return fail(PRENOM_ERR_SHAPE, "n_coarse must be >= 1 with a prior or include_coarse");
+    if (need_prior_fields && use_prior && cfg->prior_res < 2) return fail(PRENOM_ERR_SHAPE, "prior_res %d < 2", cfg->prior_res);
+    if (!(cfg->eps >= 0.0f)) return fail(PRENOM_ERR_INVALID_ARG, "eps must be >= 0");
+    if (!(cfg->near_t <= cfg->far_t)) return fail(PRENOM_ERR_INVALID_ARG, "near_t > far_t");
+    if (need_prior_fields)
+        for (int i = 0; i < 12; ++i)
+            if (!std::isfinite(cfg->world_to_obj[i])) return fail(PRENOM_ERR_INVALID_ARG, "world_to_obj not finite");
+    return PRENOM_OK;
+}
+
+prenom_status check_render_cfg(const prenom_render_cfg* cfg)
+{
+    if (!cfg) return fail(PRENOM_ERR_INVALID_ARG, "cfg is NULL");
+    if (cfg->n_samples < 1 || cfg->n_samples > 256)
+        return fail(PRENOM_ERR_SHAPE, "n_samples %d outside [1, 256]", cfg->n_samples);
+    if (cfg->loss_mode != 0 && cfg->loss_mode != 1) return fail(PRENOM_ERR_INVALID_ARG, "loss_mode %d", cfg->loss_mode);
+    if (cfg->recompute != 0 && cfg->recompute != 1) return fail(PRENOM_ERR_INVALID_ARG, "recompute %d", cfg->recompute);
+    if (!(cfg->lambda_d >= 0.0f) || !(cfg->lambda_sigma >= 0.0f))
+        return fail(PRENOM_ERR_INVALID_ARG, "negative or NaN loss weight");
+    return PRENOM_OK;
+}
+
+}  // namespace host
+}  // namespace prenom
+
+namespace {
+
+using namespace prenom;
+using namespace prenom::host;
+
 
 struct WsLayout {
     size_t y, sc, dout, dy, ray_state, loss_partial, mlp_partial;
-    size_t counts, block_max, tile_exp, tile_total, tile_start, chunk_start, work_counter, keys, vals, total;
+    size_t counts, block_max, level_max, tile_exp, tile_total, tile_start, chunk_start, work_counter, keys, vals, total;
     int n_loss_blocks, n_mlp_slots;
-    ScatterPlan plan;
+    ScatterObj plan;
 };
 
 WsLayout ws_layout(const prenom_arch* a, int64_t n_rays, int32_t S)
@@ -196,12 +217,14 @@ WsLayout ws_layout(const prenom_arch* a, int64_t n_rays, int32_t S)
     w.n_mlp_slots = mlp_bwd_waves((int64_t)n_s);
     w.mlp_partial = off;
     off = align_up(off + (size_t)w.n_mlp_slots * (size_t)mlp_params(a) * sizeof(float));
-    w.plan = scatter_plan(grid_info(a), (int64_t)n_s);
+    w.plan = scatter_obj(grid_info(a), (int64_t)n_s);
     const size_t nt = (size_t)w.plan.n_tiles;
     w.counts = off;
     off = align_up(off + nt * (size_t)w.plan.n_blocks * sizeof(uint32_t));
     w.block_max = off;
     off = align_up(off + (size_t)a->n_levels * (size_t)w.plan.n_blocks * sizeof(float));
+    w.level_max = off;
+    off = align_up(off + (size_t)a->n_levels * sizeof(float));
     w.tile_exp = off;
     off = align_up(off + nt * sizeof(int32_t));
     w.tile_total = off;
@@ -213,17 +236,11 @@ WsLayout ws_layout(const prenom_arch* a, int64_t n_rays, int32_t S)
     w.work_counter = off;
     off = align_up(off + sizeof(uint64_t));
     w.keys = off;
-    off = align_up(off + (size_t)w.plan.max_records * sizeof(uint16_t));
+    off = align_up(off + (size_t)scatter_records(w.plan) * sizeof(uint16_t));
     w.vals = off;
-    off = align_up(off + (size_t)w.plan.max_records * 2 * sizeof(float));
+    off = align_up(off + (size_t)scatter_records(w.plan) * 2 * sizeof(float));
     w.total = off;
     return w;
-}
-
-template <typename T>
-T* at(void* base, size_t off)
-{
-    return reinterpret_cast<T*>(static_cast<char*>(base) + off);
 }
 
 prenom_status check_model(const prenom_model* m, bool need_grads)
@@ -246,13 +263,8 @@ prenom_status check_render(const prenom_model* model, const prenom_render_cfg* c
 {
     prenom_status st = check_model(model, need_grads);
     if (st != PRENOM_OK) return st;
-    if (!cfg) return fail(PRENOM_ERR_INVALID_ARG, "cfg is NULL");
-    if (cfg->n_samples < 1 || cfg->n_samples > 256)
-        return fail(PRENOM_ERR_SHAPE, "n_samples %d outside [1, 256]", cfg->n_samples);
-    if (cfg->loss_mode != 0 && cfg->loss_mode != 1) return fail(PRENOM_ERR_INVALID_ARG, "loss_mode %d", cfg->loss_mode);
-    if (cfg->recompute != 0 && cfg->recompute != 1) return fail(PRENOM_ERR_INVALID_ARG, "recompute %d", cfg->recompute);
-    if (!(cfg->lambda_d >= 0.0f) || !(cfg->lambda_sigma >= 0.0f))
-        return fail(PRENOM_ERR_INVALID_ARG, "negative or NaN loss weight");
+    st = check_render_cfg(cfg);
+    if (st != PRENOM_OK) return st;
     if (n_rays < 0) return fail(PRENOM_ERR_SHAPE, "n_rays < 0");
     if ((double)n_rays * cfg->n_samples > 536870912.0) return fail(PRENOM_ERR_SHAPE, "n_rays * n_samples > 2^29");
     if (n_rays > 0 && (!ray_obj || !t || !dt || !flags))
@@ -290,18 +302,10 @@ prenom_status prenom_sample(const prenom_sample_cfg* cfg, const float* rays_o, c
                             int64_t n_rays, float* ray_obj, float* t, float* dt, int32_t* bins, uint8_t* flags,
                             void* stream)
 {
-    if (!cfg) return fail(PRENOM_ERR_INVALID_ARG, "cfg is NULL");
+    prenom_status st = check_sample_cfg(cfg, true);
+    if (st != PRENOM_OK) return st;
     if (n_rays < 0) return fail(PRENOM_ERR_SHAPE, "n_rays < 0");
-    if (cfg->n_fine < 1 || cfg->n_fine > 256) return fail(PRENOM_ERR_SHAPE, "n_fine %d outside [1, 256]", cfg->n_fine);
     const bool use_prior = !cfg->uniform_only && cfg->prior != nullptr;
-    if (cfg->n_coarse < 0 || cfg->n_coarse > 256) return fail(PRENOM_ERR_SHAPE, "n_coarse %d outside [0, 256]", cfg->n_coarse);
-    if ((use_prior || cfg->include_coarse) && cfg->n_coarse < 1)
-        return fail(PRENOM_ERR_SHAPE, "n_coarse must be >= 1 with a prior or include_coarse");
-    if (use_prior && cfg->prior_res < 2) return fail(PRENOM_ERR_SHAPE, "prior_res %d < 2", cfg->prior_res);
-    if (!(cfg->eps >= 0.0f)) return fail(PRENOM_ERR_INVALID_ARG, "eps must be >= 0");
-    if (!(cfg->near_t <= cfg->far_t)) return fail(PRENOM_ERR_INVALID_ARG, "near_t > far_t");
-    for (int i = 0; i < 12; ++i)
-        if (!std::isfinite(cfg->world_to_obj[i])) return fail(PRENOM_ERR_INVALID_ARG, "world_to_obj not finite");
     if (n_rays > 0 && (!rays_o || !rays_d || !xi || !ray_obj || !t || !dt || !bins || !flags))
         return fail(PRENOM_ERR_INVALID_ARG, "NULL array argument");
     SampleArgs a{};
@@ -441,25 +445,22 @@ prenom_status prenom_render_bwd(const prenom_model* model, const prenom_render_c
         PRENOM_LAUNCH("k_reduce_partials", s,
                       launch_reduce_partials(partial, w.n_mlp_slots, mlp_params(a), model->grads + table_params(a), s));
     ScatterArgs sa{};
-    sa.grid = grid_info(a);
-    sa.n_s = n_s;
     sa.S = cfg->n_samples;
-    sa.n_blocks = w.plan.n_blocks;
-    sa.n_tiles = w.plan.n_tiles;
+    sa.n_obj = 1;
+    sa.one = w.plan;
+    sa.objs = nullptr;
+    sa.tiles_max = scatter_tiles_max(w.plan);
     sa.reduce_blocks = device_cus();
-    sa.tiles_max = 1;
-    for (int l = 0; l < PRENOM_MAX_LEVELS; ++l) {
-        sa.tiles_max = l < a->n_levels && w.plan.tiles[l] > sa.tiles_max ? w.plan.tiles[l] : sa.tiles_max;
-        sa.tiles[l] = w.plan.tiles[l];
-        sa.tile_base[l] = w.plan.tile_base[l];
-        sa.level_rows[l] = w.plan.level_rows[l];
-    }
+    sa.n_tiles = w.plan.n_tiles;
+    sa.n_items = scatter_items(w.plan);
+    sa.n_levels_total = a->n_levels;
     sa.ray_obj = ray_obj;
     sa.t = t;
     sa.dy = reinterpret_cast<const float2*>(dy);
     sa.g_table = model->grads;
     sa.counts = at<uint32_t>(workspace, w.counts);
     sa.block_max = at<float>(workspace, w.block_max);
+    sa.level_max = at<float>(workspace, w.level_max);
     sa.tile_exp = at<int32_t>(workspace, w.tile_exp);
     sa.tile_total = at<uint64_t>(workspace, w.tile_total);
     sa.tile_start = at<uint64_t>(workspace, w.tile_start);

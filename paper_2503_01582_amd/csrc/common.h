@@ -75,6 +75,37 @@ __device__ __forceinline__ void level_corners(const GridInfo& g, int l, float x0
     }
 }
 
+// ------------------------------------------------------------------ batches
+// Device descriptor of one object of a batch (offsets index the batch's
+// concatenated arrays; objects own consecutive rays).
+struct ObjDev {
+    GridInfo grid;
+    int32_t table_dtype;  // PRENOM_F32 or PRENOM_F16 (read the FP16 parameter copy)
+    int32_t prior_res;
+    int32_t enc_blocks;   // encode blocks per level
+    int32_t pad_;
+    int64_t param_off;    // floats: first parameter (the tables) of the object
+    int64_t ray_begin, n_rays;
+    int64_t y_off;        // floats: the object's features [L][n_s][2] (and their gradient)
+    int64_t eblock_off;   // first block of the object in the batched encode grid
+    const float* prior;   // [R^3] or null (uniform sampling)
+    double A[12];         // world -> object frame
+};
+
+// Object of a batch that holds ray `ray` (objects are contiguous in rays).
+__device__ __forceinline__ int find_object(const ObjDev* objs, int n_obj, int64_t ray)
+{
+    int lo = 0, hi = n_obj - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (objs[mid].ray_begin <= ray)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
 // ------------------------------------------------------------------ launches
 // Every launcher returns hipSuccess or the launch error.
 
@@ -95,10 +126,18 @@ struct SampleArgs {
     uint8_t* flags;
 };
 hipError_t launch_sample(const SampleArgs& a, hipStream_t s);
+hipError_t launch_sample_batch(const SampleArgs& a, const ObjDev* objs, int n_obj, hipStream_t s);
 
 // Encoding of explicit positions: features [L][n][2], optional corner rows.
 hipError_t launch_encode_points(const GridInfo& g, const float* table, const float* pos, int64_t n,
                                 float* features, int32_t* corner_idx, hipStream_t s);
+
+// Encoding of the rendered samples of every object of a batch: one block per
+// (object, level, sample block); FP16 tables come from params_f16.
+hipError_t launch_encode_batch(const ObjDev* objs, int n_obj, int64_t n_blocks, const float* params,
+                               const void* params_f16, const float* ray_obj, const float* t, int32_t S, float* y,
+                               hipStream_t s);
+int encode_block_samples();
 
 // Encoding of the rendered samples (positions from rays and t); reads the
 // FP16 table copy when table_f16 is not null, the FP32 tables otherwise.
@@ -107,39 +146,58 @@ hipError_t launch_encode_samples(const GridInfo& g, const float* table, const vo
                                  hipStream_t s);
 
 // Bucketed scatter-add of the feature gradients into the table gradient.
-struct ScatterPlan {
+// Geometry of one object's scatter: its table tiles and sample blocks, and
+// where its pieces sit in the (possibly batched) arrays.
+struct ScatterObj {
+    GridInfo grid;
     int32_t n_blocks;  // sample blocks per level
-    int32_t n_tiles;   // table tiles over all levels
+    int32_t n_tiles;   // table tiles over the object's levels
+    int32_t lev_off;   // first (object, level) entry of level_max
+    int32_t pad_;
     int32_t tiles[PRENOM_MAX_LEVELS];
     int32_t tile_base[PRENOM_MAX_LEVELS];
     int64_t level_rows[PRENOM_MAX_LEVELS];
-    int64_t max_records;  // n_s * L * 8
+    int64_t n_s;        // samples
+    int64_t s_begin;    // first sample in the per-sample arrays (t; ray = sample / S)
+    int64_t dy_off;     // float2 index of the object's dy [L][n_s]
+    int64_t g_off;      // float index of the object's table gradient
+    int64_t tile_off;   // first tile in the per-tile arrays
+    int64_t count_off;  // first entry of its counts [n_tiles][n_blocks]
+    int64_t bmax_off;   // first entry of its block_max [L][n_blocks]
+    int64_t item_off;   // first (level, sample block) item of the count and place grids
 };
-ScatterPlan scatter_plan(const GridInfo& g, int64_t n_s);
+// Fills the geometry of one object (offsets within the batch are left 0).
+ScatterObj scatter_obj(const GridInfo& g, int64_t n_s);
+int64_t scatter_items(const ScatterObj& o);      // L * n_blocks
+int64_t scatter_records(const ScatterObj& o);    // n_s * L * 8
 int scatter_max_tiles_per_level();
+int scatter_tiles_max(const ScatterObj& o);      // max tiles of one level
 
 struct ScatterArgs {
-    GridInfo grid;
-    int64_t n_s;
     int32_t S;
-    int32_t n_blocks, n_tiles, reduce_blocks;
-    int32_t tiles_max;  // max tiles of one level
-    int32_t tiles[PRENOM_MAX_LEVELS];
-    int32_t tile_base[PRENOM_MAX_LEVELS];
-    int64_t level_rows[PRENOM_MAX_LEVELS];
+    int32_t n_obj;              // 1: `one` holds the object; else `objs` (device) holds n_obj of them
+    int32_t tiles_max;          // max tiles of one level over all objects
+    int32_t reduce_blocks;
+    int64_t n_tiles;            // over all objects
+    int64_t n_items;            // (object, level, sample block) items of count and place
+    int32_t n_levels_total;     // (object, level) pairs
+    int32_t pad_;
+    ScatterObj one;
+    const ScatterObj* objs;
     const float* ray_obj;
     const float* t;
     const float2* dy;
     float* g_table;
-    uint32_t* counts;       // [n_tiles][n_blocks]
-    float* block_max;       // [L][n_blocks] max |dy| per sample block
+    uint32_t* counts;       // per object [n_tiles][n_blocks]
+    float* block_max;       // per object [L][n_blocks] max |dy| per sample block
+    float* level_max;       // [n_levels_total]
     int32_t* tile_exp;      // [n_tiles] fixed-point exponent
     uint64_t* tile_total;   // [n_tiles]
     uint64_t* tile_start;   // [n_tiles + 1]
     uint64_t* chunk_start;  // [n_tiles + 1]
     unsigned long long* work_counter;
-    uint16_t* keys;         // [max_records]
-    float2* vals;           // [max_records]
+    uint16_t* keys;         // [records]
+    float2* vals;           // [records]
 };
 hipError_t launch_scatter(const ScatterArgs& a, hipStream_t s);
 
@@ -149,6 +207,15 @@ struct MlpShape {
     int32_t in_dim, width, hidden, dtype;
 };
 bool mlp_supported(const MlpShape& m);
+
+// One block's share of a batched MLP launch: tiles [tile_begin, tile_end) of
+// one object.  w_off (floats) locates the object's MLP weights in the batch
+// parameters, y_off (floats) its features (level-major [L][n_s][2]), s_off
+// (samples) its first sample in the per-sample arrays.
+struct MlpWork {
+    int64_t w_off, y_off, s_off, n_s;
+    int64_t tile_begin, tile_end;
+};
 int mlp_bwd_waves(int64_t n_samples);  // partial-gradient slots (one per block) the bwd writes
 hipError_t launch_mlp_fwd(const MlpShape& m, const float* w, const float* y, int64_t n_s, float* sc,
                           hipStream_t s);
@@ -158,8 +225,29 @@ hipError_t launch_mlp_fwd_lp(const MlpShape& m, const float* w, const float* y, 
                              hipStream_t s);
 hipError_t launch_mlp_bwd_lp(const MlpShape& m, const float* w, const float* y, const float* dout, int64_t n_s,
                              float* dy, float* partial, hipStream_t s);
+hipError_t launch_mlp_fwd_batch(const MlpShape& m, const MlpWork* work, int n_blocks, const float* params,
+                                const float* y, float* sc, hipStream_t s);
+hipError_t launch_mlp_bwd_batch(const MlpShape& m, const MlpWork* work, int n_blocks, const float* params,
+                                const float* y, const float* dout, float* dy, float* partial, int64_t slot_stride,
+                                hipStream_t s);
+hipError_t launch_mlp_fwd_lp_batch(const MlpShape& m, const MlpWork* work, int n_blocks, const float* params,
+                                   const float* y, float* sc, hipStream_t s);
+hipError_t launch_mlp_bwd_lp_batch(const MlpShape& m, const MlpWork* work, int n_blocks, const float* params,
+                                   const float* y, const float* dout, float* dy, float* partial, int64_t slot_stride,
+                                   hipStream_t s);
 hipError_t launch_reduce_partials(const float* partial, int n_slots, int64_t n_mlp, float* g_mlp,
                                   hipStream_t s);
+
+// Per object of a batch: where its backward partials sit and where its MLP
+// gradient goes.  mlp_begin is the prefix of n_mlp over the objects.
+struct MlpRed {
+    int64_t mlp_begin, n_mlp;
+    int64_t partial_off;  // floats
+    int64_t n_slots;      // partials (each n_mlp floats, consecutive)
+    int64_t g_off;        // floats: the object's MLP gradient in the batch gradient
+};
+hipError_t launch_reduce_partials_batch(const MlpRed* reds, int n_obj, int64_t n_mlp_total, const float* partial,
+                                        float* grads, hipStream_t s);
 
 // Compositing and loss.
 struct CompositeArgs {
@@ -180,6 +268,9 @@ struct CompositeArgs {
     float* opacity;
     float* ray_state;     // [n][8]: rgb(3), depth, T_S, sigma sum, -, -
     double* loss_partial; // [blocks]
+    const ObjDev* objs;   // batch: per-object loss normalisation (n = the object's rays), or null
+    int32_t n_obj;
+    double* ray_loss;     // batch fwd: [n_rays] loss term of each ray
     const float* d_rgb;   // bwd only
     const float* d_depth;
     const float* d_opacity;
@@ -190,6 +281,8 @@ int composite_loss_blocks(int64_t n_rays);
 hipError_t launch_composite_fwd(const CompositeArgs& a, hipStream_t s);
 hipError_t launch_loss_finalize(const double* partial, int n_blocks, float* loss, hipStream_t s);
 hipError_t launch_composite_bwd(const CompositeArgs& a, hipStream_t s);
+// loss[o] = sum of ray_loss over the rays of object o (FP64), one block per object.
+hipError_t launch_loss_objects(const ObjDev* objs, int n_obj, const double* ray_loss, float* loss, hipStream_t s);
 
 struct AdamArgs {
     float* p;
@@ -203,6 +296,8 @@ struct AdamArgs {
     float* loss_scale;       // null: plain Adam
     int32_t* scaler_state;   // [2] non-finite flag, finite steps since the last scale change
     int32_t growth_interval;
+    int64_t* step_dev;       // non-null: bias corrections from this device step counter, which is
+                             // advanced after every applied (not skipped) step
 };
 hipError_t launch_adam(const AdamArgs& a, hipStream_t s);
 hipError_t launch_to_f16(const float* src, void* dst, int64_t n, hipStream_t s);

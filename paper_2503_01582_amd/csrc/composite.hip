@@ -55,6 +55,22 @@ __device__ __forceinline__ float wave_excl_suffix(float x, int lane)
     return lane == 63 ? 0.0f : e;
 }
 
+// Rays over which the loss of ray r is averaged: the whole call, or the
+// ray's object in a batch.
+__device__ __forceinline__ int64_t norm_rays(const CompositeArgs& a, int64_t r)
+{
+    if (!a.objs) return a.n_rays;
+    int lo = 0, hi = a.n_obj - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.objs[mid].ray_begin <= r)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return a.objs[lo].n_rays;
+}
+
 struct RayTargets {
     float C[3];
     float D;
@@ -125,7 +141,7 @@ __global__ __launch_bounds__(64 * kRaysPerBlock) void k_composite_fwd(CompositeA
         }
         if (a.tgt_rgb) {
             const RayTargets tg = load_targets(a, r);
-            const double n = (double)a.n_rays;
+            const double n = (double)norm_rays(a, r);
             const double e0 = (double)C[0] - tg.C[0], e1 = (double)C[1] - tg.C[1], e2 = (double)C[2] - tg.C[2];
             const double ed = (double)Dh - tg.D;
             if (a.loss_mode == 0) {
@@ -137,6 +153,7 @@ __global__ __launch_bounds__(64 * kRaysPerBlock) void k_composite_fwd(CompositeA
             }
         }
     }
+    if (a.ray_loss && lane == 0 && r < a.n_rays) a.ray_loss[r] = ray_loss;
     if (a.loss_partial) {
         if (lane == 0) block_loss[wave] = ray_loss;
         __syncthreads();
@@ -163,6 +180,19 @@ __global__ __launch_bounds__(1024) void k_loss_finalize(const double* __restrict
     }
 }
 
+__global__ __launch_bounds__(256) void k_loss_objects(const ObjDev* __restrict__ objs,
+                                                      const double* __restrict__ ray_loss, float* loss)
+{
+    __shared__ double red[4];
+    const ObjDev& o = objs[blockIdx.x];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < o.n_rays; i += 256) s += ray_loss[o.ray_begin + i];
+    s = wave_sum_d(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) loss[blockIdx.x] = (float)((red[0] + red[1]) + (red[2] + red[3]));
+}
+
 __global__ __launch_bounds__(64 * kRaysPerBlock) void k_composite_bwd(CompositeArgs a)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -186,7 +216,7 @@ __global__ __launch_bounds__(64 * kRaysPerBlock) void k_composite_bwd(CompositeA
         gA = a.d_opacity ? a.d_opacity[r] : 0.0f;
     } else {
         const RayTargets tg = load_targets(a, r);
-        const float n = (float)a.n_rays;
+        const float n = (float)norm_rays(a, r);
         const float e[3] = {Ch[0] - tg.C[0], Ch[1] - tg.C[1], Ch[2] - tg.C[2]};
         const float ed = Dh - tg.D;
         if (a.loss_mode == 0) {
@@ -266,6 +296,13 @@ hipError_t launch_composite_fwd(const CompositeArgs& a, hipStream_t s)
 hipError_t launch_loss_finalize(const double* partial, int n_blocks, float* loss, hipStream_t s)
 {
     hipLaunchKernelGGL(k_loss_finalize, dim3(1), dim3(1024), 0, s, partial, n_blocks, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_loss_objects(const ObjDev* objs, int n_obj, const double* ray_loss, float* loss, hipStream_t s)
+{
+    if (n_obj == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_loss_objects, dim3((uint32_t)n_obj), dim3(256), 0, s, objs, ray_loss, loss);
     return hipGetLastError();
 }
 

@@ -54,6 +54,45 @@ __global__ __launch_bounds__(kEncBlock) void k_encode_samples(GridInfo g, const 
     y[(int64_t)l * n_s + s] = gather_blend(lt, c);
 }
 
+// Batched: block b is (object o, level l, sample block bx), object-major,
+// then level, then block (each level's table stays hot while its blocks run).
+__global__ __launch_bounds__(kEncBlock) void k_encode_batch(const ObjDev* __restrict__ objs, int n_obj,
+                                                            const float* __restrict__ params,
+                                                            const half2_t* __restrict__ params_f16,
+                                                            const float* __restrict__ ray_obj,
+                                                            const float* __restrict__ t, int32_t S,
+                                                            float2* __restrict__ y)
+{
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = n_obj - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (objs[mid].eblock_off <= b)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const ObjDev& o = objs[lo];
+    const int64_t rem = b - o.eblock_off;
+    const int l = (int)(rem / o.enc_blocks);
+    const int64_t s = (rem % o.enc_blocks) * kEncBlock + threadIdx.x;
+    const int64_t n_s = o.n_rays * S;
+    if (s >= n_s) return;
+    const int64_t gs = o.ray_begin * S + s;
+    const float* ro = ray_obj + 6 * (gs / S);
+    const float ts = t[gs];
+    Corners c;
+    level_corners(o.grid, l, sample_coord(ts, ro[3], ro[0]), sample_coord(ts, ro[4], ro[1]),
+                  sample_coord(ts, ro[5], ro[2]), c);
+    const int64_t row0 = (int64_t)l << o.grid.log2_table;  // rows of float2 / half2
+    float2 v;
+    if (o.table_dtype == PRENOM_F16)
+        v = gather_blend(params_f16 + o.param_off / 2 + row0, c);
+    else
+        v = gather_blend(reinterpret_cast<const float2*>(params + o.param_off) + row0, c);
+    reinterpret_cast<float2*>(y)[o.y_off / 2 + (int64_t)l * n_s + s] = v;
+}
+
 __global__ __launch_bounds__(kEncBlock) void k_encode_points(GridInfo g, const float2* __restrict__ table,
                                                              const float* __restrict__ pos, int64_t n,
                                                              float2* __restrict__ y,
@@ -91,6 +130,18 @@ hipError_t launch_encode_samples(const GridInfo& g, const float* table, const vo
     else
         hipLaunchKernelGGL(k_encode_samples<float2>, enc_grid(n_s, g.n_levels), dim3(kEncBlock), 0, s, g,
                            (const float2*)table, ray_obj, t, n_s, S, (float2*)y);
+    return hipGetLastError();
+}
+
+int encode_block_samples() { return kEncBlock; }
+
+hipError_t launch_encode_batch(const ObjDev* objs, int n_obj, int64_t n_blocks, const float* params,
+                               const void* params_f16, const float* ray_obj, const float* t, int32_t S, float* y,
+                               hipStream_t s)
+{
+    if (n_blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_encode_batch, dim3((uint32_t)n_blocks), dim3(kEncBlock), 0, s, objs, n_obj, params,
+                       (const half2_t*)params_f16, ray_obj, t, S, (float2*)y);
     return hipGetLastError();
 }
 

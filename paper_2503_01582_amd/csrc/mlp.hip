@@ -131,19 +131,15 @@ __device__ __forceinline__ void mlp_chain(const float* __restrict__ frag, int la
     for (int ks = 0; ks < N::KTH; ++ks) o = mfma4(frag[(N::FO + ks) * 64 + lane], hs[D - 1][ks >> 2][ks & 3], o);
 }
 
+// Forward over the 16-sample tiles tile0, tile0 + step, ... < end of one
+// object whose fragments are in LDS.
 template <int IN, int W, int D>
-__global__ __launch_bounds__(256) void k_mlp_fwd(const float* __restrict__ w, const float* __restrict__ y,
-                                                 int64_t n_s, float4* __restrict__ sc)
+__device__ __forceinline__ void mlp_fwd_tiles(const float* __restrict__ frag, const float* __restrict__ y, int64_t n_s,
+                                              float4* __restrict__ sc, int64_t tile0, int64_t end, int64_t step)
 {
     using N = Net<IN, W, D>;
-    __shared__ float frag[N::N_FWD * 64];
-    load_fragments<IN, W, D>(w, frag, N::N_FWD);
-    __syncthreads();
     const int lane = threadIdx.x & 63, q = lane >> 4, j = lane & 15;
-    const int64_t n_tiles = (n_s + 15) / 16;
-    const int64_t wave0 = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-    const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x / 64);
-    for (int64_t tile = wave0; tile < n_tiles; tile += n_waves) {
+    for (int64_t tile = tile0; tile < end; tile += step) {
         const int64_t s = tile * 16 + j;
         const bool valid = s < n_s;
         float yb[N::KT1];
@@ -155,6 +151,34 @@ __global__ __launch_bounds__(256) void k_mlp_fwd(const float* __restrict__ w, co
     }
 }
 
+template <int IN, int W, int D>
+__global__ __launch_bounds__(256) void k_mlp_fwd(const float* __restrict__ w, const float* __restrict__ y,
+                                                 int64_t n_s, float4* __restrict__ sc)
+{
+    using N = Net<IN, W, D>;
+    __shared__ float frag[N::N_FWD * 64];
+    load_fragments<IN, W, D>(w, frag, N::N_FWD);
+    __syncthreads();
+    const int64_t wave0 = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x / 64);
+    mlp_fwd_tiles<IN, W, D>(frag, y, n_s, sc, wave0, (n_s + 15) / 16, n_waves);
+}
+
+// Batched forward: block b works on tiles [tile_begin, tile_end) of object
+// work[b].obj, whose weights start at w_off[obj] and whose features and head
+// outputs live at y_off / s_off.
+template <int IN, int W, int D>
+__global__ __launch_bounds__(256) void k_mlp_fwd_batch(const MlpWork* __restrict__ work, const float* __restrict__ params,
+                                                       const float* __restrict__ y, float4* __restrict__ sc)
+{
+    using N = Net<IN, W, D>;
+    __shared__ float frag[N::N_FWD * 64];
+    const MlpWork wk = work[blockIdx.x];
+    load_fragments<IN, W, D>(params + wk.w_off, frag, N::N_FWD);
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, n_waves = blockDim.x / 64;
+    mlp_fwd_tiles<IN, W, D>(frag, y + wk.y_off, wk.n_s, sc + wk.s_off, wk.tile_begin + wave, wk.tile_end, n_waves);
+}
 
 template <int IN, int W, int D>
 struct BwdLds {
@@ -182,18 +206,17 @@ __device__ __forceinline__ void accumulate_dw(const float* __restrict__ sD, cons
     }
 }
 
+// Backward over tiles tile0, tile0 + step, ... < end (per wave) of one object
+// whose fragments are in LDS (lds[0 .. N_ALL*64)); writes dy and the block's
+// merged dW to dst.  Called by every thread of the block.
 template <int IN, int W, int D>
-__global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_bwd(const float* __restrict__ w,
-                                                            const float* __restrict__ y,
-                                                            const float4* __restrict__ dout, int64_t n_s,
-                                                            float2* __restrict__ dy, float* __restrict__ partial)
+__device__ void mlp_bwd_tiles(float* __restrict__ lds, const float* __restrict__ y, const float4* __restrict__ dout,
+                              int64_t n_s, float2* __restrict__ dy, float* __restrict__ dst, int64_t tile0,
+                              int64_t end, int64_t step)
 {
     using N = Net<IN, W, D>;
     using B = BwdLds<IN, W, D>;
-    extern __shared__ float lds[];
-    float* frag = lds;
-    load_fragments<IN, W, D>(w, frag, N::N_ALL);
-    __syncthreads();
+    const float* frag = lds;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, j = lane & 15;
     float* sD = lds + N::N_ALL * 64 + wave * B::PER_WAVE;
     float* sH = sD + 16 * B::DW;
@@ -213,10 +236,7 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_bwd(const float* __restr
         dWo[0][a] = {0.0f, 0.0f, 0.0f, 0.0f};
     }
 
-    const int64_t n_tiles = (n_s + 15) / 16;
-    const int64_t wave0 = (int64_t)blockIdx.x * kBwdWaves + wave;
-    const int64_t n_waves = (int64_t)gridDim.x * kBwdWaves;
-    for (int64_t tile = wave0; tile < n_tiles; tile += n_waves) {
+    for (int64_t tile = tile0; tile < end; tile += step) {
         const int64_t s = tile * 16 + j;
         const bool valid = s < n_s;
         float yb[N::KT1];
@@ -320,8 +340,42 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_bwd(const float* __restr
         }
         __syncthreads();
     }
-    float* dst = partial + (int64_t)blockIdx.x * N::N_PARAMS;
     for (int p = threadIdx.x; p < N::N_PARAMS; p += blockDim.x) dst[p] = red[p];
+}
+
+template <int IN, int W, int D>
+__global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_bwd(const float* __restrict__ w,
+                                                            const float* __restrict__ y,
+                                                            const float4* __restrict__ dout, int64_t n_s,
+                                                            float2* __restrict__ dy, float* __restrict__ partial)
+{
+    using N = Net<IN, W, D>;
+    extern __shared__ float lds[];
+    load_fragments<IN, W, D>(w, lds, N::N_ALL);
+    __syncthreads();
+    const int64_t wave0 = (int64_t)blockIdx.x * kBwdWaves + (threadIdx.x >> 6);
+    mlp_bwd_tiles<IN, W, D>(lds, y, dout, n_s, dy, partial + (int64_t)blockIdx.x * N::N_PARAMS, wave0,
+                            (n_s + 15) / 16, (int64_t)gridDim.x * kBwdWaves);
+}
+
+// Batched backward: block b on tiles [tile_begin, tile_end) of object
+// work[b].obj; partial dW slot b.
+template <int IN, int W, int D>
+__global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_bwd_batch(const MlpWork* __restrict__ work,
+                                                                  const float* __restrict__ params,
+                                                                  const float* __restrict__ y,
+                                                                  const float4* __restrict__ dout,
+                                                                  float2* __restrict__ dy, float* __restrict__ partial,
+                                                                  int64_t slot_stride)
+{
+    using N = Net<IN, W, D>;
+    extern __shared__ float lds[];
+    const MlpWork wk = work[blockIdx.x];
+    load_fragments<IN, W, D>(params + wk.w_off, lds, N::N_ALL);
+    __syncthreads();
+    mlp_bwd_tiles<IN, W, D>(lds, y + wk.y_off, dout + wk.s_off, wk.n_s, dy + wk.y_off / 2,
+                            partial + (int64_t)blockIdx.x * slot_stride, wk.tile_begin + (threadIdx.x >> 6),
+                            wk.tile_end, kBwdWaves);
 }
 
 __global__ void k_reduce_partials(const float* __restrict__ partial, int n_slots, int64_t n_mlp,
@@ -332,6 +386,28 @@ __global__ void k_reduce_partials(const float* __restrict__ partial, int n_slots
     double acc = 0.0;
     for (int sl = 0; sl < n_slots; ++sl) acc += (double)partial[(int64_t)sl * n_mlp + p];
     g[p] += (float)acc;
+}
+
+// Batch: thread per (object, MLP parameter); the object's partials summed in FP64.
+__global__ void k_reduce_partials_batch(const MlpRed* __restrict__ reds, int n_obj, int64_t n_total,
+                                        const float* __restrict__ partial, float* __restrict__ g)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_total) return;
+    int lo = 0, hi = n_obj - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (reds[mid].mlp_begin <= i)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const MlpRed& r = reds[lo];
+    const int64_t p = i - r.mlp_begin;
+    const float* src = partial + r.partial_off + p;
+    double acc = 0.0;
+    for (int64_t sl = 0; sl < r.n_slots; ++sl) acc += (double)src[sl * r.n_mlp];
+    g[r.g_off + p] += (float)acc;
 }
 
 template <int IN, int W, int D>
@@ -367,29 +443,34 @@ hipError_t bwd_impl(const float* w, const float* y, const float* dout, int64_t n
 
 bool mlp_supported(const MlpShape& m)
 {
-    return m.width == 64 && (m.in_dim == 16 || m.in_dim == 32) && (m.hidden == 1 || m.hidden == 2);
+    return (m.width == 32 || m.width == 64) && (m.in_dim == 16 || m.in_dim == 24 || m.in_dim == 32) &&
+           (m.hidden == 1 || m.hidden == 2);
 }
 
 int mlp_bwd_waves(int64_t n_samples) { return bwd_blocks(n_samples); }
 
-#define PRENOM_MLP_DISPATCH(CALL)                                                           \
-    if (m.width == 64 && m.in_dim == 16 && m.hidden == 1) return CALL<16, 64, 1>;          \
-    if (m.width == 64 && m.in_dim == 16 && m.hidden == 2) return CALL<16, 64, 2>;          \
-    if (m.width == 64 && m.in_dim == 32 && m.hidden == 1) return CALL<32, 64, 1>;          \
-    if (m.width == 64 && m.in_dim == 32 && m.hidden == 2) return CALL<32, 64, 2>;          \
-    return hipErrorInvalidValue;
+// Every supported (input features, width, hidden layers).
+#define PRENOM_FOR_EACH_MLP(X) \
+    X(16, 32, 1) \
+    X(16, 32, 2) \
+    X(16, 64, 1) \
+    X(16, 64, 2) \
+    X(24, 32, 1) \
+    X(24, 32, 2) \
+    X(24, 64, 1) \
+    X(24, 64, 2) \
+    X(32, 32, 1) \
+    X(32, 32, 2) \
+    X(32, 64, 1) \
+    X(32, 64, 2)
 
 hipError_t launch_mlp_fwd(const MlpShape& m, const float* w, const float* y, int64_t n_s, float* sc, hipStream_t s)
 {
     if (n_s == 0) return hipSuccess;
-#define CALL_FWD fwd_impl
-#define FWD_ARGS (w, y, n_s, sc, s)
-    if (m.width == 64 && m.in_dim == 16 && m.hidden == 1) return fwd_impl<16, 64, 1> FWD_ARGS;
-    if (m.width == 64 && m.in_dim == 16 && m.hidden == 2) return fwd_impl<16, 64, 2> FWD_ARGS;
-    if (m.width == 64 && m.in_dim == 32 && m.hidden == 1) return fwd_impl<32, 64, 1> FWD_ARGS;
-    if (m.width == 64 && m.in_dim == 32 && m.hidden == 2) return fwd_impl<32, 64, 2> FWD_ARGS;
-#undef FWD_ARGS
-#undef CALL_FWD
+#define X(I, Wd, Dp) \
+    if (m.in_dim == I && m.width == Wd && m.hidden == Dp) return fwd_impl<I, Wd, Dp>(w, y, n_s, sc, s);
+    PRENOM_FOR_EACH_MLP(X)
+#undef X
     return hipErrorInvalidValue;
 }
 
@@ -397,13 +478,55 @@ hipError_t launch_mlp_bwd(const MlpShape& m, const float* w, const float* y, con
                           float* dy, float* partial, hipStream_t s)
 {
     if (n_s == 0) return hipSuccess;
-#define BWD_ARGS (w, y, dout, n_s, dy, partial, s)
-    if (m.width == 64 && m.in_dim == 16 && m.hidden == 1) return bwd_impl<16, 64, 1> BWD_ARGS;
-    if (m.width == 64 && m.in_dim == 16 && m.hidden == 2) return bwd_impl<16, 64, 2> BWD_ARGS;
-    if (m.width == 64 && m.in_dim == 32 && m.hidden == 1) return bwd_impl<32, 64, 1> BWD_ARGS;
-    if (m.width == 64 && m.in_dim == 32 && m.hidden == 2) return bwd_impl<32, 64, 2> BWD_ARGS;
-#undef BWD_ARGS
+#define X(I, Wd, Dp) \
+    if (m.in_dim == I && m.width == Wd && m.hidden == Dp) return bwd_impl<I, Wd, Dp>(w, y, dout, n_s, dy, partial, s);
+    PRENOM_FOR_EACH_MLP(X)
+#undef X
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_mlp_fwd_batch(const MlpShape& m, const MlpWork* work, int n_blocks, const float* params,
+                                const float* y, float* sc, hipStream_t s)
+{
+    if (n_blocks == 0) return hipSuccess;
+#define X(I, Wd, Dp)                                                                                         \
+    if (m.in_dim == I && m.width == Wd && m.hidden == Dp) {                                                  \
+        hipLaunchKernelGGL((k_mlp_fwd_batch<I, Wd, Dp>), dim3((uint32_t)n_blocks), dim3(256), 0, s, work, params, y, \
+                           (float4*)sc);                                                                     \
+        return hipGetLastError();                                                                            \
+    }
+    PRENOM_FOR_EACH_MLP(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_mlp_bwd_batch(const MlpShape& m, const MlpWork* work, int n_blocks, const float* params,
+                                const float* y, const float* dout, float* dy, float* partial, int64_t slot_stride,
+                                hipStream_t s)
+{
+    if (n_blocks == 0) return hipSuccess;
+#define X(I, Wd, Dp)                                                                                          \
+    if (m.in_dim == I && m.width == Wd && m.hidden == Dp) {                                                   \
+        const size_t lds = bwd_lds_bytes<I, Wd, Dp>();                                                        \
+        auto kern = k_mlp_bwd_batch<I, Wd, Dp>;                                                               \
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+        if (e != hipSuccess) return e;                                                                        \
+        hipLaunchKernelGGL(kern, dim3((uint32_t)n_blocks), dim3(64 * kBwdWaves), lds, s, work, params, y,    \
+                           (const float4*)dout, (float2*)dy, partial, slot_stride);                           \
+        return hipGetLastError();                                                                             \
+    }
+    PRENOM_FOR_EACH_MLP(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_reduce_partials_batch(const MlpRed* reds, int n_obj, int64_t n_mlp_total, const float* partial,
+                                        float* grads, hipStream_t s)
+{
+    if (n_mlp_total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_partials_batch, dim3((uint32_t)((n_mlp_total + 255) / 256)), dim3(256), 0, s, reds,
+                       n_obj, n_mlp_total, partial, grads);
+    return hipGetLastError();
 }
 
 hipError_t launch_reduce_partials(const float* partial, int n_slots, int64_t n_mlp, float* g_mlp, hipStream_t s)

@@ -59,7 +59,7 @@ __device__ __forceinline__ typename P::vec pack(floatx4 x)
 
 template <int IN, int W, int D>
 struct NetLp {
-    static constexpr int KB1 = IN / 16;       // 16-feature K-blocks of layer 1
+    static constexpr int KB1 = (IN + 15) / 16;  // 16-feature K-blocks of layer 1 (zero-padded)
     static constexpr int OT = W / 16;         // 16-neuron tiles of a hidden layer
     static constexpr int IT = (IN + 15) / 16; // 16-feature tiles of the input
     static constexpr int F1 = 0;                        // [OT][KB1]
@@ -74,7 +74,7 @@ struct NetLp {
     static constexpr int OFF_H = W * IN;
     static constexpr int OFF_OUT = W * IN + (D - 1) * W * W;
     static constexpr int N_PARAMS = OFF_OUT + 4 * W;
-    static_assert(IN % 16 == 0 && W % 16 == 0 && D >= 1, "shape");
+    static_assert(IN % 8 == 0 && W % 16 == 0 && D >= 1, "shape");
 };
 
 // Weight fragments: fragment f, lane l holds 4 consecutive K values.
@@ -88,9 +88,9 @@ __device__ void load_fragments_lp(const float* __restrict__ w, typename P::vec* 
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             float x;
-            if (f < N::FH) {  // W1[16 to + j][16 m + 4 q + r]
-                const int to = f / N::KB1, m = f % N::KB1;
-                x = w[N::OFF_W1 + (16 * to + j) * IN + 16 * m + 4 * q + r];
+            if (f < N::FH) {  // W1[16 to + j][16 m + 4 q + r], features >= IN zero
+                const int to = f / N::KB1, m = f % N::KB1, col = 16 * m + 4 * q + r;
+                x = col < IN ? w[N::OFF_W1 + (16 * to + j) * IN + col] : 0.0f;
             } else if (f < N::FO) {  // Wk[16 to + j][16 ti + 4 q + r]
                 const int g = f - N::FH, k = g / (N::OT * N::OT), rem = g % (N::OT * N::OT);
                 const int to = rem / N::OT, ti = rem % N::OT;
@@ -116,18 +116,18 @@ __device__ void load_fragments_lp(const float* __restrict__ w, typename P::vec* 
 }
 
 // Layer-1 inputs of one lane: features 16 m + 4 q + r of sample s (levels
-// 8 m + 2 q and 8 m + 2 q + 1 of the level-major feature array).
-template <int KB1>
+// 8 m + 2 q and 8 m + 2 q + 1 of the level-major feature array); features
+// beyond IN are zero.
+template <int IN, int KB1>
 __device__ __forceinline__ void load_inputs_lp(const float2* __restrict__ y, int64_t n_s, int64_t s, bool valid, int q,
                                                floatx4 (&yf)[KB1])
 {
 #pragma unroll
     for (int m = 0; m < KB1; ++m) {
         float2 a = make_float2(0.0f, 0.0f), b = make_float2(0.0f, 0.0f);
-        if (valid) {
-            a = y[(int64_t)(8 * m + 2 * q) * n_s + s];
-            b = y[(int64_t)(8 * m + 2 * q + 1) * n_s + s];
-        }
+        const int l0 = 8 * m + 2 * q;
+        if (valid && 2 * l0 < IN) a = y[(int64_t)l0 * n_s + s];
+        if (valid && 2 * (l0 + 1) < IN) b = y[(int64_t)(l0 + 1) * n_s + s];
         yf[m] = {a.x, a.y, b.x, b.y};
     }
 }
@@ -162,6 +162,25 @@ __device__ __forceinline__ void chain_lp(const typename P::vec* __restrict__ fra
 }
 
 template <int IN, int W, int D, class P>
+__device__ __forceinline__ void mlp_fwd_tiles_lp(const typename P::vec* __restrict__ frag,
+                                                 const float2* __restrict__ y, int64_t n_s, float4* __restrict__ sc,
+                                                 int64_t tile0, int64_t end, int64_t step)
+{
+    using N = NetLp<IN, W, D>;
+    const int lane = threadIdx.x & 63, q = lane >> 4, j = lane & 15;
+    for (int64_t tile = tile0; tile < end; tile += step) {
+        const int64_t s = tile * 16 + j;
+        const bool valid = s < n_s;
+        floatx4 yf[N::KB1];
+        load_inputs_lp<IN, N::KB1>(y, n_s, s, valid, q, yf);
+        floatx4 hs[D][N::OT];
+        floatx4 o;
+        chain_lp<IN, W, D, P>(frag, lane, yf, hs, o);
+        if (q == 0 && valid) sc[s] = make_float4(__expf(o[0]), sigmoidf_(o[1]), sigmoidf_(o[2]), sigmoidf_(o[3]));
+    }
+}
+
+template <int IN, int W, int D, class P>
 __global__ __launch_bounds__(256) void k_mlp_fwd_lp(const float* __restrict__ w, const float2* __restrict__ y,
                                                     int64_t n_s, float4* __restrict__ sc)
 {
@@ -169,20 +188,23 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_lp(const float* __restrict__ w,
     __shared__ typename P::vec frag[N::N_FWD * 64];
     load_fragments_lp<IN, W, D, P>(w, frag, N::N_FWD);
     __syncthreads();
-    const int lane = threadIdx.x & 63, q = lane >> 4, j = lane & 15;
-    const int64_t n_tiles = (n_s + 15) / 16;
     const int64_t wave0 = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
     const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x / 64);
-    for (int64_t tile = wave0; tile < n_tiles; tile += n_waves) {
-        const int64_t s = tile * 16 + j;
-        const bool valid = s < n_s;
-        floatx4 yf[N::KB1];
-        load_inputs_lp<N::KB1>(y, n_s, s, valid, q, yf);
-        floatx4 hs[D][N::OT];
-        floatx4 o;
-        chain_lp<IN, W, D, P>(frag, lane, yf, hs, o);
-        if (q == 0 && valid) sc[s] = make_float4(__expf(o[0]), sigmoidf_(o[1]), sigmoidf_(o[2]), sigmoidf_(o[3]));
-    }
+    mlp_fwd_tiles_lp<IN, W, D, P>(frag, y, n_s, sc, wave0, (n_s + 15) / 16, n_waves);
+}
+
+template <int IN, int W, int D, class P>
+__global__ __launch_bounds__(256) void k_mlp_fwd_lp_batch(const MlpWork* __restrict__ work,
+                                                          const float* __restrict__ params,
+                                                          const float2* __restrict__ y, float4* __restrict__ sc)
+{
+    using N = NetLp<IN, W, D>;
+    __shared__ typename P::vec frag[N::N_FWD * 64];
+    const MlpWork wk = work[blockIdx.x];
+    load_fragments_lp<IN, W, D, P>(params + wk.w_off, frag, N::N_FWD);
+    __syncthreads();
+    mlp_fwd_tiles_lp<IN, W, D, P>(frag, y + wk.y_off / 2, wk.n_s, sc + wk.s_off, wk.tile_begin + (threadIdx.x >> 6),
+                                  wk.tile_end, blockDim.x / 64);
 }
 
 template <int IN, int W, int D>
@@ -212,19 +234,17 @@ __device__ __forceinline__ void accumulate_dw_lp(const float* __restrict__ sD, c
         for (int ti = 0; ti < ITILES; ++ti) dw[to][ti] = P::mma(a[to], b[ti], dw[to][ti]);
 }
 
+// Backward over tiles tile0, tile0 + step, ... < end of one object whose
+// fragments are at the start of smem_lp; called by every thread of the block.
 template <int IN, int W, int D, class P>
-__global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_bwd_lp(const float* __restrict__ w,
-                                                               const float2* __restrict__ y,
-                                                               const float4* __restrict__ dout, int64_t n_s,
-                                                               float2* __restrict__ dy, float* __restrict__ partial)
+__device__ void mlp_bwd_tiles_lp(unsigned char* __restrict__ smem_lp, const float2* __restrict__ y,
+                                 const float4* __restrict__ dout, int64_t n_s, float2* __restrict__ dy,
+                                 float* __restrict__ dst, int64_t tile0, int64_t end, int64_t step)
 {
     using N = NetLp<IN, W, D>;
     using B = BwdLdsLp<IN, W, D>;
-    extern __shared__ __align__(16) unsigned char smem_lp[];
-    typename P::vec* frag = reinterpret_cast<typename P::vec*>(smem_lp);
+    const typename P::vec* frag = reinterpret_cast<const typename P::vec*>(smem_lp);
     float* stage = reinterpret_cast<float*>(smem_lp + sizeof(typename P::vec) * N::N_ALL * 64);
-    load_fragments_lp<IN, W, D, P>(w, frag, N::N_ALL);
-    __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, j = lane & 15;
     float* sD = stage + wave * B::PER_WAVE;
     float* sH = sD + 16 * B::DW;
@@ -243,14 +263,11 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_bwd_lp(const float* __re
         dWo[0][a] = {0.0f, 0.0f, 0.0f, 0.0f};
     }
 
-    const int64_t n_tiles = (n_s + 15) / 16;
-    const int64_t wave0 = (int64_t)blockIdx.x * kBwdWaves + wave;
-    const int64_t n_waves = (int64_t)gridDim.x * kBwdWaves;
-    for (int64_t tile = wave0; tile < n_tiles; tile += n_waves) {
+    for (int64_t tile = tile0; tile < end; tile += step) {
         const int64_t s = tile * 16 + j;
         const bool valid = s < n_s;
         floatx4 yf[N::KB1];
-        load_inputs_lp<N::KB1>(y, n_s, s, valid, q, yf);
+        load_inputs_lp<IN, N::KB1>(y, n_s, s, valid, q, yf);
         floatx4 hs[D][N::OT];
         floatx4 o;
         chain_lp<IN, W, D, P>(frag, lane, yf, hs, o);
@@ -302,7 +319,7 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_bwd_lp(const float* __re
 #pragma unroll
         for (int m = 0; m < N::KB1; ++m)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) sH[j * B::HW + 16 * m + 4 * q + r] = yf[m][r];
+            for (int r = 0; r < 4; ++r) sH[j * B::HW + 16 * m + 4 * q + r] = yf[m][r];  // zero beyond IN
         wave_lds_sync();
         accumulate_dw_lp<N::OT, N::IT, B::DW, B::HW, P>(sD, sH, dW1, q, j);
         typename P::vec dp[N::OT];
@@ -334,8 +351,40 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_bwd_lp(const float* __re
         }
         __syncthreads();
     }
-    float* dst = partial + (int64_t)blockIdx.x * N::N_PARAMS;
     for (int p = threadIdx.x; p < N::N_PARAMS; p += blockDim.x) dst[p] = red[p];
+}
+
+template <int IN, int W, int D, class P>
+__global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_bwd_lp(const float* __restrict__ w,
+                                                               const float2* __restrict__ y,
+                                                               const float4* __restrict__ dout, int64_t n_s,
+                                                               float2* __restrict__ dy, float* __restrict__ partial)
+{
+    using N = NetLp<IN, W, D>;
+    extern __shared__ __align__(16) unsigned char smem_lp[];
+    load_fragments_lp<IN, W, D, P>(w, reinterpret_cast<typename P::vec*>(smem_lp), N::N_ALL);
+    __syncthreads();
+    const int64_t wave0 = (int64_t)blockIdx.x * kBwdWaves + (threadIdx.x >> 6);
+    mlp_bwd_tiles_lp<IN, W, D, P>(smem_lp, y, dout, n_s, dy, partial + (int64_t)blockIdx.x * N::N_PARAMS, wave0,
+                                  (n_s + 15) / 16, (int64_t)gridDim.x * kBwdWaves);
+}
+
+template <int IN, int W, int D, class P>
+__global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_bwd_lp_batch(const MlpWork* __restrict__ work,
+                                                                     const float* __restrict__ params,
+                                                                     const float2* __restrict__ y,
+                                                                     const float4* __restrict__ dout,
+                                                                     float2* __restrict__ dy,
+                                                                     float* __restrict__ partial, int64_t slot_stride)
+{
+    using N = NetLp<IN, W, D>;
+    extern __shared__ __align__(16) unsigned char smem_lp[];
+    const MlpWork wk = work[blockIdx.x];
+    load_fragments_lp<IN, W, D, P>(params + wk.w_off, reinterpret_cast<typename P::vec*>(smem_lp), N::N_ALL);
+    __syncthreads();
+    mlp_bwd_tiles_lp<IN, W, D, P>(smem_lp, y + wk.y_off / 2, dout + wk.s_off, wk.n_s, dy + wk.y_off / 2,
+                                  partial + (int64_t)blockIdx.x * slot_stride, wk.tile_begin + (threadIdx.x >> 6),
+                                  wk.tile_end, kBwdWaves);
 }
 
 template <int IN, int W, int D, class P>
@@ -364,13 +413,27 @@ hipError_t bwd_lp(const float* w, const float* y, const float* dout, int64_t n_s
     return hipGetLastError();
 }
 
+#define PRENOM_FOR_EACH_MLP_LP(X) \
+    X(16, 32, 1) \
+    X(16, 32, 2) \
+    X(16, 64, 1) \
+    X(16, 64, 2) \
+    X(24, 32, 1) \
+    X(24, 32, 2) \
+    X(24, 64, 1) \
+    X(24, 64, 2) \
+    X(32, 32, 1) \
+    X(32, 32, 2) \
+    X(32, 64, 1) \
+    X(32, 64, 2)
+
 template <class P>
 hipError_t fwd_dispatch(const MlpShape& m, const float* w, const float* y, int64_t n_s, float* sc, hipStream_t s)
 {
-    if (m.width == 64 && m.in_dim == 16 && m.hidden == 1) return fwd_lp<16, 64, 1, P>(w, y, n_s, sc, s);
-    if (m.width == 64 && m.in_dim == 16 && m.hidden == 2) return fwd_lp<16, 64, 2, P>(w, y, n_s, sc, s);
-    if (m.width == 64 && m.in_dim == 32 && m.hidden == 1) return fwd_lp<32, 64, 1, P>(w, y, n_s, sc, s);
-    if (m.width == 64 && m.in_dim == 32 && m.hidden == 2) return fwd_lp<32, 64, 2, P>(w, y, n_s, sc, s);
+#define X(I, Wd, Dp) \
+    if (m.in_dim == I && m.width == Wd && m.hidden == Dp) return fwd_lp<I, Wd, Dp, P>(w, y, n_s, sc, s);
+    PRENOM_FOR_EACH_MLP_LP(X)
+#undef X
     return hipErrorInvalidValue;
 }
 
@@ -378,10 +441,52 @@ template <class P>
 hipError_t bwd_dispatch(const MlpShape& m, const float* w, const float* y, const float* dout, int64_t n_s, float* dy,
                         float* partial, hipStream_t s)
 {
-    if (m.width == 64 && m.in_dim == 16 && m.hidden == 1) return bwd_lp<16, 64, 1, P>(w, y, dout, n_s, dy, partial, s);
-    if (m.width == 64 && m.in_dim == 16 && m.hidden == 2) return bwd_lp<16, 64, 2, P>(w, y, dout, n_s, dy, partial, s);
-    if (m.width == 64 && m.in_dim == 32 && m.hidden == 1) return bwd_lp<32, 64, 1, P>(w, y, dout, n_s, dy, partial, s);
-    if (m.width == 64 && m.in_dim == 32 && m.hidden == 2) return bwd_lp<32, 64, 2, P>(w, y, dout, n_s, dy, partial, s);
+#define X(I, Wd, Dp) \
+    if (m.in_dim == I && m.width == Wd && m.hidden == Dp) return bwd_lp<I, Wd, Dp, P>(w, y, dout, n_s, dy, partial, s);
+    PRENOM_FOR_EACH_MLP_LP(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+template <int IN, int W, int D, class P>
+size_t bwd_lds_lp()
+{
+    return sizeof(typename P::vec) * (size_t)NetLp<IN, W, D>::N_ALL * 64 +
+           sizeof(float) * (size_t)kBwdWaves * BwdLdsLp<IN, W, D>::PER_WAVE;
+}
+
+template <class P>
+hipError_t fwd_batch_dispatch(const MlpShape& m, const MlpWork* work, int n_blocks, const float* params, const float* y,
+                              float* sc, hipStream_t s)
+{
+#define X(I, Wd, Dp)                                                                                      \
+    if (m.in_dim == I && m.width == Wd && m.hidden == Dp) {                                               \
+        hipLaunchKernelGGL((k_mlp_fwd_lp_batch<I, Wd, Dp, P>), dim3((uint32_t)n_blocks), dim3(256), 0, s, work, \
+                           params, (const float2*)y, (float4*)sc);                                        \
+        return hipGetLastError();                                                                         \
+    }
+    PRENOM_FOR_EACH_MLP_LP(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+template <class P>
+hipError_t bwd_batch_dispatch(const MlpShape& m, const MlpWork* work, int n_blocks, const float* params,
+                              const float* y, const float* dout, float* dy, float* partial, int64_t slot_stride,
+                              hipStream_t s)
+{
+#define X(I, Wd, Dp)                                                                                        \
+    if (m.in_dim == I && m.width == Wd && m.hidden == Dp) {                                                 \
+        const size_t lds = bwd_lds_lp<I, Wd, Dp, P>();                                                      \
+        auto kern = k_mlp_bwd_lp_batch<I, Wd, Dp, P>;                                                       \
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+        if (e != hipSuccess) return e;                                                                      \
+        hipLaunchKernelGGL(kern, dim3((uint32_t)n_blocks), dim3(64 * kBwdWaves), lds, s, work, params,     \
+                           (const float2*)y, (const float4*)dout, (float2*)dy, partial, slot_stride);      \
+        return hipGetLastError();                                                                           \
+    }
+    PRENOM_FOR_EACH_MLP_LP(X)
+#undef X
     return hipErrorInvalidValue;
 }
 
@@ -401,6 +506,27 @@ hipError_t launch_mlp_bwd_lp(const MlpShape& m, const float* w, const float* y, 
     if (n_s == 0) return hipSuccess;
     if (m.dtype == PRENOM_BF16) return bwd_dispatch<Bf16Op>(m, w, y, dout, n_s, dy, partial, s);
     if (m.dtype == PRENOM_F16) return bwd_dispatch<F16Op>(m, w, y, dout, n_s, dy, partial, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_mlp_fwd_lp_batch(const MlpShape& m, const MlpWork* work, int n_blocks, const float* params,
+                                   const float* y, float* sc, hipStream_t s)
+{
+    if (n_blocks == 0) return hipSuccess;
+    if (m.dtype == PRENOM_BF16) return fwd_batch_dispatch<Bf16Op>(m, work, n_blocks, params, y, sc, s);
+    if (m.dtype == PRENOM_F16) return fwd_batch_dispatch<F16Op>(m, work, n_blocks, params, y, sc, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_mlp_bwd_lp_batch(const MlpShape& m, const MlpWork* work, int n_blocks, const float* params,
+                                   const float* y, const float* dout, float* dy, float* partial, int64_t slot_stride,
+                                   hipStream_t s)
+{
+    if (n_blocks == 0) return hipSuccess;
+    if (m.dtype == PRENOM_BF16)
+        return bwd_batch_dispatch<Bf16Op>(m, work, n_blocks, params, y, dout, dy, partial, slot_stride, s);
+    if (m.dtype == PRENOM_F16)
+        return bwd_batch_dispatch<F16Op>(m, work, n_blocks, params, y, dout, dy, partial, slot_stride, s);
     return hipErrorInvalidValue;
 }
 

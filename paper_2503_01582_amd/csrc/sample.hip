@@ -57,7 +57,7 @@ struct RayFrame {
 };
 
 // sigma_i * delta_i of coarse bin i (Eq. (4) with sigma_i = F(x_i)).
-__device__ __forceinline__ double coarse_tau(const SampleArgs& a, const RayFrame& r, int i)
+__device__ __forceinline__ double coarse_tau(const float* prior, int R, const RayFrame& r, int i)
 {
     const double m = r.tn + ((double)i + 0.5) * r.delta;
     double x[3];
@@ -67,14 +67,15 @@ __device__ __forceinline__ double coarse_tau(const SampleArgs& a, const RayFrame
         v = v > 1.0 ? 1.0 : v;
         x[k] = v;
     }
-    const double sig = prior_at(a.prior, a.R, x);
+    const double sig = prior_at(prior, R, x);
     return sig * r.delta * r.len;
 }
 
-__global__ __launch_bounds__(kSampleBlock) void k_sample(SampleArgs a)
+// One ray.  A, prior and R are the ray's object's pose and prior (per
+// object in a batch); everything else comes from `a`.
+__device__ void sample_ray(const SampleArgs& a, const double* A_obj, const float* prior, int R, bool use_prior,
+                           int64_t ray)
 {
-    const int64_t ray = (int64_t)blockIdx.x * kSampleBlock + threadIdx.x;
-    if (ray >= a.n) return;
     const int Nc = a.n_coarse, Nr = a.n_fine;
     const int S = Nr + (a.include_coarse ? Nc : 0);
 
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(kSampleBlock) void k_sample(SampleArgs a)
     const float* ow = a.rays_o + 3 * ray;
     const float* dw = a.rays_d + 3 * ray;
     for (int k = 0; k < 3; ++k) {
-        const double* A = a.A + 4 * k;
+        const double* A = A_obj + 4 * k;
         r.o[k] = A[0] * (double)ow[0] + A[1] * (double)ow[1] + A[2] * (double)ow[2] + A[3];
         r.d[k] = A[0] * (double)dw[0] + A[1] * (double)dw[1] + A[2] * (double)dw[2];
     }
@@ -130,19 +131,19 @@ __global__ __launch_bounds__(kSampleBlock) void k_sample(SampleArgs a)
     // pass 1: total prior mass along the ray
     bool escaped = false;
     double total_S = 0.0;
-    if (a.use_prior) {
-        for (int i = 0; i < Nc; ++i) total_S = total_S + coarse_tau(a, r, i);
+    if (use_prior) {
+        for (int i = 0; i < Nc; ++i) total_S = total_S + coarse_tau(prior, R, r, i);
         escaped = (-expm1(-total_S)) < a.eps;
     }
-    const bool cdf_draws = a.use_prior && !escaped;
-    a.flags[ray] = (uint8_t)((a.use_prior ? 0 : PRENOM_FLAG_UNIFORM) | (escaped ? PRENOM_FLAG_ESCAPED : 0));
+    const bool cdf_draws = use_prior && !escaped;
+    a.flags[ray] = (uint8_t)((use_prior ? 0 : PRENOM_FLAG_UNIFORM) | (escaped ? PRENOM_FLAG_ESCAPED : 0));
 
     // pass 2: draws in ascending u, merged with the coarse midpoints
     const double den = expm1(-total_S);
     int b = 0;
     double S_b1 = 0.0, C_b = 0.0, C_b1 = 1.0;
     if (cdf_draws) {
-        S_b1 = 0.0 + coarse_tau(a, r, 0);
+        S_b1 = 0.0 + coarse_tau(prior, R, r, 0);
         C_b1 = (Nc == 1) ? 1.0 : expm1(-S_b1) / den;
     }
     int ic = 0, j = 0;
@@ -163,7 +164,7 @@ __global__ __launch_bounds__(kSampleBlock) void k_sample(SampleArgs a)
             while (b + 1 < Nc && C_b1 < u) {  // the last CDF value is 1 > u for xi in (0,1)
                 ++b;
                 C_b = C_b1;
-                S_b1 = S_b1 + coarse_tau(a, r, b);
+                S_b1 = S_b1 + coarse_tau(prior, R, r, b);
                 C_b1 = (b + 1 == Nc) ? 1.0 : expm1(-S_b1) / den;
             }
             tk = r.tn + r.delta * ((double)b + (u - C_b) / (C_b1 - C_b));
@@ -184,7 +185,32 @@ __global__ __launch_bounds__(kSampleBlock) void k_sample(SampleArgs a)
     dtr[S - 1] = (float)((r.tf - prev) * r.len);
 }
 
+__global__ __launch_bounds__(kSampleBlock) void k_sample(SampleArgs a)
+{
+    const int64_t ray = (int64_t)blockIdx.x * kSampleBlock + threadIdx.x;
+    if (ray >= a.n) return;
+    sample_ray(a, a.A, a.prior, a.R, a.use_prior != 0, ray);
+}
+
+// All rays of a batch: the ray's object (last with ray_begin <= ray) supplies
+// pose and prior; a.use_prior == 0 forces uniform draws for every object.
+__global__ __launch_bounds__(kSampleBlock) void k_sample_batch(SampleArgs a, const ObjDev* __restrict__ objs, int n_obj)
+{
+    const int64_t ray = (int64_t)blockIdx.x * kSampleBlock + threadIdx.x;
+    if (ray >= a.n) return;
+    const ObjDev& o = objs[find_object(objs, n_obj, ray)];
+    sample_ray(a, o.A, o.prior, o.prior_res, a.use_prior != 0 && o.prior != nullptr, ray);
+}
+
 }  // namespace
+
+hipError_t launch_sample_batch(const SampleArgs& a, const ObjDev* objs, int n_obj, hipStream_t s)
+{
+    if (a.n == 0) return hipSuccess;
+    const int64_t blocks = (a.n + kSampleBlock - 1) / kSampleBlock;
+    hipLaunchKernelGGL(k_sample_batch, dim3((uint32_t)blocks), dim3(kSampleBlock), 0, s, a, objs, n_obj);
+    return hipGetLastError();
+}
 
 hipError_t launch_sample(const SampleArgs& a, hipStream_t s)
 {

@@ -28,6 +28,11 @@
 //
 // Corner rows and weights are computed by the same function as the forward
 // encoding, so count and place agree exactly.
+//
+// The same kernels serve one object (its geometry passed by value) and a
+// batch of objects with different grids (geometry in a device table): tiles,
+// sample blocks and (object, level) pairs of all objects are numbered
+// consecutively, so every phase is one launch for the whole batch.
 #include "common.h"
 
 namespace prenom {
@@ -36,8 +41,7 @@ namespace {
 constexpr int kTileBits = 13;
 constexpr int kTileRows = 1 << kTileBits;
 constexpr int kPlaceThreads = 512;
-constexpr int kSamplesPerThread = 1;
-constexpr int kSamplesPerBlock = kPlaceThreads * kSamplesPerThread;  // 512
+constexpr int kSamplesPerBlock = kPlaceThreads;  // one sample per thread
 constexpr int kRecordsPerBlock = kSamplesPerBlock * 8;
 constexpr int kMaxTilesPerLevel = 1 << (24 - kTileBits);  // T <= 2^24
 constexpr int kScanThreads = 1024;
@@ -48,6 +52,61 @@ constexpr int64_t kChunk = (int64_t)1 << 21;  // records per reduce work item
 // Levels with at most this many tiles have most lanes of a wave in the same
 // tile; their histogram atomics are combined per wave first.
 constexpr int kAggregateTiles = 16;
+
+// ---------------------------------------------------------------- object lookup
+// Index of the last object whose `field` is <= v (fields ascend with the index).
+template <bool kMany, typename F>
+__device__ __forceinline__ int last_le(const ScatterArgs& a, int64_t v, F field)
+{
+    if constexpr (!kMany) {
+        return 0;
+    } else {
+        int lo = 0, hi = a.n_obj - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (field(a.objs[mid]) <= v)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        return lo;
+    }
+}
+
+template <bool kMany>
+__device__ __forceinline__ const ScatterObj& sobj(const ScatterArgs& a, int i)
+{
+    if constexpr (kMany)
+        return a.objs[i];
+    else
+        return a.one;
+}
+
+template <bool kMany>
+__device__ __forceinline__ int obj_of_item(const ScatterArgs& a, int64_t item)
+{
+    return last_le<kMany>(a, item, [](const ScatterObj& o) { return o.item_off; });
+}
+
+template <bool kMany>
+__device__ __forceinline__ int obj_of_tile(const ScatterArgs& a, int64_t tile)
+{
+    return last_le<kMany>(a, tile, [](const ScatterObj& o) { return o.tile_off; });
+}
+
+template <bool kMany>
+__device__ __forceinline__ int obj_of_level(const ScatterArgs& a, int64_t pair)
+{
+    return last_le<kMany>(a, pair, [](const ScatterObj& o) { return (int64_t)o.lev_off; });
+}
+
+// Level of local tile lt of object o.
+__device__ __forceinline__ int level_of_tile(const ScatterObj& o, int lt)
+{
+    int l = 0;
+    while (l + 1 < o.grid.n_levels && o.tile_base[l + 1] <= lt) ++l;
+    return l;
+}
 
 // Adds 1 to hist[tile] for every active lane and returns the lane's rank
 // among the additions to that tile.  Lanes of the wave that share a tile are
@@ -72,35 +131,40 @@ __device__ __forceinline__ uint32_t wave_aggregated_add(uint32_t* hist, uint32_t
     return rank;
 }
 
-// Feature gradient and corners of one (sample, level); false when dy == 0
-// (the sample contributes nothing and is skipped by count and place alike).
-__device__ __forceinline__ bool load_contrib(const ScatterArgs& a, int l, int64_t s, float2& d, Corners& c)
+// Feature gradient and corners of local sample s on level l of object o;
+// false when dy == 0 (the sample contributes nothing and is skipped by count
+// and place alike).
+__device__ __forceinline__ bool load_contrib(const ScatterArgs& a, const ScatterObj& o, int l, int64_t s, float2& d,
+                                             Corners& c)
 {
-    d = a.dy[(int64_t)l * a.n_s + s];
+    d = a.dy[o.dy_off + (int64_t)l * o.n_s + s];
     if (d.x == 0.0f && d.y == 0.0f) return false;
-    const float* ro = a.ray_obj + 6 * (s / a.S);
-    const float ts = a.t[s];
-    level_corners(a.grid, l, sample_coord(ts, ro[3], ro[0]), sample_coord(ts, ro[4], ro[1]),
-               sample_coord(ts, ro[5], ro[2]), c);
+    const int64_t gs = o.s_begin + s;
+    const float* ro = a.ray_obj + 6 * (gs / a.S);
+    const float ts = a.t[gs];
+    level_corners(o.grid, l, sample_coord(ts, ro[3], ro[0]), sample_coord(ts, ro[4], ro[1]),
+                  sample_coord(ts, ro[5], ro[2]), c);
     return true;
 }
 
+template <bool kMany>
 __global__ __launch_bounds__(kPlaceThreads) void k_scatter_count(ScatterArgs a)
 {
     __shared__ uint32_t hist[kMaxTilesPerLevel];
     __shared__ float wmax[kPlaceThreads / 64];
-    const int l = blockIdx.y, bx = blockIdx.x;
-    const int nt = a.tiles[l];
+    const int64_t item = blockIdx.x;
+    const ScatterObj& o = sobj<kMany>(a, obj_of_item<kMany>(a, item));
+    const int64_t rem = item - o.item_off;
+    const int l = (int)(rem / o.n_blocks), bx = (int)(rem % o.n_blocks);
+    const int nt = o.tiles[l];
     for (int i = threadIdx.x; i < nt; i += kPlaceThreads) hist[i] = 0;
     __syncthreads();
     float m = 0.0f;
-    for (int k = 0; k < kSamplesPerThread; ++k) {
-        const int64_t s = (int64_t)bx * kSamplesPerBlock + k * kPlaceThreads + threadIdx.x;
-        if (s >= a.n_s) break;
-        float2 d;
-        Corners c;
-        if (!load_contrib(a, l, s, d, c)) continue;
-        m = fmaxf(m, fmaxf(fabsf(d.x), fabsf(d.y)));
+    const int64_t s = (int64_t)bx * kSamplesPerBlock + threadIdx.x;
+    float2 d;
+    Corners c;
+    if (s < o.n_s && load_contrib(a, o, l, s, d, c)) {
+        m = fmaxf(fabsf(d.x), fabsf(d.y));
         if (nt <= kAggregateTiles) {
 #pragma unroll
             for (int e = 0; e < 8; ++e) wave_aggregated_add(hist, c.row[e] >> kTileBits);
@@ -113,23 +177,44 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_count(ScatterArgs a)
     for (int dd = 32; dd >= 1; dd >>= 1) m = fmaxf(m, __shfl_xor(m, dd));
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
     __syncthreads();
-    uint32_t* out = a.counts + (int64_t)a.tile_base[l] * a.n_blocks + bx;
-    for (int i = threadIdx.x; i < nt; i += kPlaceThreads) out[(int64_t)i * a.n_blocks] = hist[i];
+    uint32_t* out = a.counts + o.count_off + (int64_t)o.tile_base[l] * o.n_blocks + bx;
+    for (int i = threadIdx.x; i < nt; i += kPlaceThreads) out[(int64_t)i * o.n_blocks] = hist[i];
     if (threadIdx.x == 0) {
         float bm = 0.0f;
         for (int w = 0; w < kPlaceThreads / 64; ++w) bm = fmaxf(bm, wmax[w]);
-        a.block_max[(int64_t)l * a.n_blocks + bx] = bm;
+        a.block_max[o.bmax_off + (int64_t)l * o.n_blocks + bx] = bm;
     }
 }
 
+// Max |dy| of each (object, level) over its sample blocks; one block per pair.
+template <bool kMany>
+__global__ __launch_bounds__(256) void k_scatter_level_max(ScatterArgs a)
+{
+    __shared__ float red[4];
+    const int pair = blockIdx.x;
+    const ScatterObj& o = sobj<kMany>(a, obj_of_level<kMany>(a, pair));
+    const int l = pair - o.lev_off;
+    const float* bm = a.block_max + o.bmax_off + (int64_t)l * o.n_blocks;
+    float m = 0.0f;
+    for (int b = threadIdx.x; b < o.n_blocks; b += 256) m = fmaxf(m, bm[b]);
+#pragma unroll
+    for (int dd = 32; dd >= 1; dd >>= 1) m = fmaxf(m, __shfl_xor(m, dd));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) a.level_max[pair] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
 // Per tile: exclusive prefix of the per-block counts (in place) and the total.
+template <bool kMany>
 __global__ __launch_bounds__(kScanThreads) void k_scatter_scan_blocks(ScatterArgs a)
 {
     __shared__ uint64_t part[kScanThreads];
-    const int tile = blockIdx.x;
-    uint32_t* row = a.counts + (int64_t)tile * a.n_blocks;
-    const int per = (a.n_blocks + kScanThreads - 1) / kScanThreads;
-    const int b0 = threadIdx.x * per, b1 = min(b0 + per, a.n_blocks);
+    const int64_t tile = blockIdx.x;
+    const ScatterObj& o = sobj<kMany>(a, obj_of_tile<kMany>(a, tile));
+    const int nb = o.n_blocks;
+    uint32_t* row = a.counts + o.count_off + (tile - o.tile_off) * nb;
+    const int per = (nb + kScanThreads - 1) / kScanThreads;
+    const int b0 = threadIdx.x * per, b1 = min(b0 + per, nb);
     uint64_t sum = 0;
     for (int b = b0; b < b1; ++b) sum += row[b];
     part[threadIdx.x] = sum;
@@ -149,26 +234,17 @@ __global__ __launch_bounds__(kScanThreads) void k_scatter_scan_blocks(ScatterArg
     if (threadIdx.x == kScanThreads - 1) a.tile_total[tile] = part[kScanThreads - 1];
 }
 
-// Over tiles: record bases, chunk counts and chunk bases, the fixed-point
+// Over all tiles: record bases, chunk counts and chunk bases, the fixed-point
 // exponent of each tile; resets the work counter.
+template <bool kMany>
 __global__ __launch_bounds__(kScanThreads) void k_scatter_scan_tiles(ScatterArgs a)
 {
     __shared__ uint64_t prec[kScanThreads], pchk[kScanThreads];
-    __shared__ float lmax[PRENOM_MAX_LEVELS];
-    // per-level max |dy| over the blocks
-    for (int l = threadIdx.x >> 6; l < a.grid.n_levels; l += kScanThreads / 64) {
-        float m = 0.0f;
-        for (int b = threadIdx.x & 63; b < a.n_blocks; b += 64) m = fmaxf(m, a.block_max[(int64_t)l * a.n_blocks + b]);
-#pragma unroll
-        for (int dd = 32; dd >= 1; dd >>= 1) m = fmaxf(m, __shfl_xor(m, dd));
-        if ((threadIdx.x & 63) == 0) lmax[l] = m;
-    }
-    __syncthreads();
-    const int n = a.n_tiles;
-    const int per = (n + kScanThreads - 1) / kScanThreads;
-    const int t0 = threadIdx.x * per, t1 = min(t0 + per, n);
+    const int64_t n = a.n_tiles;
+    const int64_t per = (n + kScanThreads - 1) / kScanThreads;
+    const int64_t t0 = threadIdx.x * per, t1 = min(t0 + per, n);
     uint64_t rs = 0, cs = 0;
-    for (int t = t0; t < t1; ++t) {
+    for (int64_t t = t0; t < t1; ++t) {
         rs += a.tile_total[t];
         cs += (a.tile_total[t] + kChunk - 1) / kChunk;
     }
@@ -184,15 +260,15 @@ __global__ __launch_bounds__(kScanThreads) void k_scatter_scan_tiles(ScatterArgs
         __syncthreads();
     }
     uint64_t r = prec[threadIdx.x] - rs, ck = pchk[threadIdx.x] - cs;
-    for (int t = t0; t < t1; ++t) {
+    for (int64_t t = t0; t < t1; ++t) {
         a.tile_start[t] = r;
         a.chunk_start[t] = ck;
         r += a.tile_total[t];
         ck += (a.tile_total[t] + kChunk - 1) / kChunk;
         // largest e with max|dy| * records * 2^e < 2^62 (bound on any row's |sum| * 2^e)
-        int l = 0;
-        while (l + 1 < a.grid.n_levels && a.tile_base[l + 1] <= t) ++l;
-        const double bound = (double)lmax[l] * (double)a.tile_total[t];
+        const ScatterObj& o = sobj<kMany>(a, obj_of_tile<kMany>(a, t));
+        const int l = level_of_tile(o, (int)(t - o.tile_off));
+        const double bound = (double)a.level_max[o.lev_off + l] * (double)a.tile_total[t];
         int e = 0;
         if (bound > 0.0) {
             int ex;
@@ -214,6 +290,7 @@ __host__ __device__ constexpr size_t place_lds_bytes(int nt)
     return (size_t)nt * 8 + (size_t)kRecordsPerBlock * 8 + (size_t)nt * 8 + 16 + (size_t)kRecordsPerBlock * 4;
 }
 
+template <bool kMany>
 __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -225,27 +302,30 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
     uint32_t* p_total = seg + nt_lds;
     uint16_t* s_key = reinterpret_cast<uint16_t*>(p_total + 4);
     uint16_t* s_tile = s_key + kRecordsPerBlock;
-    const int l = blockIdx.y, bx = blockIdx.x;
-    const int nt = a.tiles[l];
+    const int64_t item = blockIdx.x;
+    const ScatterObj& o = sobj<kMany>(a, obj_of_item<kMany>(a, item));
+    const int64_t rem = item - o.item_off;
+    const int l = (int)(rem / o.n_blocks), bx = (int)(rem % o.n_blocks);
+    const int nt = o.tiles[l];
     for (int i = threadIdx.x; i < nt; i += kPlaceThreads) hist[i] = 0;
     __syncthreads();
     // pass 1: rank of each contribution within its tile (LDS atomics)
-    uint32_t rank[kSamplesPerThread][8];
-    for (int k = 0; k < kSamplesPerThread; ++k) {
-        const int64_t s = (int64_t)bx * kSamplesPerBlock + k * kPlaceThreads + threadIdx.x;
-        float2 d;
-        Corners c;
-        if (s >= a.n_s || !load_contrib(a, l, s, d, c)) continue;
+    const int64_t s = (int64_t)bx * kSamplesPerBlock + threadIdx.x;
+    float2 d;
+    Corners c;
+    const bool has = s < o.n_s && load_contrib(a, o, l, s, d, c);
+    uint32_t rank[8];
+    if (has) {
         if (nt <= kAggregateTiles) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) rank[k][e] = wave_aggregated_add(hist, c.row[e] >> kTileBits);
+            for (int e = 0; e < 8; ++e) rank[e] = wave_aggregated_add(hist, c.row[e] >> kTileBits);
         } else {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) rank[k][e] = atomicAdd(&hist[c.row[e] >> kTileBits], 1u);
+            for (int e = 0; e < 8; ++e) rank[e] = atomicAdd(&hist[c.row[e] >> kTileBits], 1u);
         }
     }
     __syncthreads();
-    // block-local segments: exclusive scan of hist (serial over <= 1024 tiles by one wave)
+    // block-local segments: exclusive scan of hist (by one wave)
     if (threadIdx.x < 64) {
         const int lane = threadIdx.x;
         uint32_t carry = 0;
@@ -254,8 +334,8 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
             uint32_t v = i < nt ? hist[i] : 0u, incl = v;
 #pragma unroll
             for (int dd = 1; dd < 64; dd <<= 1) {
-                const uint32_t o = __shfl_up(incl, dd);
-                if (lane >= dd) incl += o;
+                const uint32_t up = __shfl_up(incl, dd);
+                if (lane >= dd) incl += up;
             }
             if (i < nt) seg[i] = carry + incl - v;
             carry += __shfl(incl, 63);
@@ -263,22 +343,19 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
         if (lane == 0) *p_total = carry;
     }
     __syncthreads();
-    // global position of record p of tile tt: gbase[tt] + p
+    // global position of record p of local tile tt: gbase[tt] + p
     {
-        const int tb = a.tile_base[l];
+        const int tb = o.tile_base[l];
+        const uint32_t* cnt = a.counts + o.count_off;
         for (int i = threadIdx.x; i < nt; i += kPlaceThreads)
-            gbase[i] = a.tile_start[tb + i] + a.counts[(int64_t)(tb + i) * a.n_blocks + bx] - seg[i];
+            gbase[i] = a.tile_start[o.tile_off + tb + i] + cnt[(int64_t)(tb + i) * o.n_blocks + bx] - seg[i];
     }
-    // pass 2: recompute and stage the records sorted by tile
-    for (int k = 0; k < kSamplesPerThread; ++k) {
-        const int64_t s = (int64_t)bx * kSamplesPerBlock + k * kPlaceThreads + threadIdx.x;
-        float2 d;
-        Corners c;
-        if (s >= a.n_s || !load_contrib(a, l, s, d, c)) continue;
+    // pass 2: stage the records sorted by tile (corners kept from pass 1)
+    if (has) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const uint32_t tt = c.row[e] >> kTileBits;
-            const uint32_t p = seg[tt] + rank[k][e];
+            const uint32_t p = seg[tt] + rank[e];
             s_key[p] = (uint16_t)(c.row[e] & (kTileRows - 1));
             s_tile[p] = (uint16_t)tt;
             s_val[p] = make_float2(c.w[e] * d.x, c.w[e] * d.y);
@@ -294,6 +371,7 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
     }
 }
 
+template <bool kMany>
 __global__ __launch_bounds__(kReduceThreads) void k_scatter_reduce(ScatterArgs a)
 {
     __shared__ unsigned long long acc[2 * kTileRows];  // fixed point: feature 0 rows, then feature 1 rows
@@ -306,20 +384,21 @@ __global__ __launch_bounds__(kReduceThreads) void k_scatter_reduce(ScatterArgs a
         __syncthreads();
         if ((uint64_t)chunk >= n_chunks) break;
         // tile of this chunk: last t with chunk_start[t] <= chunk
-        int lo = 0, hi = a.n_tiles - 1;
+        int64_t lo = 0, hi = a.n_tiles - 1;
         while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
+            const int64_t mid = (lo + hi + 1) >> 1;
             if (a.chunk_start[mid] <= (uint64_t)chunk)
                 lo = mid;
             else
                 hi = mid - 1;
         }
-        const int tile = lo;
-        int l = 0;
-        while (l + 1 < a.grid.n_levels && a.tile_base[l + 1] <= tile) ++l;
-        const int tt = tile - a.tile_base[l];
+        const int64_t tile = lo;
+        const ScatterObj& o = sobj<kMany>(a, obj_of_tile<kMany>(a, tile));
+        const int lt = (int)(tile - o.tile_off);
+        const int l = level_of_tile(o, lt);
+        const int tt = lt - o.tile_base[l];
         const int64_t row0 = (int64_t)tt << kTileBits;
-        const int n_rows = (int)min((int64_t)kTileRows, a.level_rows[l] - row0);
+        const int n_rows = (int)min((int64_t)kTileRows, o.level_rows[l] - row0);
         const uint64_t k0 = chunk - a.chunk_start[tile];
         const uint64_t r_begin = a.tile_start[tile] + k0 * kChunk;
         const uint64_t r_end = min(r_begin + (uint64_t)kChunk, a.tile_start[tile + 1]);
@@ -350,16 +429,16 @@ __global__ __launch_bounds__(kReduceThreads) void k_scatter_reduce(ScatterArgs a
             }
         }
         __syncthreads();
-        float2* g = reinterpret_cast<float2*>(a.g_table) + ((int64_t)l << a.grid.log2_table) + row0;
+        float2* g = reinterpret_cast<float2*>(a.g_table + o.g_off) + ((int64_t)l << o.grid.log2_table) + row0;
         for (int i = threadIdx.x; i < n_rows; i += kReduceThreads) {
             const long long sx = (long long)acc[i], sy = (long long)acc[kTileRows + i];
             if (sx == 0 && sy == 0) continue;
             const float2 v = make_float2((float)ldexp((double)sx, -ex), (float)ldexp((double)sy, -ex));
             if (owner) {
-                float2 o = g[i];
-                o.x += v.x;
-                o.y += v.y;
-                g[i] = o;
+                float2 w = g[i];
+                w.x += v.x;
+                w.y += v.y;
+                g[i] = w;
             } else {
                 atomicAdd(&g[i].x, v.x);
                 atomicAdd(&g[i].y, v.y);
@@ -369,48 +448,67 @@ __global__ __launch_bounds__(kReduceThreads) void k_scatter_reduce(ScatterArgs a
     }
 }
 
+template <bool kMany>
+hipError_t scatter_impl(const ScatterArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scatter_count<kMany>, dim3((uint32_t)a.n_items), dim3(kPlaceThreads), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scatter_level_max<kMany>, dim3((uint32_t)a.n_levels_total), dim3(256), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scatter_scan_blocks<kMany>, dim3((uint32_t)a.n_tiles), dim3(kScanThreads), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scatter_scan_tiles<kMany>, dim3(1), dim3(kScanThreads), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const size_t place_lds = place_lds_bytes(a.tiles_max);
+    if (place_lds > 65536 &&
+        (e = hipFuncSetAttribute((const void*)k_scatter_place<kMany>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)place_lds)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_scatter_place<kMany>, dim3((uint32_t)a.n_items), dim3(kPlaceThreads), place_lds, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_scatter_reduce<kMany>, dim3((uint32_t)a.reduce_blocks), dim3(kReduceThreads), 0, s, a);
+    return hipGetLastError();
+}
+
 }  // namespace
 
-ScatterPlan scatter_plan(const GridInfo& g, int64_t n_s)
+ScatterObj scatter_obj(const GridInfo& g, int64_t n_s)
 {
-    ScatterPlan p{};
-    p.n_blocks = (int)((n_s + kSamplesPerBlock - 1) / kSamplesPerBlock);
-    p.n_tiles = 0;
+    ScatterObj o{};
+    o.grid = g;
+    o.n_s = n_s;
+    o.n_blocks = (int32_t)((n_s + kSamplesPerBlock - 1) / kSamplesPerBlock);
+    o.n_tiles = 0;
     const int64_t T = (int64_t)1 << g.log2_table;
     for (int l = 0; l < g.n_levels; ++l) {
         const int64_t side = (int64_t)g.res[l] + 1;
         const int64_t rows = ((g.dense_mask >> l) & 1u) ? side * side * side : T;
-        p.level_rows[l] = rows;
-        p.tiles[l] = (int)((rows + kTileRows - 1) / kTileRows);
-        p.tile_base[l] = p.n_tiles;
-        p.n_tiles += p.tiles[l];
+        o.level_rows[l] = rows;
+        o.tiles[l] = (int32_t)((rows + kTileRows - 1) / kTileRows);
+        o.tile_base[l] = o.n_tiles;
+        o.n_tiles += o.tiles[l];
     }
-    p.max_records = n_s * g.n_levels * 8;
-    return p;
+    return o;
 }
+
+int64_t scatter_items(const ScatterObj& o) { return (int64_t)o.grid.n_levels * o.n_blocks; }
+
+int64_t scatter_records(const ScatterObj& o) { return o.n_s * o.grid.n_levels * 8; }
 
 int scatter_max_tiles_per_level() { return kMaxTilesPerLevel; }
 
+int scatter_tiles_max(const ScatterObj& o)
+{
+    int m = 1;
+    for (int l = 0; l < o.grid.n_levels; ++l) m = o.tiles[l] > m ? o.tiles[l] : m;
+    return m;
+}
+
 hipError_t launch_scatter(const ScatterArgs& a, hipStream_t s)
 {
-    if (a.n_s == 0) return hipSuccess;
-    const dim3 grid((uint32_t)a.n_blocks, (uint32_t)a.grid.n_levels);
-    hipLaunchKernelGGL(k_scatter_count, grid, dim3(kPlaceThreads), 0, s, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scatter_scan_blocks, dim3((uint32_t)a.n_tiles), dim3(kScanThreads), 0, s, a);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scatter_scan_tiles, dim3(1), dim3(kScanThreads), 0, s, a);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    const size_t place_lds = place_lds_bytes(a.tiles_max);
-    if (place_lds > 65536 &&
-        (e = hipFuncSetAttribute((const void*)k_scatter_place, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)place_lds)) != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k_scatter_place, grid, dim3(kPlaceThreads), place_lds, s, a);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_scatter_reduce, dim3((uint32_t)a.reduce_blocks), dim3(kReduceThreads), 0, s, a);
-    return hipGetLastError();
+    if (a.n_items == 0) return hipSuccess;
+    return a.n_obj == 1 && a.objs == nullptr ? scatter_impl<false>(a, s) : scatter_impl<true>(a, s);
 }
 
 }  // namespace prenom

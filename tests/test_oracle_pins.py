@@ -481,6 +481,62 @@ def test_p11_gradients_match_central_differences(loss_mode):
     assert checked > 0.9 * len(coords), (checked, kinks)
 
 
+def test_p11_prior_scene_full_architecture_central_differences():
+    """The gradient check at the prior workload's architecture (16 levels x
+    2^19, MLP 64 x 2) on its scene: colour MSE + 0.1 depth MSE with depth
+    targets carrying 1 cm Gaussian noise; central differences of the FP64
+    forward on 64 random touched hash entries and every one of the 6400 MLP
+    weights, over 8 rays (4 meeting the object, 4 not).  The step is
+    h = 1e-3; where a ReLU changes side within +-h (the loss has a kink
+    there), h = 1e-4 and then 1e-5 are tried.  Parameters are perturbed in
+    place, so no copy of the 16.8 M-entry array is made per coordinate."""
+    from synth.arch import ARCH_LARGE
+    from synth.workloads import LossSpec, prior_batch, prior_world
+    arch = ARCH_LARGE
+    w = prior_world(seed=1, pool_stride=9)
+    b = prior_batch(w, 512, step=77, depth_noise=0.01, loss=LossSpec(lambda_d=0.1))
+    pick = np.concatenate([np.nonzero(b.mask)[0][:4], np.nonzero(b.mask == 0)[0][:4]])
+    s = b.sample
+    r = orc.sample(b.rays_o[pick], b.rays_d[pick], b.xi[pick], n_coarse=s.n_coarse, n_fine=s.n_fine,
+                   include_coarse=s.include_coarse, uniform_only=False, eps=s.eps, near=s.near, far=s.far,
+                   world_to_obj=b.world_to_obj, prior=b.prior)
+    geo = (r["ray_obj"].astype(np.float32), r["t"].astype(np.float32), r["dt"].astype(np.float32), r["flags"])
+    params = init_params(arch, 3)
+    rng = np.random.default_rng(15)
+    params[:arch.n_table_params] = rng.uniform(-0.3, 0.3, arch.n_table_params).astype(np.float32)
+    kw = dict(tgt_rgb=b.tgt_rgb[pick], tgt_depth=b.tgt_depth[pick], mask=b.mask[pick], lambda_d=np.float32(0.1))
+    g = orc.render_bwd(arch, params, *geo, **kw)
+    sig0 = orc.render_fwd(arch, params, *geo, want_relu_signature=True, **kw)["relu_signature"]
+    nt = arch.n_table_params
+    touched = np.nonzero(g[:nt])[0]
+    coords = list(rng.choice(touched, size=64, replace=False)) + list(range(nt, arch.n_params))
+    gmax = np.abs(g).max()
+
+    def central(i, h):
+        v = params[i]
+        out = []
+        for sgn in (1.0, -1.0):
+            params[i] = np.float32(v + sgn * h)
+            x = float(params[i])
+            o = orc.render_fwd(arch, params, *geo, want_relu_signature=True, **kw)
+            out.append((x, o["loss"], np.array_equal(o["relu_signature"], sig0)))
+        params[i] = v
+        (xp, lp, okp), (xm, lm, okm) = out
+        return (lp - lm) / (xp - xm) if okp and okm else None
+
+    checked, by_h = 0, {1e-3: 0, 1e-4: 0, 1e-5: 0}
+    for i in coords:
+        for h in (1e-3, 1e-4, 1e-5):
+            fd = central(i, h)
+            if fd is not None:
+                assert abs(fd - g[i]) <= 1e-4 * gmax + 1e-9, (i, h, fd, g[i])
+                checked += 1
+                by_h[h] += 1
+                break
+    assert by_h[1e-3] > 0.3 * len(coords), by_h
+    assert checked >= 0.95 * len(coords), (checked, by_h)
+
+
 def test_p11_upstream_gradient_mode_is_vjp():
     """With upstream d_rgb / d_depth the backward is the vector-Jacobian
     product of (rgb, depth): compare with FD of sum(d_rgb*rgb + d_depth*depth)."""
