@@ -10,7 +10,7 @@ Workloads (--workload):
           prenom_adam_step on resident inputs.
   batch24 24 objects trained together (own scene, prior, pose, log-uniform
           ray count in [1k, 64k], architecture drawn from L {8,12,16},
-          T 2^14..2^19, W {32,64}, D {1,2}), FP32, one launch per phase,
+          T 2^14..2^19, W {32,64,128}, D {1,2}), FP32, one launch per phase,
           the step captured in a HIP graph, MLP tiles from the autotuner;
           also timed: the same objects as 24 single-object steps in turn.
   batch48 48 objects, 2^20 rays in all, MLP in BF16 (--mlp-dtype) on the

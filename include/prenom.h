@@ -66,7 +66,7 @@ enum {
  * PRENOM_BF16 / PRENOM_F16 operands with FP32 accumulation; weights stay FP32
  * masters).  table_dtype: PRENOM_F32, or PRENOM_F16 when the forward gathers
  * read the FP16 copy model->table_lp (gradients accumulate in FP32 always).
- * Supported: n_features = 2; n_levels in {8, 12, 16}; mlp_width in {32, 64};
+ * Supported: n_features = 2; n_levels in {8, 12, 16}; mlp_width in {32, 64, 128};
  * mlp_hidden in {1, 2}; log2_table in [10, 24]; 2 <= N_l < 2^20. */
 typedef struct prenom_arch {
     int32_t n_levels;

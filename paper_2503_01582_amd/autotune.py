@@ -147,7 +147,7 @@ def tiles_for(arches: Iterable, path: Optional[str] = None) -> List[dict]:
 def all_shapes(dtypes=("fp32",)):
     from synth.arch import Arch
     return [Arch(n_levels=L, log2_table=14, width=W, hidden=D, mlp_dtype=dt)
-            for dt in dtypes for L in (8, 12, 16) for W in (32, 64) for D in (1, 2)]
+            for dt in dtypes for L in (8, 12, 16) for W in (32, 64, 128) for D in (1, 2)]
 
 
 def main():

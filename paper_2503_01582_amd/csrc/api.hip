@@ -105,16 +105,17 @@ MlpShape mlp_shape(const prenom_arch* a)
     return MlpShape{a->n_levels * a->n_features, a->mlp_width, a->mlp_hidden, a->mlp_dtype};
 }
 
-hipError_t mlp_fwd_any(const MlpShape& m, const float* w, const float* y, int64_t n_s, float* sc, hipStream_t s)
+hipError_t mlp_fwd_any(const MlpShape& m, const float* w, const float* y, int64_t n_s, float* sc, float* act,
+                       hipStream_t s)
 {
-    return m.dtype == PRENOM_F32 ? launch_mlp_fwd(m, w, y, n_s, sc, s) : launch_mlp_fwd_lp(m, w, y, n_s, sc, s);
+    return m.dtype == PRENOM_F32 ? launch_mlp_fwd(m, w, y, n_s, sc, act, s) : launch_mlp_fwd_lp(m, w, y, n_s, sc, act, s);
 }
 
-hipError_t mlp_bwd_any(const MlpShape& m, const float* w, const float* y, const float* dout, int64_t n_s, float* dy,
-                       float* partial, hipStream_t s)
+hipError_t mlp_bwd_any(const MlpShape& m, const float* w, const float* y, const float* dout, const float* sc,
+                       int64_t n_s, float* dy, float* partial, float* act, hipStream_t s)
 {
-    return m.dtype == PRENOM_F32 ? launch_mlp_bwd(m, w, y, dout, n_s, dy, partial, s)
-                                 : launch_mlp_bwd_lp(m, w, y, dout, n_s, dy, partial, s);
+    return m.dtype == PRENOM_F32 ? launch_mlp_bwd(m, w, y, dout, sc, n_s, dy, partial, act, s)
+                                 : launch_mlp_bwd_lp(m, w, y, dout, sc, n_s, dy, partial, act, s);
 }
 
 prenom_status check_supported(const prenom_arch* a)
@@ -190,7 +191,7 @@ using namespace prenom::host;
 
 
 struct WsLayout {
-    size_t y, sc, dout, dy, ray_state, loss_partial, mlp_partial;
+    size_t y, sc, dout, dy, ray_state, loss_partial, mlp_partial, act;
     size_t counts, block_max, level_max, tile_exp, tile_total, tile_start, chunk_start, work_counter, keys, vals, total;
     int n_loss_blocks, n_mlp_slots;
     ScatterObj plan;
@@ -217,6 +218,8 @@ WsLayout ws_layout(const prenom_arch* a, int64_t n_rays, int32_t S)
     w.n_mlp_slots = mlp_bwd_waves((int64_t)n_s);
     w.mlp_partial = off;
     off = align_up(off + (size_t)w.n_mlp_slots * (size_t)mlp_params(a) * sizeof(float));
+    w.act = off;
+    off = align_up(off + (size_t)mlp_act_floats(mlp_shape(a), (int64_t)n_s) * sizeof(float));
     w.plan = scatter_obj(grid_info(a), (int64_t)n_s);
     const size_t nt = (size_t)w.plan.n_tiles;
     w.counts = off;
@@ -353,7 +356,7 @@ prenom_status prenom_render_fwd(const prenom_model* model, const prenom_render_c
     PRENOM_LAUNCH("k_encode_fwd", s,
                   launch_encode_samples(g, model->params, tlp, ray_obj, t, n_rays, cfg->n_samples, y, s));
     const MlpShape m = mlp_shape(a);
-    PRENOM_LAUNCH("k_mlp_fwd", s, mlp_fwd_any(m, model->params + table_params(a), y, n_s, sc, s));
+    PRENOM_LAUNCH("k_mlp_fwd", s, mlp_fwd_any(m, model->params + table_params(a), y, n_s, sc, at<float>(workspace, w.act), s));
     CompositeArgs c{};
     c.n_rays = n_rays;
     c.S = cfg->n_samples;
@@ -403,7 +406,7 @@ prenom_status prenom_render_bwd(const prenom_model* model, const prenom_render_c
         PRENOM_LAUNCH("k_encode_fwd", s, launch_encode_samples(grid_info(a), model->params, tlp, ray_obj, t, n_rays,
                                                                cfg->n_samples, y, s));
         PRENOM_LAUNCH("k_mlp_fwd", s, mlp_fwd_any(m, model->params + table_params(a), y, n_s,
-                                                  at<float>(workspace, w.sc), s));
+                                                  at<float>(workspace, w.sc), at<float>(workspace, w.act), s));
         CompositeArgs f{};
         f.n_rays = n_rays;
         f.S = cfg->n_samples;
@@ -439,8 +442,8 @@ prenom_status prenom_render_bwd(const prenom_model* model, const prenom_render_c
     float* partial = at<float>(workspace, w.mlp_partial);
     float* dy = at<float>(workspace, w.dy);
     PRENOM_LAUNCH("k_mlp_bwd", s,
-                  mlp_bwd_any(m, model->params + table_params(a), at<float>(workspace, w.y), c.dout, n_s, dy,
-                              partial, s));
+                  mlp_bwd_any(m, model->params + table_params(a), at<float>(workspace, w.y), c.dout,
+                              at<float>(workspace, w.sc), n_s, dy, partial, at<float>(workspace, w.act), s));
     if (n_s > 0)
         PRENOM_LAUNCH("k_reduce_partials", s,
                       launch_reduce_partials(partial, w.n_mlp_slots, mlp_params(a), model->grads + table_params(a), s));

@@ -46,12 +46,12 @@ struct Plan {
     std::vector<MlpWork> fwd, bwd;
     std::vector<Group> groups;
     int64_t n_rays = 0, n_params = 0, n_mlp_total = 0, enc_blocks = 0, n_tiles = 0, n_items = 0, records = 0;
-    int64_t y_floats = 0, partial_floats = 0, counts = 0, bmax = 0;
+    int64_t y_floats = 0, partial_floats = 0, counts = 0, bmax = 0, act_floats = 0;
     int32_t n_levels_total = 0, tiles_max = 1;
     bool any_f16_table = false;
     // workspace offsets (bytes)
     size_t o_dev, o_sc, o_red, o_fwd, o_bwd;
-    size_t y, sc_out, dout, dy, ray_state, ray_loss, partial, cnt, block_max, level_max, tile_exp, tile_total,
+    size_t y, sc_out, dout, dy, ray_state, ray_loss, partial, act, cnt, block_max, level_max, tile_exp, tile_total,
         tile_start, chunk_start, work_counter, keys, vals, total;
     uint64_t fingerprint = 0;
 };
@@ -201,7 +201,7 @@ prenom_status build_plan(const prenom_batch* b, int32_t S, Plan& p)
         tiles_for(b, m, g.fwd_tiles, g.bwd_tiles);
         p.groups.push_back(g);
     }
-    int64_t partial = 0;
+    int64_t partial = 0, act = 0;
     for (Group& g : p.groups) {
         g.fwd_first = (int64_t)p.fwd.size();
         g.bwd_first = (int64_t)p.bwd.size();
@@ -218,6 +218,8 @@ prenom_status build_plan(const prenom_batch* b, int32_t S, Plan& p)
             w.y_off = p.dev[i].y_off;
             w.s_off = p.dev[i].ray_begin * S;
             w.n_s = n_s;
+            w.a_off = act;
+            act += mlp_act_floats(m, n_s);
             for (int64_t t0 = 0; t0 < n_t; t0 += g.fwd_tiles) {
                 w.tile_begin = t0;
                 w.tile_end = t0 + g.fwd_tiles < n_t ? t0 + g.fwd_tiles : n_t;
@@ -241,6 +243,7 @@ prenom_status build_plan(const prenom_batch* b, int32_t S, Plan& p)
             return fail(PRENOM_ERR_SHAPE, "MLP grid too large");
     }
     p.partial_floats = partial;
+    p.act_floats = act;
     for (int i = 0; i < b->n_tiles; ++i) h = fnv(h, &b->tiles[i], sizeof b->tiles[i]);
     p.fingerprint = h;
 
@@ -264,6 +267,7 @@ prenom_status build_plan(const prenom_batch* b, int32_t S, Plan& p)
     p.ray_state = take(sizeof(float) * 8 * (size_t)p.n_rays);
     p.ray_loss = take(sizeof(double) * (size_t)p.n_rays);
     p.partial = take(sizeof(float) * (size_t)p.partial_floats);
+    p.act = take(sizeof(float) * (size_t)p.act_floats);
     p.cnt = take(sizeof(uint32_t) * (size_t)p.counts);
     p.block_max = take(sizeof(float) * (size_t)p.bmax);
     p.level_max = take(sizeof(float) * (size_t)p.n_levels_total);
@@ -346,8 +350,9 @@ prenom_status fwd_features(const prenom_batch* b, const Plan& p, const float* ra
         float* sc = at<float>(ws, p.sc_out);
         PRENOM_LAUNCH("k_mlp_fwd", s,
                       g.shape.dtype == PRENOM_F32
-                          ? launch_mlp_fwd_batch(g.shape, work, (int)g.n_fwd, b->params, y, sc, s)
-                          : launch_mlp_fwd_lp_batch(g.shape, work, (int)g.n_fwd, b->params, y, sc, s));
+                          ? launch_mlp_fwd_batch(g.shape, work, (int)g.n_fwd, b->params, y, sc, at<float>(ws, p.act), s)
+                          : launch_mlp_fwd_lp_batch(g.shape, work, (int)g.n_fwd, b->params, y, sc, at<float>(ws, p.act),
+                                                    s));
     }
     return PRENOM_OK;
 }
@@ -545,10 +550,10 @@ prenom_status prenom_batch_render_bwd(const prenom_batch* batch, const prenom_re
         float* dy = at<float>(workspace, p.dy);
         PRENOM_LAUNCH("k_mlp_bwd", s,
                       g.shape.dtype == PRENOM_F32
-                          ? launch_mlp_bwd_batch(g.shape, work, (int)g.n_bwd, batch->params, y, c.dout, dy,
-                                                 partial + g.partial_off, n_mlp, s)
-                          : launch_mlp_bwd_lp_batch(g.shape, work, (int)g.n_bwd, batch->params, y, c.dout, dy,
-                                                    partial + g.partial_off, n_mlp, s));
+                          ? launch_mlp_bwd_batch(g.shape, work, (int)g.n_bwd, batch->params, y, c.dout, c.sc, dy,
+                                                 partial + g.partial_off, n_mlp, at<float>(workspace, p.act), s)
+                          : launch_mlp_bwd_lp_batch(g.shape, work, (int)g.n_bwd, batch->params, y, c.dout, c.sc, dy,
+                                                    partial + g.partial_off, n_mlp, at<float>(workspace, p.act), s));
     }
     PRENOM_LAUNCH("k_reduce_partials", s,
                   launch_reduce_partials_batch(at<const MlpRed>(workspace, p.o_red), p.n_obj, p.n_mlp_total, partial,

@@ -39,9 +39,10 @@ int device_cus();  // compute units of the current device
 prenom_status check_arch(const prenom_arch* a);
 prenom_status check_supported(const prenom_arch* a);
 MlpShape mlp_shape(const prenom_arch* a);
-hipError_t mlp_fwd_any(const MlpShape& m, const float* w, const float* y, int64_t n_s, float* sc, hipStream_t s);
-hipError_t mlp_bwd_any(const MlpShape& m, const float* w, const float* y, const float* dout, int64_t n_s, float* dy,
-                       float* partial, hipStream_t s);
+hipError_t mlp_fwd_any(const MlpShape& m, const float* w, const float* y, int64_t n_s, float* sc, float* act,
+                       hipStream_t s);
+hipError_t mlp_bwd_any(const MlpShape& m, const float* w, const float* y, const float* dout, const float* sc,
+                       int64_t n_s, float* dy, float* partial, float* act, hipStream_t s);
 int64_t table_params(const prenom_arch* a);
 int64_t mlp_params(const prenom_arch* a);
 int64_t mlp_params_of(const MlpShape& m);

@@ -211,30 +211,42 @@ bool mlp_supported(const MlpShape& m);
 // One block's share of a batched MLP launch: tiles [tile_begin, tile_end) of
 // one object.  w_off (floats) locates the object's MLP weights in the batch
 // parameters, y_off (floats) its features (level-major [L][n_s][2]), s_off
-// (samples) its first sample in the per-sample arrays.
+// (samples) its first sample in the per-sample arrays, a_off (floats) its
+// stored activations and deltas when the MLP is 128 wide.
 struct MlpWork {
     int64_t w_off, y_off, s_off, n_s;
     int64_t tile_begin, tile_end;
+    int64_t a_off;
 };
+
+// The 128-wide MLP stores its hidden activations in the forward and runs its
+// backward as a chain kernel (deltas, dy) and a weight-gradient kernel; the
+// two buffers hold act[D][n_s][W] and delta[D][n_s][W] FP32.
+constexpr int kWideWidth = 128;
+inline int64_t mlp_act_floats(const MlpShape& m, int64_t n_s)
+{
+    return m.width >= kWideWidth ? 2 * (int64_t)m.hidden * n_s * m.width : 0;
+}
 int mlp_bwd_waves(int64_t n_samples);  // partial-gradient slots (one per block) the bwd writes
-hipError_t launch_mlp_fwd(const MlpShape& m, const float* w, const float* y, int64_t n_s, float* sc,
+// act: activation/delta buffer of mlp_act_floats floats (128-wide MLPs; else unused)
+hipError_t launch_mlp_fwd(const MlpShape& m, const float* w, const float* y, int64_t n_s, float* sc, float* act,
                           hipStream_t s);
-hipError_t launch_mlp_bwd(const MlpShape& m, const float* w, const float* y, const float* dout,
-                          int64_t n_s, float* dy, float* partial, hipStream_t s);
-hipError_t launch_mlp_fwd_lp(const MlpShape& m, const float* w, const float* y, int64_t n_s, float* sc,
+hipError_t launch_mlp_bwd(const MlpShape& m, const float* w, const float* y, const float* dout, const float* sc,
+                          int64_t n_s, float* dy, float* partial, float* act, hipStream_t s);
+hipError_t launch_mlp_fwd_lp(const MlpShape& m, const float* w, const float* y, int64_t n_s, float* sc, float* act,
                              hipStream_t s);
-hipError_t launch_mlp_bwd_lp(const MlpShape& m, const float* w, const float* y, const float* dout, int64_t n_s,
-                             float* dy, float* partial, hipStream_t s);
+hipError_t launch_mlp_bwd_lp(const MlpShape& m, const float* w, const float* y, const float* dout, const float* sc,
+                             int64_t n_s, float* dy, float* partial, float* act, hipStream_t s);
 hipError_t launch_mlp_fwd_batch(const MlpShape& m, const MlpWork* work, int n_blocks, const float* params,
-                                const float* y, float* sc, hipStream_t s);
+                                const float* y, float* sc, float* act, hipStream_t s);
 hipError_t launch_mlp_bwd_batch(const MlpShape& m, const MlpWork* work, int n_blocks, const float* params,
-                                const float* y, const float* dout, float* dy, float* partial, int64_t slot_stride,
-                                hipStream_t s);
+                                const float* y, const float* dout, const float* sc, float* dy, float* partial,
+                                int64_t slot_stride, float* act, hipStream_t s);
 hipError_t launch_mlp_fwd_lp_batch(const MlpShape& m, const MlpWork* work, int n_blocks, const float* params,
-                                   const float* y, float* sc, hipStream_t s);
+                                   const float* y, float* sc, float* act, hipStream_t s);
 hipError_t launch_mlp_bwd_lp_batch(const MlpShape& m, const MlpWork* work, int n_blocks, const float* params,
-                                   const float* y, const float* dout, float* dy, float* partial, int64_t slot_stride,
-                                   hipStream_t s);
+                                   const float* y, const float* dout, const float* sc, float* dy, float* partial,
+                                   int64_t slot_stride, float* act, hipStream_t s);
 hipError_t launch_reduce_partials(const float* partial, int n_slots, int64_t n_mlp, float* g_mlp,
                                   hipStream_t s);
 

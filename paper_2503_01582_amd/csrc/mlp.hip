@@ -53,13 +53,13 @@ struct Net {
     static_assert(IN % 4 == 0 && W % 16 == 0 && D >= 1, "shape");
 };
 
-// Builds the weight fragments of one block in LDS.
+// Builds weight fragments f0 .. f0 + n_frag - 1 of one block in LDS (at 0).
 template <int IN, int W, int D>
-__device__ void load_fragments(const float* __restrict__ w, float* __restrict__ frag, int n_frag)
+__device__ void load_fragments(const float* __restrict__ w, float* __restrict__ frag, int n_frag, int f0 = 0)
 {
     using N = Net<IN, W, D>;
     for (int idx = threadIdx.x; idx < n_frag * 64; idx += blockDim.x) {
-        const int f = idx >> 6, l = idx & 63, q = l >> 4, j = l & 15;
+        const int f = f0 + (idx >> 6), l = idx & 63, q = l >> 4, j = l & 15;
         float v = 0.0f;
         if (f < N::FH) {  // W1[16 to + j][4 kk + q]
             const int to = f / N::KT1, kk = f % N::KT1;
@@ -100,6 +100,26 @@ __device__ __forceinline__ void load_inputs(const float* __restrict__ y, int64_t
     }
 }
 
+// acc[to] = sum_ks A(fragment f0 + to * stride + ks) x B_ks over one layer,
+// K-steps outer and output tiles inner: OT independent accumulators
+// interleave, hiding MFMA latency when one wave runs per SIMD (the widest
+// MLP).  B_ks = b[ks >> 2][ks & 3] (a previous layer's output registers).
+template <int OT, int KS>
+__device__ __forceinline__ void layer_ks_outer(const float* __restrict__ frag, int lane, int f0, int stride,
+                                               const floatx4 (&b)[KS / 4], floatx4 (&acc)[OT])
+{
+#pragma unroll
+    for (int to = 0; to < OT; ++to) acc[to] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+#pragma unroll
+        for (int to = 0; to < OT; ++to) acc[to] = mfma4(frag[(f0 + to * stride + ks) * 64 + lane], b[ks >> 2][ks & 3], acc[to]);
+        // keep the scheduler from hoisting the fragment loads of the whole
+        // layer (it would hold hundreds of them in registers)
+        if ((ks & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 // Forward through the hidden layers and the head; hs[k] = output of layer k.
 template <int IN, int W, int D>
 __device__ __forceinline__ void mlp_chain(const float* __restrict__ frag, int lane,
@@ -107,23 +127,41 @@ __device__ __forceinline__ void mlp_chain(const float* __restrict__ frag, int la
                                           floatx4 (&hs)[D][Net<IN, W, D>::OT], floatx4& o)
 {
     using N = Net<IN, W, D>;
+    if constexpr (W >= kWideWidth) {
+        floatx4 acc[N::OT];
 #pragma unroll
-    for (int to = 0; to < N::OT; ++to) {
-        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int to = 0; to < N::OT; ++to) acc[to] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int kk = 0; kk < N::KT1; ++kk) acc = mfma4(frag[(N::F1 + to * N::KT1 + kk) * 64 + lane], yb[kk], acc);
-        hs[0][to] = relu4(acc);
-    }
+        for (int kk = 0; kk < N::KT1; ++kk)
 #pragma unroll
-    for (int k = 1; k < D; ++k) {
+            for (int to = 0; to < N::OT; ++to) acc[to] = mfma4(frag[(N::F1 + to * N::KT1 + kk) * 64 + lane], yb[kk], acc[to]);
+#pragma unroll
+        for (int to = 0; to < N::OT; ++to) hs[0][to] = relu4(acc[to]);
+#pragma unroll
+        for (int k = 1; k < D; ++k) {
+            layer_ks_outer<N::OT, N::KTH>(frag, lane, N::FH + (k - 1) * N::OT * N::KTH, N::KTH, hs[k - 1], acc);
+#pragma unroll
+            for (int to = 0; to < N::OT; ++to) hs[k][to] = relu4(acc[to]);
+        }
+    } else {
 #pragma unroll
         for (int to = 0; to < N::OT; ++to) {
             floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int ks = 0; ks < N::KTH; ++ks)
-                acc = mfma4(frag[(N::FH + ((k - 1) * N::OT + to) * N::KTH + ks) * 64 + lane], hs[k - 1][ks >> 2][ks & 3],
-                            acc);
-            hs[k][to] = relu4(acc);
+            for (int kk = 0; kk < N::KT1; ++kk) acc = mfma4(frag[(N::F1 + to * N::KT1 + kk) * 64 + lane], yb[kk], acc);
+            hs[0][to] = relu4(acc);
+        }
+#pragma unroll
+        for (int k = 1; k < D; ++k) {
+#pragma unroll
+            for (int to = 0; to < N::OT; ++to) {
+                floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int ks = 0; ks < N::KTH; ++ks)
+                    acc = mfma4(frag[(N::FH + ((k - 1) * N::OT + to) * N::KTH + ks) * 64 + lane], hs[k - 1][ks >> 2][ks & 3],
+                                acc);
+                hs[k][to] = relu4(acc);
+            }
         }
     }
     o = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -132,10 +170,12 @@ __device__ __forceinline__ void mlp_chain(const float* __restrict__ frag, int la
 }
 
 // Forward over the 16-sample tiles tile0, tile0 + step, ... < end of one
-// object whose fragments are in LDS.
+// object whose fragments are in LDS.  act (or null): the hidden activations
+// are also stored, h_k of sample s at act[(k n_s + s) W ...] (rows of W floats).
 template <int IN, int W, int D>
 __device__ __forceinline__ void mlp_fwd_tiles(const float* __restrict__ frag, const float* __restrict__ y, int64_t n_s,
-                                              float4* __restrict__ sc, int64_t tile0, int64_t end, int64_t step)
+                                              float4* __restrict__ sc, float* __restrict__ act, int64_t tile0,
+                                              int64_t end, int64_t step)
 {
     using N = Net<IN, W, D>;
     const int lane = threadIdx.x & 63, q = lane >> 4, j = lane & 15;
@@ -148,36 +188,45 @@ __device__ __forceinline__ void mlp_fwd_tiles(const float* __restrict__ frag, co
         floatx4 o;
         mlp_chain<IN, W, D>(frag, lane, yb, hs, o);
         if (q == 0 && valid) sc[s] = make_float4(__expf(o[0]), sigmoidf_(o[1]), sigmoidf_(o[2]), sigmoidf_(o[3]));
+        if (act && valid) {
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+#pragma unroll
+                for (int to = 0; to < N::OT; ++to)
+                    *reinterpret_cast<floatx4*>(act + ((int64_t)k * n_s + s) * W + 16 * to + 4 * q) = hs[k][to];
+        }
     }
 }
 
 template <int IN, int W, int D>
 __global__ __launch_bounds__(256) void k_mlp_fwd(const float* __restrict__ w, const float* __restrict__ y,
-                                                 int64_t n_s, float4* __restrict__ sc)
+                                                 int64_t n_s, float4* __restrict__ sc, float* __restrict__ act)
 {
     using N = Net<IN, W, D>;
-    __shared__ float frag[N::N_FWD * 64];
+    extern __shared__ float frag[];
     load_fragments<IN, W, D>(w, frag, N::N_FWD);
     __syncthreads();
     const int64_t wave0 = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
     const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x / 64);
-    mlp_fwd_tiles<IN, W, D>(frag, y, n_s, sc, wave0, (n_s + 15) / 16, n_waves);
+    mlp_fwd_tiles<IN, W, D>(frag, y, n_s, sc, act, wave0, (n_s + 15) / 16, n_waves);
 }
 
 // Batched forward: block b works on tiles [tile_begin, tile_end) of object
 // work[b].obj, whose weights start at w_off[obj] and whose features and head
-// outputs live at y_off / s_off.
+// outputs live at y_off / s_off (activations at a_off when act is given).
 template <int IN, int W, int D>
 __global__ __launch_bounds__(256) void k_mlp_fwd_batch(const MlpWork* __restrict__ work, const float* __restrict__ params,
-                                                       const float* __restrict__ y, float4* __restrict__ sc)
+                                                       const float* __restrict__ y, float4* __restrict__ sc,
+                                                       float* __restrict__ act)
 {
     using N = Net<IN, W, D>;
-    __shared__ float frag[N::N_FWD * 64];
+    extern __shared__ float frag[];
     const MlpWork wk = work[blockIdx.x];
     load_fragments<IN, W, D>(params + wk.w_off, frag, N::N_FWD);
     __syncthreads();
     const int wave = threadIdx.x >> 6, n_waves = blockDim.x / 64;
-    mlp_fwd_tiles<IN, W, D>(frag, y + wk.y_off, wk.n_s, sc + wk.s_off, wk.tile_begin + wave, wk.tile_end, n_waves);
+    mlp_fwd_tiles<IN, W, D>(frag, y + wk.y_off, wk.n_s, sc + wk.s_off, act ? act + wk.a_off : nullptr,
+                            wk.tile_begin + wave, wk.tile_end, n_waves);
 }
 
 template <int IN, int W, int D>
@@ -388,6 +437,228 @@ __global__ void k_reduce_partials(const float* __restrict__ partial, int n_slots
     g[p] += (float)acc;
 }
 
+// ---------------------------------------------------------------- 128 wide
+// One wave cannot hold the 128 x 128 weight gradient in registers (256 VGPRs
+// per lane) beside the chain, and the forward plus transposed fragments
+// (2 x 88 KB) exceed LDS.  So the widest MLP stores its hidden activations in
+// the forward and runs its backward as two kernels:
+//   chain : transposed fragments only; ReLU masks from the stored
+//           activations, head adjoint from the stored head outputs; writes
+//           every layer's delta and dy;
+//   dW    : dW_k = sum_s delta_k(s) h_{k-1}(s)^T over the block's samples on
+//           MFMA, the 4 waves splitting the output rows; one partial per block.
+constexpr int kWideWaves = 4;
+
+template <int IN, int W, int D>
+__device__ void mlp_chain_bwd_tiles(const float* __restrict__ bfrag, const float4* __restrict__ sc,
+                                    const float4* __restrict__ dout, const float* __restrict__ act,
+                                    float* __restrict__ dlt, int64_t n_s, float2* __restrict__ dy, int64_t tile0,
+                                    int64_t end, int64_t step)
+{
+    using N = Net<IN, W, D>;
+    constexpr int BO = 0, BH = N::BH - N::N_FWD, B1 = N::B1 - N::N_FWD;  // fragments rebased to the transposed set
+    const int lane = threadIdx.x & 63, q = lane >> 4, j = lane & 15;
+    for (int64_t tile = tile0; tile < end; tile += step) {
+        const int64_t s = tile * 16 + j;
+        const bool valid = s < n_s;
+        float dq0 = 0.0f, dq1 = 0.0f, dq2 = 0.0f, dq3 = 0.0f;
+        if (q == 0 && valid) {  // d sigma / d o0 = sigma, d c / d o = c (1 - c)
+            const float4 g = dout[s], v = sc[s];
+            dq0 = g.x * v.x;
+            dq1 = g.y * v.y * (1.0f - v.y);
+            dq2 = g.z * v.z * (1.0f - v.z);
+            dq3 = g.w * v.w * (1.0f - v.w);
+        }
+        const float v0 = __shfl(dq0, j), v1 = __shfl(dq1, j), v2 = __shfl(dq2, j), v3 = __shfl(dq3, j);
+        const float dqb = q == 0 ? v0 : (q == 1 ? v1 : (q == 2 ? v2 : v3));
+        floatx4 hk[N::OT], delta[N::OT];
+#pragma unroll
+        for (int to = 0; to < N::OT; ++to)
+            hk[to] = valid ? *reinterpret_cast<const floatx4*>(act + ((int64_t)(D - 1) * n_s + s) * W + 16 * to + 4 * q)
+                           : floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int to = 0; to < N::OT; ++to) {
+            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            acc = mfma4(bfrag[(BO + to) * 64 + lane], dqb, acc);
+            delta[to] = mask_pos(acc, hk[to]);
+            if (valid) *reinterpret_cast<floatx4*>(dlt + ((int64_t)(D - 1) * n_s + s) * W + 16 * to + 4 * q) = delta[to];
+        }
+#pragma unroll
+        for (int k = D - 1; k >= 1; --k) {
+#pragma unroll
+            for (int to = 0; to < N::OT; ++to)
+                hk[to] = valid ? *reinterpret_cast<const floatx4*>(act + ((int64_t)(k - 1) * n_s + s) * W + 16 * to + 4 * q)
+                               : floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            floatx4 nd[N::OT];
+            layer_ks_outer<N::OT, N::KTH>(bfrag, lane, BH + (k - 1) * N::OT * N::KTH, N::KTH, delta, nd);
+#pragma unroll
+            for (int to = 0; to < N::OT; ++to) {
+                delta[to] = mask_pos(nd[to], hk[to]);
+                if (valid) *reinterpret_cast<floatx4*>(dlt + ((int64_t)(k - 1) * n_s + s) * W + 16 * to + 4 * q) = delta[to];
+            }
+        }
+        floatx4 gy[N::IT];
+        layer_ks_outer<N::IT, N::KTH>(bfrag, lane, B1, N::KTH, delta, gy);
+#pragma unroll
+        for (int to = 0; to < N::IT; ++to) {
+            const floatx4 acc = gy[to];
+            const int f = 16 * to + 4 * q;
+            if (valid && f < IN) {
+                dy[(int64_t)(f >> 1) * n_s + s] = make_float2(acc[0], acc[1]);
+                dy[(int64_t)((f >> 1) + 1) * n_s + s] = make_float2(acc[2], acc[3]);
+            }
+        }
+    }
+}
+
+// Weight gradient over samples [s_begin, s_end) of one object: wave w owns
+// rows [16 RT w, 16 RT (w + 1)) of W_1 and the hidden matrices and columns
+// [16 RT w, 16 RT (w + 1)) of W_out, so the block's partial is written
+// without any merge.  MFMA K = 4 consecutive samples.
+template <int IN, int W, int D>
+__device__ void mlp_dw_range(const float* __restrict__ y, const float4* __restrict__ sc, const float4* __restrict__ dout,
+                             const float* __restrict__ act, const float* __restrict__ dlt, int64_t n_s,
+                             int64_t s_begin, int64_t s_end, float* __restrict__ dst)
+{
+    using N = Net<IN, W, D>;
+    constexpr int RT = N::OT / kWideWaves;
+    static_assert(N::OT % kWideWaves == 0, "rows per wave");
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, j = lane & 15;
+    floatx4 aH[D > 1 ? D - 1 : 1][RT][N::OT], a1[RT][N::IT], aO[RT];
+#pragma unroll
+    for (int a = 0; a < RT; ++a) {
+        aO[a] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int t = 0; t < N::IT; ++t) a1[a][t] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int k = 0; k < (D > 1 ? D - 1 : 1); ++k)
+#pragma unroll
+            for (int t = 0; t < N::OT; ++t) aH[k][a][t] = {0.0f, 0.0f, 0.0f, 0.0f};
+    }
+    for (int64_t s0 = s_begin; s0 < s_end; s0 += 4) {
+        const int64_t sk = s0 + q;
+        const bool ok = sk < s_end;
+        // W_out: A[i][k] = dO_i(sample s0 + k), rows i >= 4 zero; B = h_{D-1}
+        float dOi = 0.0f;
+        if (ok && j < 4) {
+            const float4 g = dout[sk], v = sc[sk];
+            dOi = j == 0 ? g.x * v.x : (j == 1 ? g.y * v.y * (1.0f - v.y)
+                                               : (j == 2 ? g.z * v.z * (1.0f - v.z) : g.w * v.w * (1.0f - v.w)));
+        }
+        const float* hl = act + ((int64_t)(D - 1) * n_s + sk) * W;
+#pragma unroll
+        for (int a = 0; a < RT; ++a) aO[a] = mfma4(dOi, ok ? hl[16 * (RT * wave + a) + j] : 0.0f, aO[a]);
+        // hidden layers: A = delta_k rows, B = h_{k-1}
+#pragma unroll
+        for (int k = 1; k < D; ++k) {
+            const float* dk = dlt + ((int64_t)k * n_s + sk) * W;
+            const float* hk = act + ((int64_t)(k - 1) * n_s + sk) * W;
+            float av[RT], bv[N::OT];
+#pragma unroll
+            for (int a = 0; a < RT; ++a) av[a] = ok ? dk[16 * (RT * wave + a) + j] : 0.0f;
+#pragma unroll
+            for (int t = 0; t < N::OT; ++t) bv[t] = ok ? hk[16 * t + j] : 0.0f;
+#pragma unroll
+            for (int a = 0; a < RT; ++a)
+#pragma unroll
+                for (int t = 0; t < N::OT; ++t) aH[k - 1][a][t] = mfma4(av[a], bv[t], aH[k - 1][a][t]);
+        }
+        // W_1: A = delta_0 rows, B = the input features (zero beyond IN)
+        {
+            const float* d0 = dlt + sk * W;
+            float av[RT], bv[N::IT];
+#pragma unroll
+            for (int a = 0; a < RT; ++a) av[a] = ok ? d0[16 * (RT * wave + a) + j] : 0.0f;
+#pragma unroll
+            for (int t = 0; t < N::IT; ++t) {
+                const int f = 16 * t + j;
+                bv[t] = (ok && f < IN) ? y[((int64_t)(f >> 1) * n_s + sk) * 2 + (f & 1)] : 0.0f;
+            }
+#pragma unroll
+            for (int a = 0; a < RT; ++a)
+#pragma unroll
+                for (int t = 0; t < N::IT; ++t) a1[a][t] = mfma4(av[a], bv[t], a1[a][t]);
+        }
+    }
+    // D layout: row 16 (RT w + a) + 4 q + r, column 16 t + j
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * (RT * wave + a) + 4 * q + r;
+#pragma unroll
+            for (int t = 0; t < N::IT; ++t) {
+                const int col = 16 * t + j;
+                if (col < IN) dst[N::OFF_W1 + row * IN + col] = a1[a][t][r];
+            }
+#pragma unroll
+            for (int k = 1; k < D; ++k)
+#pragma unroll
+                for (int t = 0; t < N::OT; ++t) dst[N::OFF_H + (k - 1) * W * W + row * W + 16 * t + j] = aH[k - 1][a][t][r];
+            if (q == 0) dst[N::OFF_OUT + r * W + 16 * (RT * wave + a) + j] = aO[a][r];
+        }
+}
+
+template <int IN, int W, int D>
+__global__ __launch_bounds__(256) void k_mlp_chain_bwd(const float* __restrict__ w, const float4* __restrict__ sc,
+                                                       const float4* __restrict__ dout, float* __restrict__ act,
+                                                       int64_t n_s, float2* __restrict__ dy)
+{
+    using N = Net<IN, W, D>;
+    extern __shared__ float frag[];
+    load_fragments<IN, W, D>(w, frag, N::N_ALL - N::N_FWD, N::N_FWD);
+    __syncthreads();
+    const int64_t wave0 = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    mlp_chain_bwd_tiles<IN, W, D>(frag, sc, dout, act, act + (int64_t)D * n_s * W, n_s, dy, wave0, (n_s + 15) / 16,
+                                  (int64_t)gridDim.x * (blockDim.x / 64));
+}
+
+template <int IN, int W, int D>
+__global__ __launch_bounds__(256) void k_mlp_chain_bwd_batch(const MlpWork* __restrict__ work,
+                                                             const float* __restrict__ params,
+                                                             const float4* __restrict__ sc,
+                                                             const float4* __restrict__ dout, float* __restrict__ act,
+                                                             float2* __restrict__ dy)
+{
+    using N = Net<IN, W, D>;
+    extern __shared__ float frag[];
+    const MlpWork wk = work[blockIdx.x];
+    load_fragments<IN, W, D>(params + wk.w_off, frag, N::N_ALL - N::N_FWD, N::N_FWD);
+    __syncthreads();
+    const float* a = act + wk.a_off;
+    mlp_chain_bwd_tiles<IN, W, D>(frag, sc + wk.s_off, dout + wk.s_off, a, act + wk.a_off + (int64_t)D * wk.n_s * W,
+                                  wk.n_s, dy + wk.y_off / 2, wk.tile_begin + (threadIdx.x >> 6), wk.tile_end,
+                                  blockDim.x / 64);
+}
+
+template <int IN, int W, int D>
+__global__ __launch_bounds__(64 * kWideWaves) void k_mlp_dw(const float* __restrict__ y, const float4* __restrict__ sc,
+                                                            const float4* __restrict__ dout,
+                                                            const float* __restrict__ act, int64_t n_s,
+                                                            int64_t tiles_per_block, float* __restrict__ partial)
+{
+    using N = Net<IN, W, D>;
+    const int64_t b = (int64_t)blockIdx.x * tiles_per_block * 16;
+    const int64_t e = min(b + tiles_per_block * 16, n_s);
+    mlp_dw_range<IN, W, D>(y, sc, dout, act, act + (int64_t)D * n_s * W, n_s, b, e,
+                           partial + (int64_t)blockIdx.x * N::N_PARAMS);
+}
+
+template <int IN, int W, int D>
+__global__ __launch_bounds__(64 * kWideWaves) void k_mlp_dw_batch(const MlpWork* __restrict__ work,
+                                                                  const float* __restrict__ y,
+                                                                  const float4* __restrict__ sc,
+                                                                  const float4* __restrict__ dout,
+                                                                  const float* __restrict__ act,
+                                                                  float* __restrict__ partial, int64_t slot_stride)
+{
+    const MlpWork wk = work[blockIdx.x];
+    const int64_t b = wk.tile_begin * 16, e = min(wk.tile_end * 16, wk.n_s);
+    const float* a = act + wk.a_off;
+    mlp_dw_range<IN, W, D>(y + wk.y_off, sc + wk.s_off, dout + wk.s_off, a, a + (int64_t)D * wk.n_s * W, wk.n_s, b, e,
+                           partial + (int64_t)blockIdx.x * slot_stride);
+}
+
 // Batch: thread per (object, MLP parameter); the object's partials summed in FP64.
 __global__ void k_reduce_partials_batch(const MlpRed* __restrict__ reds, int n_obj, int64_t n_total,
                                         const float* __restrict__ partial, float* __restrict__ g)
@@ -410,13 +681,36 @@ __global__ void k_reduce_partials_batch(const MlpRed* __restrict__ reds, int n_o
     g[r.g_off + p] += (float)acc;
 }
 
+template <class K>
+hipError_t set_lds(K kern, size_t bytes)
+{
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 template <int IN, int W, int D>
-hipError_t fwd_impl(const float* w, const float* y, int64_t n_s, float* sc, hipStream_t s)
+size_t fwd_lds_bytes()
+{
+    return sizeof(float) * (size_t)Net<IN, W, D>::N_FWD * 64;
+}
+
+template <int IN, int W, int D>
+size_t chain_bwd_lds_bytes()
+{
+    return sizeof(float) * (size_t)(Net<IN, W, D>::N_ALL - Net<IN, W, D>::N_FWD) * 64;
+}
+
+template <int IN, int W, int D>
+hipError_t fwd_impl(const float* w, const float* y, int64_t n_s, float* sc, float* act, hipStream_t s)
 {
     const int64_t n_tiles = (n_s + 15) / 16;
     int64_t blocks = (n_tiles + 3) / 4;
     blocks = blocks > 2048 ? 2048 : blocks;
-    hipLaunchKernelGGL((k_mlp_fwd<IN, W, D>), dim3((uint32_t)blocks), dim3(256), 0, s, w, y, n_s, (float4*)sc);
+    const size_t lds = fwd_lds_bytes<IN, W, D>();
+    hipError_t e = set_lds(k_mlp_fwd<IN, W, D>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_mlp_fwd<IN, W, D>), dim3((uint32_t)blocks), dim3(256), lds, s, w, y, n_s, (float4*)sc,
+                       W >= kWideWidth ? act : nullptr);
     return hipGetLastError();
 }
 
@@ -427,23 +721,77 @@ size_t bwd_lds_bytes()
 }
 
 template <int IN, int W, int D>
-hipError_t bwd_impl(const float* w, const float* y, const float* dout, int64_t n_s, float* dy, float* partial,
-                    hipStream_t s)
+hipError_t bwd_impl(const float* w, const float* y, const float* dout, const float* sc, int64_t n_s, float* dy,
+                    float* partial, float* act, hipStream_t s)
 {
-    const size_t lds = bwd_lds_bytes<IN, W, D>();
-    auto kern = k_mlp_bwd<IN, W, D>;
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if constexpr (W >= kWideWidth) {
+        const int64_t n_tiles = (n_s + 15) / 16;
+        int64_t blocks = (n_tiles + 3) / 4;
+        blocks = blocks > 2048 ? 2048 : blocks;
+        const size_t lds = chain_bwd_lds_bytes<IN, W, D>();
+        hipError_t e = set_lds(k_mlp_chain_bwd<IN, W, D>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_mlp_chain_bwd<IN, W, D>), dim3((uint32_t)blocks), dim3(256), lds, s, w,
+                           (const float4*)sc, (const float4*)dout, act, n_s, (float2*)dy);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const int nb = bwd_blocks(n_s);
+        const int64_t per = (n_tiles + nb - 1) / nb;
+        hipLaunchKernelGGL((k_mlp_dw<IN, W, D>), dim3((uint32_t)nb), dim3(64 * kWideWaves), 0, s, y,
+                           (const float4*)sc, (const float4*)dout, act, n_s, per, partial);
+        return hipGetLastError();
+    } else {
+        const size_t lds = bwd_lds_bytes<IN, W, D>();
+        auto kern = k_mlp_bwd<IN, W, D>;
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3((uint32_t)bwd_blocks(n_s)), dim3(64 * kBwdWaves), lds, s, w, y,
+                           (const float4*)dout, n_s, (float2*)dy, partial);
+        return hipGetLastError();
+    }
+}
+
+template <int IN, int W, int D>
+hipError_t fwd_batch_impl(const MlpWork* work, int n_blocks, const float* params, const float* y, float* sc, float* act,
+                          hipStream_t s)
+{
+    const size_t lds = fwd_lds_bytes<IN, W, D>();
+    hipError_t e = set_lds(k_mlp_fwd_batch<IN, W, D>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3((uint32_t)bwd_blocks(n_s)), dim3(64 * kBwdWaves), lds, s, w, y,
-                       (const float4*)dout, n_s, (float2*)dy, partial);
+    hipLaunchKernelGGL((k_mlp_fwd_batch<IN, W, D>), dim3((uint32_t)n_blocks), dim3(256), lds, s, work, params, y,
+                       (float4*)sc, W >= kWideWidth ? act : nullptr);
     return hipGetLastError();
+}
+
+template <int IN, int W, int D>
+hipError_t bwd_batch_impl(const MlpWork* work, int n_blocks, const float* params, const float* y, const float* dout,
+                          const float* sc, float* dy, float* partial, int64_t slot_stride, float* act, hipStream_t s)
+{
+    if constexpr (W >= kWideWidth) {
+        const size_t lds = chain_bwd_lds_bytes<IN, W, D>();
+        hipError_t e = set_lds(k_mlp_chain_bwd_batch<IN, W, D>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_mlp_chain_bwd_batch<IN, W, D>), dim3((uint32_t)n_blocks), dim3(256), lds, s, work,
+                           params, (const float4*)sc, (const float4*)dout, act, (float2*)dy);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_mlp_dw_batch<IN, W, D>), dim3((uint32_t)n_blocks), dim3(64 * kWideWaves), 0, s, work, y,
+                           (const float4*)sc, (const float4*)dout, act, partial, slot_stride);
+        return hipGetLastError();
+    } else {
+        const size_t lds = bwd_lds_bytes<IN, W, D>();
+        auto kern = k_mlp_bwd_batch<IN, W, D>;
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3((uint32_t)n_blocks), dim3(64 * kBwdWaves), lds, s, work, params, y,
+                           (const float4*)dout, (float2*)dy, partial, slot_stride);
+        return hipGetLastError();
+    }
 }
 
 }  // namespace
 
 bool mlp_supported(const MlpShape& m)
 {
-    return (m.width == 32 || m.width == 64) && (m.in_dim == 16 || m.in_dim == 24 || m.in_dim == 32) &&
+    return (m.width == 32 || m.width == 64 || m.width == 128) && (m.in_dim == 16 || m.in_dim == 24 || m.in_dim == 32) &&
            (m.hidden == 1 || m.hidden == 2);
 }
 
@@ -455,66 +803,64 @@ int mlp_bwd_waves(int64_t n_samples) { return bwd_blocks(n_samples); }
     X(16, 32, 2) \
     X(16, 64, 1) \
     X(16, 64, 2) \
+    X(16, 128, 1) \
+    X(16, 128, 2) \
     X(24, 32, 1) \
     X(24, 32, 2) \
     X(24, 64, 1) \
     X(24, 64, 2) \
+    X(24, 128, 1) \
+    X(24, 128, 2) \
     X(32, 32, 1) \
     X(32, 32, 2) \
     X(32, 64, 1) \
-    X(32, 64, 2)
+    X(32, 64, 2) \
+    X(32, 128, 1) \
+    X(32, 128, 2)
 
-hipError_t launch_mlp_fwd(const MlpShape& m, const float* w, const float* y, int64_t n_s, float* sc, hipStream_t s)
+hipError_t launch_mlp_fwd(const MlpShape& m, const float* w, const float* y, int64_t n_s, float* sc, float* act,
+                          hipStream_t s)
 {
     if (n_s == 0) return hipSuccess;
 #define X(I, Wd, Dp) \
-    if (m.in_dim == I && m.width == Wd && m.hidden == Dp) return fwd_impl<I, Wd, Dp>(w, y, n_s, sc, s);
+    if (m.in_dim == I && m.width == Wd && m.hidden == Dp) return fwd_impl<I, Wd, Dp>(w, y, n_s, sc, act, s);
     PRENOM_FOR_EACH_MLP(X)
 #undef X
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_mlp_bwd(const MlpShape& m, const float* w, const float* y, const float* dout, int64_t n_s,
-                          float* dy, float* partial, hipStream_t s)
+hipError_t launch_mlp_bwd(const MlpShape& m, const float* w, const float* y, const float* dout, const float* sc,
+                          int64_t n_s, float* dy, float* partial, float* act, hipStream_t s)
 {
     if (n_s == 0) return hipSuccess;
-#define X(I, Wd, Dp) \
-    if (m.in_dim == I && m.width == Wd && m.hidden == Dp) return bwd_impl<I, Wd, Dp>(w, y, dout, n_s, dy, partial, s);
+#define X(I, Wd, Dp)                                        \
+    if (m.in_dim == I && m.width == Wd && m.hidden == Dp) \
+        return bwd_impl<I, Wd, Dp>(w, y, dout, sc, n_s, dy, partial, act, s);
     PRENOM_FOR_EACH_MLP(X)
 #undef X
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_mlp_fwd_batch(const MlpShape& m, const MlpWork* work, int n_blocks, const float* params,
-                                const float* y, float* sc, hipStream_t s)
+                                const float* y, float* sc, float* act, hipStream_t s)
 {
     if (n_blocks == 0) return hipSuccess;
-#define X(I, Wd, Dp)                                                                                         \
-    if (m.in_dim == I && m.width == Wd && m.hidden == Dp) {                                                  \
-        hipLaunchKernelGGL((k_mlp_fwd_batch<I, Wd, Dp>), dim3((uint32_t)n_blocks), dim3(256), 0, s, work, params, y, \
-                           (float4*)sc);                                                                     \
-        return hipGetLastError();                                                                            \
-    }
+#define X(I, Wd, Dp)                                        \
+    if (m.in_dim == I && m.width == Wd && m.hidden == Dp) \
+        return fwd_batch_impl<I, Wd, Dp>(work, n_blocks, params, y, sc, act, s);
     PRENOM_FOR_EACH_MLP(X)
 #undef X
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_mlp_bwd_batch(const MlpShape& m, const MlpWork* work, int n_blocks, const float* params,
-                                const float* y, const float* dout, float* dy, float* partial, int64_t slot_stride,
-                                hipStream_t s)
+                                const float* y, const float* dout, const float* sc, float* dy, float* partial,
+                                int64_t slot_stride, float* act, hipStream_t s)
 {
     if (n_blocks == 0) return hipSuccess;
-#define X(I, Wd, Dp)                                                                                          \
-    if (m.in_dim == I && m.width == Wd && m.hidden == Dp) {                                                   \
-        const size_t lds = bwd_lds_bytes<I, Wd, Dp>();                                                        \
-        auto kern = k_mlp_bwd_batch<I, Wd, Dp>;                                                               \
-        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
-        if (e != hipSuccess) return e;                                                                        \
-        hipLaunchKernelGGL(kern, dim3((uint32_t)n_blocks), dim3(64 * kBwdWaves), lds, s, work, params, y,    \
-                           (const float4*)dout, (float2*)dy, partial, slot_stride);                           \
-        return hipGetLastError();                                                                             \
-    }
+#define X(I, Wd, Dp)                                        \
+    if (m.in_dim == I && m.width == Wd && m.hidden == Dp) \
+        return bwd_batch_impl<I, Wd, Dp>(work, n_blocks, params, y, dout, sc, dy, partial, slot_stride, act, s);
     PRENOM_FOR_EACH_MLP(X)
 #undef X
     return hipErrorInvalidValue;

@@ -79,11 +79,11 @@ struct NetLp {
 
 // Weight fragments: fragment f, lane l holds 4 consecutive K values.
 template <int IN, int W, int D, class P>
-__device__ void load_fragments_lp(const float* __restrict__ w, typename P::vec* __restrict__ frag, int n_frag)
+__device__ void load_fragments_lp(const float* __restrict__ w, typename P::vec* __restrict__ frag, int n_frag, int f0 = 0)
 {
     using N = NetLp<IN, W, D>;
     for (int idx = threadIdx.x; idx < n_frag * 64; idx += blockDim.x) {
-        const int f = idx >> 6, l = idx & 63, q = l >> 4, j = l & 15;
+        const int f = f0 + (idx >> 6), l = idx & 63, q = l >> 4, j = l & 15;
         float v[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
@@ -132,28 +132,64 @@ __device__ __forceinline__ void load_inputs_lp(const float2* __restrict__ y, int
     }
 }
 
+// acc[to] = sum_ti A(fragment f0 + to * stride + ti) x b[ti], K-blocks outer
+// and output tiles inner (independent accumulators interleave), with a
+// scheduling fence every 4 K-blocks so fragment loads are not all hoisted.
+template <class P, int OT, int KT>
+__device__ __forceinline__ void layer_lp_ks_outer(const typename P::vec* __restrict__ frag, int lane, int f0, int stride,
+                                                  const typename P::vec (&b)[KT], floatx4 (&acc)[OT])
+{
+#pragma unroll
+    for (int to = 0; to < OT; ++to) acc[to] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int ti = 0; ti < KT; ++ti) {
+#pragma unroll
+        for (int to = 0; to < OT; ++to) acc[to] = P::mma(frag[(f0 + to * stride + ti) * 64 + lane], b[ti], acc[to]);
+        if ((ti & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 template <int IN, int W, int D, class P>
 __device__ __forceinline__ void chain_lp(const typename P::vec* __restrict__ frag, int lane,
                                          const floatx4 (&yf)[NetLp<IN, W, D>::KB1],
                                          floatx4 (&hs)[D][NetLp<IN, W, D>::OT], floatx4& o)
 {
     using N = NetLp<IN, W, D>;
+    if constexpr (W >= kWideWidth) {
+        typename P::vec b1[N::KB1];
 #pragma unroll
-    for (int to = 0; to < N::OT; ++to) {
-        floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int m = 0; m < N::KB1; ++m) b1[m] = pack<P>(yf[m]);
+        floatx4 acc[N::OT];
+        layer_lp_ks_outer<P, N::OT, N::KB1>(frag, lane, N::F1, N::KB1, b1, acc);
 #pragma unroll
-        for (int m = 0; m < N::KB1; ++m) acc = P::mma(frag[(N::F1 + to * N::KB1 + m) * 64 + lane], pack<P>(yf[m]), acc);
-        hs[0][to] = relu4(acc);
-    }
+        for (int to = 0; to < N::OT; ++to) hs[0][to] = relu4(acc[to]);
 #pragma unroll
-    for (int k = 1; k < D; ++k) {
+        for (int k = 1; k < D; ++k) {
+            typename P::vec b[N::OT];
+#pragma unroll
+            for (int ti = 0; ti < N::OT; ++ti) b[ti] = pack<P>(hs[k - 1][ti]);
+            layer_lp_ks_outer<P, N::OT, N::OT>(frag, lane, N::FH + (k - 1) * N::OT * N::OT, N::OT, b, acc);
+#pragma unroll
+            for (int to = 0; to < N::OT; ++to) hs[k][to] = relu4(acc[to]);
+        }
+    } else {
 #pragma unroll
         for (int to = 0; to < N::OT; ++to) {
             floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int ti = 0; ti < N::OT; ++ti)
-                acc = P::mma(frag[(N::FH + ((k - 1) * N::OT + to) * N::OT + ti) * 64 + lane], pack<P>(hs[k - 1][ti]), acc);
-            hs[k][to] = relu4(acc);
+            for (int m = 0; m < N::KB1; ++m) acc = P::mma(frag[(N::F1 + to * N::KB1 + m) * 64 + lane], pack<P>(yf[m]), acc);
+            hs[0][to] = relu4(acc);
+        }
+#pragma unroll
+        for (int k = 1; k < D; ++k) {
+#pragma unroll
+            for (int to = 0; to < N::OT; ++to) {
+                floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int ti = 0; ti < N::OT; ++ti)
+                    acc = P::mma(frag[(N::FH + ((k - 1) * N::OT + to) * N::OT + ti) * 64 + lane], pack<P>(hs[k - 1][ti]), acc);
+                hs[k][to] = relu4(acc);
+            }
         }
     }
     o = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -164,7 +200,7 @@ __device__ __forceinline__ void chain_lp(const typename P::vec* __restrict__ fra
 template <int IN, int W, int D, class P>
 __device__ __forceinline__ void mlp_fwd_tiles_lp(const typename P::vec* __restrict__ frag,
                                                  const float2* __restrict__ y, int64_t n_s, float4* __restrict__ sc,
-                                                 int64_t tile0, int64_t end, int64_t step)
+                                                 float* __restrict__ act, int64_t tile0, int64_t end, int64_t step)
 {
     using N = NetLp<IN, W, D>;
     const int lane = threadIdx.x & 63, q = lane >> 4, j = lane & 15;
@@ -177,34 +213,44 @@ __device__ __forceinline__ void mlp_fwd_tiles_lp(const typename P::vec* __restri
         floatx4 o;
         chain_lp<IN, W, D, P>(frag, lane, yf, hs, o);
         if (q == 0 && valid) sc[s] = make_float4(__expf(o[0]), sigmoidf_(o[1]), sigmoidf_(o[2]), sigmoidf_(o[3]));
+        if (act && valid) {
+#pragma unroll
+            for (int k = 0; k < D; ++k)
+#pragma unroll
+                for (int to = 0; to < N::OT; ++to)
+                    *reinterpret_cast<floatx4*>(act + ((int64_t)k * n_s + s) * W + 16 * to + 4 * q) = hs[k][to];
+        }
     }
 }
 
 template <int IN, int W, int D, class P>
 __global__ __launch_bounds__(256) void k_mlp_fwd_lp(const float* __restrict__ w, const float2* __restrict__ y,
-                                                    int64_t n_s, float4* __restrict__ sc)
+                                                    int64_t n_s, float4* __restrict__ sc, float* __restrict__ act)
 {
     using N = NetLp<IN, W, D>;
-    __shared__ typename P::vec frag[N::N_FWD * 64];
+    extern __shared__ __align__(16) unsigned char smem_f[];
+    typename P::vec* frag = reinterpret_cast<typename P::vec*>(smem_f);
     load_fragments_lp<IN, W, D, P>(w, frag, N::N_FWD);
     __syncthreads();
     const int64_t wave0 = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
     const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x / 64);
-    mlp_fwd_tiles_lp<IN, W, D, P>(frag, y, n_s, sc, wave0, (n_s + 15) / 16, n_waves);
+    mlp_fwd_tiles_lp<IN, W, D, P>(frag, y, n_s, sc, act, wave0, (n_s + 15) / 16, n_waves);
 }
 
 template <int IN, int W, int D, class P>
 __global__ __launch_bounds__(256) void k_mlp_fwd_lp_batch(const MlpWork* __restrict__ work,
                                                           const float* __restrict__ params,
-                                                          const float2* __restrict__ y, float4* __restrict__ sc)
+                                                          const float2* __restrict__ y, float4* __restrict__ sc,
+                                                          float* __restrict__ act)
 {
     using N = NetLp<IN, W, D>;
-    __shared__ typename P::vec frag[N::N_FWD * 64];
+    extern __shared__ __align__(16) unsigned char smem_f[];
+    typename P::vec* frag = reinterpret_cast<typename P::vec*>(smem_f);
     const MlpWork wk = work[blockIdx.x];
     load_fragments_lp<IN, W, D, P>(params + wk.w_off, frag, N::N_FWD);
     __syncthreads();
-    mlp_fwd_tiles_lp<IN, W, D, P>(frag, y + wk.y_off / 2, wk.n_s, sc + wk.s_off, wk.tile_begin + (threadIdx.x >> 6),
-                                  wk.tile_end, blockDim.x / 64);
+    mlp_fwd_tiles_lp<IN, W, D, P>(frag, y + wk.y_off / 2, wk.n_s, sc + wk.s_off, act ? act + wk.a_off : nullptr,
+                                  wk.tile_begin + (threadIdx.x >> 6), wk.tile_end, blockDim.x / 64);
 }
 
 template <int IN, int W, int D>
@@ -387,65 +433,261 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_bwd_lp_batch(const MlpWo
                                   wk.tile_end, kBwdWaves);
 }
 
-template <int IN, int W, int D, class P>
-hipError_t fwd_lp(const float* w, const float* y, int64_t n_s, float* sc, hipStream_t s)
-{
-    const int64_t n_tiles = (n_s + 15) / 16;
-    int64_t blocks = (n_tiles + 3) / 4;
-    blocks = blocks > 2048 ? 2048 : blocks;
-    hipLaunchKernelGGL((k_mlp_fwd_lp<IN, W, D, P>), dim3((uint32_t)blocks), dim3(256), 0, s, w, (const float2*)y,
-                       n_s, (float4*)sc);
-    return hipGetLastError();
-}
+// ---------------------------------------------------------------- 128 wide
+// As in the FP32 form: the forward stores the hidden activations (FP32); a
+// chain kernel with only the transposed fragments writes every layer's delta
+// (FP32) and dy; a weight-gradient kernel contracts deltas with activations
+// over the block's samples (operands rounded to the MFMA type, FP32
+// accumulation), the 4 waves splitting the output rows.
+constexpr int kWideWavesLp = 4;
 
 template <int IN, int W, int D, class P>
-hipError_t bwd_lp(const float* w, const float* y, const float* dout, int64_t n_s, float* dy, float* partial,
-                  hipStream_t s)
+__device__ void mlp_chain_bwd_tiles_lp(const typename P::vec* __restrict__ bfrag, const float4* __restrict__ sc,
+                                       const float4* __restrict__ dout, const float* __restrict__ act,
+                                       float* __restrict__ dlt, int64_t n_s, float2* __restrict__ dy, int64_t tile0,
+                                       int64_t end, int64_t step)
 {
     using N = NetLp<IN, W, D>;
-    const size_t lds = sizeof(typename P::vec) * (size_t)N::N_ALL * 64 +
-                       sizeof(float) * (size_t)kBwdWaves * BwdLdsLp<IN, W, D>::PER_WAVE;
-    auto kern = k_mlp_bwd_lp<IN, W, D, P>;
-    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3((uint32_t)bwd_blocks(n_s)), dim3(64 * kBwdWaves), lds, s, w, (const float2*)y,
-                       (const float4*)dout, n_s, (float2*)dy, partial);
-    return hipGetLastError();
+    constexpr int BO = 0, BH = N::BH - N::N_FWD, B1 = N::B1 - N::N_FWD;
+    const int lane = threadIdx.x & 63, q = lane >> 4, j = lane & 15;
+    for (int64_t tile = tile0; tile < end; tile += step) {
+        const int64_t s = tile * 16 + j;
+        const bool valid = s < n_s;
+        floatx4 dO = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (q == 0 && valid) {
+            const float4 g = dout[s], v = sc[s];
+            dO = {g.x * v.x, g.y * v.y * (1.0f - v.y), g.z * v.z * (1.0f - v.z), g.w * v.w * (1.0f - v.w)};
+        }
+        const typename P::vec dOp = pack<P>(dO);
+        floatx4 hk[N::OT], delta[N::OT];
+#pragma unroll
+        for (int to = 0; to < N::OT; ++to)
+            hk[to] = valid ? *reinterpret_cast<const floatx4*>(act + ((int64_t)(D - 1) * n_s + s) * W + 16 * to + 4 * q)
+                           : floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int to = 0; to < N::OT; ++to) {
+            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+            acc = P::mma(bfrag[(BO + to) * 64 + lane], dOp, acc);
+            delta[to] = mask_pos(acc, hk[to]);
+            if (valid) *reinterpret_cast<floatx4*>(dlt + ((int64_t)(D - 1) * n_s + s) * W + 16 * to + 4 * q) = delta[to];
+        }
+#pragma unroll
+        for (int k = D - 1; k >= 1; --k) {
+#pragma unroll
+            for (int to = 0; to < N::OT; ++to)
+                hk[to] = valid ? *reinterpret_cast<const floatx4*>(act + ((int64_t)(k - 1) * n_s + s) * W + 16 * to + 4 * q)
+                               : floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            typename P::vec dp[N::OT];
+#pragma unroll
+            for (int ti = 0; ti < N::OT; ++ti) dp[ti] = pack<P>(delta[ti]);
+            floatx4 nd[N::OT];
+            layer_lp_ks_outer<P, N::OT, N::OT>(bfrag, lane, BH + (k - 1) * N::OT * N::OT, N::OT, dp, nd);
+#pragma unroll
+            for (int to = 0; to < N::OT; ++to) {
+                delta[to] = mask_pos(nd[to], hk[to]);
+                if (valid) *reinterpret_cast<floatx4*>(dlt + ((int64_t)(k - 1) * n_s + s) * W + 16 * to + 4 * q) = delta[to];
+            }
+        }
+        typename P::vec dp[N::OT];
+#pragma unroll
+        for (int ti = 0; ti < N::OT; ++ti) dp[ti] = pack<P>(delta[ti]);
+        floatx4 gy[N::IT];
+        layer_lp_ks_outer<P, N::IT, N::OT>(bfrag, lane, B1, N::OT, dp, gy);
+#pragma unroll
+        for (int to = 0; to < N::IT; ++to) {
+            const int f = 16 * to + 4 * q;
+            if (valid && f < IN) {
+                dy[(int64_t)(f >> 1) * n_s + s] = make_float2(gy[to][0], gy[to][1]);
+                dy[(int64_t)((f >> 1) + 1) * n_s + s] = make_float2(gy[to][2], gy[to][3]);
+            }
+        }
+    }
 }
 
-#define PRENOM_FOR_EACH_MLP_LP(X) \
-    X(16, 32, 1) \
-    X(16, 32, 2) \
-    X(16, 64, 1) \
-    X(16, 64, 2) \
-    X(24, 32, 1) \
-    X(24, 32, 2) \
-    X(24, 64, 1) \
-    X(24, 64, 2) \
-    X(32, 32, 1) \
-    X(32, 32, 2) \
-    X(32, 64, 1) \
-    X(32, 64, 2)
-
-template <class P>
-hipError_t fwd_dispatch(const MlpShape& m, const float* w, const float* y, int64_t n_s, float* sc, hipStream_t s)
+// Weight gradient over samples [s_begin, s_end): MFMA K = 16 consecutive
+// samples (lane q holds samples 4q .. 4q + 3 of the block of 16).
+template <int IN, int W, int D, class P>
+__device__ void mlp_dw_range_lp(const float* __restrict__ y, const float4* __restrict__ sc,
+                                const float4* __restrict__ dout, const float* __restrict__ act,
+                                const float* __restrict__ dlt, int64_t n_s, int64_t s_begin, int64_t s_end,
+                                float* __restrict__ dst)
 {
-#define X(I, Wd, Dp) \
-    if (m.in_dim == I && m.width == Wd && m.hidden == Dp) return fwd_lp<I, Wd, Dp, P>(w, y, n_s, sc, s);
-    PRENOM_FOR_EACH_MLP_LP(X)
-#undef X
-    return hipErrorInvalidValue;
+    using N = NetLp<IN, W, D>;
+    constexpr int RT = N::OT / kWideWavesLp;
+    static_assert(N::OT % kWideWavesLp == 0, "rows per wave");
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, j = lane & 15;
+    floatx4 aH[D > 1 ? D - 1 : 1][RT][N::OT], a1[RT][N::IT], aO[RT];
+#pragma unroll
+    for (int a = 0; a < RT; ++a) {
+        aO[a] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int t = 0; t < N::IT; ++t) a1[a][t] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int k = 0; k < (D > 1 ? D - 1 : 1); ++k)
+#pragma unroll
+            for (int t = 0; t < N::OT; ++t) aH[k][a][t] = {0.0f, 0.0f, 0.0f, 0.0f};
+    }
+    for (int64_t s0 = s_begin; s0 < s_end; s0 += 16) {
+        int64_t sk[4];
+        bool ok[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            sk[r] = s0 + 4 * q + r;
+            ok[r] = sk[r] < s_end;
+        }
+        // W_out: A[i][k] = dO_i(sample k), rows i >= 4 zero; B = h_{D-1}
+        float dOv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            dOv[r] = 0.0f;
+            if (ok[r] && j < 4) {
+                const float4 g = dout[sk[r]], v = sc[sk[r]];
+                dOv[r] = j == 0 ? g.x * v.x
+                                : (j == 1 ? g.y * v.y * (1.0f - v.y)
+                                          : (j == 2 ? g.z * v.z * (1.0f - v.z) : g.w * v.w * (1.0f - v.w)));
+            }
+        }
+        const typename P::vec dOp = pack<P>(dOv[0], dOv[1], dOv[2], dOv[3]);
+        auto col4 = [&](const float* base, int col) {  // 4 samples' value of one column
+            float v[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = ok[r] ? base[sk[r] * W + col] : 0.0f;
+            return pack<P>(v[0], v[1], v[2], v[3]);
+        };
+        {
+            const float* hl = act + (int64_t)(D - 1) * n_s * W;
+#pragma unroll
+            for (int a = 0; a < RT; ++a) aO[a] = P::mma(dOp, col4(hl, 16 * (RT * wave + a) + j), aO[a]);
+        }
+#pragma unroll
+        for (int k = 1; k < D; ++k) {
+            const float* dk = dlt + (int64_t)k * n_s * W;
+            const float* hk = act + (int64_t)(k - 1) * n_s * W;
+            typename P::vec av[RT], bv[N::OT];
+#pragma unroll
+            for (int a = 0; a < RT; ++a) av[a] = col4(dk, 16 * (RT * wave + a) + j);
+#pragma unroll
+            for (int t = 0; t < N::OT; ++t) bv[t] = col4(hk, 16 * t + j);
+#pragma unroll
+            for (int a = 0; a < RT; ++a)
+#pragma unroll
+                for (int t = 0; t < N::OT; ++t) aH[k - 1][a][t] = P::mma(av[a], bv[t], aH[k - 1][a][t]);
+        }
+        {
+            typename P::vec av[RT], bv[N::IT];
+#pragma unroll
+            for (int a = 0; a < RT; ++a) av[a] = col4(dlt, 16 * (RT * wave + a) + j);
+#pragma unroll
+            for (int t = 0; t < N::IT; ++t) {
+                const int f = 16 * t + j;
+                float v[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[r] = (ok[r] && f < IN) ? y[((int64_t)(f >> 1) * n_s + sk[r]) * 2 + (f & 1)] : 0.0f;
+                bv[t] = pack<P>(v[0], v[1], v[2], v[3]);
+            }
+#pragma unroll
+            for (int a = 0; a < RT; ++a)
+#pragma unroll
+                for (int t = 0; t < N::IT; ++t) a1[a][t] = P::mma(av[a], bv[t], a1[a][t]);
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < RT; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * (RT * wave + a) + 4 * q + r;
+#pragma unroll
+            for (int t = 0; t < N::IT; ++t) {
+                const int col = 16 * t + j;
+                if (col < IN) dst[N::OFF_W1 + row * IN + col] = a1[a][t][r];
+            }
+#pragma unroll
+            for (int k = 1; k < D; ++k)
+#pragma unroll
+                for (int t = 0; t < N::OT; ++t) dst[N::OFF_H + (k - 1) * W * W + row * W + 16 * t + j] = aH[k - 1][a][t][r];
+            if (q == 0) dst[N::OFF_OUT + r * W + 16 * (RT * wave + a) + j] = aO[a][r];
+        }
 }
 
-template <class P>
-hipError_t bwd_dispatch(const MlpShape& m, const float* w, const float* y, const float* dout, int64_t n_s, float* dy,
-                        float* partial, hipStream_t s)
+template <int IN, int W, int D, class P>
+__global__ __launch_bounds__(256) void k_mlp_chain_bwd_lp(const float* __restrict__ w, const float4* __restrict__ sc,
+                                                          const float4* __restrict__ dout, float* __restrict__ act,
+                                                          int64_t n_s, float2* __restrict__ dy)
 {
-#define X(I, Wd, Dp) \
-    if (m.in_dim == I && m.width == Wd && m.hidden == Dp) return bwd_lp<I, Wd, Dp, P>(w, y, dout, n_s, dy, partial, s);
-    PRENOM_FOR_EACH_MLP_LP(X)
-#undef X
-    return hipErrorInvalidValue;
+    using N = NetLp<IN, W, D>;
+    extern __shared__ __align__(16) unsigned char smem_b[];
+    typename P::vec* frag = reinterpret_cast<typename P::vec*>(smem_b);
+    load_fragments_lp<IN, W, D, P>(w, frag, N::N_ALL - N::N_FWD, N::N_FWD);
+    __syncthreads();
+    const int64_t wave0 = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    mlp_chain_bwd_tiles_lp<IN, W, D, P>(frag, sc, dout, act, act + (int64_t)D * n_s * W, n_s, dy, wave0,
+                                        (n_s + 15) / 16, (int64_t)gridDim.x * (blockDim.x / 64));
+}
+
+template <int IN, int W, int D, class P>
+__global__ __launch_bounds__(256) void k_mlp_chain_bwd_lp_batch(const MlpWork* __restrict__ work,
+                                                                const float* __restrict__ params,
+                                                                const float4* __restrict__ sc,
+                                                                const float4* __restrict__ dout,
+                                                                float* __restrict__ act, float2* __restrict__ dy)
+{
+    using N = NetLp<IN, W, D>;
+    extern __shared__ __align__(16) unsigned char smem_b[];
+    typename P::vec* frag = reinterpret_cast<typename P::vec*>(smem_b);
+    const MlpWork wk = work[blockIdx.x];
+    load_fragments_lp<IN, W, D, P>(params + wk.w_off, frag, N::N_ALL - N::N_FWD, N::N_FWD);
+    __syncthreads();
+    mlp_chain_bwd_tiles_lp<IN, W, D, P>(frag, sc + wk.s_off, dout + wk.s_off, act + wk.a_off,
+                                        act + wk.a_off + (int64_t)D * wk.n_s * W, wk.n_s, dy + wk.y_off / 2,
+                                        wk.tile_begin + (threadIdx.x >> 6), wk.tile_end, blockDim.x / 64);
+}
+
+template <int IN, int W, int D, class P>
+__global__ __launch_bounds__(64 * kWideWavesLp) void k_mlp_dw_lp(const float* __restrict__ y,
+                                                                 const float4* __restrict__ sc,
+                                                                 const float4* __restrict__ dout,
+                                                                 const float* __restrict__ act, int64_t n_s,
+                                                                 int64_t tiles_per_block, float* __restrict__ partial)
+{
+    using N = NetLp<IN, W, D>;
+    const int64_t b = (int64_t)blockIdx.x * tiles_per_block * 16;
+    const int64_t e = min(b + tiles_per_block * 16, n_s);
+    mlp_dw_range_lp<IN, W, D, P>(y, sc, dout, act, act + (int64_t)D * n_s * W, n_s, b, e,
+                                 partial + (int64_t)blockIdx.x * N::N_PARAMS);
+}
+
+template <int IN, int W, int D, class P>
+__global__ __launch_bounds__(64 * kWideWavesLp) void k_mlp_dw_lp_batch(const MlpWork* __restrict__ work,
+                                                                       const float* __restrict__ y,
+                                                                       const float4* __restrict__ sc,
+                                                                       const float4* __restrict__ dout,
+                                                                       const float* __restrict__ act,
+                                                                       float* __restrict__ partial, int64_t slot_stride)
+{
+    const MlpWork wk = work[blockIdx.x];
+    const int64_t b = wk.tile_begin * 16, e = min(wk.tile_end * 16, wk.n_s);
+    const float* a = act + wk.a_off;
+    mlp_dw_range_lp<IN, W, D, P>(y + wk.y_off, sc + wk.s_off, dout + wk.s_off, a, a + (int64_t)D * wk.n_s * W, wk.n_s,
+                                 b, e, partial + (int64_t)blockIdx.x * slot_stride);
+}
+
+template <class K>
+hipError_t set_lds_lp(K kern, size_t bytes)
+{
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <int IN, int W, int D, class P>
+size_t fwd_lds_lp()
+{
+    return sizeof(typename P::vec) * (size_t)NetLp<IN, W, D>::N_FWD * 64;
+}
+
+template <int IN, int W, int D, class P>
+size_t chain_lds_lp()
+{
+    return sizeof(typename P::vec) * (size_t)(NetLp<IN, W, D>::N_ALL - NetLp<IN, W, D>::N_FWD) * 64;
 }
 
 template <int IN, int W, int D, class P>
@@ -455,16 +697,137 @@ size_t bwd_lds_lp()
            sizeof(float) * (size_t)kBwdWaves * BwdLdsLp<IN, W, D>::PER_WAVE;
 }
 
+template <int IN, int W, int D, class P>
+hipError_t fwd_lp(const float* w, const float* y, int64_t n_s, float* sc, float* act, hipStream_t s)
+{
+    const int64_t n_tiles = (n_s + 15) / 16;
+    int64_t blocks = (n_tiles + 3) / 4;
+    blocks = blocks > 2048 ? 2048 : blocks;
+    const size_t lds = fwd_lds_lp<IN, W, D, P>();
+    hipError_t e = set_lds_lp(k_mlp_fwd_lp<IN, W, D, P>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_mlp_fwd_lp<IN, W, D, P>), dim3((uint32_t)blocks), dim3(256), lds, s, w, (const float2*)y,
+                       n_s, (float4*)sc, W >= kWideWidth ? act : nullptr);
+    return hipGetLastError();
+}
+
+template <int IN, int W, int D, class P>
+hipError_t bwd_lp(const float* w, const float* y, const float* dout, const float* sc, int64_t n_s, float* dy,
+                  float* partial, float* act, hipStream_t s)
+{
+    if constexpr (W >= kWideWidth) {
+        const int64_t n_tiles = (n_s + 15) / 16;
+        int64_t blocks = (n_tiles + 3) / 4;
+        blocks = blocks > 2048 ? 2048 : blocks;
+        const size_t lds = chain_lds_lp<IN, W, D, P>();
+        hipError_t e = set_lds_lp(k_mlp_chain_bwd_lp<IN, W, D, P>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_mlp_chain_bwd_lp<IN, W, D, P>), dim3((uint32_t)blocks), dim3(256), lds, s, w,
+                           (const float4*)sc, (const float4*)dout, act, n_s, (float2*)dy);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        const int nb = bwd_blocks(n_s);
+        const int64_t per = (n_tiles + nb - 1) / nb;
+        hipLaunchKernelGGL((k_mlp_dw_lp<IN, W, D, P>), dim3((uint32_t)nb), dim3(64 * kWideWavesLp), 0, s, y,
+                           (const float4*)sc, (const float4*)dout, act, n_s, per, partial);
+        return hipGetLastError();
+    } else {
+        const size_t lds = bwd_lds_lp<IN, W, D, P>();
+        auto kern = k_mlp_bwd_lp<IN, W, D, P>;
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3((uint32_t)bwd_blocks(n_s)), dim3(64 * kBwdWaves), lds, s, w, (const float2*)y,
+                           (const float4*)dout, n_s, (float2*)dy, partial);
+        return hipGetLastError();
+    }
+}
+
+template <int IN, int W, int D, class P>
+hipError_t fwd_lp_batch(const MlpWork* work, int n_blocks, const float* params, const float* y, float* sc, float* act,
+                        hipStream_t s)
+{
+    const size_t lds = fwd_lds_lp<IN, W, D, P>();
+    hipError_t e = set_lds_lp(k_mlp_fwd_lp_batch<IN, W, D, P>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_mlp_fwd_lp_batch<IN, W, D, P>), dim3((uint32_t)n_blocks), dim3(256), lds, s, work, params,
+                       (const float2*)y, (float4*)sc, W >= kWideWidth ? act : nullptr);
+    return hipGetLastError();
+}
+
+template <int IN, int W, int D, class P>
+hipError_t bwd_lp_batch(const MlpWork* work, int n_blocks, const float* params, const float* y, const float* dout,
+                        const float* sc, float* dy, float* partial, int64_t slot_stride, float* act, hipStream_t s)
+{
+    if constexpr (W >= kWideWidth) {
+        const size_t lds = chain_lds_lp<IN, W, D, P>();
+        hipError_t e = set_lds_lp(k_mlp_chain_bwd_lp_batch<IN, W, D, P>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_mlp_chain_bwd_lp_batch<IN, W, D, P>), dim3((uint32_t)n_blocks), dim3(256), lds, s, work,
+                           params, (const float4*)sc, (const float4*)dout, act, (float2*)dy);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_mlp_dw_lp_batch<IN, W, D, P>), dim3((uint32_t)n_blocks), dim3(64 * kWideWavesLp), 0, s,
+                           work, y, (const float4*)sc, (const float4*)dout, act, partial, slot_stride);
+        return hipGetLastError();
+    } else {
+        const size_t lds = bwd_lds_lp<IN, W, D, P>();
+        auto kern = k_mlp_bwd_lp_batch<IN, W, D, P>;
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3((uint32_t)n_blocks), dim3(64 * kBwdWaves), lds, s, work, params,
+                           (const float2*)y, (const float4*)dout, (float2*)dy, partial, slot_stride);
+        return hipGetLastError();
+    }
+}
+
+#define PRENOM_FOR_EACH_MLP_LP(X) \
+    X(16, 32, 1) \
+    X(16, 32, 2) \
+    X(16, 64, 1) \
+    X(16, 64, 2) \
+    X(16, 128, 1) \
+    X(16, 128, 2) \
+    X(24, 32, 1) \
+    X(24, 32, 2) \
+    X(24, 64, 1) \
+    X(24, 64, 2) \
+    X(24, 128, 1) \
+    X(24, 128, 2) \
+    X(32, 32, 1) \
+    X(32, 32, 2) \
+    X(32, 64, 1) \
+    X(32, 64, 2) \
+    X(32, 128, 1) \
+    X(32, 128, 2)
+
+template <class P>
+hipError_t fwd_dispatch(const MlpShape& m, const float* w, const float* y, int64_t n_s, float* sc, float* act,
+                        hipStream_t s)
+{
+#define X(I, Wd, Dp) \
+    if (m.in_dim == I && m.width == Wd && m.hidden == Dp) return fwd_lp<I, Wd, Dp, P>(w, y, n_s, sc, act, s);
+    PRENOM_FOR_EACH_MLP_LP(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+template <class P>
+hipError_t bwd_dispatch(const MlpShape& m, const float* w, const float* y, const float* dout, const float* sc,
+                        int64_t n_s, float* dy, float* partial, float* act, hipStream_t s)
+{
+#define X(I, Wd, Dp)                                        \
+    if (m.in_dim == I && m.width == Wd && m.hidden == Dp) \
+        return bwd_lp<I, Wd, Dp, P>(w, y, dout, sc, n_s, dy, partial, act, s);
+    PRENOM_FOR_EACH_MLP_LP(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
 template <class P>
 hipError_t fwd_batch_dispatch(const MlpShape& m, const MlpWork* work, int n_blocks, const float* params, const float* y,
-                              float* sc, hipStream_t s)
+                              float* sc, float* act, hipStream_t s)
 {
-#define X(I, Wd, Dp)                                                                                      \
-    if (m.in_dim == I && m.width == Wd && m.hidden == Dp) {                                               \
-        hipLaunchKernelGGL((k_mlp_fwd_lp_batch<I, Wd, Dp, P>), dim3((uint32_t)n_blocks), dim3(256), 0, s, work, \
-                           params, (const float2*)y, (float4*)sc);                                        \
-        return hipGetLastError();                                                                         \
-    }
+#define X(I, Wd, Dp)                                        \
+    if (m.in_dim == I && m.width == Wd && m.hidden == Dp) \
+        return fwd_lp_batch<I, Wd, Dp, P>(work, n_blocks, params, y, sc, act, s);
     PRENOM_FOR_EACH_MLP_LP(X)
 #undef X
     return hipErrorInvalidValue;
@@ -472,19 +835,12 @@ hipError_t fwd_batch_dispatch(const MlpShape& m, const MlpWork* work, int n_bloc
 
 template <class P>
 hipError_t bwd_batch_dispatch(const MlpShape& m, const MlpWork* work, int n_blocks, const float* params,
-                              const float* y, const float* dout, float* dy, float* partial, int64_t slot_stride,
-                              hipStream_t s)
+                              const float* y, const float* dout, const float* sc, float* dy, float* partial,
+                              int64_t slot_stride, float* act, hipStream_t s)
 {
-#define X(I, Wd, Dp)                                                                                        \
-    if (m.in_dim == I && m.width == Wd && m.hidden == Dp) {                                                 \
-        const size_t lds = bwd_lds_lp<I, Wd, Dp, P>();                                                      \
-        auto kern = k_mlp_bwd_lp_batch<I, Wd, Dp, P>;                                                       \
-        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
-        if (e != hipSuccess) return e;                                                                      \
-        hipLaunchKernelGGL(kern, dim3((uint32_t)n_blocks), dim3(64 * kBwdWaves), lds, s, work, params,     \
-                           (const float2*)y, (const float4*)dout, (float2*)dy, partial, slot_stride);      \
-        return hipGetLastError();                                                                           \
-    }
+#define X(I, Wd, Dp)                                        \
+    if (m.in_dim == I && m.width == Wd && m.hidden == Dp) \
+        return bwd_lp_batch<I, Wd, Dp, P>(work, n_blocks, params, y, dout, sc, dy, partial, slot_stride, act, s);
     PRENOM_FOR_EACH_MLP_LP(X)
 #undef X
     return hipErrorInvalidValue;
@@ -492,41 +848,42 @@ hipError_t bwd_batch_dispatch(const MlpShape& m, const MlpWork* work, int n_bloc
 
 }  // namespace
 
-hipError_t launch_mlp_fwd_lp(const MlpShape& m, const float* w, const float* y, int64_t n_s, float* sc, hipStream_t s)
+hipError_t launch_mlp_fwd_lp(const MlpShape& m, const float* w, const float* y, int64_t n_s, float* sc, float* act,
+                             hipStream_t s)
 {
     if (n_s == 0) return hipSuccess;
-    if (m.dtype == PRENOM_BF16) return fwd_dispatch<Bf16Op>(m, w, y, n_s, sc, s);
-    if (m.dtype == PRENOM_F16) return fwd_dispatch<F16Op>(m, w, y, n_s, sc, s);
+    if (m.dtype == PRENOM_BF16) return fwd_dispatch<Bf16Op>(m, w, y, n_s, sc, act, s);
+    if (m.dtype == PRENOM_F16) return fwd_dispatch<F16Op>(m, w, y, n_s, sc, act, s);
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_mlp_bwd_lp(const MlpShape& m, const float* w, const float* y, const float* dout, int64_t n_s,
-                             float* dy, float* partial, hipStream_t s)
+hipError_t launch_mlp_bwd_lp(const MlpShape& m, const float* w, const float* y, const float* dout, const float* sc,
+                             int64_t n_s, float* dy, float* partial, float* act, hipStream_t s)
 {
     if (n_s == 0) return hipSuccess;
-    if (m.dtype == PRENOM_BF16) return bwd_dispatch<Bf16Op>(m, w, y, dout, n_s, dy, partial, s);
-    if (m.dtype == PRENOM_F16) return bwd_dispatch<F16Op>(m, w, y, dout, n_s, dy, partial, s);
+    if (m.dtype == PRENOM_BF16) return bwd_dispatch<Bf16Op>(m, w, y, dout, sc, n_s, dy, partial, act, s);
+    if (m.dtype == PRENOM_F16) return bwd_dispatch<F16Op>(m, w, y, dout, sc, n_s, dy, partial, act, s);
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_mlp_fwd_lp_batch(const MlpShape& m, const MlpWork* work, int n_blocks, const float* params,
-                                   const float* y, float* sc, hipStream_t s)
+                                   const float* y, float* sc, float* act, hipStream_t s)
 {
     if (n_blocks == 0) return hipSuccess;
-    if (m.dtype == PRENOM_BF16) return fwd_batch_dispatch<Bf16Op>(m, work, n_blocks, params, y, sc, s);
-    if (m.dtype == PRENOM_F16) return fwd_batch_dispatch<F16Op>(m, work, n_blocks, params, y, sc, s);
+    if (m.dtype == PRENOM_BF16) return fwd_batch_dispatch<Bf16Op>(m, work, n_blocks, params, y, sc, act, s);
+    if (m.dtype == PRENOM_F16) return fwd_batch_dispatch<F16Op>(m, work, n_blocks, params, y, sc, act, s);
     return hipErrorInvalidValue;
 }
 
 hipError_t launch_mlp_bwd_lp_batch(const MlpShape& m, const MlpWork* work, int n_blocks, const float* params,
-                                   const float* y, const float* dout, float* dy, float* partial, int64_t slot_stride,
-                                   hipStream_t s)
+                                   const float* y, const float* dout, const float* sc, float* dy, float* partial,
+                                   int64_t slot_stride, float* act, hipStream_t s)
 {
     if (n_blocks == 0) return hipSuccess;
     if (m.dtype == PRENOM_BF16)
-        return bwd_batch_dispatch<Bf16Op>(m, work, n_blocks, params, y, dout, dy, partial, slot_stride, s);
+        return bwd_batch_dispatch<Bf16Op>(m, work, n_blocks, params, y, dout, sc, dy, partial, slot_stride, act, s);
     if (m.dtype == PRENOM_F16)
-        return bwd_batch_dispatch<F16Op>(m, work, n_blocks, params, y, dout, dy, partial, slot_stride, s);
+        return bwd_batch_dispatch<F16Op>(m, work, n_blocks, params, y, dout, sc, dy, partial, slot_stride, act, s);
     return hipErrorInvalidValue;
 }
 

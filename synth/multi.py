@@ -75,7 +75,7 @@ def largest_remainder(weights: Sequence[float], total: int) -> List[int]:
 
 
 def multi_objects(seed: int, n_objects: int, total_rays: Optional[int] = None,
-                  widths: Sequence[int] = (32, 64), mlp_dtype: str = "fp32", table_dtype: str = "fp32",
+                  widths: Sequence[int] = (32, 64, 128), mlp_dtype: str = "fp32", table_dtype: str = "fp32",
                   n_cams: int = 16, width: int = 640, height: int = 480,
                   pool_stride: int = 7) -> List[ObjectSpec]:
     rng = np.random.default_rng([seed, 4242])

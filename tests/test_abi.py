@@ -48,7 +48,7 @@ def test_param_and_workspace_sizes(L):
 
 def test_unsupported_architecture_is_rejected_before_launch(L):
     from paper_2503_01582_amd import api
-    arch = Arch(n_levels=16, log2_table=19, width=128, hidden=2)  # MLP width not compiled
+    arch = Arch(n_levels=16, log2_table=19, width=96, hidden=2)  # MLP width not compiled
     m = L.PrenomModel()
     m.arch = api.make_arch(arch)
     cfg = L.PrenomRenderCfg(64, 0, 0.0, 0.0)

@@ -27,10 +27,12 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 TOL_LOWP = 2e-3
 
-# (L, log2 T, W, D) per object: every level count, width and depth, hashed and
-# dense levels; ray counts ragged, one object without rays, one without a prior.
-ARCHS = [(8, 14, 64, 1), (12, 15, 32, 2), (16, 15, 64, 2), (8, 16, 32, 1), (16, 14, 32, 1),
-         (12, 14, 64, 2), (8, 15, 64, 2)]
+# (L, log2 T, W, D) per object: every level count, width (the 128-wide MLP runs
+# its backward as separate chain and weight-gradient kernels) and depth, hashed
+# and dense levels; ray counts ragged, one object without rays, one without a
+# prior.
+ARCHS = [(8, 14, 64, 1), (12, 15, 32, 2), (16, 15, 128, 2), (8, 16, 32, 1), (16, 14, 32, 1),
+         (12, 14, 128, 1), (8, 15, 64, 2)]
 COUNTS = [300, 0, 129, 777, 1, 1100, 65]
 NO_PRIOR = 3
 

@@ -1,0 +1,100 @@
+"""Training many objects at once in the reduced-precision form against the
+FP32 form: same objects, initial weights and ray batches, trained by the
+batched step; held-out PSNR per object after the same number of steps.
+
+Reduced precision here is the MLP in BF16 or FP16 on the matrix cores with
+FP32 accumulation and FP32 master weights, the forward reading an FP16 copy
+of the hash tables, FP32 table-gradient accumulation and scans, and dynamic
+loss scaling from 2^12.  The held-out PSNR of the reduced-precision forms
+must stay within 0.1 dB of the FP32 form (mean over objects)."""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import pytest
+
+from synth.multi import multi_batch, multi_objects, object_eval_views
+from synth.params import init_params
+from synth.workloads import LossSpec, PRIOR_SAMPLE
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+N_OBJ, TOTAL_RAYS, STEPS, N_BATCHES = 8, 1 << 16, 300, 12
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def psnr(mse):
+    return float(-10.0 * np.log10(max(mse, 1e-12)))
+
+
+def eval_psnr(objs, params_flat, offsets, views):
+    """Held-out PSNR per object, rendered by the batched forward with
+    mid-stratum draws."""
+    from paper_2503_01582_amd import batch as B
+    counts = [sum(v[0].shape[0] for v in vs) for vs in views]
+    eobjs = [B.BatchObject(o.arch, n, torch.as_tensor(o.prior).cuda(), o.world_to_obj) for o, n in zip(objs, counts)]
+    bm = B.BatchModel(eobjs, [np.zeros(o.arch.n_params, np.float32) for o in objs], device_step=False)
+    assert bm.offsets == offsets
+    bm.params.copy_(params_flat)
+    if bm.params_lp is not None:
+        B.prenom_batch_refresh_lowp(bm)
+    ws = B.alloc_workspace(bm, PRIOR_SAMPLE.n_samples)
+    cat = lambda i: torch.as_tensor(np.concatenate([v[i] for vs in views for v in vs])).cuda()
+    n = sum(counts)
+    xi = torch.full((n, PRIOR_SAMPLE.n_fine), 0.5, device="cuda")
+    samp = B.prenom_batch_sample(bm, PRIOR_SAMPLE, cat(0), cat(1), xi, ws)
+    out = B.prenom_batch_render_fwd(bm, samp, None, ws, want_loss=False)
+    rgb = out["rgb"].cpu().numpy()
+    col = np.concatenate([v[2] for vs in views for v in vs])
+    res, b = [], 0
+    for c in counts:
+        res.append(psnr(((rgb[b:b + c] - col[b:b + c]) ** 2).mean()))
+        b += c
+    return np.array(res)
+
+
+def train(objs, params, batches, lowp):
+    from paper_2503_01582_amd.batch import BatchObject, BatchTrainer
+    bobjs = [BatchObject(o.arch, o.n_rays, torch.as_tensor(o.prior).cuda(), o.world_to_obj) for o in objs]
+    tr = BatchTrainer(bobjs, params, PRIOR_SAMPLE, LossSpec(), loss_scale=4096.0 if lowp else None)
+    losses = []
+    for i in range(STEPS):
+        tr.load(batches[i % len(batches)])
+        out = tr.step()
+        if i % 100 == 0 or i == STEPS - 1:
+            losses.append(float(out["loss"].mean().item()))
+    torch.cuda.synchronize()
+    extra = ""
+    if lowp:
+        extra = f", loss scale {tr.model.loss_scale.item():.0f}"
+    return tr.model, losses, extra
+
+
+def test_batched_reduced_precision_training_matches_fp32_psnr():
+    say("test_batched_reduced_precision_training_matches_fp32_psnr")
+    base = multi_objects(5, N_OBJ, total_rays=TOTAL_RAYS, n_cams=8, width=320, height=240, pool_stride=3)
+    batches = [multi_batch(base, step=k) for k in range(N_BATCHES)]
+    views = [object_eval_views(o, n_views=2, res=48) for o in base]
+    params = [init_params(o.arch, i) for i, o in enumerate(base)]
+    results = {}
+    for mlp_dtype, table_dtype in (("fp32", "fp32"), ("bf16", "fp16"), ("fp16", "fp16")):
+        objs = [dataclasses.replace(o, arch=dataclasses.replace(o.arch, mlp_dtype=mlp_dtype, table_dtype=table_dtype))
+                for o in base]
+        model, losses, extra = train(objs, params, batches, mlp_dtype != "fp32")
+        p = eval_psnr(objs, model.params, model.offsets, views)
+        results[mlp_dtype] = p
+        say(f"  {mlp_dtype:4s} MLP / {table_dtype} table: mean held-out PSNR {p.mean():6.2f} dB "
+            f"(per object {np.array2string(p, precision=2)}); loss {losses}{extra}")
+    init = eval_psnr(base, torch.cat([torch.as_tensor(np.pad(p, (0, (-len(p)) % 64))) for p in params]).cuda(),
+                     model.offsets, views)
+    say(f"  untrained: mean {init.mean():6.2f} dB")
+    for k in ("bf16", "fp16"):
+        d = results[k].mean() - results["fp32"].mean()
+        say(f"  {k} - fp32: {d:+.3f} dB")
+        assert abs(d) <= 0.1, (k, d)
+    assert results["fp32"].mean() > init.mean() + 5.0

@@ -240,6 +240,23 @@ def test_render_fwd_bwd_parity(kind):
     check_grads(arch, gr.bwd(b), oracle_bwd(arch, params, geo, b))
 
 
+@pytest.mark.parametrize("hidden", [1, 2])
+def test_render_wide_mlp_parity(hidden):
+    """128-wide MLP (stored activations, separate chain and weight-gradient
+    kernels) against the oracle, on a ragged ray count."""
+    say(f"test_render_wide_mlp_parity[hidden={hidden}]")
+    b = prior_batch(world(), 777, step=3)
+    arch = Arch(n_levels=16, log2_table=15, width=128, hidden=hidden)
+    params = init_params(arch, 9)
+    params[:arch.n_table_params] = np.random.default_rng(10).uniform(-0.3, 0.3, arch.n_table_params).astype(np.float32)
+    ref = oracle_sample(b)
+    geo = (ref["ray_obj"].astype(np.float32), ref["t"].astype(np.float32), ref["dt"].astype(np.float32), ref["flags"])
+    live = (geo[3] & orc.FLAG_MISS) == 0
+    gr = GpuRender(arch, params, geo)
+    check_fwd(gr.fwd(b), oracle_fwd(arch, params, geo, b), live)
+    check_grads(arch, gr.bwd(b), oracle_bwd(arch, params, geo, b))
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_render_loss_terms_and_background(mode):
     say(f"test_render_loss_terms_and_background[mode={mode}]")
