@@ -31,6 +31,8 @@ class OrcArch(C.Structure):
         ("res", C.c_int32 * MAX_LEVELS),
         ("width", C.c_int32),
         ("hidden", C.c_int32),
+        ("mlp_dtype", C.c_int32),
+        ("table_dtype", C.c_int32),
     ]
 
 
@@ -76,6 +78,7 @@ def lib():
                                  _f64p, _f64p, _f64p, _i32p, _u8p, _f64p]
         L.orc_encode.argtypes = [C.POINTER(OrcArch), _f32p, _f32p, C.c_int64, _f64p, _i32p, _f64p]
         L.orc_mlp_fwd.argtypes = [C.POINTER(OrcArch), _f32p, _f64p, C.c_int64, _f64p]
+        L.orc_round16_array.argtypes = [_f64p, C.c_int64, C.c_int32, _f64p]
         L.orc_composite_fwd.argtypes = [C.c_int64, C.c_int32, _f64p, _f64p, _f64p, _f64p, _f64p,
                                         _f64p, _f64p, _f64p, _f64p, _f64p]
         L.orc_composite_bwd.argtypes = [C.c_int64, C.c_int32, _f64p, _f64p, _f64p, _f64p, _f64p,
@@ -114,9 +117,11 @@ def _u8(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.uint8)
 
 
-def make_arch(arch) -> OrcArch:
+def make_arch(arch, emulate: bool = False) -> OrcArch:
     """arch: any object with n_levels, log2_table, n_features, resolutions,
-    width, hidden (e.g. synth.arch.Arch)."""
+    width, hidden (e.g. synth.arch.Arch).  emulate: take the arch's
+    mlp_dtype / table_dtype into account (reduced-precision emulation);
+    otherwise the oracle is plain FP64 whatever the arch says."""
     a = OrcArch()
     a.n_levels = arch.n_levels
     a.log2_table = arch.log2_table
@@ -125,6 +130,8 @@ def make_arch(arch) -> OrcArch:
         a.res[i] = int(r)
     a.width = arch.width
     a.hidden = arch.hidden
+    a.mlp_dtype = {"fp32": 0, "bf16": 1, "fp16": 2}[getattr(arch, "mlp_dtype", "fp32")] if emulate else 0
+    a.table_dtype = {"fp32": 0, "fp16": 2}[getattr(arch, "table_dtype", "fp32")] if emulate else 0
     return a
 
 
@@ -194,13 +201,13 @@ def positions(ray_obj, t):
     return out
 
 
-def encode(arch, table, pos, with_corners=False):
+def encode(arch, table, pos, with_corners=False, emulate=False):
     """Hash-grid features y [L, n, F] (FP64); optionally the corner indices
     and weights [L, n, 8]."""
     table = _f32(table)
     pos = _f32(pos).reshape(-1, 3)
     n = pos.shape[0]
-    a = make_arch(arch)
+    a = make_arch(arch, emulate)
     y = np.empty((arch.n_levels, n, arch.n_features), np.float64)
     idx = np.empty((arch.n_levels, n, 8), np.int32) if with_corners else None
     w = np.empty((arch.n_levels, n, 8), np.float64) if with_corners else None
@@ -209,13 +216,22 @@ def encode(arch, table, pos, with_corners=False):
     return (y, idx, w) if with_corners else y
 
 
-def mlp_fwd(arch, mlp, y):
+def mlp_fwd(arch, mlp, y, emulate=False):
     """Raw head outputs [n, 4] for row-major inputs y [n, L*F]."""
     mlp = _f32(mlp)
     y = _f64(y)
     n = y.shape[0]
     out = np.empty((n, 4), np.float64)
-    lib().orc_mlp_fwd(C.byref(make_arch(arch)), _p(mlp, _f32p), _p(y, _f64p), n, _p(out, _f64p))
+    lib().orc_mlp_fwd(C.byref(make_arch(arch, emulate)), _p(mlp, _f32p), _p(y, _f64p), n, _p(out, _f64p))
+    return out
+
+
+def round16(x, dtype: str):
+    """The emulation's rounding: via FP32 to the nearest bfloat16 / binary16
+    value, ties to even ("fp32" leaves x unchanged)."""
+    x = _f64(np.asarray(x, np.float64)).ravel()
+    out = np.empty_like(x)
+    lib().orc_round16_array(_p(x, _f64p), x.size, {"fp32": 0, "bf16": 1, "fp16": 2}[dtype], _p(out, _f64p))
     return out
 
 
@@ -244,9 +260,9 @@ def composite_bwd(sigma, rgb, t, dt, bg, gC, gD, gA=None):
 
 # ---------------------------------------------------------------- render
 
-def _render_cfg(arch, n_samples, loss_mode, lambda_d, lambda_sigma):
+def _render_cfg(arch, n_samples, loss_mode, lambda_d, lambda_sigma, emulate=False):
     c = OrcRenderCfg()
-    c.arch = make_arch(arch)
+    c.arch = make_arch(arch, emulate)
     c.n_samples = n_samples
     c.loss_mode = loss_mode
     c.lambda_d = float(np.float32(lambda_d))
@@ -256,7 +272,7 @@ def _render_cfg(arch, n_samples, loss_mode, lambda_d, lambda_sigma):
 
 def render_fwd(arch, params, ray_obj, t, dt, flags, *, bg=None, tgt_rgb=None, tgt_depth=None,
                mask=None, loss_mode=0, lambda_d=0.0, lambda_sigma=0.0, want_samples=False,
-               want_relu_signature=False):
+               want_relu_signature=False, emulate=False):
     params = _f32(params)
     ray_obj = _f32(ray_obj).reshape(-1, 6)
     n = ray_obj.shape[0]
@@ -265,7 +281,7 @@ def render_fwd(arch, params, ray_obj, t, dt, flags, *, bg=None, tgt_rgb=None, tg
     dt = _f32(dt).reshape(n, S)
     flags = _u8(flags)
     bg, tgt_rgb, tgt_depth, mask = _f32(bg), _f32(tgt_rgb), _f32(tgt_depth), _u8(mask)
-    cfg = _render_cfg(arch, S, loss_mode, lambda_d, lambda_sigma)
+    cfg = _render_cfg(arch, S, loss_mode, lambda_d, lambda_sigma, emulate)
     out = dict(rgb=np.empty((n, 3)), depth=np.empty(n), opacity=np.empty(n))
     ray_loss = np.empty(n) if tgt_rgb is not None else None
     loss = np.zeros(1) if tgt_rgb is not None else None
@@ -288,9 +304,11 @@ def render_fwd(arch, params, ray_obj, t, dt, flags, *, bg=None, tgt_rgb=None, tg
 
 def render_bwd(arch, params, ray_obj, t, dt, flags, *, bg=None, tgt_rgb=None, tgt_depth=None,
                mask=None, d_rgb=None, d_depth=None, d_opacity=None, loss_mode=0, lambda_d=0.0,
-               lambda_sigma=0.0):
+               lambda_sigma=0.0, emulate=False):
     """Parameter gradient [n_params] (FP64) of the fused loss, or of
-    sum(d_rgb * rgb + d_depth * depth + d_opacity * opacity) when d_rgb is given."""
+    sum(d_rgb * rgb + d_depth * depth + d_opacity * opacity) when d_rgb is given.
+    emulate: the reduced-precision method's own gradient (operands rounded
+    as the arch's mlp_dtype / table_dtype say)."""
     params = _f32(params)
     ray_obj = _f32(ray_obj).reshape(-1, 6)
     n = ray_obj.shape[0]
@@ -300,7 +318,7 @@ def render_bwd(arch, params, ray_obj, t, dt, flags, *, bg=None, tgt_rgb=None, tg
     flags = _u8(flags)
     bg, tgt_rgb, tgt_depth, mask = _f32(bg), _f32(tgt_rgb), _f32(tgt_depth), _u8(mask)
     d_rgb, d_depth, d_opacity = _f32(d_rgb), _f32(d_depth), _f32(d_opacity)
-    cfg = _render_cfg(arch, S, loss_mode, lambda_d, lambda_sigma)
+    cfg = _render_cfg(arch, S, loss_mode, lambda_d, lambda_sigma, emulate)
     grads = np.zeros(params.shape[0], np.float64)
     lib().orc_render_bwd(C.byref(cfg), _p(params, _f32p), _p(ray_obj, _f32p), _p(t, _f32p),
                          _p(dt, _f32p), _p(flags, _u8p), n, _p(bg, _f32p), _p(tgt_rgb, _f32p),

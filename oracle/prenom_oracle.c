@@ -22,6 +22,21 @@
  *     product x * N_l.
  * Everything else is plain FP64 and compared with the GPU under tolerance.
  *
+ * Reduced-precision emulation (arch.mlp_dtype BF16 or FP16, arch.table_dtype
+ * FP16).  The reduced-precision form rounds every operand of an MLP matrix
+ * product to the 16-bit type (from its FP32 value, round to nearest even)
+ * and accumulates in FP32; the forward gathers read an FP16 copy of the
+ * tables.  A ReLU's on/off decision is a float deciding an integer, and
+ * operand rounding moves pre-activations by ~2^-9 (BF16) of their scale, so
+ * an oracle without that rounding disagrees on a fraction of the masks and
+ * therefore on O(sqrt(eps)) of every gradient.  In this mode the oracle
+ * rounds the same operands at the same points (weights, layer inputs, head
+ * adjoint, deltas, the activations of the weight-gradient products, FP16
+ * table values in the forward) and keeps everything else FP64, so it is the
+ * exact result of the reduced-precision method.  The rounding helpers follow
+ * the IEEE 754 binary16 and the bfloat16 (binary32 with 8 significand bits)
+ * definitions.
+ *
  * Parallelism: OpenMP over rays for per-ray work; every reduction (loss,
  * gradients) is summed serially in ray order, so results do not depend on the
  * thread count.
@@ -50,7 +65,34 @@ typedef struct {
     int32_t res[ORC_MAX_LEVELS];
     int32_t width;
     int32_t hidden;
+    int32_t mlp_dtype;   /* 0: FP64 products; 1: BF16 operands; 2: FP16 operands */
+    int32_t table_dtype; /* 0: FP32 table values; 2: the forward reads them rounded to FP16 */
 } orc_arch;
+
+#define ORC_F32 0
+#define ORC_BF16 1
+#define ORC_F16 2
+
+/* x rounded to FP32 (the value a kernel holds), then to the nearest value of
+ * the 16-bit type, ties to even.  bfloat16: 8 significand bits, the binary32
+ * exponent range.  binary16: 11 significand bits, normal exponents -14..15,
+ * subnormal spacing 2^-24, overflow to infinity from 65520 up. */
+static double orc_round16(double x, int dtype)
+{
+    if (dtype == ORC_F32) return x;
+    const double f = (double)(float)x;
+    if (f == 0.0 || isnan(f) || isinf(f)) return f;
+    int e;
+    frexp(f, &e);  /* |f| in [2^(e-1), 2^e) */
+    if (dtype == ORC_BF16) {
+        const double q = ldexp(1.0, e - 1 - 7);  /* spacing of 8 significand bits */
+        return rint(f / q) * q;                  /* rint: nearest, ties to even */
+    }
+    if (fabs(f) >= 65520.0) return f > 0 ? INFINITY : -INFINITY;
+    const int ee = (e - 1 < -14) ? -14 : e - 1;  /* subnormals share the 2^-14 binade's spacing */
+    const double q = ldexp(1.0, ee - 10);
+    return rint(f / q) * q;
+}
 
 typedef struct {
     int32_t n_coarse;       /* N_c */
@@ -334,6 +376,9 @@ static void orc_level_corners(int32_t N, int32_t log2T, const float x[3], uint32
     }
 }
 
+/* A table value as the forward gathers read it. */
+static double orc_table_value(const orc_arch* a, float v) { return orc_round16((double)v, a->table_dtype); }
+
 static void orc_encode_point(const orc_arch* a, const float* table, const float x[3], double* y)
 {
     const int64_t T = (int64_t)1 << a->log2_table;
@@ -344,7 +389,7 @@ static void orc_encode_point(const orc_arch* a, const float* table, const float 
         orc_level_corners(a->res[l], a->log2_table, x, idx, w);
         for (int p = 0; p < F; ++p) {
             double s = 0.0;
-            for (int e = 0; e < 8; ++e) s += w[e] * (double)table[((int64_t)l * T + idx[e]) * F + p];
+            for (int e = 0; e < 8; ++e) s += w[e] * orc_table_value(a, table[((int64_t)l * T + idx[e]) * F + p]);
             y[l * F + p] = s;
         }
     }
@@ -364,7 +409,7 @@ void orc_encode(const orc_arch* a, const float* table, const float* pos, int64_t
             orc_level_corners(a->res[l], a->log2_table, pos + 3 * i, idx, w);
             for (int p = 0; p < F; ++p) {
                 double s = 0.0;
-                for (int e = 0; e < 8; ++e) s += w[e] * (double)table[((int64_t)l * T + idx[e]) * F + p];
+                for (int e = 0; e < 8; ++e) s += w[e] * orc_table_value(a, table[((int64_t)l * T + idx[e]) * F + p]);
                 y[((int64_t)l * n + i) * F + p] = s;
             }
             for (int e = 0; e < 8; ++e) {
@@ -387,6 +432,7 @@ typedef struct {
     int in_dim[8];
     int out_dim[8];
     int n_layers;
+    int dtype;         /* operand type of the products (orc_round16) */
 } orc_mlp_view;
 
 static orc_mlp_view orc_mlp_layers(const orc_arch* a, const float* mlp)
@@ -395,6 +441,7 @@ static orc_mlp_view orc_mlp_layers(const orc_arch* a, const float* mlp)
     const int in = a->n_levels * a->n_features;
     int64_t off = 0;
     v.n_layers = a->hidden + 1;
+    v.dtype = a->mlp_dtype;
     for (int k = 0; k < v.n_layers; ++k) {
         v.in_dim[k] = (k == 0) ? in : a->width;
         v.out_dim[k] = (k == a->hidden) ? ORC_N_OUT : a->width;
@@ -415,7 +462,8 @@ static void orc_mlp_point(const orc_mlp_view* v, const double* y, double* h /* [
         const float* W = v->W[k];
         for (int i = 0; i < v->out_dim[k]; ++i) {
             double s = 0.0;
-            for (int j = 0; j < v->in_dim[k]; ++j) s += (double)W[(int64_t)i * v->in_dim[k] + j] * hin[j];
+            for (int j = 0; j < v->in_dim[k]; ++j)
+                s += orc_round16((double)W[(int64_t)i * v->in_dim[k] + j], v->dtype) * orc_round16(hin[j], v->dtype);
             hout[i] = (k + 1 < v->n_layers) ? (s > 0.0 ? s : 0.0) : s;
         }
     }
@@ -801,11 +849,14 @@ void orc_render_bwd(const orc_render_cfg* c, const float* params, const float* r
                         const double* hin = hj + (size_t)k * s.maxw;
                         const float* W = mv.W[k];
                         double* gout = (k > 0) ? dh2 : (dY + (q * S + j) * in_dim);
+                        const int dt = mv.dtype;
                         for (int i = 0; i < out; ++i)
-                            for (int jj = 0; jj < in; ++jj) dWr[off + (int64_t)i * in + jj] += g[i] * hin[jj];
+                            for (int jj = 0; jj < in; ++jj)
+                                dWr[off + (int64_t)i * in + jj] += orc_round16(g[i], dt) * orc_round16(hin[jj], dt);
                         for (int jj = 0; jj < in; ++jj) {
                             double acc = 0.0;
-                            for (int i = 0; i < out; ++i) acc += (double)W[(int64_t)i * in + jj] * g[i];
+                            for (int i = 0; i < out; ++i)
+                                acc += orc_round16((double)W[(int64_t)i * in + jj], dt) * orc_round16(g[i], dt);
                             /* ReLU' of the layer below (hin > 0 <=> pre-activation > 0) */
                             gout[jj] = (k > 0) ? (hin[jj] > 0.0 ? acc : 0.0) : acc;
                         }
@@ -869,6 +920,12 @@ void orc_adam(int64_t n, const float* p, const float* g, const float* m, const f
         m_out[i] = mi;
         v_out[i] = vi;
     }
+}
+
+/* Element-wise orc_round16 (for the pins of the rounding rule). */
+void orc_round16_array(const double* x, int64_t n, int32_t dtype, double* out)
+{
+    for (int64_t i = 0; i < n; ++i) out[i] = orc_round16(x[i], dtype);
 }
 
 int32_t orc_max_threads(void)

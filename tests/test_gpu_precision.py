@@ -1,8 +1,17 @@
 """Reduced-precision form: MLP operands in BF16 or FP16 on the matrix cores
 with FP32 accumulation, FP16 table storage read by the forward gathers, FP32
-master weights and table-gradient accumulation, dynamic loss scaling.  Errors
-against the FP64 oracle (which uses the FP32 masters) are reported per output
-and held to 2e-3; the loss-scaling state machine is driven from the host."""
+master weights and table-gradient accumulation, dynamic loss scaling.
+
+Two comparisons per output (colour, depth, opacity, loss, table and MLP
+gradients), both reported:
+  * against the oracle emulating the reduced-precision method (the same
+    operands rounded at the same points, FP64 elsewhere): held to 2e-3;
+  * against the plain FP64 method: reported.  Forward outputs stay within
+    2e-3 of it; gradients do not, because operand rounding moves ReLU
+    pre-activations across zero for ~eps of the units and each such flip
+    changes that unit's delta by O(1), so gradients differ by O(sqrt(eps))
+    (about 5% for BF16, 1.5% for FP16); they are held to 10%.
+The loss-scaling state machine is driven from the host."""
 from __future__ import annotations
 
 import dataclasses
@@ -61,24 +70,30 @@ def test_reduced_precision_against_oracle(mlp_dtype, table_dtype):
     out = api.prenom_render_fwd(model, samp, b.loss, ws, **kw)
     api.prenom_render_bwd(model, samp, b.loss, ws, **kw)
     torch.cuda.synchronize()
-    ref = orc.render_fwd(arch, params, *geo, tgt_rgb=b.tgt_rgb, tgt_depth=b.tgt_depth, mask=b.mask,
-                         lambda_d=0.1)
-    g_ref = orc.render_bwd(arch, params, *geo, tgt_rgb=b.tgt_rgb, tgt_depth=b.tgt_depth,
-                           mask=b.mask, lambda_d=0.1)
+    got = {"rgb": out["rgb"].cpu().numpy(), "depth": out["depth"].cpu().numpy(),
+           "opacity": out["opacity"].cpu().numpy(), "loss": out["loss"].cpu().numpy()}
     g = model.grads.cpu().numpy().astype(np.float64) / scale
     nt = arch.n_table_params
-    errs = {
-        "rgb": rel_errors(out["rgb"].cpu().numpy(), ref["rgb"]),
-        "depth": rel_errors(out["depth"].cpu().numpy(), ref["depth"]),
-        "opacity": rel_errors(out["opacity"].cpu().numpy(), ref["opacity"]),
-        "loss": rel_errors(out["loss"].cpu().numpy(), [ref["loss"]]),
-        "g_table": rel_errors(g[:nt], g_ref[:nt]),
-        "g_mlp": rel_errors(g[nt:], g_ref[nt:]),
-    }
-    for k, (em, e2) in errs.items():
-        print(f"  {k:8s} max-rel {em:.2e}  2-rel {e2:.2e}", flush=True)
-    bad = {k: v for k, v in errs.items() if not (v[0] <= TOL_LOWP and v[1] <= TOL_LOWP)}
+    kw = dict(tgt_rgb=b.tgt_rgb, tgt_depth=b.tgt_depth, mask=b.mask, lambda_d=np.float32(0.1))
+    report = {}
+    for emulate in (True, False):
+        ref = orc.render_fwd(arch, params, *geo, emulate=emulate, **kw)
+        g_ref = orc.render_bwd(arch, params, *geo, emulate=emulate, **kw)
+        errs = {k: rel_errors(got[k], ref[k] if k != "loss" else [ref["loss"]])
+                for k in ("rgb", "depth", "opacity", "loss")}
+        errs["g_table"] = rel_errors(g[:nt], g_ref[:nt])
+        errs["g_mlp"] = rel_errors(g[nt:], g_ref[nt:])
+        report[emulate] = errs
+    print("  output    vs emulated method (max-rel / 2-rel)   vs plain FP64 method", flush=True)
+    for k in report[True]:
+        e, p_ = report[True][k], report[False][k]
+        print(f"  {k:8s}  {e[0]:.2e} / {e[1]:.2e}               {p_[0]:.2e} / {p_[1]:.2e}", flush=True)
+    bad = {k: v for k, v in report[True].items() if not (v[0] <= TOL_LOWP and v[1] <= TOL_LOWP)}
     assert not bad, bad
+    for k in ("rgb", "depth", "opacity", "loss"):
+        assert report[False][k][1] <= TOL_LOWP, (k, report[False][k])
+    for k in ("g_table", "g_mlp"):
+        assert report[False][k][1] <= 0.1, (k, report[False][k])
 
 
 def test_loss_scaling_skips_non_finite_steps_and_adapts():

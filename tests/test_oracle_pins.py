@@ -559,20 +559,19 @@ def test_p11_upstream_gradient_mode_is_vjp():
         assert abs(fd - g[i]) <= 2e-4 * gmax + 1e-9, (i, fd, g[i])
 
 
-def test_p11_backward_matches_float64_autograd():
-    """Independent cross-check of the hand-written adjoint: the same forward
-    written with torch float64 autograd (corner indices and weights, which do
-    not depend on the parameters, taken from the oracle's encoder)."""
-    torch = pytest.importorskip("torch")
-    arch, params, geo, kw, rng = _fd_setup(lambda_d=0.2, lambda_sigma=1e-2)
+def _torch_render_loss(torch, arch, params, geo, kw, matmul, table_view):
+    """The render + fused loss of the oracle's workload written in torch
+    float64 autograd; `matmul(h, W)` forms each layer's product and
+    `table_view(T)` what the forward gathers read of the tables.  Corner
+    indices and weights (independent of the parameters) come from the
+    oracle's encoder."""
     ray_obj, t, dt, flags = geo
     n, S = t.shape
-    g = orc.render_bwd(arch, params, *geo, **kw)
     pos = orc.positions(ray_obj, t)  # FP32 positions as the kernels form them
     _, idx, w = orc.encode(arch, params[:arch.n_table_params], pos.reshape(-1, 3), with_corners=True)
     P = torch.tensor(params.astype(np.float64), requires_grad=True)
     T_ = arch.table_size
-    tab = P[:arch.n_table_params].view(arch.n_levels, T_, 2)
+    tab = table_view(P[:arch.n_table_params]).view(arch.n_levels, T_, 2)
     ys = []
     for l in range(arch.n_levels):
         rows = tab[l][torch.tensor(idx[l].astype(np.int64))]          # [n*S, 8, 2]
@@ -584,8 +583,8 @@ def test_p11_backward_matches_float64_autograd():
         Ws.append(P[off:off + o_ * i_].view(o_, i_))
         off += o_ * i_
     for W in Ws[:-1]:
-        h = torch.relu(h @ W.T)
-    out = h @ Ws[-1].T
+        h = torch.relu(matmul(h, W))
+    out = matmul(h, Ws[-1])
     sigma = torch.exp(out[:, 0]).view(n, S)
     col = torch.sigmoid(out[:, 1:]).view(n, S, 3)
     dtt = torch.tensor(dt.astype(np.float64))
@@ -606,9 +605,80 @@ def test_p11_backward_matches_float64_autograd():
     L = ((C - tgt) ** 2).sum() / (3 * n) + lam_d * (m * (D - td) ** 2).sum() / n \
         + lam_s * ((1 - m) * (sigma * live[:, None]).sum(1)).sum() / n
     L.backward()
-    np.testing.assert_allclose(g, P.grad.numpy(), rtol=1e-9, atol=1e-12 * np.abs(g).max())
+    return L.item(), P.grad.numpy()
+
+
+def test_p11_backward_matches_float64_autograd():
+    """Independent cross-check of the hand-written adjoint: the same forward
+    written with torch float64 autograd."""
+    torch = pytest.importorskip("torch")
+    arch, params, geo, kw, rng = _fd_setup(lambda_d=0.2, lambda_sigma=1e-2)
+    g = orc.render_bwd(arch, params, *geo, **kw)
+    L, gt = _torch_render_loss(torch, arch, params, geo, kw, lambda h, W: h @ W.T, lambda T: T)
+    np.testing.assert_allclose(g, gt, rtol=1e-9, atol=1e-12 * np.abs(g).max())
     lo = orc.render_fwd(arch, params, *geo, **kw)["loss"]
-    assert abs(lo - L.item()) < 1e-12
+    assert abs(lo - L) < 1e-12
+
+
+# --------------------------------------------------------------------------
+# P15: reduced-precision emulation
+
+def test_p15_rounding_matches_numpy_and_torch_casts():
+    """The emulation's rounding (via FP32, nearest, ties to even) equals
+    numpy's binary16 cast and torch's bfloat16 cast, over 12 decades plus
+    subnormals, overflow and exact ties."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=200000) * np.exp(rng.uniform(-30, 12, 200000))
+    ties = np.array([1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, 1 + 2.0 ** -11, 1 + 3 * 2.0 ** -11, 65504.0, 65519.0, 65520.0,
+                     2.0 ** -24, 3 * 2.0 ** -25, 2.0 ** -25, -0.0, 0.0])
+    x = np.concatenate([x, ties, -ties])
+    with np.errstate(over="ignore"):
+        ref16 = x.astype(np.float32).astype(np.float16).astype(np.float64)
+    np.testing.assert_array_equal(orc.round16(x, "fp16"), ref16)
+    refb = torch.tensor(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(orc.round16(x, "bf16"), refb)
+    np.testing.assert_array_equal(orc.round16(x, "fp32"), x)
+
+
+@pytest.mark.parametrize("mlp_dtype,table_dtype", [("bf16", "fp32"), ("fp16", "fp16")])
+def test_p15_emulated_gradient_matches_rounded_autograd(mlp_dtype, table_dtype):
+    """The emulated method against the same method written in torch float64
+    autograd: each layer product takes operands rounded by torch's own casts
+    (forward R(h) R(W)^T; adjoint R(g) R(W) and R(g)^T R(h)), the forward
+    reads FP16-rounded table values with the gradient passed straight to the
+    FP32 entries.  Both the loss and every gradient entry must agree."""
+    torch = pytest.importorskip("torch")
+    import dataclasses
+    arch0, params, geo, kw, rng = _fd_setup(lambda_d=0.2, lambda_sigma=1e-2)
+    arch = dataclasses.replace(arch0, mlp_dtype=mlp_dtype, table_dtype=table_dtype)
+    tdt = {"bf16": torch.bfloat16, "fp16": torch.float16}[mlp_dtype]
+    R = lambda x: x.to(torch.float32).to(tdt).to(torch.float64)
+
+    class RoundedProduct(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, h, W):
+            ctx.save_for_backward(h, W)
+            return R(h) @ R(W).T
+
+        @staticmethod
+        def backward(ctx, g):
+            h, W = ctx.saved_tensors
+            return R(g) @ R(W), R(g).T @ R(h)
+
+    def table_view(T):
+        if table_dtype == "fp32":
+            return T
+        return T + (T.detach().to(torch.float32).to(torch.float16).to(torch.float64) - T.detach())
+
+    L, gt = _torch_render_loss(torch, arch, params, geo, kw, RoundedProduct.apply, table_view)
+    g = orc.render_bwd(arch, params, *geo, emulate=True, **kw)
+    lo = orc.render_fwd(arch, params, *geo, emulate=True, **kw)["loss"]
+    assert abs(lo - L) < 1e-12 * max(1.0, abs(L))
+    np.testing.assert_allclose(g, gt, rtol=1e-9, atol=1e-12 * np.abs(g).max())
+    # and it is not the plain method
+    g_plain = orc.render_bwd(arch0, params, *geo, **kw)
+    assert np.abs(g - g_plain).max() > 1e-6 * np.abs(g_plain).max()
 
 
 # --------------------------------------------------------------------------
