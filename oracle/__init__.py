@@ -58,6 +58,7 @@ class OrcRenderCfg(C.Structure):
         ("loss_mode", C.c_int32),
         ("lambda_d", C.c_double),
         ("lambda_sigma", C.c_double),
+        ("grad_scale", C.c_double),
     ]
 
 
@@ -260,13 +261,14 @@ def composite_bwd(sigma, rgb, t, dt, bg, gC, gD, gA=None):
 
 # ---------------------------------------------------------------- render
 
-def _render_cfg(arch, n_samples, loss_mode, lambda_d, lambda_sigma, emulate=False):
+def _render_cfg(arch, n_samples, loss_mode, lambda_d, lambda_sigma, emulate=False, grad_scale=1.0):
     c = OrcRenderCfg()
     c.arch = make_arch(arch, emulate)
     c.n_samples = n_samples
     c.loss_mode = loss_mode
     c.lambda_d = float(np.float32(lambda_d))
     c.lambda_sigma = float(np.float32(lambda_sigma))
+    c.grad_scale = float(grad_scale)
     return c
 
 
@@ -304,11 +306,12 @@ def render_fwd(arch, params, ray_obj, t, dt, flags, *, bg=None, tgt_rgb=None, tg
 
 def render_bwd(arch, params, ray_obj, t, dt, flags, *, bg=None, tgt_rgb=None, tgt_depth=None,
                mask=None, d_rgb=None, d_depth=None, d_opacity=None, loss_mode=0, lambda_d=0.0,
-               lambda_sigma=0.0, emulate=False):
+               lambda_sigma=0.0, emulate=False, loss_scale=1.0):
     """Parameter gradient [n_params] (FP64) of the fused loss, or of
     sum(d_rgb * rgb + d_depth * depth + d_opacity * opacity) when d_rgb is given.
     emulate: the reduced-precision method's own gradient (operands rounded
-    as the arch's mlp_dtype / table_dtype say)."""
+    as the arch's mlp_dtype / table_dtype say, gradient operands carrying
+    the power-of-two loss_scale when rounded); the result is unscaled."""
     params = _f32(params)
     ray_obj = _f32(ray_obj).reshape(-1, 6)
     n = ray_obj.shape[0]
@@ -318,7 +321,7 @@ def render_bwd(arch, params, ray_obj, t, dt, flags, *, bg=None, tgt_rgb=None, tg
     flags = _u8(flags)
     bg, tgt_rgb, tgt_depth, mask = _f32(bg), _f32(tgt_rgb), _f32(tgt_depth), _u8(mask)
     d_rgb, d_depth, d_opacity = _f32(d_rgb), _f32(d_depth), _f32(d_opacity)
-    cfg = _render_cfg(arch, S, loss_mode, lambda_d, lambda_sigma, emulate)
+    cfg = _render_cfg(arch, S, loss_mode, lambda_d, lambda_sigma, emulate, loss_scale)
     grads = np.zeros(params.shape[0], np.float64)
     lib().orc_render_bwd(C.byref(cfg), _p(params, _f32p), _p(ray_obj, _f32p), _p(t, _f32p),
                          _p(dt, _f32p), _p(flags, _u8p), n, _p(bg, _f32p), _p(tgt_rgb, _f32p),

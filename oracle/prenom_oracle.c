@@ -33,7 +33,10 @@
  * rounds the same operands at the same points (weights, layer inputs, head
  * adjoint, deltas, the activations of the weight-gradient products, FP16
  * table values in the forward) and keeps everything else FP64, so it is the
- * exact result of the reduced-precision method.  The rounding helpers follow
+ * exact result of the reduced-precision method.  Gradients reach the matrix
+ * cores multiplied by the loss scale s (a power of two, so scaling is
+ * exact), which keeps small FP16 values out of the subnormal range: a
+ * gradient operand g is rounded as round(g s) / s.  The rounding helpers follow
  * the IEEE 754 binary16 and the bfloat16 (binary32 with 8 significand bits)
  * definitions.
  *
@@ -112,6 +115,7 @@ typedef struct {
     int32_t loss_mode;  /* 0: mean squared errors, 1: the norms of Eq. (8) */
     double lambda_d;
     double lambda_sigma;
+    double grad_scale;  /* emulation: gradients carry this loss scale (a power of two) when rounded */
 } orc_render_cfg;
 
 /* ------------------------------------------------------------------------ */
@@ -808,6 +812,7 @@ void orc_render_bwd(const orc_render_cfg* c, const float* params, const float* r
             double* drgb = (double*)malloc(sizeof(double) * (size_t)S * 3);
             double* dh = (double*)malloc(sizeof(double) * (size_t)(s.maxw));
             double* dh2 = (double*)malloc(sizeof(double) * (size_t)(s.maxw));
+            double* gr = (double*)malloc(sizeof(double) * (size_t)(s.maxw > ORC_N_OUT ? s.maxw : ORC_N_OUT));
 #pragma omp for schedule(dynamic, 4)
             for (int64_t r = r0; r < r1; ++r) {
                 const int64_t q = r - r0;
@@ -850,13 +855,14 @@ void orc_render_bwd(const orc_render_cfg* c, const float* params, const float* r
                         const float* W = mv.W[k];
                         double* gout = (k > 0) ? dh2 : (dY + (q * S + j) * in_dim);
                         const int dt = mv.dtype;
+                        const double gs = (dt == ORC_F32 || !(c->grad_scale > 0.0)) ? 1.0 : c->grad_scale;
+                        for (int i = 0; i < out; ++i) gr[i] = orc_round16(g[i] * gs, dt) / gs;
                         for (int i = 0; i < out; ++i)
                             for (int jj = 0; jj < in; ++jj)
-                                dWr[off + (int64_t)i * in + jj] += orc_round16(g[i], dt) * orc_round16(hin[jj], dt);
+                                dWr[off + (int64_t)i * in + jj] += gr[i] * orc_round16(hin[jj], dt);
                         for (int jj = 0; jj < in; ++jj) {
                             double acc = 0.0;
-                            for (int i = 0; i < out; ++i)
-                                acc += orc_round16((double)W[(int64_t)i * in + jj], dt) * orc_round16(g[i], dt);
+                            for (int i = 0; i < out; ++i) acc += orc_round16((double)W[(int64_t)i * in + jj], dt) * gr[i];
                             /* ReLU' of the layer below (hin > 0 <=> pre-activation > 0) */
                             gout[jj] = (k > 0) ? (hin[jj] > 0.0 ? acc : 0.0) : acc;
                         }
@@ -872,6 +878,7 @@ void orc_render_bwd(const orc_render_cfg* c, const float* params, const float* r
             free(drgb);
             free(dh);
             free(dh2);
+            free(gr);
             orc_state_free(&s);
         }
         /* serial accumulation in ray order */

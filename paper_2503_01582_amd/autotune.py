@@ -22,7 +22,7 @@ from typing import Dict, Iterable, List, Optional
 import numpy as np
 
 FWD_CANDIDATES = (16, 32, 64, 128, 256, 512)
-BWD_CANDIDATES = (128, 256, 512, 1024, 2048, 4096)
+BWD_CANDIDATES = (32, 64, 128, 256, 512, 1024)
 PACKAGED = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tiles_gfx950.json")
 
 

@@ -471,7 +471,8 @@ prenom_status prenom_render_bwd(const prenom_model* model, const prenom_render_c
     sa.work_counter = at<unsigned long long>(workspace, w.work_counter);
     sa.keys = at<uint16_t>(workspace, w.keys);
     sa.vals = at<float2>(workspace, w.vals);
-    PRENOM_LAUNCH("k_encode_bwd", s, launch_scatter(sa, s));
+    for (int ph = 0; ph < kScatterPhases; ++ph)
+        PRENOM_LAUNCH(kScatterPhaseNames[ph], s, launch_scatter_phase(sa, ph, s));
     return PRENOM_OK;
 }
 

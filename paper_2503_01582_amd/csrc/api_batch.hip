@@ -558,7 +558,11 @@ prenom_status prenom_batch_render_bwd(const prenom_batch* batch, const prenom_re
     PRENOM_LAUNCH("k_reduce_partials", s,
                   launch_reduce_partials_batch(at<const MlpRed>(workspace, p.o_red), p.n_obj, p.n_mlp_total, partial,
                                                batch->grads, s));
-    PRENOM_LAUNCH("k_encode_bwd", s, launch_scatter(scatter_args(p, workspace, ray_obj, t, batch->grads), s));
+    {
+        const ScatterArgs sa = scatter_args(p, workspace, ray_obj, t, batch->grads);
+        for (int ph = 0; ph < kScatterPhases; ++ph)
+            PRENOM_LAUNCH(kScatterPhaseNames[ph], s, launch_scatter_phase(sa, ph, s));
+    }
     return PRENOM_OK;
 }
 

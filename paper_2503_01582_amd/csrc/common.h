@@ -199,7 +199,12 @@ struct ScatterArgs {
     uint16_t* keys;         // [records]
     float2* vals;           // [records]
 };
-hipError_t launch_scatter(const ScatterArgs& a, hipStream_t s);
+// The scatter runs as kScatterPhases dependent kernels, launched in order
+// (phase 0 .. kScatterPhases - 1): count, per-level max, scan over blocks,
+// scan over tiles, place, reduce.
+constexpr int kScatterPhases = 6;
+extern const char* const kScatterPhaseNames[kScatterPhases];
+hipError_t launch_scatter_phase(const ScatterArgs& a, int phase, hipStream_t s);
 
 // MLP: forward writes (sigma, r, g, b) per sample; backward recomputes the
 // activations, writes dy and per-wave partial weight gradients.

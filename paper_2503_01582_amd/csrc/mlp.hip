@@ -511,18 +511,25 @@ __device__ void mlp_chain_bwd_tiles(const float* __restrict__ bfrag, const float
     }
 }
 
-// Weight gradient over samples [s_begin, s_end) of one object: wave w owns
-// rows [16 RT w, 16 RT (w + 1)) of W_1 and the hidden matrices and columns
-// [16 RT w, 16 RT (w + 1)) of W_out, so the block's partial is written
-// without any merge.  MFMA K = 4 consecutive samples.
+// Weight gradient over samples [s_begin, s_end) of one object, staged
+// kDwChunk samples at a time in LDS: wave w owns rows [16 RT w, 16 RT (w+1))
+// of W_1 and the hidden matrices and columns [16 RT w, 16 RT (w+1)) of W_out,
+// so the block's partial is written without any merge.  MFMA K = 4
+// consecutive samples.
+constexpr int kDwPitchF32 = kWideWidth + 16;  // 144 = 16 mod 64: lanes q one sample apart, no bank conflict
+constexpr int kDwPitchY = 48;
+
 template <int IN, int W, int D>
-__device__ void mlp_dw_range(const float* __restrict__ y, const float4* __restrict__ sc, const float4* __restrict__ dout,
-                             const float* __restrict__ act, const float* __restrict__ dlt, int64_t n_s,
-                             int64_t s_begin, int64_t s_end, float* __restrict__ dst)
+__device__ void mlp_dw_range(float* __restrict__ lds, const float* __restrict__ y, const float4* __restrict__ sc,
+                             const float4* __restrict__ dout, const float* __restrict__ act,
+                             const float* __restrict__ dlt, int64_t n_s, int64_t s_begin, int64_t s_end,
+                             float* __restrict__ dst)
 {
     using N = Net<IN, W, D>;
+    constexpr int PW = kDwPitchF32, PY = kDwPitchY;
+    using St = DwStage<W, D, PW, PY>;
     constexpr int RT = N::OT / kWideWaves;
-    static_assert(N::OT % kWideWaves == 0, "rows per wave");
+    static_assert(N::OT % kWideWaves == 0 && W + 16 == PW, "rows per wave, pitch");
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, j = lane & 15;
     floatx4 aH[D > 1 ? D - 1 : 1][RT][N::OT], a1[RT][N::IT], aO[RT];
 #pragma unroll
@@ -535,50 +542,46 @@ __device__ void mlp_dw_range(const float* __restrict__ y, const float4* __restri
 #pragma unroll
             for (int t = 0; t < N::OT; ++t) aH[k][a][t] = {0.0f, 0.0f, 0.0f, 0.0f};
     }
-    for (int64_t s0 = s_begin; s0 < s_end; s0 += 4) {
-        const int64_t sk = s0 + q;
-        const bool ok = sk < s_end;
-        // W_out: A[i][k] = dO_i(sample s0 + k), rows i >= 4 zero; B = h_{D-1}
-        float dOi = 0.0f;
-        if (ok && j < 4) {
-            const float4 g = dout[sk], v = sc[sk];
-            dOi = j == 0 ? g.x * v.x : (j == 1 ? g.y * v.y * (1.0f - v.y)
-                                               : (j == 2 ? g.z * v.z * (1.0f - v.z) : g.w * v.w * (1.0f - v.w)));
-        }
-        const float* hl = act + ((int64_t)(D - 1) * n_s + sk) * W;
+    for (int64_t c0 = s_begin; c0 < s_end; c0 += kDwChunk) {
+        dw_stage<IN, W, D, PW, PY>(lds, y, sc, dout, act, dlt, n_s, c0, s_end);
+        __syncthreads();
+#pragma unroll 2
+        for (int ks = 0; ks < kDwChunk / 4; ++ks) {
+            const int r = 4 * ks + q;  // the lane's sample within the chunk
+            // W_out: A[i][k] = dO_i (rows i >= 4 zero), B = h_{D-1}
+            const float dOi = j < 4 ? lds[St::DO + r * 4 + j] : 0.0f;
+            const float* hl = lds + St::AC + ((D - 1) * kDwChunk + r) * PW;
 #pragma unroll
-        for (int a = 0; a < RT; ++a) aO[a] = mfma4(dOi, ok ? hl[16 * (RT * wave + a) + j] : 0.0f, aO[a]);
-        // hidden layers: A = delta_k rows, B = h_{k-1}
+            for (int a = 0; a < RT; ++a) aO[a] = mfma4(dOi, hl[16 * (RT * wave + a) + j], aO[a]);
 #pragma unroll
-        for (int k = 1; k < D; ++k) {
-            const float* dk = dlt + ((int64_t)k * n_s + sk) * W;
-            const float* hk = act + ((int64_t)(k - 1) * n_s + sk) * W;
-            float av[RT], bv[N::OT];
+            for (int k = 1; k < D; ++k) {
+                const float* dk = lds + St::DL + (k * kDwChunk + r) * PW;
+                const float* hk = lds + St::AC + ((k - 1) * kDwChunk + r) * PW;
+                float av[RT], bv[N::OT];
 #pragma unroll
-            for (int a = 0; a < RT; ++a) av[a] = ok ? dk[16 * (RT * wave + a) + j] : 0.0f;
+                for (int a = 0; a < RT; ++a) av[a] = dk[16 * (RT * wave + a) + j];
 #pragma unroll
-            for (int t = 0; t < N::OT; ++t) bv[t] = ok ? hk[16 * t + j] : 0.0f;
+                for (int t = 0; t < N::OT; ++t) bv[t] = hk[16 * t + j];
 #pragma unroll
-            for (int a = 0; a < RT; ++a)
+                for (int a = 0; a < RT; ++a)
 #pragma unroll
-                for (int t = 0; t < N::OT; ++t) aH[k - 1][a][t] = mfma4(av[a], bv[t], aH[k - 1][a][t]);
-        }
-        // W_1: A = delta_0 rows, B = the input features (zero beyond IN)
-        {
-            const float* d0 = dlt + sk * W;
-            float av[RT], bv[N::IT];
-#pragma unroll
-            for (int a = 0; a < RT; ++a) av[a] = ok ? d0[16 * (RT * wave + a) + j] : 0.0f;
-#pragma unroll
-            for (int t = 0; t < N::IT; ++t) {
-                const int f = 16 * t + j;
-                bv[t] = (ok && f < IN) ? y[((int64_t)(f >> 1) * n_s + sk) * 2 + (f & 1)] : 0.0f;
+                    for (int t = 0; t < N::OT; ++t) aH[k - 1][a][t] = mfma4(av[a], bv[t], aH[k - 1][a][t]);
             }
+            {
+                const float* d0 = lds + St::DL + r * PW;
+                const float* yr = lds + St::Y + r * PY;
+                float av[RT], bv[N::IT];
 #pragma unroll
-            for (int a = 0; a < RT; ++a)
+                for (int a = 0; a < RT; ++a) av[a] = d0[16 * (RT * wave + a) + j];
 #pragma unroll
-                for (int t = 0; t < N::IT; ++t) a1[a][t] = mfma4(av[a], bv[t], a1[a][t]);
+                for (int t = 0; t < N::IT; ++t) bv[t] = yr[16 * t + j];
+#pragma unroll
+                for (int a = 0; a < RT; ++a)
+#pragma unroll
+                    for (int t = 0; t < N::IT; ++t) a1[a][t] = mfma4(av[a], bv[t], a1[a][t]);
+            }
         }
+        __syncthreads();
     }
     // D layout: row 16 (RT w + a) + 4 q + r, column 16 t + j
 #pragma unroll
@@ -597,6 +600,12 @@ __device__ void mlp_dw_range(const float* __restrict__ y, const float4* __restri
                 for (int t = 0; t < N::OT; ++t) dst[N::OFF_H + (k - 1) * W * W + row * W + 16 * t + j] = aH[k - 1][a][t][r];
             if (q == 0) dst[N::OFF_OUT + r * W + 16 * (RT * wave + a) + j] = aO[a][r];
         }
+}
+
+template <int IN, int W, int D>
+constexpr size_t dw_lds_bytes()
+{
+    return sizeof(float) * (size_t)DwStage<W, D, kDwPitchF32, kDwPitchY>::FLOATS;
 }
 
 template <int IN, int W, int D>
@@ -638,9 +647,10 @@ __global__ __launch_bounds__(64 * kWideWaves) void k_mlp_dw(const float* __restr
                                                             int64_t tiles_per_block, float* __restrict__ partial)
 {
     using N = Net<IN, W, D>;
+    extern __shared__ float dw_lds[];
     const int64_t b = (int64_t)blockIdx.x * tiles_per_block * 16;
     const int64_t e = min(b + tiles_per_block * 16, n_s);
-    mlp_dw_range<IN, W, D>(y, sc, dout, act, act + (int64_t)D * n_s * W, n_s, b, e,
+    mlp_dw_range<IN, W, D>(dw_lds, y, sc, dout, act, act + (int64_t)D * n_s * W, n_s, b, e,
                            partial + (int64_t)blockIdx.x * N::N_PARAMS);
 }
 
@@ -652,11 +662,12 @@ __global__ __launch_bounds__(64 * kWideWaves) void k_mlp_dw_batch(const MlpWork*
                                                                   const float* __restrict__ act,
                                                                   float* __restrict__ partial, int64_t slot_stride)
 {
+    extern __shared__ float dw_lds[];
     const MlpWork wk = work[blockIdx.x];
     const int64_t b = wk.tile_begin * 16, e = min(wk.tile_end * 16, wk.n_s);
     const float* a = act + wk.a_off;
-    mlp_dw_range<IN, W, D>(y + wk.y_off, sc + wk.s_off, dout + wk.s_off, a, a + (int64_t)D * wk.n_s * W, wk.n_s, b, e,
-                           partial + (int64_t)blockIdx.x * slot_stride);
+    mlp_dw_range<IN, W, D>(dw_lds, y + wk.y_off, sc + wk.s_off, dout + wk.s_off, a, a + (int64_t)D * wk.n_s * W, wk.n_s,
+                           b, e, partial + (int64_t)blockIdx.x * slot_stride);
 }
 
 // Batch: thread per (object, MLP parameter); the object's partials summed in FP64.
@@ -736,7 +747,9 @@ hipError_t bwd_impl(const float* w, const float* y, const float* dout, const flo
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const int nb = bwd_blocks(n_s);
         const int64_t per = (n_tiles + nb - 1) / nb;
-        hipLaunchKernelGGL((k_mlp_dw<IN, W, D>), dim3((uint32_t)nb), dim3(64 * kWideWaves), 0, s, y,
+        const size_t dwl = dw_lds_bytes<IN, W, D>();
+        if ((e = set_lds(k_mlp_dw<IN, W, D>, dwl)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_mlp_dw<IN, W, D>), dim3((uint32_t)nb), dim3(64 * kWideWaves), dwl, s, y,
                            (const float4*)sc, (const float4*)dout, act, n_s, per, partial);
         return hipGetLastError();
     } else {
@@ -773,7 +786,9 @@ hipError_t bwd_batch_impl(const MlpWork* work, int n_blocks, const float* params
         hipLaunchKernelGGL((k_mlp_chain_bwd_batch<IN, W, D>), dim3((uint32_t)n_blocks), dim3(256), lds, s, work,
                            params, (const float4*)sc, (const float4*)dout, act, (float2*)dy);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_mlp_dw_batch<IN, W, D>), dim3((uint32_t)n_blocks), dim3(64 * kWideWaves), 0, s, work, y,
+        const size_t dwl = dw_lds_bytes<IN, W, D>();
+        if ((e = set_lds(k_mlp_dw_batch<IN, W, D>, dwl)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_mlp_dw_batch<IN, W, D>), dim3((uint32_t)n_blocks), dim3(64 * kWideWaves), dwl, s, work, y,
                            (const float4*)sc, (const float4*)dout, act, partial, slot_stride);
         return hipGetLastError();
     } else {

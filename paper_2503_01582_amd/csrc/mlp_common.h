@@ -88,4 +88,64 @@ __device__ __forceinline__ void merge_dw(float* __restrict__ dst, const floatx4 
             }
 }
 
+// ---------------------------------------------------------------- 128-wide weight gradient
+// The weight-gradient kernels of the 128-wide MLP stage a chunk of
+// kDwChunk samples in LDS: every layer's delta and activation rows (pitch PW
+// floats), the input features (pitch PY, zero beyond IN) and the head adjoint
+// dO, all loaded with coalesced vector reads; the MFMA operands are then read
+// from LDS.  PW is chosen per operand pattern so those reads are free of bank
+// conflicts (FP32: lanes q step one sample, PW = 16 mod 64; 16-bit operands:
+// lanes q step four samples, PW = 4 mod 16).
+constexpr int kDwChunk = 32;
+
+template <int W, int D, int PW, int PY>
+struct DwStage {
+    static constexpr int DL = 0;                          // deltas [D][chunk][PW]
+    static constexpr int AC = DL + D * kDwChunk * PW;     // activations [D][chunk][PW]
+    static constexpr int Y = AC + D * kDwChunk * PW;      // inputs [chunk][PY]
+    static constexpr int DO = Y + kDwChunk * PY;          // head adjoint [chunk][4]
+    static constexpr int FLOATS = DO + kDwChunk * 4;
+};
+
+// Samples [s0, min(s0 + kDwChunk, s_end)) of one object into LDS (zeros past
+// the end).  act/dlt: [D][n_s][W]; y: level-major [L][n_s][2].
+template <int IN, int W, int D, int PW, int PY>
+__device__ __forceinline__ void dw_stage(float* __restrict__ lds, const float* __restrict__ y,
+                                         const float4* __restrict__ sc, const float4* __restrict__ dout,
+                                         const float* __restrict__ act, const float* __restrict__ dlt, int64_t n_s,
+                                         int64_t s0, int64_t s_end)
+{
+    using St = DwStage<W, D, PW, PY>;
+    constexpr int V = W / 4;  // float4 per row
+    for (int i = threadIdx.x; i < D * kDwChunk * V; i += blockDim.x) {
+        const int k = i / (kDwChunk * V), rem = i % (kDwChunk * V), r = rem / V, c = rem % V;
+        const int64_t s = s0 + r;
+        floatx4 a = {0.0f, 0.0f, 0.0f, 0.0f}, d = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (s < s_end) {
+            a = *reinterpret_cast<const floatx4*>(act + ((int64_t)k * n_s + s) * W + 4 * c);
+            d = *reinterpret_cast<const floatx4*>(dlt + ((int64_t)k * n_s + s) * W + 4 * c);
+        }
+        *reinterpret_cast<floatx4*>(lds + St::AC + (k * kDwChunk + r) * PW + 4 * c) = a;
+        *reinterpret_cast<floatx4*>(lds + St::DL + (k * kDwChunk + r) * PW + 4 * c) = d;
+    }
+    // inputs: level pairs (2 features each) of every sample; columns >= IN zero
+    for (int i = threadIdx.x; i < kDwChunk * (PY / 2); i += blockDim.x) {
+        const int r = i / (PY / 2), l = i % (PY / 2);
+        const int64_t s = s0 + r;
+        float2 v = make_float2(0.0f, 0.0f);
+        if (s < s_end && 2 * l < IN) v = reinterpret_cast<const float2*>(y)[(int64_t)l * n_s + s];
+        *reinterpret_cast<float2*>(lds + St::Y + r * PY + 2 * l) = v;
+    }
+    if (threadIdx.x < kDwChunk) {
+        const int r = threadIdx.x;
+        const int64_t s = s0 + r;
+        floatx4 o = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (s < s_end) {  // d sigma / d o0 = sigma, d c / d o = c (1 - c)
+            const float4 g = dout[s], v = sc[s];
+            o = {g.x * v.x, g.y * v.y * (1.0f - v.y), g.z * v.z * (1.0f - v.z), g.w * v.w * (1.0f - v.w)};
+        }
+        *reinterpret_cast<floatx4*>(lds + St::DO + r * 4) = o;
+    }
+}
+
 }  // namespace prenom

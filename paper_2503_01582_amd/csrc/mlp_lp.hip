@@ -504,17 +504,23 @@ __device__ void mlp_chain_bwd_tiles_lp(const typename P::vec* __restrict__ bfrag
     }
 }
 
-// Weight gradient over samples [s_begin, s_end): MFMA K = 16 consecutive
-// samples (lane q holds samples 4q .. 4q + 3 of the block of 16).
+// Weight gradient over samples [s_begin, s_end), staged kDwChunk samples at
+// a time in LDS: MFMA K = 16 consecutive samples (lane q holds samples
+// 4q .. 4q + 3 of the group of 16), operands rounded to the MFMA type.
+constexpr int kDwPitchLp = kWideWidth + 4;  // 132: 4 x pitch = 16 mod 64, lanes q four samples apart
+constexpr int kDwPitchYLp = 36;             // 4 x 36 = 16 mod 64
+
 template <int IN, int W, int D, class P>
-__device__ void mlp_dw_range_lp(const float* __restrict__ y, const float4* __restrict__ sc,
+__device__ void mlp_dw_range_lp(float* __restrict__ lds, const float* __restrict__ y, const float4* __restrict__ sc,
                                 const float4* __restrict__ dout, const float* __restrict__ act,
                                 const float* __restrict__ dlt, int64_t n_s, int64_t s_begin, int64_t s_end,
                                 float* __restrict__ dst)
 {
     using N = NetLp<IN, W, D>;
+    constexpr int PW = kDwPitchLp, PY = kDwPitchYLp;
+    using St = DwStage<W, D, PW, PY>;
     constexpr int RT = N::OT / kWideWavesLp;
-    static_assert(N::OT % kWideWavesLp == 0, "rows per wave");
+    static_assert(N::OT % kWideWavesLp == 0 && W + 4 == PW && IN <= 32, "rows per wave, pitch");
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, j = lane & 15;
     floatx4 aH[D > 1 ? D - 1 : 1][RT][N::OT], a1[RT][N::IT], aO[RT];
 #pragma unroll
@@ -527,69 +533,46 @@ __device__ void mlp_dw_range_lp(const float* __restrict__ y, const float4* __res
 #pragma unroll
             for (int t = 0; t < N::OT; ++t) aH[k][a][t] = {0.0f, 0.0f, 0.0f, 0.0f};
     }
-    for (int64_t s0 = s_begin; s0 < s_end; s0 += 16) {
-        int64_t sk[4];
-        bool ok[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            sk[r] = s0 + 4 * q + r;
-            ok[r] = sk[r] < s_end;
-        }
-        // W_out: A[i][k] = dO_i(sample k), rows i >= 4 zero; B = h_{D-1}
-        float dOv[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            dOv[r] = 0.0f;
-            if (ok[r] && j < 4) {
-                const float4 g = dout[sk[r]], v = sc[sk[r]];
-                dOv[r] = j == 0 ? g.x * v.x
-                                : (j == 1 ? g.y * v.y * (1.0f - v.y)
-                                          : (j == 2 ? g.z * v.z * (1.0f - v.z) : g.w * v.w * (1.0f - v.w)));
-            }
-        }
-        const typename P::vec dOp = pack<P>(dOv[0], dOv[1], dOv[2], dOv[3]);
-        auto col4 = [&](const float* base, int col) {  // 4 samples' value of one column
-            float v[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) v[r] = ok[r] ? base[sk[r] * W + col] : 0.0f;
-            return pack<P>(v[0], v[1], v[2], v[3]);
-        };
-        {
-            const float* hl = act + (int64_t)(D - 1) * n_s * W;
-#pragma unroll
-            for (int a = 0; a < RT; ++a) aO[a] = P::mma(dOp, col4(hl, 16 * (RT * wave + a) + j), aO[a]);
-        }
-#pragma unroll
-        for (int k = 1; k < D; ++k) {
-            const float* dk = dlt + (int64_t)k * n_s * W;
-            const float* hk = act + (int64_t)(k - 1) * n_s * W;
-            typename P::vec av[RT], bv[N::OT];
-#pragma unroll
-            for (int a = 0; a < RT; ++a) av[a] = col4(dk, 16 * (RT * wave + a) + j);
-#pragma unroll
-            for (int t = 0; t < N::OT; ++t) bv[t] = col4(hk, 16 * t + j);
+    // 4 consecutive samples' value of one column of a staged array
+    auto col4 = [&](int base, int pitch, int r0, int col) {
+        return pack<P>(lds[base + (r0 + 0) * pitch + col], lds[base + (r0 + 1) * pitch + col],
+                       lds[base + (r0 + 2) * pitch + col], lds[base + (r0 + 3) * pitch + col]);
+    };
+    for (int64_t c0 = s_begin; c0 < s_end; c0 += kDwChunk) {
+        dw_stage<IN, W, D, PW, PY>(lds, y, sc, dout, act, dlt, n_s, c0, s_end);
+        __syncthreads();
+#pragma unroll 1
+        for (int ks = 0; ks < kDwChunk / 16; ++ks) {
+            const int r0 = 16 * ks + 4 * q;
+            const typename P::vec dOp = j < 4 ? col4(St::DO, 4, r0, j) : pack<P>(0.0f, 0.0f, 0.0f, 0.0f);
 #pragma unroll
             for (int a = 0; a < RT; ++a)
+                aO[a] = P::mma(dOp, col4(St::AC + (D - 1) * kDwChunk * PW, PW, r0, 16 * (RT * wave + a) + j), aO[a]);
 #pragma unroll
-                for (int t = 0; t < N::OT; ++t) aH[k - 1][a][t] = P::mma(av[a], bv[t], aH[k - 1][a][t]);
-        }
-        {
-            typename P::vec av[RT], bv[N::IT];
+            for (int k = 1; k < D; ++k) {
+                typename P::vec av[RT], bv[N::OT];
 #pragma unroll
-            for (int a = 0; a < RT; ++a) av[a] = col4(dlt, 16 * (RT * wave + a) + j);
+                for (int a = 0; a < RT; ++a) av[a] = col4(St::DL + k * kDwChunk * PW, PW, r0, 16 * (RT * wave + a) + j);
 #pragma unroll
-            for (int t = 0; t < N::IT; ++t) {
-                const int f = 16 * t + j;
-                float v[4];
+                for (int t = 0; t < N::OT; ++t) {
+                    bv[t] = col4(St::AC + (k - 1) * kDwChunk * PW, PW, r0, 16 * t + j);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) v[r] = (ok[r] && f < IN) ? y[((int64_t)(f >> 1) * n_s + sk[r]) * 2 + (f & 1)] : 0.0f;
-                bv[t] = pack<P>(v[0], v[1], v[2], v[3]);
+                    for (int a = 0; a < RT; ++a) aH[k - 1][a][t] = P::mma(av[a], bv[t], aH[k - 1][a][t]);
+                }
             }
+            {
+                typename P::vec av[RT], bv[N::IT];
 #pragma unroll
-            for (int a = 0; a < RT; ++a)
+                for (int a = 0; a < RT; ++a) av[a] = col4(St::DL, PW, r0, 16 * (RT * wave + a) + j);
 #pragma unroll
-                for (int t = 0; t < N::IT; ++t) a1[a][t] = P::mma(av[a], bv[t], a1[a][t]);
+                for (int t = 0; t < N::IT; ++t) bv[t] = col4(St::Y, PY, r0, 16 * t + j);
+#pragma unroll
+                for (int a = 0; a < RT; ++a)
+#pragma unroll
+                    for (int t = 0; t < N::IT; ++t) a1[a][t] = P::mma(av[a], bv[t], a1[a][t]);
+            }
         }
+        __syncthreads();
     }
 #pragma unroll
     for (int a = 0; a < RT; ++a)
@@ -607,6 +590,12 @@ __device__ void mlp_dw_range_lp(const float* __restrict__ y, const float4* __res
                 for (int t = 0; t < N::OT; ++t) dst[N::OFF_H + (k - 1) * W * W + row * W + 16 * t + j] = aH[k - 1][a][t][r];
             if (q == 0) dst[N::OFF_OUT + r * W + 16 * (RT * wave + a) + j] = aO[a][r];
         }
+}
+
+template <int IN, int W, int D>
+constexpr size_t dw_lds_bytes_lp()
+{
+    return sizeof(float) * (size_t)DwStage<W, D, kDwPitchLp, kDwPitchYLp>::FLOATS;
 }
 
 template <int IN, int W, int D, class P>
@@ -650,9 +639,10 @@ __global__ __launch_bounds__(64 * kWideWavesLp) void k_mlp_dw_lp(const float* __
                                                                  int64_t tiles_per_block, float* __restrict__ partial)
 {
     using N = NetLp<IN, W, D>;
+    extern __shared__ float dw_lds[];
     const int64_t b = (int64_t)blockIdx.x * tiles_per_block * 16;
     const int64_t e = min(b + tiles_per_block * 16, n_s);
-    mlp_dw_range_lp<IN, W, D, P>(y, sc, dout, act, act + (int64_t)D * n_s * W, n_s, b, e,
+    mlp_dw_range_lp<IN, W, D, P>(dw_lds, y, sc, dout, act, act + (int64_t)D * n_s * W, n_s, b, e,
                                  partial + (int64_t)blockIdx.x * N::N_PARAMS);
 }
 
@@ -664,11 +654,12 @@ __global__ __launch_bounds__(64 * kWideWavesLp) void k_mlp_dw_lp_batch(const Mlp
                                                                        const float* __restrict__ act,
                                                                        float* __restrict__ partial, int64_t slot_stride)
 {
+    extern __shared__ float dw_lds[];
     const MlpWork wk = work[blockIdx.x];
     const int64_t b = wk.tile_begin * 16, e = min(wk.tile_end * 16, wk.n_s);
     const float* a = act + wk.a_off;
-    mlp_dw_range_lp<IN, W, D, P>(y + wk.y_off, sc + wk.s_off, dout + wk.s_off, a, a + (int64_t)D * wk.n_s * W, wk.n_s,
-                                 b, e, partial + (int64_t)blockIdx.x * slot_stride);
+    mlp_dw_range_lp<IN, W, D, P>(dw_lds, y + wk.y_off, sc + wk.s_off, dout + wk.s_off, a, a + (int64_t)D * wk.n_s * W,
+                                 wk.n_s, b, e, partial + (int64_t)blockIdx.x * slot_stride);
 }
 
 template <class K>
@@ -727,7 +718,9 @@ hipError_t bwd_lp(const float* w, const float* y, const float* dout, const float
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const int nb = bwd_blocks(n_s);
         const int64_t per = (n_tiles + nb - 1) / nb;
-        hipLaunchKernelGGL((k_mlp_dw_lp<IN, W, D, P>), dim3((uint32_t)nb), dim3(64 * kWideWavesLp), 0, s, y,
+        const size_t dwl = dw_lds_bytes_lp<IN, W, D>();
+        if ((e = set_lds_lp(k_mlp_dw_lp<IN, W, D, P>, dwl)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_mlp_dw_lp<IN, W, D, P>), dim3((uint32_t)nb), dim3(64 * kWideWavesLp), dwl, s, y,
                            (const float4*)sc, (const float4*)dout, act, n_s, per, partial);
         return hipGetLastError();
     } else {
@@ -764,7 +757,9 @@ hipError_t bwd_lp_batch(const MlpWork* work, int n_blocks, const float* params, 
         hipLaunchKernelGGL((k_mlp_chain_bwd_lp_batch<IN, W, D, P>), dim3((uint32_t)n_blocks), dim3(256), lds, s, work,
                            params, (const float4*)sc, (const float4*)dout, act, (float2*)dy);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL((k_mlp_dw_lp_batch<IN, W, D, P>), dim3((uint32_t)n_blocks), dim3(64 * kWideWavesLp), 0, s,
+        const size_t dwl = dw_lds_bytes_lp<IN, W, D>();
+        if ((e = set_lds_lp(k_mlp_dw_lp_batch<IN, W, D, P>, dwl)) != hipSuccess) return e;
+        hipLaunchKernelGGL((k_mlp_dw_lp_batch<IN, W, D, P>), dim3((uint32_t)n_blocks), dim3(64 * kWideWavesLp), dwl, s,
                            work, y, (const float4*)sc, (const float4*)dout, act, partial, slot_stride);
         return hipGetLastError();
     } else {

@@ -315,7 +315,7 @@ def test_batch_reduced_precision(mlp_dtype, table_dtype):
         kw = dict(tgt_rgb=b.tgt_rgb[sl], tgt_depth=b.tgt_depth[sl], mask=b.mask[sl], lambda_d=np.float32(0.1),
                   emulate=True)
         ref = orc.render_fwd(o.arch, params[i], *g, **kw)
-        g_ref = orc.render_bwd(o.arch, params[i], *g, **kw)
+        g_ref = orc.render_bwd(o.arch, params[i], *g, loss_scale=scale, **kw)
         nt = o.arch.n_table_params
         gi = grads[i].astype(np.float64) / scale
         errs = {"rgb": rel_errors(got["rgb"][sl], ref["rgb"]), "depth": rel_errors(got["depth"][sl], ref["depth"]),

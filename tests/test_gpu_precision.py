@@ -78,7 +78,7 @@ def test_reduced_precision_against_oracle(mlp_dtype, table_dtype):
     report = {}
     for emulate in (True, False):
         ref = orc.render_fwd(arch, params, *geo, emulate=emulate, **kw)
-        g_ref = orc.render_bwd(arch, params, *geo, emulate=emulate, **kw)
+        g_ref = orc.render_bwd(arch, params, *geo, emulate=emulate, loss_scale=scale, **kw)
         errs = {k: rel_errors(got[k], ref[k] if k != "loss" else [ref["loss"]])
                 for k in ("rgb", "depth", "opacity", "loss")}
         errs["g_table"] = rel_errors(g[:nt], g_ref[:nt])

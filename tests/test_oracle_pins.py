@@ -673,6 +673,24 @@ def test_p15_emulated_gradient_matches_rounded_autograd(mlp_dtype, table_dtype):
 
     L, gt = _torch_render_loss(torch, arch, params, geo, kw, RoundedProduct.apply, table_view)
     g = orc.render_bwd(arch, params, *geo, emulate=True, **kw)
+    # with a loss scale the gradient operands are rounded scaled: round(g s) / s
+    s_ = 4096.0
+    Rs = lambda x: (x * s_).to(torch.float32).to(tdt).to(torch.float64) / s_
+
+    class ScaledRoundedProduct(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, h, W):
+            ctx.save_for_backward(h, W)
+            return R(h) @ R(W).T
+
+        @staticmethod
+        def backward(ctx, g):
+            h, W = ctx.saved_tensors
+            return Rs(g) @ R(W), Rs(g).T @ R(h)
+
+    _, gts = _torch_render_loss(torch, arch, params, geo, kw, ScaledRoundedProduct.apply, table_view)
+    gs = orc.render_bwd(arch, params, *geo, emulate=True, loss_scale=s_, **kw)
+    np.testing.assert_allclose(gs, gts, rtol=1e-9, atol=1e-12 * np.abs(gs).max())
     lo = orc.render_fwd(arch, params, *geo, emulate=True, **kw)["loss"]
     assert abs(lo - L) < 1e-12 * max(1.0, abs(L))
     np.testing.assert_allclose(g, gt, rtol=1e-9, atol=1e-12 * np.abs(g).max())
