@@ -67,6 +67,31 @@ def algorithmic_work(arch, n_rays, S, n_fine):
     }
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_prior_65536rays.md")
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per step of `kernel` from the committed counter summary (the
+    fenced json block of profiles/hbm_traffic_prior_65536rays.md), or None
+    when there is none or a source it was measured with has changed since."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+        block = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    entry = block.get("kernels", {}).get(kernel)
+    if not entry:
+        return None
+    for rel, digest in entry.get("sources", {}).items():
+        try:
+            if hashlib.sha256(open(os.path.join(ROOT, rel), "rb").read()).hexdigest() != digest:
+                return None
+        except OSError:
+            return None
+    return entry.get("hbm_bytes_per_step")
+
+
 def summed_work(items):
     """Sum of algorithmic_work over (arch, n_rays, S, n_fine) items."""
     tot = {}
@@ -191,6 +216,8 @@ def run_prior(args):
         f"loss {float(tr._out['loss'].item()):.4e}")
     kern, roofline = kernel_table(kt, args.steps, ms_per_step, algorithmic_work(arch, args.rays, S, batch.sample.n_fine),
                                   FP32_MFMA_PEAK_TFLOPS, log)
+    if args.rays == 65536:
+        roofline["traffic"] = measured_traffic(roofline["kernel"])
     cpu = None
     if not args.no_cpu_baseline:
         log(f"bench: CPU oracle on {args.cpu_rays} rays")

@@ -226,11 +226,15 @@ struct MlpWork {
 
 // The 128-wide MLP stores its hidden activations in the forward and runs its
 // backward as a chain kernel (deltas, dy) and a weight-gradient kernel; the
-// two buffers hold act[D][n_s][W] and delta[D][n_s][W] FP32.
+// two buffers hold act[D][n_s][W] and delta[D][n_s][W], FP32 in the FP32
+// form and already rounded to the MFMA type (16 bits) in the reduced form,
+// where they only ever enter the matrix cores rounded (and the ReLU masks
+// only need their sign).
 constexpr int kWideWidth = 128;
 inline int64_t mlp_act_floats(const MlpShape& m, int64_t n_s)
 {
-    return m.width >= kWideWidth ? 2 * (int64_t)m.hidden * n_s * m.width : 0;
+    if (m.width < kWideWidth) return 0;
+    return (m.dtype == PRENOM_F32 ? 2 : 1) * (int64_t)m.hidden * n_s * m.width;
 }
 int mlp_bwd_waves(int64_t n_samples);  // partial-gradient slots (one per block) the bwd writes
 // act: activation/delta buffer of mlp_act_floats floats (128-wide MLPs; else unused)

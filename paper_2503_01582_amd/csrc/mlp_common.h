@@ -107,8 +107,35 @@ struct DwStage {
     static constexpr int FLOATS = DO + kDwChunk * 4;
 };
 
-// Samples [s0, min(s0 + kDwChunk, s_end)) of one object into LDS (zeros past
-// the end).  act/dlt: [D][n_s][W]; y: level-major [L][n_s][2].
+// Input features and head adjoint of samples [s0, min(s0 + kDwChunk, s_end))
+// into LDS (zeros past the end; input columns >= IN zero).  y: level-major
+// [L][n_s][2].
+template <int IN, int W, int D, int PW, int PY>
+__device__ __forceinline__ void dw_stage_inputs(float* __restrict__ lds, const float* __restrict__ y,
+                                                const float4* __restrict__ sc, const float4* __restrict__ dout,
+                                                int64_t n_s, int64_t s0, int64_t s_end)
+{
+    using St = DwStage<W, D, PW, PY>;
+    for (int i = threadIdx.x; i < kDwChunk * (PY / 2); i += blockDim.x) {
+        const int r = i / (PY / 2), l = i % (PY / 2);
+        const int64_t s = s0 + r;
+        float2 v = make_float2(0.0f, 0.0f);
+        if (s < s_end && 2 * l < IN) v = reinterpret_cast<const float2*>(y)[(int64_t)l * n_s + s];
+        *reinterpret_cast<float2*>(lds + St::Y + r * PY + 2 * l) = v;
+    }
+    if (threadIdx.x < kDwChunk) {
+        const int r = threadIdx.x;
+        const int64_t s = s0 + r;
+        floatx4 o = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (s < s_end) {  // d sigma / d o0 = sigma, d c / d o = c (1 - c)
+            const float4 g = dout[s], v = sc[s];
+            o = {g.x * v.x, g.y * v.y * (1.0f - v.y), g.z * v.z * (1.0f - v.z), g.w * v.w * (1.0f - v.w)};
+        }
+        *reinterpret_cast<floatx4*>(lds + St::DO + r * 4) = o;
+    }
+}
+
+// Every layer's activation and delta rows (FP32, [D][n_s][W]) of the chunk.
 template <int IN, int W, int D, int PW, int PY>
 __device__ __forceinline__ void dw_stage(float* __restrict__ lds, const float* __restrict__ y,
                                          const float4* __restrict__ sc, const float4* __restrict__ dout,
@@ -128,24 +155,7 @@ __device__ __forceinline__ void dw_stage(float* __restrict__ lds, const float* _
         *reinterpret_cast<floatx4*>(lds + St::AC + (k * kDwChunk + r) * PW + 4 * c) = a;
         *reinterpret_cast<floatx4*>(lds + St::DL + (k * kDwChunk + r) * PW + 4 * c) = d;
     }
-    // inputs: level pairs (2 features each) of every sample; columns >= IN zero
-    for (int i = threadIdx.x; i < kDwChunk * (PY / 2); i += blockDim.x) {
-        const int r = i / (PY / 2), l = i % (PY / 2);
-        const int64_t s = s0 + r;
-        float2 v = make_float2(0.0f, 0.0f);
-        if (s < s_end && 2 * l < IN) v = reinterpret_cast<const float2*>(y)[(int64_t)l * n_s + s];
-        *reinterpret_cast<float2*>(lds + St::Y + r * PY + 2 * l) = v;
-    }
-    if (threadIdx.x < kDwChunk) {
-        const int r = threadIdx.x;
-        const int64_t s = s0 + r;
-        floatx4 o = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (s < s_end) {  // d sigma / d o0 = sigma, d c / d o = c (1 - c)
-            const float4 g = dout[s], v = sc[s];
-            o = {g.x * v.x, g.y * v.y * (1.0f - v.y), g.z * v.z * (1.0f - v.z), g.w * v.w * (1.0f - v.w)};
-        }
-        *reinterpret_cast<floatx4*>(lds + St::DO + r * 4) = o;
-    }
+    dw_stage_inputs<IN, W, D, PW, PY>(lds, y, sc, dout, n_s, s0, s_end);
 }
 
 }  // namespace prenom

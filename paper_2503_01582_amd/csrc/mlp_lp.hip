@@ -25,6 +25,10 @@ typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 struct Bf16Op {
     using vec = short4_t;
     static __device__ __forceinline__ short cvt(float x) { return __builtin_bit_cast(short, (__bf16)x); }
+    static __device__ __forceinline__ float back(short h)
+    {
+        return __builtin_bit_cast(float, (uint32_t)(uint16_t)h << 16);
+    }
     static __device__ __forceinline__ floatx4 mma(vec a, vec b, floatx4 c)
     {
         return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
@@ -34,6 +38,7 @@ struct Bf16Op {
 struct F16Op {
     using vec = half4_t;
     static __device__ __forceinline__ _Float16 cvt(float x) { return (_Float16)x; }
+    static __device__ __forceinline__ float back(_Float16 h) { return (float)h; }
     static __device__ __forceinline__ floatx4 mma(vec a, vec b, floatx4 c)
     {
         return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
@@ -55,6 +60,12 @@ template <class P>
 __device__ __forceinline__ typename P::vec pack(floatx4 x)
 {
     return pack<P>(x[0], x[1], x[2], x[3]);
+}
+
+template <class P>
+__device__ __forceinline__ floatx4 unpack(typename P::vec v)
+{
+    return {P::back(v[0]), P::back(v[1]), P::back(v[2]), P::back(v[3])};
 }
 
 template <int IN, int W, int D>
@@ -213,12 +224,12 @@ __device__ __forceinline__ void mlp_fwd_tiles_lp(const typename P::vec* __restri
         floatx4 o;
         chain_lp<IN, W, D, P>(frag, lane, yf, hs, o);
         if (q == 0 && valid) sc[s] = make_float4(__expf(o[0]), sigmoidf_(o[1]), sigmoidf_(o[2]), sigmoidf_(o[3]));
-        if (act && valid) {
+        if (act && valid) {  // stored already rounded: the values every later use sees
+            typename P::vec* a16 = reinterpret_cast<typename P::vec*>(act);
 #pragma unroll
             for (int k = 0; k < D; ++k)
 #pragma unroll
-                for (int to = 0; to < N::OT; ++to)
-                    *reinterpret_cast<floatx4*>(act + ((int64_t)k * n_s + s) * W + 16 * to + 4 * q) = hs[k][to];
+                for (int to = 0; to < N::OT; ++to) a16[(((int64_t)k * n_s + s) * W + 16 * to + 4 * q) / 4] = pack<P>(hs[k][to]);
         }
     }
 }
@@ -441,11 +452,12 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_bwd_lp_batch(const MlpWo
 // accumulation), the 4 waves splitting the output rows.
 constexpr int kWideWavesLp = 4;
 
+// act16 / dlt16: [D][n_s][W] 16-bit values, indexed in groups of 4 (P::vec).
 template <int IN, int W, int D, class P>
 __device__ void mlp_chain_bwd_tiles_lp(const typename P::vec* __restrict__ bfrag, const float4* __restrict__ sc,
-                                       const float4* __restrict__ dout, const float* __restrict__ act,
-                                       float* __restrict__ dlt, int64_t n_s, float2* __restrict__ dy, int64_t tile0,
-                                       int64_t end, int64_t step)
+                                       const float4* __restrict__ dout, const typename P::vec* __restrict__ act16,
+                                       typename P::vec* __restrict__ dlt16, int64_t n_s, float2* __restrict__ dy,
+                                       int64_t tile0, int64_t end, int64_t step)
 {
     using N = NetLp<IN, W, D>;
     constexpr int BO = 0, BH = N::BH - N::N_FWD, B1 = N::B1 - N::N_FWD;
@@ -460,23 +472,22 @@ __device__ void mlp_chain_bwd_tiles_lp(const typename P::vec* __restrict__ bfrag
         }
         const typename P::vec dOp = pack<P>(dO);
         floatx4 hk[N::OT], delta[N::OT];
+        auto vi = [&](int k, int to) { return (((int64_t)k * n_s + s) * W + 16 * to + 4 * q) / 4; };
 #pragma unroll
         for (int to = 0; to < N::OT; ++to)
-            hk[to] = valid ? *reinterpret_cast<const floatx4*>(act + ((int64_t)(D - 1) * n_s + s) * W + 16 * to + 4 * q)
-                           : floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            hk[to] = valid ? unpack<P>(act16[vi(D - 1, to)]) : floatx4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
         for (int to = 0; to < N::OT; ++to) {
             floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
             acc = P::mma(bfrag[(BO + to) * 64 + lane], dOp, acc);
             delta[to] = mask_pos(acc, hk[to]);
-            if (valid) *reinterpret_cast<floatx4*>(dlt + ((int64_t)(D - 1) * n_s + s) * W + 16 * to + 4 * q) = delta[to];
+            if (valid) dlt16[vi(D - 1, to)] = pack<P>(delta[to]);
         }
 #pragma unroll
         for (int k = D - 1; k >= 1; --k) {
 #pragma unroll
             for (int to = 0; to < N::OT; ++to)
-                hk[to] = valid ? *reinterpret_cast<const floatx4*>(act + ((int64_t)(k - 1) * n_s + s) * W + 16 * to + 4 * q)
-                               : floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+                hk[to] = valid ? unpack<P>(act16[vi(k - 1, to)]) : floatx4{0.0f, 0.0f, 0.0f, 0.0f};
             typename P::vec dp[N::OT];
 #pragma unroll
             for (int ti = 0; ti < N::OT; ++ti) dp[ti] = pack<P>(delta[ti]);
@@ -485,7 +496,7 @@ __device__ void mlp_chain_bwd_tiles_lp(const typename P::vec* __restrict__ bfrag
 #pragma unroll
             for (int to = 0; to < N::OT; ++to) {
                 delta[to] = mask_pos(nd[to], hk[to]);
-                if (valid) *reinterpret_cast<floatx4*>(dlt + ((int64_t)(k - 1) * n_s + s) * W + 16 * to + 4 * q) = delta[to];
+                if (valid) dlt16[vi(k - 1, to)] = pack<P>(delta[to]);
             }
         }
         typename P::vec dp[N::OT];
@@ -510,11 +521,36 @@ __device__ void mlp_chain_bwd_tiles_lp(const typename P::vec* __restrict__ bfrag
 constexpr int kDwPitchLp = kWideWidth + 4;  // 132: 4 x pitch = 16 mod 64, lanes q four samples apart
 constexpr int kDwPitchYLp = 36;             // 4 x 36 = 16 mod 64
 
+// Every layer's activation and delta rows of the chunk from the 16-bit
+// buffers (already rounded), widened into the FP32 staging arrays.
+template <int IN, int W, int D, int PW, int PY, class P>
+__device__ __forceinline__ void dw_stage_lp(float* __restrict__ lds, const float* __restrict__ y,
+                                            const float4* __restrict__ sc, const float4* __restrict__ dout,
+                                            const typename P::vec* __restrict__ act16,
+                                            const typename P::vec* __restrict__ dlt16, int64_t n_s, int64_t s0,
+                                            int64_t s_end)
+{
+    using St = DwStage<W, D, PW, PY>;
+    constexpr int V = W / 4;
+    for (int i = threadIdx.x; i < D * kDwChunk * V; i += blockDim.x) {
+        const int k = i / (kDwChunk * V), rem = i % (kDwChunk * V), r = rem / V, c = rem % V;
+        const int64_t s = s0 + r;
+        floatx4 a = {0.0f, 0.0f, 0.0f, 0.0f}, d = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (s < s_end) {
+            a = unpack<P>(act16[((int64_t)k * n_s + s) * V + c]);
+            d = unpack<P>(dlt16[((int64_t)k * n_s + s) * V + c]);
+        }
+        *reinterpret_cast<floatx4*>(lds + St::AC + (k * kDwChunk + r) * PW + 4 * c) = a;
+        *reinterpret_cast<floatx4*>(lds + St::DL + (k * kDwChunk + r) * PW + 4 * c) = d;
+    }
+    dw_stage_inputs<IN, W, D, PW, PY>(lds, y, sc, dout, n_s, s0, s_end);
+}
+
 template <int IN, int W, int D, class P>
 __device__ void mlp_dw_range_lp(float* __restrict__ lds, const float* __restrict__ y, const float4* __restrict__ sc,
-                                const float4* __restrict__ dout, const float* __restrict__ act,
-                                const float* __restrict__ dlt, int64_t n_s, int64_t s_begin, int64_t s_end,
-                                float* __restrict__ dst)
+                                const float4* __restrict__ dout, const typename P::vec* __restrict__ act16,
+                                const typename P::vec* __restrict__ dlt16, int64_t n_s, int64_t s_begin,
+                                int64_t s_end, float* __restrict__ dst)
 {
     using N = NetLp<IN, W, D>;
     constexpr int PW = kDwPitchLp, PY = kDwPitchYLp;
@@ -539,7 +575,7 @@ __device__ void mlp_dw_range_lp(float* __restrict__ lds, const float* __restrict
                        lds[base + (r0 + 2) * pitch + col], lds[base + (r0 + 3) * pitch + col]);
     };
     for (int64_t c0 = s_begin; c0 < s_end; c0 += kDwChunk) {
-        dw_stage<IN, W, D, PW, PY>(lds, y, sc, dout, act, dlt, n_s, c0, s_end);
+        dw_stage_lp<IN, W, D, PW, PY, P>(lds, y, sc, dout, act16, dlt16, n_s, c0, s_end);
         __syncthreads();
 #pragma unroll 1
         for (int ks = 0; ks < kDwChunk / 16; ++ks) {
@@ -609,7 +645,8 @@ __global__ __launch_bounds__(256) void k_mlp_chain_bwd_lp(const float* __restric
     load_fragments_lp<IN, W, D, P>(w, frag, N::N_ALL - N::N_FWD, N::N_FWD);
     __syncthreads();
     const int64_t wave0 = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-    mlp_chain_bwd_tiles_lp<IN, W, D, P>(frag, sc, dout, act, act + (int64_t)D * n_s * W, n_s, dy, wave0,
+    typename P::vec* a16 = reinterpret_cast<typename P::vec*>(act);
+    mlp_chain_bwd_tiles_lp<IN, W, D, P>(frag, sc, dout, a16, a16 + (int64_t)D * n_s * W / 4, n_s, dy, wave0,
                                         (n_s + 15) / 16, (int64_t)gridDim.x * (blockDim.x / 64));
 }
 
@@ -626,9 +663,10 @@ __global__ __launch_bounds__(256) void k_mlp_chain_bwd_lp_batch(const MlpWork* _
     const MlpWork wk = work[blockIdx.x];
     load_fragments_lp<IN, W, D, P>(params + wk.w_off, frag, N::N_ALL - N::N_FWD, N::N_FWD);
     __syncthreads();
-    mlp_chain_bwd_tiles_lp<IN, W, D, P>(frag, sc + wk.s_off, dout + wk.s_off, act + wk.a_off,
-                                        act + wk.a_off + (int64_t)D * wk.n_s * W, wk.n_s, dy + wk.y_off / 2,
-                                        wk.tile_begin + (threadIdx.x >> 6), wk.tile_end, blockDim.x / 64);
+    typename P::vec* a16 = reinterpret_cast<typename P::vec*>(act + wk.a_off);
+    mlp_chain_bwd_tiles_lp<IN, W, D, P>(frag, sc + wk.s_off, dout + wk.s_off, a16, a16 + (int64_t)D * wk.n_s * W / 4,
+                                        wk.n_s, dy + wk.y_off / 2, wk.tile_begin + (threadIdx.x >> 6), wk.tile_end,
+                                        blockDim.x / 64);
 }
 
 template <int IN, int W, int D, class P>
@@ -642,7 +680,8 @@ __global__ __launch_bounds__(64 * kWideWavesLp) void k_mlp_dw_lp(const float* __
     extern __shared__ float dw_lds[];
     const int64_t b = (int64_t)blockIdx.x * tiles_per_block * 16;
     const int64_t e = min(b + tiles_per_block * 16, n_s);
-    mlp_dw_range_lp<IN, W, D, P>(dw_lds, y, sc, dout, act, act + (int64_t)D * n_s * W, n_s, b, e,
+    const typename P::vec* a16 = reinterpret_cast<const typename P::vec*>(act);
+    mlp_dw_range_lp<IN, W, D, P>(dw_lds, y, sc, dout, a16, a16 + (int64_t)D * n_s * W / 4, n_s, b, e,
                                  partial + (int64_t)blockIdx.x * N::N_PARAMS);
 }
 
@@ -657,9 +696,10 @@ __global__ __launch_bounds__(64 * kWideWavesLp) void k_mlp_dw_lp_batch(const Mlp
     extern __shared__ float dw_lds[];
     const MlpWork wk = work[blockIdx.x];
     const int64_t b = wk.tile_begin * 16, e = min(wk.tile_end * 16, wk.n_s);
-    const float* a = act + wk.a_off;
-    mlp_dw_range_lp<IN, W, D, P>(dw_lds, y + wk.y_off, sc + wk.s_off, dout + wk.s_off, a, a + (int64_t)D * wk.n_s * W,
-                                 wk.n_s, b, e, partial + (int64_t)blockIdx.x * slot_stride);
+    const typename P::vec* a16 = reinterpret_cast<const typename P::vec*>(act + wk.a_off);
+    mlp_dw_range_lp<IN, W, D, P>(dw_lds, y + wk.y_off, sc + wk.s_off, dout + wk.s_off, a16,
+                                 a16 + (int64_t)D * wk.n_s * W / 4, wk.n_s, b, e,
+                                 partial + (int64_t)blockIdx.x * slot_stride);
 }
 
 template <class K>

@@ -49,10 +49,9 @@ constexpr int kReduceThreads = 1024;
 constexpr int kReduceUnroll = 8;  // records in flight per thread
 constexpr int64_t kChunk = (int64_t)1 << 21;  // records per reduce work item
 
-// Levels with at most this many tiles (every level up to T = 2^19) rank
-// their records with wave ballots instead of LDS atomics.
-constexpr int kBallotTiles = 64;
-constexpr int kWaves = kPlaceThreads / 64;
+// Levels with at most this many tiles have most lanes of a wave in the same
+// tile; their histogram atomics are combined per wave first.
+constexpr int kAggregateTiles = 16;
 
 // ---------------------------------------------------------------- object lookup
 // Index of the last object whose `field` is <= v (fields ascend with the index).
@@ -109,38 +108,28 @@ __device__ __forceinline__ int level_of_tile(const ScatterObj& o, int lt)
     return l;
 }
 
-// Per-wave ranking of the 8 corner records of every lane by tile, without
-// atomics (levels of at most 64 tiles, kb = ceil(log2 tiles) bits).  For
-// each corner, kb ballots give the bit planes of the lanes' tile ids; lane v
-// counts the active lanes whose tile is v, and a lane's rank among the
-// wave's records of its tile is the running count of that tile before this
-// corner (held by lane v = tile) plus the active lanes below it with the same
-// tile.  Records are ordered corner-major.  Called by every lane of the wave.
-__device__ __forceinline__ uint32_t wave_tile_ranks(bool has, const uint32_t (&tile)[8], int kb, uint32_t (&rank)[8])
+// Adds 1 to hist[tile] for every active lane and returns the lane's rank
+// among the additions to that tile.  Lanes of the wave that share a tile are
+// combined into one LDS atomic issued by their first lane (same-address
+// atomics of one instruction would otherwise serialise).
+__device__ __forceinline__ uint32_t wave_aggregated_add(uint32_t* hist, uint32_t tile)
 {
     const int lane = threadIdx.x & 63;
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const uint64_t active = __ballot(has);
-    uint32_t run = 0;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const uint32_t t = has ? tile[e] : 0u;
-        uint64_t mine = active, mv = active;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            if (k < kb) {
-                const uint64_t pl = __ballot(has && ((t >> k) & 1u));
-                mine &= ((t >> k) & 1u) ? pl : ~pl;
-                mv &= ((lane >> k) & 1) ? pl : ~pl;
-            }
-        }
-        rank[e] = __shfl(run, (int)t) + (uint32_t)__popcll(mine & below);
-        run += (uint32_t)__popcll(mv);
+    const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint64_t remaining = __ballot(1);
+    uint32_t rank = 0;
+    while (remaining) {
+        const int leader = __ffsll((unsigned long long)remaining) - 1;
+        const uint32_t lt = __shfl(tile, leader);
+        const uint64_t mask = __ballot(tile == lt);
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&hist[lt], (uint32_t)__popcll(mask));
+        base = __shfl(base, leader);
+        if (tile == lt) rank = base + (uint32_t)__popcll(mask & lane_lt);
+        remaining &= ~mask;
     }
-    return run;  // lane v: the wave's records of tile v (meaningful for v < tiles)
+    return rank;
 }
-
-__device__ __forceinline__ int tile_bits(int nt) { return nt <= 1 ? 0 : 32 - __clz(nt - 1); }
 
 // Feature gradient and corners of local sample s on level l of object o;
 // false when dy == 0 (the sample contributes nothing and is skipped by count
@@ -174,18 +163,15 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_count(ScatterArgs a)
     const int64_t s = (int64_t)bx * kSamplesPerBlock + threadIdx.x;
     float2 d;
     Corners c;
-    const bool has = s < o.n_s && load_contrib(a, o, l, s, d, c);
-    if (has) m = fmaxf(fabsf(d.x), fabsf(d.y));
-    if (nt <= kBallotTiles) {
-        uint32_t tile[8], rank[8];
+    if (s < o.n_s && load_contrib(a, o, l, s, d, c)) {
+        m = fmaxf(fabsf(d.x), fabsf(d.y));
+        if (nt <= kAggregateTiles) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) tile[e] = has ? c.row[e] >> kTileBits : 0u;
-        const uint32_t cnt = wave_tile_ranks(has, tile, tile_bits(nt), rank);
-        const int lane = threadIdx.x & 63;
-        if (lane < nt && cnt) atomicAdd(&hist[lane], cnt);
-    } else if (has) {
+            for (int e = 0; e < 8; ++e) wave_aggregated_add(hist, c.row[e] >> kTileBits);
+        } else {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) atomicAdd(&hist[c.row[e] >> kTileBits], 1u);
+            for (int e = 0; e < 8; ++e) atomicAdd(&hist[c.row[e] >> kTileBits], 1u);
+        }
     }
 #pragma unroll
     for (int dd = 32; dd >= 1; dd >>= 1) m = fmaxf(m, __shfl_xor(m, dd));
@@ -298,13 +284,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scatter_scan_tiles(ScatterArgs
     }
 }
 
-// Dynamic LDS of the place kernel for up to nt tiles per level: tile bases
-// (u64), staged values (float2), histogram and segments (u32), total, staged
-// keys and tiles (u16), per-wave tile counts (u32).
+// Dynamic LDS of the place kernel for nt tiles of one level.
 __host__ __device__ constexpr size_t place_lds_bytes(int nt)
 {
-    return (size_t)nt * 8 + (size_t)kRecordsPerBlock * 8 + (size_t)nt * 8 + 16 + (size_t)kRecordsPerBlock * 4 +
-           (size_t)kWaves * kBallotTiles * 4;
+    return (size_t)nt * 8 + (size_t)kRecordsPerBlock * 8 + (size_t)nt * 8 + 16 + (size_t)kRecordsPerBlock * 4;
 }
 
 template <bool kMany>
@@ -319,7 +302,6 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
     uint32_t* p_total = seg + nt_lds;
     uint16_t* s_key = reinterpret_cast<uint16_t*>(p_total + 4);
     uint16_t* s_tile = s_key + kRecordsPerBlock;
-    uint32_t* wcnt = reinterpret_cast<uint32_t*>(s_tile + kRecordsPerBlock);  // [kWaves][kBallotTiles]
     const int64_t item = blockIdx.x;
     const ScatterObj& o = sobj<kMany>(a, obj_of_item<kMany>(a, item));
     const int64_t rem = item - o.item_off;
@@ -327,33 +309,20 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
     const int nt = o.tiles[l];
     for (int i = threadIdx.x; i < nt; i += kPlaceThreads) hist[i] = 0;
     __syncthreads();
-    // pass 1: rank of each contribution within its tile
+    // pass 1: rank of each contribution within its tile (LDS atomics)
     const int64_t s = (int64_t)bx * kSamplesPerBlock + threadIdx.x;
     float2 d;
     Corners c;
     const bool has = s < o.n_s && load_contrib(a, o, l, s, d, c);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const bool ballot = nt <= kBallotTiles;
     uint32_t rank[8];
-    if (ballot) {  // wave ballots; then wave bases per tile, block totals in hist
-        uint32_t tile[8];
+    if (has) {
+        if (nt <= kAggregateTiles) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) tile[e] = has ? c.row[e] >> kTileBits : 0u;
-        const uint32_t cnt = wave_tile_ranks(has, tile, tile_bits(nt), rank);
-        if (lane < nt) wcnt[wave * kBallotTiles + lane] = cnt;
-        __syncthreads();
-        for (int t = threadIdx.x; t < nt; t += kPlaceThreads) {
-            uint32_t run = 0;
-            for (int w = 0; w < kWaves; ++w) {  // exclusive prefix over waves, in place
-                const uint32_t v = wcnt[w * kBallotTiles + t];
-                wcnt[w * kBallotTiles + t] = run;
-                run += v;
-            }
-            hist[t] = run;
+            for (int e = 0; e < 8; ++e) rank[e] = wave_aggregated_add(hist, c.row[e] >> kTileBits);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) rank[e] = atomicAdd(&hist[c.row[e] >> kTileBits], 1u);
         }
-    } else if (has) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) rank[e] = atomicAdd(&hist[c.row[e] >> kTileBits], 1u);
     }
     __syncthreads();
     // block-local segments: exclusive scan of hist (by one wave)
@@ -386,7 +355,7 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const uint32_t tt = c.row[e] >> kTileBits;
-            const uint32_t p = seg[tt] + (ballot ? wcnt[wave * kBallotTiles + tt] : 0u) + rank[e];
+            const uint32_t p = seg[tt] + rank[e];
             s_key[p] = (uint16_t)(c.row[e] & (kTileRows - 1));
             s_tile[p] = (uint16_t)tt;
             s_val[p] = make_float2(c.w[e] * d.x, c.w[e] * d.y);

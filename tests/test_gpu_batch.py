@@ -18,6 +18,7 @@ import pytest
 
 import oracle as orc
 from parity_util import TOL_FP32, assert_close, rel_errors
+from test_gpu_precision import lowp_ok
 from synth.arch import Arch
 from synth.multi import multi_batch, multi_objects
 from synth.params import init_params
@@ -322,7 +323,7 @@ def test_batch_reduced_precision(mlp_dtype, table_dtype):
                 "loss": rel_errors([got["loss"][i]], [ref["loss"]]),
                 "g_table": rel_errors(gi[:nt], g_ref[:nt]), "g_mlp": rel_errors(gi[nt:], g_ref[nt:])}
         for k, v in errs.items():
-            worst[k] = max(worst.get(k, (0, 0)), v)
-            assert v[0] <= TOL_LOWP and v[1] <= TOL_LOWP, (i, k, v)
+            worst[k] = (max(worst.get(k, (0, 0))[0], v[0]), max(worst.get(k, (0, 0))[1], v[1]))
+            assert lowp_ok(k, v), (i, k, v)
     say("  worst per output vs the emulating oracle: " +
         ", ".join(f"{k} {v[0]:.1e}/{v[1]:.1e}" for k, v in worst.items()))
