@@ -161,6 +161,7 @@ __device__ __forceinline__ void mlp_chain(const float* __restrict__ frag, int la
                     acc = mfma4(frag[(N::FH + ((k - 1) * N::OT + to) * N::KTH + ks) * 64 + lane], hs[k - 1][ks >> 2][ks & 3],
                                 acc);
                 hs[k][to] = relu4(acc);
+                __builtin_amdgcn_sched_barrier(0);  // bound fragment-load hoisting (registers)
             }
         }
     }
@@ -179,11 +180,16 @@ __device__ __forceinline__ void mlp_fwd_tiles(const float* __restrict__ frag, co
 {
     using N = Net<IN, W, D>;
     const int lane = threadIdx.x & 63, q = lane >> 4, j = lane & 15;
+    float yn[N::KT1];  // the next tile's inputs, loaded while the current tile runs
+    if (tile0 < end) load_inputs<N::KT1>(y, n_s, tile0 * 16 + j, tile0 * 16 + j < n_s, q, yn);
     for (int64_t tile = tile0; tile < end; tile += step) {
         const int64_t s = tile * 16 + j;
         const bool valid = s < n_s;
         float yb[N::KT1];
-        load_inputs<N::KT1>(y, n_s, s, valid, q, yb);
+#pragma unroll
+        for (int kk = 0; kk < N::KT1; ++kk) yb[kk] = yn[kk];
+        const int64_t sn = (tile + step) * 16 + j;
+        if (tile + step < end) load_inputs<N::KT1>(y, n_s, sn, sn < n_s, q, yn);
         floatx4 hs[D][N::OT];
         floatx4 o;
         mlp_chain<IN, W, D>(frag, lane, yb, hs, o);

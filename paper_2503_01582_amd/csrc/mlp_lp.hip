@@ -215,11 +215,16 @@ __device__ __forceinline__ void mlp_fwd_tiles_lp(const typename P::vec* __restri
 {
     using N = NetLp<IN, W, D>;
     const int lane = threadIdx.x & 63, q = lane >> 4, j = lane & 15;
+    floatx4 yn[N::KB1];  // the next tile's inputs, loaded while the current tile runs
+    if (tile0 < end) load_inputs_lp<IN, N::KB1>(y, n_s, tile0 * 16 + j, tile0 * 16 + j < n_s, q, yn);
     for (int64_t tile = tile0; tile < end; tile += step) {
         const int64_t s = tile * 16 + j;
         const bool valid = s < n_s;
         floatx4 yf[N::KB1];
-        load_inputs_lp<IN, N::KB1>(y, n_s, s, valid, q, yf);
+#pragma unroll
+        for (int m = 0; m < N::KB1; ++m) yf[m] = yn[m];
+        const int64_t sn = (tile + step) * 16 + j;
+        if (tile + step < end) load_inputs_lp<IN, N::KB1>(y, n_s, sn, sn < n_s, q, yn);
         floatx4 hs[D][N::OT];
         floatx4 o;
         chain_lp<IN, W, D, P>(frag, lane, yf, hs, o);

@@ -46,7 +46,8 @@ constexpr int kRecordsPerBlock = kSamplesPerBlock * 8;
 constexpr int kMaxTilesPerLevel = 1 << (24 - kTileBits);  // T <= 2^24
 constexpr int kScanThreads = 1024;
 constexpr int kReduceThreads = 1024;
-constexpr int kReduceUnroll = 8;  // records in flight per thread
+constexpr int kRun = 8;            // consecutive records per thread and load
+constexpr int kRunsPerThread = 2;  // runs in flight per thread
 constexpr int64_t kChunk = (int64_t)1 << 21;  // records per reduce work item
 
 // Levels with at most this many tiles have most lanes of a wave in the same
@@ -131,20 +132,35 @@ __device__ __forceinline__ uint32_t wave_aggregated_add(uint32_t* hist, uint32_t
     return rank;
 }
 
+// Ray of global sample gs (S samples per ray); 32-bit division when it fits.
+__device__ __forceinline__ int64_t ray_of_sample(int64_t gs, int S)
+{
+    return gs < ((int64_t)1 << 32) ? (int64_t)((uint32_t)gs / (uint32_t)S) : gs / S;
+}
+
 // Feature gradient and corners of local sample s on level l of object o;
 // false when dy == 0 (the sample contributes nothing and is skipped by count
-// and place alike).
+// and place alike).  The gradient, t and the ray are loaded together and the
+// corners computed whatever dy is, so the loads are not serialised behind the
+// test.
 __device__ __forceinline__ bool load_contrib(const ScatterArgs& a, const ScatterObj& o, int l, int64_t s, float2& d,
                                              Corners& c)
 {
-    d = a.dy[o.dy_off + (int64_t)l * o.n_s + s];
-    if (d.x == 0.0f && d.y == 0.0f) return false;
     const int64_t gs = o.s_begin + s;
-    const float* ro = a.ray_obj + 6 * (gs / a.S);
+    const float* ro = a.ray_obj + 6 * ray_of_sample(gs, a.S);
+    d = a.dy[o.dy_off + (int64_t)l * o.n_s + s];
     const float ts = a.t[gs];
     level_corners(o.grid, l, sample_coord(ts, ro[3], ro[0]), sample_coord(ts, ro[4], ro[1]),
                   sample_coord(ts, ro[5], ro[2]), c);
-    return true;
+    return d.x != 0.0f || d.y != 0.0f;
+}
+
+// Level and sample block of count/place item `rem` of an object (fits 32 bits).
+__device__ __forceinline__ void split_item(int64_t rem, int n_blocks, int& l, int& bx)
+{
+    const uint32_t r = (uint32_t)rem;
+    l = (int)(r / (uint32_t)n_blocks);
+    bx = (int)(r - (uint32_t)l * (uint32_t)n_blocks);
 }
 
 template <bool kMany>
@@ -154,8 +170,8 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_count(ScatterArgs a)
     __shared__ float wmax[kPlaceThreads / 64];
     const int64_t item = blockIdx.x;
     const ScatterObj& o = sobj<kMany>(a, obj_of_item<kMany>(a, item));
-    const int64_t rem = item - o.item_off;
-    const int l = (int)(rem / o.n_blocks), bx = (int)(rem % o.n_blocks);
+    int l, bx;
+    split_item(item - o.item_off, o.n_blocks, l, bx);
     const int nt = o.tiles[l];
     for (int i = threadIdx.x; i < nt; i += kPlaceThreads) hist[i] = 0;
     __syncthreads();
@@ -304,8 +320,8 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
     uint16_t* s_tile = s_key + kRecordsPerBlock;
     const int64_t item = blockIdx.x;
     const ScatterObj& o = sobj<kMany>(a, obj_of_item<kMany>(a, item));
-    const int64_t rem = item - o.item_off;
-    const int l = (int)(rem / o.n_blocks), bx = (int)(rem % o.n_blocks);
+    int l, bx;
+    split_item(item - o.item_off, o.n_blocks, l, bx);
     const int nt = o.tiles[l];
     for (int i = threadIdx.x; i < nt; i += kPlaceThreads) hist[i] = 0;
     __syncthreads();
@@ -409,23 +425,57 @@ __global__ __launch_bounds__(kReduceThreads) void k_scatter_reduce(ScatterArgs a
             acc[kTileRows + i] = 0ull;
         }
         __syncthreads();
-        // kReduceUnroll independent, coalesced record loads in flight per thread
-        for (uint64_t r0 = r_begin; r0 < r_end; r0 += (uint64_t)kReduceThreads * kReduceUnroll) {
-            uint32_t key[kReduceUnroll];
-            float2 v[kReduceUnroll];
+        // Each thread takes runs of kRun consecutive records (one 16-byte key
+        // load, four 16-byte value loads; runs start at multiples of kRun, so
+        // the loads are aligned and stay inside the record arrays, whose
+        // length is a multiple of kRun).  Records of a run outside
+        // [r_begin, r_end) add zero.  Consecutive records often carry the same
+        // row (neighbouring samples of one ray on a coarse level); such
+        // repeats are summed in registers first, so one LDS atomic per row
+        // and run is issued instead of one per record.
+        const uint64_t q_begin = r_begin / kRun, q_end = (r_end + kRun - 1) / kRun;
+        for (uint64_t q0 = q_begin + threadIdx.x; q0 < q_end; q0 += (uint64_t)kReduceThreads * kRunsPerThread) {
+            uint4 kw[kRunsPerThread];
+            float4 v4[kRunsPerThread][kRun / 2];
 #pragma unroll
-            for (int u = 0; u < kReduceUnroll; ++u) {
-                const uint64_t r = r0 + (uint64_t)u * kReduceThreads + threadIdx.x;
-                const bool ok = r < r_end;
-                key[u] = ok ? a.keys[r] : 0u;
-                v[u] = ok ? a.vals[r] : make_float2(0.0f, 0.0f);
+            for (int u = 0; u < kRunsPerThread; ++u) {
+                const uint64_t q = q0 + (uint64_t)u * kReduceThreads;
+                const uint64_t qc = q < q_end ? q : q_begin;
+                kw[u] = *reinterpret_cast<const uint4*>(a.keys + qc * kRun);
+                const float4* vp = reinterpret_cast<const float4*>(a.vals + qc * kRun);
+#pragma unroll
+                for (int i = 0; i < kRun / 2; ++i) v4[u][i] = vp[i];
             }
 #pragma unroll
-            for (int u = 0; u < kReduceUnroll; ++u) {
-                const long long qx = (long long)rintf(ldexpf(v[u].x, ex));
-                const long long qy = (long long)rintf(ldexpf(v[u].y, ex));
-                if (qx != 0) atomicAdd(&acc[key[u]], (unsigned long long)qx);
-                if (qy != 0) atomicAdd(&acc[kTileRows + key[u]], (unsigned long long)qy);
+            for (int u = 0; u < kRunsPerThread; ++u) {
+                const uint64_t q = q0 + (uint64_t)u * kReduceThreads;
+                const uint64_t rec0 = q * kRun;
+                uint32_t key[kRun];
+                long long sx[kRun], sy[kRun];
+#pragma unroll
+                for (int i = 0; i < kRun; ++i) {
+                    const uint32_t w = i < 2 ? kw[u].x : i < 4 ? kw[u].y : i < 6 ? kw[u].z : kw[u].w;
+                    key[i] = (i & 1) ? (w >> 16) : (w & 0xffffu);
+                    const float vx = (i & 1) ? v4[u][i >> 1].z : v4[u][i >> 1].x;
+                    const float vy = (i & 1) ? v4[u][i >> 1].w : v4[u][i >> 1].y;
+                    const bool ok = q < q_end && rec0 + i >= r_begin && rec0 + i < r_end;
+                    sx[i] = ok ? (long long)rintf(ldexpf(vx, ex)) : 0ll;
+                    sy[i] = ok ? (long long)rintf(ldexpf(vy, ex)) : 0ll;
+                }
+#pragma unroll
+                for (int i = 1; i < kRun; ++i) {
+                    if (key[i] == key[i - 1]) {
+                        sx[i] += sx[i - 1];
+                        sy[i] += sy[i - 1];
+                        sx[i - 1] = 0;
+                        sy[i - 1] = 0;
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < kRun; ++i) {
+                    if (sx[i] != 0) atomicAdd(&acc[key[i]], (unsigned long long)sx[i]);
+                    if (sy[i] != 0) atomicAdd(&acc[kTileRows + key[i]], (unsigned long long)sy[i]);
+                }
             }
         }
         __syncthreads();
@@ -506,7 +556,9 @@ ScatterObj scatter_obj(const GridInfo& g, int64_t n_s)
 
 int64_t scatter_items(const ScatterObj& o) { return (int64_t)o.grid.n_levels * o.n_blocks; }
 
+// A multiple of kRun: the reduce reads whole aligned runs.
 int64_t scatter_records(const ScatterObj& o) { return o.n_s * o.grid.n_levels * 8; }
+static_assert(8 % kRun == 0, "record arrays must hold whole runs");
 
 int scatter_max_tiles_per_level() { return kMaxTilesPerLevel; }
 
