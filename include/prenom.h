@@ -242,7 +242,8 @@ prenom_status prenom_refresh_lowp(const prenom_model* model, void* stream);
  * prenom_encode -- the hash encoding alone (Sec. III-B "Object-level NeRFs"):
  * pos [n][3] in [0,1]^3 -> features [L][n][F] (level-major); corner_idx
  * [L][n][8] (int32 table row of each cell corner, corner e = (e&1, e>>1&1,
- * e>>2&1)) or NULL.  table: [L][T][F].
+ * e>>2&1)) or NULL.  table: [L][T][F], 16-byte aligned (rows are read in
+ * aligned pairs); features 8-byte aligned; otherwise PRENOM_ERR_INVALID_ARG.
  * ---------------------------------------------------------------------- */
 prenom_status prenom_encode(const prenom_arch* arch, const float* table, const float* pos, int64_t n,
                             float* features, int32_t* corner_idx, void* stream);

@@ -526,7 +526,7 @@ prenom_status prenom_encode(const prenom_arch* arch, const float* table, const f
     if (st != PRENOM_OK) return st;
     if (n < 0 || n >= (int64_t)1 << 31) return fail(PRENOM_ERR_SHAPE, "n outside [0, 2^31)");
     if (n > 0 && (!table || !pos || !features)) return fail(PRENOM_ERR_INVALID_ARG, "NULL array argument");
-    if (table && !aligned(table, 8)) return fail(PRENOM_ERR_INVALID_ARG, "table not 8-byte aligned");
+    if (table && !aligned(table, 16)) return fail(PRENOM_ERR_INVALID_ARG, "table not 16-byte aligned");
     if (features && !aligned(features, 8)) return fail(PRENOM_ERR_INVALID_ARG, "features not 8-byte aligned");
     PRENOM_LAUNCH("k_encode_points", (hipStream_t)stream,
                   launch_encode_points(grid_info(arch), table, pos, n, features, corner_idx, (hipStream_t)stream));

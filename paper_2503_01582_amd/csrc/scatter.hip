@@ -22,9 +22,10 @@
 //
 // The LDS accumulation is 64-bit fixed point (integer LDS atomics run several
 // times faster than FP32 ones).  With e chosen so that max|dy| * records * 2^e
-// < 2^62, no sum can overflow and each contribution is rounded by at most
-// 2^-(e+1), far below FP32 resolution of the result; integer sums do not
-// depend on order, so a tile with one chunk gets a bit-reproducible gradient.
+// < 2^62, no sum can overflow; with max|dy| * 2^e < 2^50 as well, each
+// contribution is rounded by at most 2^-(e+1) <= 2^-51 max|dy|, far below FP32
+// resolution of the result.  Integer sums do not depend on order, so a tile
+// with one chunk gets a bit-reproducible gradient.
 //
 // Corner rows and weights are computed by the same function as the forward
 // encoding, so count and place agree exactly.
@@ -281,15 +282,19 @@ __global__ __launch_bounds__(kScanThreads) void k_scatter_scan_tiles(ScatterArgs
         a.chunk_start[t] = ck;
         r += a.tile_total[t];
         ck += (a.tile_total[t] + kChunk - 1) / kChunk;
-        // largest e with max|dy| * records * 2^e < 2^62 (bound on any row's |sum| * 2^e)
+        // largest e with max|dy| * records * 2^e < 2^62 (bound on any row's
+        // |sum| * 2^e) and max|dy| * 2^e < 2^50 (bound on one contribution,
+        // for the reduce's FP64 rounding)
         const ScatterObj& o = sobj<kMany>(a, obj_of_tile<kMany>(a, t));
         const int l = level_of_tile(o, (int)(t - o.tile_off));
-        const double bound = (double)a.level_max[o.lev_off + l] * (double)a.tile_total[t];
+        const double vmax = (double)a.level_max[o.lev_off + l];
+        const double bound = vmax * (double)a.tile_total[t];
         int e = 0;
         if (bound > 0.0) {
-            int ex;
+            int ex, evx;
             frexp(bound, &ex);  // bound < 2^ex
-            e = 62 - ex;
+            frexp(vmax, &evx);  // vmax < 2^evx
+            e = min(62 - ex, 50 - evx);
         }
         a.tile_exp[t] = e;
     }
@@ -323,6 +328,14 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
     int l, bx;
     split_item(item - o.item_off, o.n_blocks, l, bx);
     const int nt = o.tiles[l];
+    // Global start of this block's run in the thread's tile (thread i holds
+    // tile i; threads past the level's tiles load tile nt - 1 and ignore it).
+    // Loaded first, together with the contribution, so the block waits on
+    // global memory once.
+    const int tb = o.tile_base[l];
+    const int own = min((int)threadIdx.x, nt - 1);
+    const uint64_t own_start = a.tile_start[o.tile_off + tb + own];
+    const uint32_t own_off = a.counts[o.count_off + (int64_t)(tb + own) * o.n_blocks + bx];
     for (int i = threadIdx.x; i < nt; i += kPlaceThreads) hist[i] = 0;
     __syncthreads();
     // pass 1: rank of each contribution within its tile (LDS atomics)
@@ -361,9 +374,9 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
     __syncthreads();
     // global position of record p of local tile tt: gbase[tt] + p
     {
-        const int tb = o.tile_base[l];
         const uint32_t* cnt = a.counts + o.count_off;
-        for (int i = threadIdx.x; i < nt; i += kPlaceThreads)
+        if ((int)threadIdx.x < nt) gbase[threadIdx.x] = own_start + own_off - seg[threadIdx.x];
+        for (int i = threadIdx.x + kPlaceThreads; i < nt; i += kPlaceThreads)
             gbase[i] = a.tile_start[o.tile_off + tb + i] + cnt[(int64_t)(tb + i) * o.n_blocks + bx] - seg[i];
     }
     // pass 2: stage the records sorted by tile (corners kept from pass 1)
@@ -379,12 +392,40 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
     }
     __syncthreads();
     // write each tile's run to its global range: consecutive threads, consecutive records
+    // The staging arrays hold kRecordsPerBlock entries, so the LDS reads of
+    // several records are issued before the guarded stores.
     const uint32_t total = *p_total;
-    for (uint32_t p = threadIdx.x; p < total; p += kPlaceThreads) {
-        const uint64_t dst = gbase[s_tile[p]] + p;
-        a.keys[dst] = s_key[p];
-        a.vals[dst] = s_val[p];
+    constexpr int kPer = kRecordsPerBlock / kPlaceThreads, kHalf = kPer / 2;
+#pragma unroll
+    for (int h = 0; h < kPer; h += kHalf) {
+        if (h * kPlaceThreads >= (int)total) break;
+        uint32_t tt[kHalf];
+#pragma unroll
+        for (int k = 0; k < kHalf; ++k)
+            tt[k] = min((uint32_t)s_tile[threadIdx.x + (h + k) * kPlaceThreads], (uint32_t)nt - 1u);
+#pragma unroll
+        for (int k = 0; k < kHalf; ++k) {
+            const uint32_t p = threadIdx.x + (h + k) * kPlaceThreads;
+            const uint64_t dst = gbase[tt[k]] + p;
+            const uint16_t key = s_key[p];
+            const float2 v = s_val[p];
+            if (p < total) {
+                a.keys[dst] = key;
+                a.vals[dst] = v;
+            }
+        }
     }
+}
+
+// round(v * 2^ex) as an integer, for |v * 2^ex| < 2^51 (the tile exponent
+// guarantees it).  v * 2^ex is exact in FP64; adding 1.5 * 2^52 rounds it to an
+// integer (to nearest, ties to even, as rintf) held in the low mantissa bits,
+// and subtracting the constant's bit pattern leaves that integer.
+__device__ __forceinline__ long long quantize(float v, int ex)
+{
+    constexpr double kMagic = 6755399441055744.0;  // 1.5 * 2^52
+    const double q = ldexp((double)v, ex) + kMagic;
+    return (long long)(__double_as_longlong(q) - __double_as_longlong(kMagic));
 }
 
 template <bool kMany>
@@ -459,8 +500,8 @@ __global__ __launch_bounds__(kReduceThreads) void k_scatter_reduce(ScatterArgs a
                     const float vx = (i & 1) ? v4[u][i >> 1].z : v4[u][i >> 1].x;
                     const float vy = (i & 1) ? v4[u][i >> 1].w : v4[u][i >> 1].y;
                     const bool ok = q < q_end && rec0 + i >= r_begin && rec0 + i < r_end;
-                    sx[i] = ok ? (long long)rintf(ldexpf(vx, ex)) : 0ll;
-                    sy[i] = ok ? (long long)rintf(ldexpf(vy, ex)) : 0ll;
+                    sx[i] = ok ? quantize(vx, ex) : 0ll;
+                    sy[i] = ok ? quantize(vy, ex) : 0ll;
                 }
 #pragma unroll
                 for (int i = 1; i < kRun; ++i) {

@@ -73,6 +73,17 @@ def test_invalid_sampler_arguments(L):
     assert L.lib().prenom_status_string(0) == b"ok"
 
 
+def test_encode_rejects_misaligned_table(L):
+    """Table rows are read in aligned pairs (16 bytes); an 8-byte aligned
+    table is refused on the host, before any launch."""
+    from paper_2503_01582_amd import api
+    a = api.make_arch(ARCH_SMALL)
+    fake = 1 << 20  # never dereferenced: the checks fail first
+    st = L.lib().prenom_encode(C.byref(a), C.c_void_p(fake + 8), C.c_void_p(fake), 4, C.c_void_p(fake), None, None)
+    assert L.STATUS[st] == "PRENOM_ERR_INVALID_ARG"
+    assert b"16-byte" in L.lib().prenom_last_error()
+
+
 def test_product_path_never_touches_the_oracle():
     pkg = os.path.join(ROOT, "paper_2503_01582_amd")
     for dirpath, _, files in os.walk(pkg):
