@@ -1,14 +1,25 @@
 // Prior-based probabilistic ray sampling (Sec. III-B "Probabilistic Ray
 // Sampling", Eq. (4)-(6) and the escape rule).
 //
-// One thread per ray.  The whole decision chain (object-frame transform, slab
-// test, coarse midpoints, trilinear prior lookup, prefix sums of
+// One wavefront per ray.  The whole decision chain (object-frame transform,
+// slab test, coarse midpoints, trilinear prior lookup, prefix sums of
 // sigma_i * delta_i, the expm1 ratio that forms the CDF, the comparison with
 // u_k) is evaluated in FP64 with contraction disabled, so the sampled bins do
-// not hinge on FP32 rounding.  The CDF is never stored: the ray is walked
-// twice over its N_c coarse bins -- once for the total mass, once merged with
-// the ascending draws u_k -- recomputing each bin's prior value, which keeps
-// the kernel free of per-thread arrays (no scratch memory).
+// not hinge on FP32 rounding.  The lanes share the work of one ray:
+//
+//   * the N_c coarse bins' sigma_i * delta_i, one bin per lane (prior lookups
+//     in parallel), kept in LDS;
+//   * the CDF value at the end of each bin, each lane summing the bins before
+//     its own in bin order (the same FP64 additions, in the same order, as a
+//     single sequential pass);
+//   * the draws u_k, one per lane: the bin of draw k is the first bin whose
+//     CDF end reaches u_k, found by binary search when the CDF ends do not
+//     decrease (always, for a non-negative prior); otherwise one lane walks
+//     the bins for all draws in order;
+//   * the merge of draws and midpoints by rank: before draw k come the
+//     midpoints not above any earlier draw (a running maximum of per-draw
+//     counts), before midpoint i the draws whose running count is <= i;
+//   * t and dt written by consecutive lanes (coalesced).
 #include "common.h"
 
 #pragma clang fp contract(off)
@@ -16,7 +27,6 @@
 namespace prenom {
 namespace {
 
-constexpr int kSampleBlock = 128;
 
 // Trilinear, vertex-aligned lookup (value F[i] at i/(R-1)), x clamped.
 __device__ double prior_at(const float* __restrict__ F, int R, const double xin[3])
@@ -71,13 +81,43 @@ __device__ __forceinline__ double coarse_tau(const float* prior, int R, const Ra
     return sig * r.delta * r.len;
 }
 
-// One ray.  A, prior and R are the ray's object's pose and prior (per
-// object in a batch); everything else comes from `a`.
-__device__ void sample_ray(const SampleArgs& a, const double* A_obj, const float* prior, int R, bool use_prior,
-                           int64_t ray)
+// LDS of one ray: tau[N_c], cdf[N_c] (FP64), draws[N_r] (FP64), out[S]
+// (FP64), run[N_r] (int32 running midpoint counts), bin[N_r] (int32).
+__host__ __device__ constexpr size_t sample_lds_bytes(int Nc, int Nr, int S)
 {
+    return (size_t)(2 * Nc + Nr + S) * sizeof(double) + (size_t)2 * Nr * sizeof(int32_t);
+}
+
+// Number of midpoints i in [0, Nc) with m_i <= tk (m_i ascends in i).
+__device__ __forceinline__ int midpoints_upto(const RayFrame& r, int Nc, double tk)
+{
+    int lo = 0, hi = Nc;  // answer in [lo, hi]
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const double m = r.tn + ((double)mid + 0.5) * r.delta;
+        if (m <= tk)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// One ray, by one wavefront (blockDim.x == 64).  A, prior and R are the ray's
+// object's pose and prior (per object in a batch); everything else comes from
+// `a`.
+__device__ void sample_ray(const SampleArgs& a, const double* A_obj, const float* prior, int R, bool use_prior,
+                           int64_t ray, double* lds)
+{
+    const int lane = threadIdx.x;
     const int Nc = a.n_coarse, Nr = a.n_fine;
     const int S = Nr + (a.include_coarse ? Nc : 0);
+    double* tau = lds;
+    double* cdf = tau + Nc;
+    double* draws = cdf + Nc;
+    double* out = draws + Nr;
+    int32_t* run = reinterpret_cast<int32_t*>(out + S);
+    int32_t* bin = run + Nr;
 
     RayFrame r;
     const float* ow = a.rays_o + 3 * ray;
@@ -87,10 +127,10 @@ __device__ void sample_ray(const SampleArgs& a, const double* A_obj, const float
         r.o[k] = A[0] * (double)ow[0] + A[1] * (double)ow[1] + A[2] * (double)ow[2] + A[3];
         r.d[k] = A[0] * (double)dw[0] + A[1] * (double)dw[1] + A[2] * (double)dw[2];
     }
-    float* ro = a.ray_obj + 6 * ray;
-    for (int k = 0; k < 3; ++k) {
-        ro[k] = (float)r.o[k];
-        ro[3 + k] = (float)r.d[k];
+    if (lane < 6) {  // constant indices only, so the frame stays in registers
+        const double v = lane == 0 ? r.o[0] : lane == 1 ? r.o[1] : lane == 2 ? r.o[2]
+                       : lane == 3 ? r.d[0] : lane == 4 ? r.d[1] : r.d[2];
+        a.ray_obj[6 * ray + lane] = (float)v;
     }
 
     // slab test against [0,1]^3 and [near, far]
@@ -117,106 +157,169 @@ __device__ void sample_ray(const SampleArgs& a, const double* A_obj, const float
     int32_t* br = a.bins + (int64_t)Nr * ray;
     const float* xr = a.xi + (int64_t)Nr * ray;
     if (!hit) {
-        for (int j = 0; j < S; ++j) {
+        for (int j = lane; j < S; j += 64) {
             tr[j] = 0.0f;
             dtr[j] = 0.0f;
         }
-        for (int k = 0; k < Nr; ++k) br[k] = -1;
-        a.flags[ray] = PRENOM_FLAG_MISS;
+        for (int k = lane; k < Nr; k += 64) br[k] = -1;
+        if (lane == 0) a.flags[ray] = PRENOM_FLAG_MISS;
         return;
     }
     r.len = sqrt(r.d[0] * r.d[0] + r.d[1] * r.d[1] + r.d[2] * r.d[2]);
     r.delta = Nc > 0 ? (r.tf - r.tn) / (double)Nc : 0.0;
 
-    // pass 1: total prior mass along the ray
+    // coarse bins: sigma_i delta_i, then the total mass (bin order)
+    if (use_prior)
+        for (int i = lane; i < Nc; i += 64) tau[i] = coarse_tau(prior, R, r, i);
+    __syncthreads();
     bool escaped = false;
     double total_S = 0.0;
     if (use_prior) {
-        for (int i = 0; i < Nc; ++i) total_S = total_S + coarse_tau(prior, R, r, i);
+        for (int i = 0; i < Nc; ++i) total_S = total_S + tau[i];
         escaped = (-expm1(-total_S)) < a.eps;
     }
     const bool cdf_draws = use_prior && !escaped;
-    a.flags[ray] = (uint8_t)((use_prior ? 0 : PRENOM_FLAG_UNIFORM) | (escaped ? PRENOM_FLAG_ESCAPED : 0));
+    if (lane == 0)
+        a.flags[ray] = (uint8_t)((use_prior ? 0 : PRENOM_FLAG_UNIFORM) | (escaped ? PRENOM_FLAG_ESCAPED : 0));
 
-    // pass 2: draws in ascending u, merged with the coarse midpoints
+    // CDF at the end of each bin (1 at the last): prefix of the bins in order
     const double den = expm1(-total_S);
-    int b = 0;
-    double S_b1 = 0.0, C_b = 0.0, C_b1 = 1.0;
+    bool ascending = true;
     if (cdf_draws) {
-        S_b1 = 0.0 + coarse_tau(prior, R, r, 0);
-        C_b1 = (Nc == 1) ? 1.0 : expm1(-S_b1) / den;
+        for (int b = lane; b < Nc; b += 64) {
+            double Sb = 0.0;
+            for (int i = 0; i <= b; ++i) Sb = Sb + tau[i];
+            cdf[b] = (b + 1 == Nc) ? 1.0 : expm1(-Sb) / den;
+        }
+        __syncthreads();
+        // Searching each draw's bin on its own equals the walk when the CDF
+        // ends below the last bin do not decrease and the draws u_k do not
+        // either (both hold for a non-negative prior and xi in [0, 1]).
+        for (int b = lane; b + 2 < Nc; b += 64)
+            if (!(cdf[b] <= cdf[b + 1])) ascending = false;
+        for (int k = lane; k + 1 < Nr; k += 64)
+            if (!(((double)k + (double)xr[k]) / (double)Nr <= ((double)(k + 1) + (double)xr[k + 1]) / (double)Nr))
+                ascending = false;
+        ascending = __syncthreads_and(ascending);
+        if (!ascending && lane == 0) {  // sequential walk over the draws, in order
+            int bb = 0;
+            for (int k = 0; k < Nr; ++k) {
+                const double u = ((double)k + (double)xr[k]) / (double)Nr;
+                while (bb + 1 < Nc && cdf[bb] < u) ++bb;
+                bin[k] = bb;
+            }
+        }
+        __syncthreads();
     }
-    int ic = 0, j = 0;
-    double prev = 0.0;
-    auto emit = [&](double tv) {
-        if (j > 0) dtr[j - 1] = (float)((tv - prev) * r.len);
-        tr[j] = (float)tv;
-        prev = tv;
-        ++j;
-    };
-    for (int k = 0; k < Nr; ++k) {
+
+    // draws: inverse CDF within the bin (Eq. (6)), or uniform in [tn, tf]
+    for (int k = lane; k < Nr; k += 64) {
         const double u = ((double)k + (double)xr[k]) / (double)Nr;
         double tk;
+        int bk = -1;
         if (!cdf_draws) {
             tk = r.tn + u * (r.tf - r.tn);
-            br[k] = -1;
         } else {
-            while (b + 1 < Nc && C_b1 < u) {  // the last CDF value is 1 > u for xi in (0,1)
-                ++b;
-                C_b = C_b1;
-                S_b1 = S_b1 + coarse_tau(prior, R, r, b);
-                C_b1 = (b + 1 == Nc) ? 1.0 : expm1(-S_b1) / den;
+            if (ascending) {  // first b in [0, Nc - 1) with cdf[b] >= u, else Nc - 1
+                int lo = 0, hi = Nc - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (cdf[mid] < u)
+                        lo = mid + 1;
+                    else
+                        hi = mid;
+                }
+                bk = lo;
+            } else {
+                bk = bin[k];
             }
-            tk = r.tn + r.delta * ((double)b + (u - C_b) / (C_b1 - C_b));
-            br[k] = b;
+            const double C_b = bk == 0 ? 0.0 : cdf[bk - 1];
+            const double C_b1 = cdf[bk];
+            tk = r.tn + r.delta * ((double)bk + (u - C_b) / (C_b1 - C_b));
         }
-        if (a.include_coarse) {
-            while (ic < Nc) {
-                const double m = r.tn + ((double)ic + 0.5) * r.delta;
-                if (!(m <= tk)) break;
-                emit(m);
-                ++ic;
-            }
-        }
-        emit(tk);
+        br[k] = bk;
+        draws[k] = tk;
+        run[k] = a.include_coarse ? midpoints_upto(r, Nc, tk) : 0;
     }
-    if (a.include_coarse)
-        for (; ic < Nc; ++ic) emit(r.tn + ((double)ic + 0.5) * r.delta);
-    dtr[S - 1] = (float)((r.tf - prev) * r.len);
+    __syncthreads();
+
+    // ranks: midpoints emitted before draw k = max over k' <= k of the counts
+    if (a.include_coarse) {
+        int carry = 0;  // running maximum, 64 draws at a time
+        for (int k0 = 0; k0 < Nr; k0 += 64) {
+            const int k = k0 + lane;
+            int v = k < Nr ? run[k] : 0;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int up = __shfl_up(v, d);
+                if (lane >= d) v = v > up ? v : up;
+            }
+            v = v > carry ? v : carry;
+            if (k < Nr) run[k] = v;
+            carry = __shfl(v, 63);
+        }
+        __syncthreads();
+        for (int k = lane; k < Nr; k += 64) out[k + run[k]] = draws[k];
+        for (int i = lane; i < Nc; i += 64) {
+            int lo = 0, hi = Nr;  // draws before midpoint i: first k with run[k] > i
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (run[mid] <= i)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            out[i + lo] = r.tn + ((double)i + 0.5) * r.delta;
+        }
+    } else {
+        for (int k = lane; k < Nr; k += 64) out[k] = draws[k];
+    }
+    __syncthreads();
+    for (int j = lane; j < S; j += 64) {
+        const double tv = out[j];
+        const double next = j + 1 < S ? out[j + 1] : r.tf;
+        tr[j] = (float)tv;
+        dtr[j] = (float)((next - tv) * r.len);
+    }
 }
 
-__global__ __launch_bounds__(kSampleBlock) void k_sample(SampleArgs a)
+__global__ __launch_bounds__(64) void k_sample(SampleArgs a)
 {
-    const int64_t ray = (int64_t)blockIdx.x * kSampleBlock + threadIdx.x;
-    if (ray >= a.n) return;
-    sample_ray(a, a.A, a.prior, a.R, a.use_prior != 0, ray);
+    extern __shared__ double lds[];
+    sample_ray(a, a.A, a.prior, a.R, a.use_prior != 0, blockIdx.x, lds);
 }
 
 // All rays of a batch: the ray's object (last with ray_begin <= ray) supplies
 // pose and prior; a.use_prior == 0 forces uniform draws for every object.
-__global__ __launch_bounds__(kSampleBlock) void k_sample_batch(SampleArgs a, const ObjDev* __restrict__ objs, int n_obj)
+__global__ __launch_bounds__(64) void k_sample_batch(SampleArgs a, const ObjDev* __restrict__ objs, int n_obj)
 {
-    const int64_t ray = (int64_t)blockIdx.x * kSampleBlock + threadIdx.x;
-    if (ray >= a.n) return;
+    extern __shared__ double lds[];
+    const int64_t ray = blockIdx.x;
     const ObjDev& o = objs[find_object(objs, n_obj, ray)];
-    sample_ray(a, o.A, o.prior, o.prior_res, a.use_prior != 0 && o.prior != nullptr, ray);
+    sample_ray(a, o.A, o.prior, o.prior_res, a.use_prior != 0 && o.prior != nullptr, ray, lds);
+}
+
+size_t sample_lds(const SampleArgs& a)
+{
+    return sample_lds_bytes(a.n_coarse, a.n_fine, a.n_fine + (a.include_coarse ? a.n_coarse : 0));
 }
 
 }  // namespace
 
+// One block (one wavefront) per ray: at most 2^32 - 1 rays per launch.
 hipError_t launch_sample_batch(const SampleArgs& a, const ObjDev* objs, int n_obj, hipStream_t s)
 {
     if (a.n == 0) return hipSuccess;
-    const int64_t blocks = (a.n + kSampleBlock - 1) / kSampleBlock;
-    hipLaunchKernelGGL(k_sample_batch, dim3((uint32_t)blocks), dim3(kSampleBlock), 0, s, a, objs, n_obj);
+    if (a.n > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sample_batch, dim3((uint32_t)a.n), dim3(64), sample_lds(a), s, a, objs, n_obj);
     return hipGetLastError();
 }
 
 hipError_t launch_sample(const SampleArgs& a, hipStream_t s)
 {
     if (a.n == 0) return hipSuccess;
-    const int64_t blocks = (a.n + kSampleBlock - 1) / kSampleBlock;
-    hipLaunchKernelGGL(k_sample, dim3((uint32_t)blocks), dim3(kSampleBlock), 0, s, a);
+    if (a.n > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sample, dim3((uint32_t)a.n), dim3(64), sample_lds(a), s, a);
     return hipGetLastError();
 }
 
