@@ -1,22 +1,28 @@
 // Volume rendering and losses (Sec. III-B "Volume Rendering", Eq. (5),
 // (7)-(9)) and their adjoint.
 //
-// One 64-lane wavefront per ray, one lane per sample: the transmittance
-// T_j = exp(-sum_{i<j} sigma_i delta_i) is an exclusive prefix scan of
-// sigma delta across the wave, the adjoint's sum_{k>j} w_k a_k an exclusive
-// suffix scan; rays longer than 64 samples are walked in 64-sample chunks
-// with the scan carried between chunks.  FP32 scans; the batch loss is summed
-// per block in FP64 and finished by one block.
+// Sixteen lanes (one DPP row) per ray, four rays per wavefront.  A ray is
+// walked in chunks of 64 samples; lane l holds samples l, l + 16, l + 32,
+// l + 48 of the chunk (so each load and store of a row covers 16 consecutive
+// samples).  The transmittance T_j = exp(-sum_{i<j} sigma_i delta_i) is an
+// exclusive prefix scan of sigma delta along the ray and the adjoint's
+// sum_{k>j} w_k a_k an exclusive suffix scan: one 16-lane row scan per sample
+// slot, carried from slot to slot and from chunk to chunk.  Row scans and sums
+// are DPP row operations (no LDS, no cross-row traffic), and the per-ray work
+// (loss, upstream gradients) is shared by the four rays of a wavefront.  FP32
+// scans; the loss is summed per block in FP64 and finished by one block.
 #include "common.h"
 
 namespace prenom {
 namespace {
 
-constexpr int kRaysPerBlock = 4;  // one wave per ray
-constexpr int kMaxChunks = 4;     // S <= 256
+constexpr int kRow = 16;                        // lanes per ray
+constexpr int kSlots = 4;                       // samples per lane and chunk
+constexpr int kChunk = kRow * kSlots;           // 64 samples
+constexpr int kWaves = 4;                       // waves per block
+constexpr int kRaysPerBlock = kWaves * (64 / kRow);  // 16
+constexpr int kMaxChunks = 4;                   // S <= 256
 
-// Wave-wide sums and scans on DPP row operations (rows of 16 lanes) with
-// v_readlane for the four row results, in place of LDS-routed shuffles.
 // DPP controls: quad_perm [1,0,3,2] and [2,3,0,1] (0xB1, 0x4E), row_shr:n
 // (0x110 + n: lane i reads lane i - n of its row, zero below the row start),
 // row_shl:n (0x100 + n: lane i reads lane i + n, zero past the row end),
@@ -27,12 +33,7 @@ __device__ __forceinline__ float dpp(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, 0xf, 0xf, true));
 }
 
-__device__ __forceinline__ float lane_value(float v, int lane)
-{
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
-}
-
-// Sum over the 16 lanes of each row, in every lane of the row.
+// Sum over the 16 lanes of the row, in every lane of the row.
 __device__ __forceinline__ float row_sum(float v)
 {
     v += dpp<0xB1>(v);
@@ -42,11 +43,26 @@ __device__ __forceinline__ float row_sum(float v)
     return v;
 }
 
-// Sum over the 64 lanes, in every lane.
-__device__ __forceinline__ float wave_sum(float v)
+// Exclusive prefix sum over the lanes of the row (0 in its first lane).
+__device__ __forceinline__ float row_excl_prefix(float x)
 {
-    v = row_sum(v);
-    return (lane_value(v, 0) + lane_value(v, 16)) + (lane_value(v, 32) + lane_value(v, 48));
+    float v = x;
+    v += dpp<0x111>(v);
+    v += dpp<0x112>(v);
+    v += dpp<0x114>(v);
+    v += dpp<0x118>(v);
+    return dpp<0x111>(v);
+}
+
+// Exclusive suffix sum over the lanes of the row (0 in its last lane).
+__device__ __forceinline__ float row_excl_suffix(float x)
+{
+    float v = x;
+    v += dpp<0x101>(v);
+    v += dpp<0x102>(v);
+    v += dpp<0x104>(v);
+    v += dpp<0x108>(v);
+    return dpp<0x101>(v);
 }
 
 __device__ __forceinline__ double wave_sum_d(double v)
@@ -54,34 +70,6 @@ __device__ __forceinline__ double wave_sum_d(double v)
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
     return v;
-}
-
-// exclusive prefix sum over the 64 lanes
-__device__ __forceinline__ float wave_excl_prefix(float x, int lane)
-{
-    float v = x;  // inclusive prefix within the row
-    v += dpp<0x111>(v);
-    v += dpp<0x112>(v);
-    v += dpp<0x114>(v);
-    v += dpp<0x118>(v);
-    const float r0 = lane_value(v, 15), r1 = lane_value(v, 31), r2 = lane_value(v, 47);
-    const int row = lane >> 4;
-    const float before = row == 0 ? 0.0f : row == 1 ? r0 : row == 2 ? r0 + r1 : (r0 + r1) + r2;
-    return dpp<0x111>(v) + before;  // the previous lane's inclusive prefix (0 at a row start)
-}
-
-// exclusive suffix sum (sum over lanes above this one)
-__device__ __forceinline__ float wave_excl_suffix(float x, int lane)
-{
-    float v = x;  // inclusive suffix within the row
-    v += dpp<0x101>(v);
-    v += dpp<0x102>(v);
-    v += dpp<0x104>(v);
-    v += dpp<0x108>(v);
-    const float r1 = lane_value(v, 16), r2 = lane_value(v, 32), r3 = lane_value(v, 48);
-    const int row = lane >> 4;
-    const float after = row == 3 ? 0.0f : row == 2 ? r3 : row == 1 ? r2 + r3 : r1 + (r2 + r3);
-    return dpp<0x101>(v) + after;  // the next lane's inclusive suffix (0 at a row end)
 }
 
 // Rays over which the loss of ray r is averaged: the whole call, or the
@@ -141,100 +129,129 @@ __device__ __forceinline__ RayTargets targets_of(const CompositeArgs& a, const R
     return tg;
 }
 
-// One lane's sample of a 64-sample chunk of ray r: (sigma, rgb), dt and t.
-// Lanes past the end of the ray read sample 0 of the ray (S >= 1) and are
-// masked where the values are used (their optical depth and density count as
-// zero), so the loads are unconditional and are issued together with the
-// ray's other inputs.
-struct SampleIn {
-    float4 v;
-    float dt, t;
-    bool valid;
+// A lane's kSlots samples of one chunk of ray r: (sigma, rgb), dt and t.
+// Samples past the end of the ray read sample 0 of the ray (S >= 1) and are
+// masked where used, so every load is unconditional.
+struct Slots {
+    float4 v[kSlots];
+    float dt[kSlots], t[kSlots];
+    bool valid[kSlots];
 };
 
-__device__ __forceinline__ SampleIn load_sample(const CompositeArgs& a, int64_t r, int S, int jj)
+__device__ __forceinline__ Slots load_slots(const CompositeArgs& a, int64_t r, int c0, int l)
 {
-    SampleIn x;
-    x.valid = jj < S;
-    const int64_t sidx = r * S + (x.valid ? jj : 0);
-    x.v = reinterpret_cast<const float4*>(a.sc)[sidx];
-    x.dt = a.dt[sidx];
-    x.t = a.t[sidx];
+    const int S = a.S;
+    Slots x;
+#pragma unroll
+    for (int m = 0; m < kSlots; ++m) {
+        const int j = c0 + l + kRow * m;
+        x.valid[m] = j < S;
+        const int64_t idx = r * S + (x.valid[m] ? j : 0);
+        x.v[m] = reinterpret_cast<const float4*>(a.sc)[idx];
+        x.dt[m] = a.dt[idx];
+        x.t[m] = a.t[idx];
+    }
     return x;
 }
 
-__global__ __launch_bounds__(64 * kRaysPerBlock) void k_composite_fwd(CompositeArgs a)
+// Row of this lane's ray within the wave, and the ray (rows past the last ray
+// work on the last ray and write nothing).
+struct RayLane {
+    int l, g;
+    int64_t r, rc;
+    bool live;
+};
+
+__device__ __forceinline__ RayLane ray_lane(const CompositeArgs& a)
 {
-    __shared__ double block_loss[kRaysPerBlock];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t r = (int64_t)blockIdx.x * kRaysPerBlock + wave;
-    double ray_loss = 0.0;
-    if (r < a.n_rays) {
-        const int S = a.S;
-        // every input of the ray is requested before the first wait
-        const uint8_t flags = a.flags[r];
-        const SampleIn first = load_sample(a, r, S, lane);
-        const RayExtras ex = load_extras(a, r);
-        float C[3] = {0.0f, 0.0f, 0.0f}, Dh = 0.0f, A = 0.0f, sig_sum = 0.0f, T_S = 1.0f;
-        if (!(flags & PRENOM_FLAG_MISS)) {
-            float carry = 0.0f;
-            for (int c0 = 0; c0 < S; c0 += 64) {
-                const SampleIn x = c0 == 0 ? first : load_sample(a, r, S, c0 + lane);
-                const float4 v = x.v;
-                const float tj = x.t;
-                const float tau = x.valid ? v.x * x.dt : 0.0f;  // w = 0 past the end
-                const float excl = wave_excl_prefix(tau, lane) + carry;
-                const float w = expf(-excl) * (-expm1f(-tau));
-                C[0] += w * v.y;
-                C[1] += w * v.z;
-                C[2] += w * v.w;
-                Dh += w * tj;
-                A += w;
-                sig_sum += x.valid ? v.x : 0.0f;
-                carry += wave_sum(tau);
-            }
-            for (int k = 0; k < 3; ++k) C[k] = wave_sum(C[k]);
-            Dh = wave_sum(Dh);
-            A = wave_sum(A);
-            sig_sum = wave_sum(sig_sum);
-            T_S = expf(-carry);
-        }
-        for (int k = 0; k < 3; ++k) C[k] += a.bg ? T_S * ex.bg[k] : 0.0f;
-        if (lane == 0) {
-            if (a.rgb) {
-                for (int k = 0; k < 3; ++k) a.rgb[3 * r + k] = C[k];
-                a.depth[r] = Dh;
-                a.opacity[r] = A;
-            }
-            float* st = a.ray_state + 8 * r;
-            st[0] = C[0];
-            st[1] = C[1];
-            st[2] = C[2];
-            st[3] = Dh;
-            st[4] = T_S;
-            st[5] = sig_sum;
-        }
-        if (a.tgt_rgb) {
-            const RayTargets tg = targets_of(a, ex);
-            const double n = (double)norm_rays(a, r);
-            const double e0 = (double)C[0] - tg.C[0], e1 = (double)C[1] - tg.C[1], e2 = (double)C[2] - tg.C[2];
-            const double ed = (double)Dh - tg.D;
-            if (a.loss_mode == 0) {
-                ray_loss = (e0 * e0 + e1 * e1 + e2 * e2) / (3.0 * n);
-                ray_loss += tg.obj ? (double)a.lambda_d * ed * ed / n : (double)a.lambda_sigma * sig_sum / n;
-            } else {
-                ray_loss = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
-                ray_loss += tg.obj ? (double)a.lambda_d * fabs(ed) : (double)a.lambda_sigma * sig_sum;
-            }
+    RayLane x;
+    const int lane = threadIdx.x & 63;
+    x.l = lane & (kRow - 1);
+    x.g = lane / kRow;
+    x.r = ((int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6)) * (64 / kRow) + x.g;
+    x.live = x.r < a.n_rays;
+    x.rc = x.live ? x.r : a.n_rays - 1;
+    return x;
+}
+
+__global__ __launch_bounds__(64 * kWaves) void k_composite_fwd(CompositeArgs a)
+{
+    __shared__ double block_loss[kWaves];
+    const RayLane rl = ray_lane(a);
+    const int S = a.S;
+    const int64_t r = rl.rc;
+    // every input of the ray is requested before the first wait
+    const uint8_t flags = a.flags[r];
+    const Slots first = load_slots(a, r, 0, rl.l);
+    const RayExtras ex = load_extras(a, r);
+
+    float C[3] = {0.0f, 0.0f, 0.0f}, Dh = 0.0f, A = 0.0f, sig_sum = 0.0f, carry = 0.0f;
+    for (int c0 = 0; c0 < S; c0 += kChunk) {
+        const Slots x = c0 == 0 ? first : load_slots(a, r, c0, rl.l);
+#pragma unroll
+        for (int m = 0; m < kSlots; ++m) {
+            const float4 v = x.v[m];
+            const float tau = x.valid[m] ? v.x * x.dt[m] : 0.0f;  // w = 0 past the end
+            const float excl = row_excl_prefix(tau) + carry;
+            const float w = expf(-excl) * (-expm1f(-tau));
+            C[0] += w * v.y;
+            C[1] += w * v.z;
+            C[2] += w * v.w;
+            Dh += w * x.t[m];
+            A += w;
+            sig_sum += x.valid[m] ? v.x : 0.0f;
+            carry += row_sum(tau);
         }
     }
-    if (a.ray_loss && lane == 0 && r < a.n_rays) a.ray_loss[r] = ray_loss;
+    const bool miss = flags & PRENOM_FLAG_MISS;
+    for (int k = 0; k < 3; ++k) C[k] = miss ? 0.0f : row_sum(C[k]);
+    Dh = miss ? 0.0f : row_sum(Dh);
+    A = miss ? 0.0f : row_sum(A);
+    sig_sum = miss ? 0.0f : row_sum(sig_sum);
+    const float T_S = miss ? 1.0f : expf(-carry);
+    for (int k = 0; k < 3; ++k) C[k] += a.bg ? T_S * ex.bg[k] : 0.0f;
+    if (rl.l == 0 && rl.live) {
+        if (a.rgb) {
+            for (int k = 0; k < 3; ++k) a.rgb[3 * r + k] = C[k];
+            a.depth[r] = Dh;
+            a.opacity[r] = A;
+        }
+        float* st = a.ray_state + 8 * r;
+        st[0] = C[0];
+        st[1] = C[1];
+        st[2] = C[2];
+        st[3] = Dh;
+        st[4] = T_S;
+        st[5] = sig_sum;
+    }
+    double ray_loss = 0.0;
+    if (a.tgt_rgb && rl.live) {
+        const RayTargets tg = targets_of(a, ex);
+        const double n = (double)norm_rays(a, r);
+        const double e0 = (double)C[0] - tg.C[0], e1 = (double)C[1] - tg.C[1], e2 = (double)C[2] - tg.C[2];
+        const double ed = (double)Dh - tg.D;
+        if (a.loss_mode == 0) {
+            ray_loss = (e0 * e0 + e1 * e1 + e2 * e2) / (3.0 * n);
+            ray_loss += tg.obj ? (double)a.lambda_d * ed * ed / n : (double)a.lambda_sigma * sig_sum / n;
+        } else {
+            ray_loss = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+            ray_loss += tg.obj ? (double)a.lambda_d * fabs(ed) : (double)a.lambda_sigma * sig_sum;
+        }
+    }
+    if (a.ray_loss && rl.l == 0 && rl.live) a.ray_loss[r] = ray_loss;
     if (a.loss_partial) {
-        if (lane == 0) block_loss[wave] = ray_loss;
+        // the wave's rays in row order, then the waves in order
+        double wl = 0.0;
+#pragma unroll
+        for (int g = 0; g < 64 / kRow; ++g) {
+            const double v = __shfl(ray_loss, g * kRow);
+            wl += v;
+        }
+        if ((threadIdx.x & 63) == 0) block_loss[threadIdx.x >> 6] = wl;
         __syncthreads();
         if (threadIdx.x == 0) {
             double s = 0.0;
-            for (int w = 0; w < kRaysPerBlock; ++w) s += block_loss[w];
+            for (int w = 0; w < kWaves; ++w) s += block_loss[w];
             a.loss_partial[blockIdx.x] = s;
         }
     }
@@ -268,16 +285,14 @@ __global__ __launch_bounds__(256) void k_loss_objects(const ObjDev* __restrict__
     if (threadIdx.x == 0) loss[blockIdx.x] = (float)((red[0] + red[1]) + (red[2] + red[3]));
 }
 
-__global__ __launch_bounds__(64 * kRaysPerBlock) void k_composite_bwd(CompositeArgs a)
+__global__ __launch_bounds__(64 * kWaves) void k_composite_bwd(CompositeArgs a)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t r = (int64_t)blockIdx.x * kRaysPerBlock + wave;
-    if (r >= a.n_rays) return;
+    const RayLane rl = ray_lane(a);
     const int S = a.S;
-    float4* dout = reinterpret_cast<float4*>(a.dout) + r * S;
+    const int64_t r = rl.rc;
     // every input of the ray is requested before the first wait
     const uint8_t flags = a.flags[r];
-    const SampleIn first = load_sample(a, r, S, lane);
+    const Slots first = load_slots(a, r, 0, rl.l);
     const float* st = a.ray_state + 8 * r;
     const float Ch[3] = {st[0], st[1], st[2]};
     const float Dh = st[3], T_S = st[4];
@@ -288,10 +303,7 @@ __global__ __launch_bounds__(64 * kRaysPerBlock) void k_composite_bwd(CompositeA
         gdin = a.d_depth ? a.d_depth[r] : 0.0f;
         gain = a.d_opacity ? a.d_opacity[r] : 0.0f;
     }
-    if (flags & PRENOM_FLAG_MISS) {
-        for (int jj = lane; jj < S; jj += 64) dout[jj] = make_float4(0, 0, 0, 0);
-        return;
-    }
+    const bool miss = flags & PRENOM_FLAG_MISS;
 
     // upstream gradients of this ray: dL/dC, dL/dD and the per-sample density term
     float gC[3], gD = 0.0f, gA = 0.0f, extra = 0.0f;
@@ -331,52 +343,63 @@ __global__ __launch_bounds__(64 * kRaysPerBlock) void k_composite_bwd(CompositeA
     float bg_term = 0.0f;
     if (a.bg) bg_term = T_S * (gC[0] * ex.bg[0] + gC[1] * ex.bg[1] + gC[2] * ex.bg[2]);
 
-    // optical depth carried into each chunk (zero into the first, so a ray of
-    // at most 64 samples needs no pass for it)
-    const int n_chunks = (S + 63) / 64;
+    // optical depth carried into each chunk (zero into the first)
+    const int n_chunks = (S + kChunk - 1) / kChunk;
     float carry_in[kMaxChunks];
     carry_in[0] = 0.0f;
     if (n_chunks > 1) {
-        float c = wave_sum(first.valid ? first.v.x * first.dt : 0.0f);
+        float c = 0.0f;
+#pragma unroll
+        for (int m = 0; m < kSlots; ++m) c += row_sum(first.valid[m] ? first.v[m].x * first.dt[m] : 0.0f);
         for (int ch = 1; ch < n_chunks; ++ch) {
             carry_in[ch] = c;
-            const int jj = ch * 64 + lane;
-            const int64_t sidx = r * S + jj;
-            const float tau = jj < S ? a.sc[4 * sidx] * a.dt[sidx] : 0.0f;
-            c += wave_sum(tau);
+            const Slots x = load_slots(a, r, ch * kChunk, rl.l);
+#pragma unroll
+            for (int m = 0; m < kSlots; ++m) c += row_sum(x.valid[m] ? x.v[m].x * x.dt[m] : 0.0f);
         }
     }
+    float4* dout = reinterpret_cast<float4*>(a.dout) + r * S;
     float suffix_carry = 0.0f;
     for (int ch = n_chunks - 1; ch >= 0; --ch) {
-        const int jj = ch * 64 + lane;
-        const bool valid = jj < S;
-        const SampleIn x = ch == 0 ? first : load_sample(a, r, S, jj);
-        const float4 v = x.v;
-        const float dtj = x.dt;
-        const float tj = x.t;
-        const float tau = valid ? v.x * dtj : 0.0f;
-        const float excl = wave_excl_prefix(tau, lane) + carry_in[ch];
-        const float Tj = expf(-excl);
-        const float Tj1 = expf(-(excl + tau));
-        const float w = Tj * (-expm1f(-tau));
-        const float aj = gC[0] * v.y + gC[1] * v.z + gC[2] * v.w + gD * tj + gA;
-        const float wa = valid ? w * aj : 0.0f;
-        const float suffix = wave_excl_suffix(wa, lane) + suffix_carry;
-        const float dsig = dtj * (Tj1 * aj - suffix - bg_term) + extra;
-        if (valid) dout[jj] = make_float4(dsig, w * gC[0], w * gC[1], w * gC[2]);
-        suffix_carry += wave_sum(wa);
+        const int c0 = ch * kChunk;
+        const Slots x = ch == 0 ? first : load_slots(a, r, c0, rl.l);
+        // forward quantities of the chunk's slots, in ray order
+        float tau[kSlots], excl[kSlots], w[kSlots], aj[kSlots], wa[kSlots];
+        float carry = carry_in[ch];
+#pragma unroll
+        for (int m = 0; m < kSlots; ++m) {
+            const float4 v = x.v[m];
+            tau[m] = x.valid[m] ? v.x * x.dt[m] : 0.0f;
+            excl[m] = row_excl_prefix(tau[m]) + carry;
+            carry += row_sum(tau[m]);
+            w[m] = expf(-excl[m]) * (-expm1f(-tau[m]));
+            aj[m] = gC[0] * v.y + gC[1] * v.z + gC[2] * v.w + gD * x.t[m] + gA;
+            wa[m] = x.valid[m] ? w[m] * aj[m] : 0.0f;
+        }
+        // adjoint: suffix sums of w a, last slot first
+#pragma unroll
+        for (int m = kSlots - 1; m >= 0; --m) {
+            const float suffix = row_excl_suffix(wa[m]) + suffix_carry;
+            suffix_carry += row_sum(wa[m]);
+            const float Tj1 = expf(-(excl[m] + tau[m]));
+            const float dsig = x.dt[m] * (Tj1 * aj[m] - suffix - bg_term) + extra;
+            const int j = c0 + rl.l + kRow * m;
+            if (rl.live && j < S)
+                dout[j] = miss ? make_float4(0.0f, 0.0f, 0.0f, 0.0f)
+                               : make_float4(dsig, w[m] * gC[0], w[m] * gC[1], w[m] * gC[2]);
+        }
     }
 }
 
 }  // namespace
 
+// Forward blocks (one loss partial each): kWaves waves of 64 / kRow rays.
 int composite_loss_blocks(int64_t n_rays) { return (int)((n_rays + kRaysPerBlock - 1) / kRaysPerBlock); }
 
 hipError_t launch_composite_fwd(const CompositeArgs& a, hipStream_t s)
 {
     if (a.n_rays == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_composite_fwd, dim3((uint32_t)composite_loss_blocks(a.n_rays)), dim3(64 * kRaysPerBlock), 0,
-                       s, a);
+    hipLaunchKernelGGL(k_composite_fwd, dim3((uint32_t)composite_loss_blocks(a.n_rays)), dim3(64 * kWaves), 0, s, a);
     return hipGetLastError();
 }
 
@@ -396,8 +419,7 @@ hipError_t launch_loss_objects(const ObjDev* objs, int n_obj, const double* ray_
 hipError_t launch_composite_bwd(const CompositeArgs& a, hipStream_t s)
 {
     if (a.n_rays == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_composite_bwd, dim3((uint32_t)composite_loss_blocks(a.n_rays)), dim3(64 * kRaysPerBlock), 0,
-                       s, a);
+    hipLaunchKernelGGL(k_composite_bwd, dim3((uint32_t)composite_loss_blocks(a.n_rays)), dim3(64 * kWaves), 0, s, a);
     return hipGetLastError();
 }
 

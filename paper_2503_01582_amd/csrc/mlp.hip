@@ -433,14 +433,37 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_bwd_batch(const MlpWork*
                             wk.tile_end, kBwdWaves);
 }
 
-__global__ void k_reduce_partials(const float* __restrict__ partial, int n_slots, int64_t n_mlp,
-                                  float* __restrict__ g)
+// Sum of the per-block partial weight gradients.  A block takes kRedParams
+// consecutive parameters (lane = parameter, coalesced) and kRedGroups waves;
+// wave w sums slots w, w + kRedGroups, ... in FP64, then the group sums are
+// added in wave order (a fixed order: the result does not depend on timing).
+constexpr int kRedParams = 64, kRedGroups = 16;
+
+__device__ __forceinline__ void reduce_slots(const float* __restrict__ src, int64_t n_slots, int64_t stride,
+                                             bool active, float* __restrict__ dst, double (*part)[kRedParams])
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n_mlp) return;
+    const int i = threadIdx.x % kRedParams, grp = threadIdx.x / kRedParams;
     double acc = 0.0;
-    for (int sl = 0; sl < n_slots; ++sl) acc += (double)partial[(int64_t)sl * n_mlp + p];
-    g[p] += (float)acc;
+    if (active)
+        for (int64_t sl = grp; sl < n_slots; sl += kRedGroups) acc += (double)src[sl * stride];
+    part[grp][i] = acc;
+    __syncthreads();
+    if (grp == 0 && active) {
+        double sum = 0.0;
+        for (int k = 0; k < kRedGroups; ++k) sum += part[k][i];
+        *dst += (float)sum;
+    }
+}
+
+__global__ __launch_bounds__(kRedParams * kRedGroups) void k_reduce_partials(const float* __restrict__ partial,
+                                                                              int n_slots, int64_t n_mlp,
+                                                                              float* __restrict__ g)
+{
+    __shared__ double part[kRedGroups][kRedParams];
+    const int64_t p = (int64_t)blockIdx.x * kRedParams + threadIdx.x % kRedParams;
+    const bool active = p < n_mlp;
+    const int64_t pc = active ? p : 0;
+    reduce_slots(partial + pc, n_slots, n_mlp, active, g + pc, part);
 }
 
 // ---------------------------------------------------------------- 128 wide
@@ -677,25 +700,28 @@ __global__ __launch_bounds__(64 * kWideWaves) void k_mlp_dw_batch(const MlpWork*
 }
 
 // Batch: thread per (object, MLP parameter); the object's partials summed in FP64.
-__global__ void k_reduce_partials_batch(const MlpRed* __restrict__ reds, int n_obj, int64_t n_total,
-                                        const float* __restrict__ partial, float* __restrict__ g)
+// Batched: parameter i of the batch's MLP gradients belongs to the last
+// object with mlp_begin <= i.
+__global__ __launch_bounds__(kRedParams * kRedGroups) void k_reduce_partials_batch(const MlpRed* __restrict__ reds,
+                                                                                    int n_obj, int64_t n_total,
+                                                                                    const float* __restrict__ partial,
+                                                                                    float* __restrict__ g)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_total) return;
+    __shared__ double part[kRedGroups][kRedParams];
+    const int64_t i = (int64_t)blockIdx.x * kRedParams + threadIdx.x % kRedParams;
+    const bool active = i < n_total;
+    const int64_t ic = active ? i : 0;
     int lo = 0, hi = n_obj - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (reds[mid].mlp_begin <= i)
+        if (reds[mid].mlp_begin <= ic)
             lo = mid;
         else
             hi = mid - 1;
     }
     const MlpRed& r = reds[lo];
-    const int64_t p = i - r.mlp_begin;
-    const float* src = partial + r.partial_off + p;
-    double acc = 0.0;
-    for (int64_t sl = 0; sl < r.n_slots; ++sl) acc += (double)src[sl * r.n_mlp];
-    g[r.g_off + p] += (float)acc;
+    const int64_t p = ic - r.mlp_begin;
+    reduce_slots(partial + r.partial_off + p, r.n_slots, r.n_mlp, active, g + r.g_off + p, part);
 }
 
 template <class K>
@@ -891,16 +917,16 @@ hipError_t launch_reduce_partials_batch(const MlpRed* reds, int n_obj, int64_t n
                                         float* grads, hipStream_t s)
 {
     if (n_mlp_total == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce_partials_batch, dim3((uint32_t)((n_mlp_total + 255) / 256)), dim3(256), 0, s, reds,
-                       n_obj, n_mlp_total, partial, grads);
+    hipLaunchKernelGGL(k_reduce_partials_batch, dim3((uint32_t)((n_mlp_total + kRedParams - 1) / kRedParams)),
+                       dim3(kRedParams * kRedGroups), 0, s, reds, n_obj, n_mlp_total, partial, grads);
     return hipGetLastError();
 }
 
 hipError_t launch_reduce_partials(const float* partial, int n_slots, int64_t n_mlp, float* g_mlp, hipStream_t s)
 {
     if (n_slots == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce_partials, dim3((uint32_t)((n_mlp + 255) / 256)), dim3(256), 0, s, partial, n_slots,
-                       n_mlp, g_mlp);
+    hipLaunchKernelGGL(k_reduce_partials, dim3((uint32_t)((n_mlp + kRedParams - 1) / kRedParams)),
+                       dim3(kRedParams * kRedGroups), 0, s, partial, n_slots, n_mlp, g_mlp);
     return hipGetLastError();
 }
 

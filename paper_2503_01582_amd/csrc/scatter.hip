@@ -221,34 +221,50 @@ __global__ __launch_bounds__(256) void k_scatter_level_max(ScatterArgs a)
     if (threadIdx.x == 0) a.level_max[pair] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v, int lane)
+{
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint64_t up = __shfl_up(v, d);
+        if (lane >= d) v += up;
+    }
+    return v;
+}
+
 // Per tile: exclusive prefix of the per-block counts (in place) and the total.
+// Thread t owns a contiguous run of blocks; the runs' sums are scanned within
+// each wave, then across the block's waves.
 template <bool kMany>
 __global__ __launch_bounds__(kScanThreads) void k_scatter_scan_blocks(ScatterArgs a)
 {
-    __shared__ uint64_t part[kScanThreads];
+    constexpr int kWaves = kScanThreads / 64;
+    __shared__ uint64_t wave_tot[kWaves];
     const int64_t tile = blockIdx.x;
     const ScatterObj& o = sobj<kMany>(a, obj_of_tile<kMany>(a, tile));
     const int nb = o.n_blocks;
     uint32_t* row = a.counts + o.count_off + (tile - o.tile_off) * nb;
     const int per = (nb + kScanThreads - 1) / kScanThreads;
-    const int b0 = threadIdx.x * per, b1 = min(b0 + per, nb);
+    const int b0 = min((int)threadIdx.x * per, nb), b1 = min(b0 + per, nb);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint64_t sum = 0;
     for (int b = b0; b < b1; ++b) sum += row[b];
-    part[threadIdx.x] = sum;
+    const uint64_t incl = wave_incl_scan(sum, lane);
+    if (lane == 63) wave_tot[wave] = incl;
     __syncthreads();
-    for (int d = 1; d < kScanThreads; d <<= 1) {  // inclusive Hillis-Steele scan
-        const uint64_t v = threadIdx.x >= d ? part[threadIdx.x - d] : 0;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
+    if (wave == 0) {
+        const uint64_t t = lane < kWaves ? wave_tot[lane] : 0;
+        const uint64_t ti = wave_incl_scan(t, lane);
+        if (lane < kWaves) wave_tot[lane] = ti - t;  // exclusive over waves
+        if (lane == kWaves - 1) a.tile_total[tile] = ti;
     }
-    uint64_t run = part[threadIdx.x] - sum;
+    __syncthreads();
+    uint64_t run = wave_tot[wave] + incl - sum;
     for (int b = b0; b < b1; ++b) {
         const uint32_t c = row[b];
         row[b] = (uint32_t)run;  // offsets within a tile fit 32 bits
         run += c;
     }
-    if (threadIdx.x == kScanThreads - 1) a.tile_total[tile] = part[kScanThreads - 1];
 }
 
 // Over all tiles: record bases, chunk counts and chunk bases, the fixed-point
