@@ -55,7 +55,7 @@ struct Net {
 
 // Builds weight fragments f0 .. f0 + n_frag - 1 of one block in LDS (at 0).
 template <int IN, int W, int D>
-__device__ void load_fragments(const float* __restrict__ w, float* __restrict__ frag, int n_frag, int f0 = 0)
+__device__ __forceinline__ void load_fragments(const float* __restrict__ w, float* __restrict__ frag, int n_frag, int f0 = 0)
 {
     using N = Net<IN, W, D>;
     for (int idx = threadIdx.x; idx < n_frag * 64; idx += blockDim.x) {
@@ -265,7 +265,7 @@ __device__ __forceinline__ void accumulate_dw(const float* __restrict__ sD, cons
 // whose fragments are in LDS (lds[0 .. N_ALL*64)); writes dy and the block's
 // merged dW to dst.  Called by every thread of the block.
 template <int IN, int W, int D>
-__device__ void mlp_bwd_tiles(float* __restrict__ lds, const float* __restrict__ y, const float4* __restrict__ dout,
+__device__ __forceinline__ void mlp_bwd_tiles(float* __restrict__ lds, const float* __restrict__ y, const float4* __restrict__ dout,
                               int64_t n_s, float2* __restrict__ dy, float* __restrict__ dst, int64_t tile0,
                               int64_t end, int64_t step)
 {
@@ -479,7 +479,7 @@ __global__ __launch_bounds__(kRedParams * kRedGroups) void k_reduce_partials(con
 constexpr int kWideWaves = 4;
 
 template <int IN, int W, int D>
-__device__ void mlp_chain_bwd_tiles(const float* __restrict__ bfrag, const float4* __restrict__ sc,
+__device__ __forceinline__ void mlp_chain_bwd_tiles(const float* __restrict__ bfrag, const float4* __restrict__ sc,
                                     const float4* __restrict__ dout, const float* __restrict__ act,
                                     float* __restrict__ dlt, int64_t n_s, float2* __restrict__ dy, int64_t tile0,
                                     int64_t end, int64_t step)
@@ -549,7 +549,7 @@ constexpr int kDwPitchF32 = kWideWidth + 16;  // 144 = 16 mod 64: lanes q one sa
 constexpr int kDwPitchY = 48;
 
 template <int IN, int W, int D>
-__device__ void mlp_dw_range(float* __restrict__ lds, const float* __restrict__ y, const float4* __restrict__ sc,
+__device__ __forceinline__ void mlp_dw_range(float* __restrict__ lds, const float* __restrict__ y, const float4* __restrict__ sc,
                              const float4* __restrict__ dout, const float* __restrict__ act,
                              const float* __restrict__ dlt, int64_t n_s, int64_t s_begin, int64_t s_end,
                              float* __restrict__ dst)

@@ -90,7 +90,7 @@ struct NetLp {
 
 // Weight fragments: fragment f, lane l holds 4 consecutive K values.
 template <int IN, int W, int D, class P>
-__device__ void load_fragments_lp(const float* __restrict__ w, typename P::vec* __restrict__ frag, int n_frag, int f0 = 0)
+__device__ __forceinline__ void load_fragments_lp(const float* __restrict__ w, typename P::vec* __restrict__ frag, int n_frag, int f0 = 0)
 {
     using N = NetLp<IN, W, D>;
     for (int idx = threadIdx.x; idx < n_frag * 64; idx += blockDim.x) {
@@ -299,7 +299,7 @@ __device__ __forceinline__ void accumulate_dw_lp(const float* __restrict__ sD, c
 // Backward over tiles tile0, tile0 + step, ... < end of one object whose
 // fragments are at the start of smem_lp; called by every thread of the block.
 template <int IN, int W, int D, class P>
-__device__ void mlp_bwd_tiles_lp(unsigned char* __restrict__ smem_lp, const float2* __restrict__ y,
+__device__ __forceinline__ void mlp_bwd_tiles_lp(unsigned char* __restrict__ smem_lp, const float2* __restrict__ y,
                                  const float4* __restrict__ dout, int64_t n_s, float2* __restrict__ dy,
                                  float* __restrict__ dst, int64_t tile0, int64_t end, int64_t step)
 {
@@ -459,7 +459,7 @@ constexpr int kWideWavesLp = 4;
 
 // act16 / dlt16: [D][n_s][W] 16-bit values, indexed in groups of 4 (P::vec).
 template <int IN, int W, int D, class P>
-__device__ void mlp_chain_bwd_tiles_lp(const typename P::vec* __restrict__ bfrag, const float4* __restrict__ sc,
+__device__ __forceinline__ void mlp_chain_bwd_tiles_lp(const typename P::vec* __restrict__ bfrag, const float4* __restrict__ sc,
                                        const float4* __restrict__ dout, const typename P::vec* __restrict__ act16,
                                        typename P::vec* __restrict__ dlt16, int64_t n_s, float2* __restrict__ dy,
                                        int64_t tile0, int64_t end, int64_t step)
@@ -523,45 +523,122 @@ __device__ void mlp_chain_bwd_tiles_lp(const typename P::vec* __restrict__ bfrag
 // Weight gradient over samples [s_begin, s_end), staged kDwChunk samples at
 // a time in LDS: MFMA K = 16 consecutive samples (lane q holds samples
 // 4q .. 4q + 3 of the group of 16), operands rounded to the MFMA type.
-constexpr int kDwPitchLp = kWideWidth + 4;  // 132: 4 x pitch = 16 mod 64, lanes q four samples apart
-constexpr int kDwPitchYLp = 36;             // 4 x 36 = 16 mod 64
+// The chunk of samples is staged in 16-bit form, neuron-major: row n of a
+// staged array holds neuron (or feature) n of the chunk's kDwChunk samples,
+// so the 4 consecutive samples an MFMA operand needs in a lane are one 8-byte
+// LDS read.  Rows are padded to kDwRowLp halfwords (80 bytes) to spread the 16
+// rows a wave reads over the banks.  Layout, in halfwords:
+//   DL [D][W][row]  deltas      AC [D][W][row]  activations
+//   Y  [32][row]    inputs (rows >= IN zero)
+//   DO [16][row]    head adjoint (rows >= 4 zero, written once)
+constexpr int kDwRowLp = kDwChunk + 8;
 
-// Every layer's activation and delta rows of the chunk from the 16-bit
-// buffers (already rounded), widened into the FP32 staging arrays.
-template <int IN, int W, int D, int PW, int PY, class P>
-__device__ __forceinline__ void dw_stage_lp(float* __restrict__ lds, const float* __restrict__ y,
+template <int W, int D>
+struct DwStageLp {
+    static constexpr int DL = 0;
+    static constexpr int AC = DL + D * W * kDwRowLp;
+    static constexpr int Y = AC + D * W * kDwRowLp;
+    static constexpr int DO = Y + 32 * kDwRowLp;
+    static constexpr int HALVES = DO + 16 * kDwRowLp;
+};
+
+// 4 x 4 transpose of 16-bit values: in[r] holds columns 0..3 of row r (two
+// per 32-bit word); out[c] holds rows 0..3 of column c.
+__device__ __forceinline__ void transpose4x4_16(const uint2 (&in)[4], uint2 (&out)[4])
+{
+    out[0] = make_uint2((in[0].x & 0xffffu) | (in[1].x << 16), (in[2].x & 0xffffu) | (in[3].x << 16));
+    out[1] = make_uint2((in[0].x >> 16) | (in[1].x & 0xffff0000u), (in[2].x >> 16) | (in[3].x & 0xffff0000u));
+    out[2] = make_uint2((in[0].y & 0xffffu) | (in[1].y << 16), (in[2].y & 0xffffu) | (in[3].y << 16));
+    out[3] = make_uint2((in[0].y >> 16) | (in[1].y & 0xffff0000u), (in[2].y >> 16) | (in[3].y & 0xffff0000u));
+}
+
+template <class P>
+__device__ __forceinline__ uint2 bits(typename P::vec v)
+{
+    return __builtin_bit_cast(uint2, v);
+}
+
+// Stage samples [s0, min(s0 + kDwChunk, s_end)) (zeros past the end).
+// act16 / dlt16: [D][n_s][W] 16-bit rows; y: level-major [L][n_s][2].
+template <int IN, int W, int D, class P>
+__device__ __forceinline__ void dw_stage_lp(uint16_t* __restrict__ lds, const float* __restrict__ y,
                                             const float4* __restrict__ sc, const float4* __restrict__ dout,
                                             const typename P::vec* __restrict__ act16,
                                             const typename P::vec* __restrict__ dlt16, int64_t n_s, int64_t s0,
                                             int64_t s_end)
 {
-    using St = DwStage<W, D, PW, PY>;
-    constexpr int V = W / 4;
-    for (int i = threadIdx.x; i < D * kDwChunk * V; i += blockDim.x) {
-        const int k = i / (kDwChunk * V), rem = i % (kDwChunk * V), r = rem / V, c = rem % V;
-        const int64_t s = s0 + r;
-        floatx4 a = {0.0f, 0.0f, 0.0f, 0.0f}, d = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (s < s_end) {
-            a = unpack<P>(act16[((int64_t)k * n_s + s) * V + c]);
-            d = unpack<P>(dlt16[((int64_t)k * n_s + s) * V + c]);
+    using St = DwStageLp<W, D>;
+    constexpr int V = W / 4;                 // 4-neuron groups per row
+    constexpr int SG = kDwChunk / 4;         // 4-sample groups per chunk
+    // activations and deltas: one 4 x 4 block (4 samples x 4 neurons) per item
+    for (int i = threadIdx.x; i < 2 * D * SG * V; i += blockDim.x) {
+        const int arr = i / (D * SG * V), rem = i % (D * SG * V);
+        const int k = rem / (SG * V), r2 = rem % (SG * V), sg = r2 / V, c = r2 % V;
+        const typename P::vec* src = arr == 0 ? dlt16 : act16;
+        uint2 in[4], out[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t s = s0 + 4 * sg + r;
+            in[r] = s < s_end ? bits<P>(src[((int64_t)k * n_s + s) * V + c]) : make_uint2(0u, 0u);
         }
-        *reinterpret_cast<floatx4*>(lds + St::AC + (k * kDwChunk + r) * PW + 4 * c) = a;
-        *reinterpret_cast<floatx4*>(lds + St::DL + (k * kDwChunk + r) * PW + 4 * c) = d;
+        transpose4x4_16(in, out);
+        uint16_t* base = lds + (arr == 0 ? St::DL : St::AC) + (k * W + 4 * c) * kDwRowLp + 4 * sg;
+#pragma unroll
+        for (int n = 0; n < 4; ++n) *reinterpret_cast<uint2*>(base + n * kDwRowLp) = out[n];
     }
-    dw_stage_inputs<IN, W, D, PW, PY>(lds, y, sc, dout, n_s, s0, s_end);
+    // inputs: features 2l, 2l + 1 of 4 samples per item (rounded to P)
+    for (int i = threadIdx.x; i < 16 * SG; i += blockDim.x) {
+        const int l = i / SG, sg = i % SG;
+        float f0[4], f1[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t s = s0 + 4 * sg + r;
+            float2 v = make_float2(0.0f, 0.0f);
+            if (s < s_end && 2 * l < IN) v = reinterpret_cast<const float2*>(y)[(int64_t)l * n_s + s];
+            f0[r] = v.x;
+            f1[r] = v.y;
+        }
+        uint16_t* base = lds + St::Y + (2 * l) * kDwRowLp + 4 * sg;
+        *reinterpret_cast<uint2*>(base) = bits<P>(pack<P>(f0[0], f0[1], f0[2], f0[3]));
+        *reinterpret_cast<uint2*>(base + kDwRowLp) = bits<P>(pack<P>(f1[0], f1[1], f1[2], f1[3]));
+    }
+    // head adjoint (d sigma / d o0 = sigma, d c / d o = c (1 - c)) of 4 samples per item
+    for (int sg = threadIdx.x; sg < SG; sg += blockDim.x) {
+        float o[4][4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t s = s0 + 4 * sg + r;
+            float4 g = make_float4(0.0f, 0.0f, 0.0f, 0.0f), v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (s < s_end) {
+                g = dout[s];
+                v = sc[s];
+            }
+            o[0][r] = g.x * v.x;
+            o[1][r] = g.y * v.y * (1.0f - v.y);
+            o[2][r] = g.z * v.z * (1.0f - v.z);
+            o[3][r] = g.w * v.w * (1.0f - v.w);
+        }
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+            *reinterpret_cast<uint2*>(lds + St::DO + n * kDwRowLp + 4 * sg) =
+                bits<P>(pack<P>(o[n][0], o[n][1], o[n][2], o[n][3]));
+    }
 }
 
+// Weight gradient over samples [s_begin, s_end): dW = sum_s delta(s) h(s)^T
+// per layer, MFMA K = 16 consecutive samples (lane q holds samples
+// 4q .. 4q + 3 of the group of 16), operands rounded to the MFMA type, the 4
+// waves splitting the output rows.  One partial per block.
 template <int IN, int W, int D, class P>
-__device__ void mlp_dw_range_lp(float* __restrict__ lds, const float* __restrict__ y, const float4* __restrict__ sc,
+__device__ __forceinline__ void mlp_dw_range_lp(uint16_t* __restrict__ lds, const float* __restrict__ y, const float4* __restrict__ sc,
                                 const float4* __restrict__ dout, const typename P::vec* __restrict__ act16,
                                 const typename P::vec* __restrict__ dlt16, int64_t n_s, int64_t s_begin,
                                 int64_t s_end, float* __restrict__ dst)
 {
     using N = NetLp<IN, W, D>;
-    constexpr int PW = kDwPitchLp, PY = kDwPitchYLp;
-    using St = DwStage<W, D, PW, PY>;
+    using St = DwStageLp<W, D>;
     constexpr int RT = N::OT / kWideWavesLp;
-    static_assert(N::OT % kWideWavesLp == 0 && W + 4 == PW && IN <= 32, "rows per wave, pitch");
+    static_assert(N::OT % kWideWavesLp == 0 && IN <= 32 && N::IT <= 2, "rows per wave, inputs");
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, q = lane >> 4, j = lane & 15;
     floatx4 aH[D > 1 ? D - 1 : 1][RT][N::OT], a1[RT][N::IT], aO[RT];
 #pragma unroll
@@ -574,39 +651,41 @@ __device__ void mlp_dw_range_lp(float* __restrict__ lds, const float* __restrict
 #pragma unroll
             for (int t = 0; t < N::OT; ++t) aH[k][a][t] = {0.0f, 0.0f, 0.0f, 0.0f};
     }
-    // 4 consecutive samples' value of one column of a staged array
-    auto col4 = [&](int base, int pitch, int r0, int col) {
-        return pack<P>(lds[base + (r0 + 0) * pitch + col], lds[base + (r0 + 1) * pitch + col],
-                       lds[base + (r0 + 2) * pitch + col], lds[base + (r0 + 3) * pitch + col]);
+    // rows 4..15 of the head adjoint stay zero (the A operand of the head's
+    // 16-row tile); rows 0..3 are restaged with every chunk
+    for (int i = threadIdx.x; i < 12 * kDwRowLp; i += blockDim.x) lds[St::DO + 4 * kDwRowLp + i] = 0;
+    // 4 samples of staged row `row`, as an MFMA operand
+    auto op = [&](int base, int row, int k0) {
+        return __builtin_bit_cast(typename P::vec, *reinterpret_cast<const uint2*>(lds + base + row * kDwRowLp + k0));
     };
     for (int64_t c0 = s_begin; c0 < s_end; c0 += kDwChunk) {
-        dw_stage_lp<IN, W, D, PW, PY, P>(lds, y, sc, dout, act16, dlt16, n_s, c0, s_end);
+        dw_stage_lp<IN, W, D, P>(lds, y, sc, dout, act16, dlt16, n_s, c0, s_end);
         __syncthreads();
 #pragma unroll 1
-        for (int ks = 0; ks < kDwChunk / 16; ++ks) {
-            const int r0 = 16 * ks + 4 * q;
-            const typename P::vec dOp = j < 4 ? col4(St::DO, 4, r0, j) : pack<P>(0.0f, 0.0f, 0.0f, 0.0f);
+        for (int ks = 0; ks < kDwChunk / 16; ++ks) {  // not unrolled: bounds the operands in flight
+            const int k0 = 16 * ks + 4 * q;
+            const typename P::vec dOp = op(St::DO, j, k0);
 #pragma unroll
             for (int a = 0; a < RT; ++a)
-                aO[a] = P::mma(dOp, col4(St::AC + (D - 1) * kDwChunk * PW, PW, r0, 16 * (RT * wave + a) + j), aO[a]);
+                aO[a] = P::mma(dOp, op(St::AC + (D - 1) * W * kDwRowLp, 16 * (RT * wave + a) + j, k0), aO[a]);
 #pragma unroll
             for (int k = 1; k < D; ++k) {
-                typename P::vec av[RT], bv[N::OT];
+                typename P::vec av[RT];
 #pragma unroll
-                for (int a = 0; a < RT; ++a) av[a] = col4(St::DL + k * kDwChunk * PW, PW, r0, 16 * (RT * wave + a) + j);
+                for (int a = 0; a < RT; ++a) av[a] = op(St::DL + k * W * kDwRowLp, 16 * (RT * wave + a) + j, k0);
 #pragma unroll
                 for (int t = 0; t < N::OT; ++t) {
-                    bv[t] = col4(St::AC + (k - 1) * kDwChunk * PW, PW, r0, 16 * t + j);
+                    const typename P::vec bv = op(St::AC + (k - 1) * W * kDwRowLp, 16 * t + j, k0);
 #pragma unroll
-                    for (int a = 0; a < RT; ++a) aH[k - 1][a][t] = P::mma(av[a], bv[t], aH[k - 1][a][t]);
+                    for (int a = 0; a < RT; ++a) aH[k - 1][a][t] = P::mma(av[a], bv, aH[k - 1][a][t]);
                 }
             }
             {
                 typename P::vec av[RT], bv[N::IT];
 #pragma unroll
-                for (int a = 0; a < RT; ++a) av[a] = col4(St::DL, PW, r0, 16 * (RT * wave + a) + j);
+                for (int a = 0; a < RT; ++a) av[a] = op(St::DL, 16 * (RT * wave + a) + j, k0);
 #pragma unroll
-                for (int t = 0; t < N::IT; ++t) bv[t] = col4(St::Y, PY, r0, 16 * t + j);
+                for (int t = 0; t < N::IT; ++t) bv[t] = op(St::Y, 16 * t + j, k0);
 #pragma unroll
                 for (int a = 0; a < RT; ++a)
 #pragma unroll
@@ -636,7 +715,7 @@ __device__ void mlp_dw_range_lp(float* __restrict__ lds, const float* __restrict
 template <int IN, int W, int D>
 constexpr size_t dw_lds_bytes_lp()
 {
-    return sizeof(float) * (size_t)DwStage<W, D, kDwPitchLp, kDwPitchYLp>::FLOATS;
+    return sizeof(uint16_t) * (size_t)DwStageLp<W, D>::HALVES;
 }
 
 template <int IN, int W, int D, class P>
@@ -682,7 +761,7 @@ __global__ __launch_bounds__(64 * kWideWavesLp) void k_mlp_dw_lp(const float* __
                                                                  int64_t tiles_per_block, float* __restrict__ partial)
 {
     using N = NetLp<IN, W, D>;
-    extern __shared__ float dw_lds[];
+    extern __shared__ __align__(16) uint16_t dw_lds[];
     const int64_t b = (int64_t)blockIdx.x * tiles_per_block * 16;
     const int64_t e = min(b + tiles_per_block * 16, n_s);
     const typename P::vec* a16 = reinterpret_cast<const typename P::vec*>(act);
@@ -698,7 +777,7 @@ __global__ __launch_bounds__(64 * kWideWavesLp) void k_mlp_dw_lp_batch(const Mlp
                                                                        const float* __restrict__ act,
                                                                        float* __restrict__ partial, int64_t slot_stride)
 {
-    extern __shared__ float dw_lds[];
+    extern __shared__ __align__(16) uint16_t dw_lds[];
     const MlpWork wk = work[blockIdx.x];
     const int64_t b = wk.tile_begin * 16, e = min(wk.tile_end * 16, wk.n_s);
     const typename P::vec* a16 = reinterpret_cast<const typename P::vec*>(act + wk.a_off);
