@@ -8,6 +8,9 @@ Workloads (--workload):
           mean-squared colour loss, Adam.  A step is prenom_sample +
           prenom_render_fwd (fused loss) + prenom_render_bwd +
           prenom_adam_step on resident inputs.
+  autograd the differentiation configuration: the prior scene at 2^18 rays
+          x 64 samples, colour + 0.1 x depth MSE (1 cm depth noise) in torch
+          on top of PrenomRender, Adam; store vs recompute, with peak memory.
   batch24 24 objects trained together (own scene, prior, pose, log-uniform
           ray count in [1k, 64k], architecture drawn from L {8,12,16},
           T 2^14..2^19, W {32,64,128}, D {1,2}), FP32, one launch per phase,
@@ -229,6 +232,79 @@ def run_prior(args):
     return value, ms_per_step, "fp32", config, roofline, kern, cpu, {}
 
 
+def held_between_passes(tr, db):
+    """Device memory allocated by one forward through PrenomRender and still
+    held when its backward starts (one untimed step)."""
+    import torch
+    from paper_2503_01582_amd.autograd import render
+    samp = tr.sample(db)
+    torch.cuda.synchronize()
+    base = torch.cuda.memory_allocated()
+    rgb, depth, _ = render(tr.model, samp, db.bg, tr.recompute)
+    torch.cuda.synchronize()
+    held = torch.cuda.memory_allocated() - base
+    ((rgb - db.tgt_rgb) ** 2).sum().backward()
+    tr.model.params.grad = None
+    torch.cuda.synchronize()
+    return held
+
+
+def run_autograd(args):
+    """The differentiation configuration: the prior workload's scene at 2^18
+    rays x 64 samples, colour MSE plus 0.1 x depth MSE against depths with
+    1 cm Gaussian noise, written in torch on top of PrenomRender (the
+    hand-written adjoint behind torch.autograd.Function), then Adam.  Timed
+    with the features kept between forward and backward (store) and rebuilt
+    in the backward (recompute); peak device memory of each."""
+    import torch
+    from paper_2503_01582_amd import api
+    from paper_2503_01582_amd.trainer import AutogradTrainer, to_device
+    from synth.params import init_params
+    from synth.workloads import LossSpec, prior_batch, prior_world
+
+    n_rays = 1 << 18
+    log("bench: building the synthetic scene and batch")
+    world = prior_world(seed=1)
+    loss = LossSpec(lambda_d=0.1)
+    batch = prior_batch(world, n_rays, step=0, depth_noise=0.01, loss=loss)
+    arch = batch.arch
+    params = init_params(arch, 0)
+    db = to_device(batch)
+    S = batch.sample.n_samples
+    modes, kt = {}, None
+    for recompute in (False, True):
+        name = "recompute" if recompute else "store"
+        torch.cuda.empty_cache()
+        tr = AutogradTrainer(arch, params, batch.sample, loss, recompute=recompute)
+        log(f"bench: {name}: {args.warmup} warm-up steps")
+        for _ in range(args.warmup):
+            tr.step(db)
+        torch.cuda.synchronize()
+        torch.cuda.reset_peak_memory_stats()
+        log(f"bench: {name}: {args.steps} timed steps")
+        if recompute:
+            api.prenom_profile_begin()
+        ms = timed_loop(lambda: tr.step(db), args.steps)
+        if recompute:
+            kt = api.prenom_profile_end()
+        peak = torch.cuda.max_memory_allocated()
+        held = held_between_passes(tr, db)
+        modes[name] = dict(ms_per_step=round(ms / args.steps, 4),
+                           rays_per_s=round(n_rays * args.steps / (ms / 1e3), 1),
+                           peak_mib=round(peak / 2**20, 1), held_between_passes_mib=round(held / 2**20, 1))
+        log(f"bench: {name}: {ms / args.steps:.3f} ms/step, peak {peak / 2**20:.0f} MiB, "
+            f"held between forward and backward {held / 2**20:.0f} MiB")
+        del tr
+    ms_per_step = modes["recompute"]["ms_per_step"]
+    kern, roofline = kernel_table(kt, args.steps, ms_per_step,
+                                  algorithmic_work(arch, n_rays, S, batch.sample.n_fine), FP32_MFMA_PEAK_TFLOPS, log)
+    config = dict(workload="differentiable rendering step through torch.autograd (recompute)", n_rays=n_rays,
+                  samples_per_ray=S, hash_levels=arch.n_levels, log2_table=arch.log2_table, mlp_width=arch.width,
+                  mlp_hidden=arch.hidden, lambda_d=0.1, depth_noise_m=0.01,
+                  samples_per_s=round(n_rays / (ms_per_step / 1e3) * S, 1))
+    return modes["recompute"]["rays_per_s"], ms_per_step, "fp32", config, roofline, kern, None, dict(modes=modes)
+
+
 def run_batch(args, n_objects, total_rays, mlp_dtype, table_dtype, seed):
     import dataclasses
     import torch
@@ -328,7 +404,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", choices=("prior", "batch24", "batch48"), default="prior")
+    ap.add_argument("--workload", choices=("prior", "autograd", "batch24", "batch48"), default="prior")
     ap.add_argument("--mlp-dtype", choices=("bf16", "fp16"), default="bf16", help="batch48 only")
     ap.add_argument("--rays", type=int, default=65536, help="prior workload only")
     ap.add_argument("--cpu-rays", type=int, default=65536)
@@ -347,6 +423,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "prior":
         res = run_prior(args)
+    elif args.workload == "autograd":
+        res = run_autograd(args)
     elif args.workload == "batch24":
         res = run_batch(args, 24, None, "fp32", "fp32", seed=4)
     else:
