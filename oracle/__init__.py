@@ -79,6 +79,7 @@ def lib():
                                  _f64p, _f64p, _f64p, _i32p, _u8p, _f64p]
         L.orc_encode.argtypes = [C.POINTER(OrcArch), _f32p, _f32p, C.c_int64, _f64p, _i32p, _f64p]
         L.orc_mlp_fwd.argtypes = [C.POINTER(OrcArch), _f32p, _f64p, C.c_int64, _f64p]
+        L.orc_prior_refresh.argtypes = [C.POINTER(OrcArch), _f32p, C.c_int32, _f64p]
         L.orc_round16_array.argtypes = [_f64p, C.c_int64, C.c_int32, _f64p]
         L.orc_composite_fwd.argtypes = [C.c_int64, C.c_int32, _f64p, _f64p, _f64p, _f64p, _f64p,
                                         _f64p, _f64p, _f64p, _f64p, _f64p]
@@ -224,6 +225,16 @@ def mlp_fwd(arch, mlp, y, emulate=False):
     n = y.shape[0]
     out = np.empty((n, 4), np.float64)
     lib().orc_mlp_fwd(C.byref(make_arch(arch, emulate)), _p(mlp, _f32p), _p(y, _f64p), n, _p(out, _f64p))
+    return out
+
+
+def prior_refresh(arch, params, R, emulate=False):
+    """Density grid of the NeRF: sigma = exp(o_0) at the vertices
+    (i, j, k) / (R - 1), as [R, R, R] FP64 indexed [k][j][i] (x fastest), the
+    layout the sampler's prior lookup reads."""
+    params = _f32(params)
+    out = np.empty((R, R, R), np.float64)
+    lib().orc_prior_refresh(C.byref(make_arch(arch, emulate)), _p(params, _f32p), R, _p(out, _f64p))
     return out
 
 

@@ -488,6 +488,40 @@ void orc_mlp_fwd(const orc_arch* a, const float* mlp, const double* y, int64_t n
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Prior refresh.  The category prior is the NeRF's density output over a  */
+/* cubic grid of resolution R (Sec. III-A, "Normalized mesh generation"),   */
+/* and during online mapping it is recomputed from the object's current    */
+/* NeRF every m iterations (Sec. III-B, "Probabilistic Ray Sampling").      */
+/* Vertex (i, j, k) sits at x = (i, j, k) / (R - 1), the alignment of the   */
+/* prior lookup; each coordinate is rounded to FP32, the precision of the   */
+/* sample positions.  out[(k R + j) R + i] = sigma = exp(o_0).              */
+/* ------------------------------------------------------------------------ */
+void orc_prior_refresh(const orc_arch* a, const float* params, int32_t R, double* out)
+{
+    const orc_mlp_view v = orc_mlp_layers(a, params + orc_table_params(a));
+    const int in = a->n_levels * a->n_features;
+    const int maxw = (a->width > in) ? a->width : in;
+    const int64_t n = (int64_t)R * R * R;
+#pragma omp parallel
+    {
+        double* y = (double*)malloc(sizeof(double) * (size_t)in);
+        double* h = (double*)malloc(sizeof(double) * (size_t)maxw * (size_t)(v.n_layers + 1));
+#pragma omp for schedule(static)
+        for (int64_t p = 0; p < n; ++p) {
+            const int64_t idx[3] = {p % R, (p / R) % R, p / ((int64_t)R * R)};
+            float x[3];
+            for (int k = 0; k < 3; ++k) x[k] = (float)((double)idx[k] / (double)(R - 1));
+            double o[ORC_N_OUT];
+            orc_encode_point(a, params, x, y);
+            orc_mlp_point(&v, y, h, maxw, o);
+            out[p] = exp(o[0]);
+        }
+        free(y);
+        free(h);
+    }
+}
+
 static double orc_sigmoid(double z) { return 1.0 / (1.0 + exp(-z)); }
 
 /* ------------------------------------------------------------------------ */

@@ -797,3 +797,56 @@ def test_paper_constants_fixture_matches_workload_defaults():
     import inspect
     assert inspect.signature(occupancy_prior).parameters["R"].default == g["prior_grid_resolution"]["value"]
     assert g["n_coarse"]["value"] == g["n_fine"]["value"] == 32
+
+
+# --------------------------------------------------------------------------
+# P16: prior refresh (density grid of the NeRF, Sec. III-A "Normalized mesh
+# generation"; recomputed every m iterations, Sec. III-B)
+
+def refresh_params(arch, seed):
+    """Parameters with a varied density field (table entries U(-0.3, 0.3))."""
+    p = init_params(arch, seed)
+    p[:arch.n_table_params] = np.random.default_rng(seed).uniform(-0.3, 0.3, arch.n_table_params).astype(np.float32)
+    return p
+
+
+def test_p16_refresh_of_constant_density_is_constant():
+    """A model whose density is exp(s) everywhere refreshes to exp(s) at every vertex."""
+    arch = ARCH_SMALL
+    for s in (-2.0, 0.5, 3.0):
+        grid = orc.prior_refresh(arch, const_model(arch, s), 9)
+        np.testing.assert_allclose(grid, math.exp(s), rtol=1e-6)
+
+
+def test_p16_refresh_equals_rendered_density_at_each_vertex():
+    """Cross-path check: a one-sample ray placed exactly on vertex (i, j, k)
+    (o = the vertex, t = 0) renders the density that the refreshed grid holds
+    at [k][j][i] -- pins the vertex coordinates, the [z][y][x] layout and
+    the split of the parameter vector."""
+    arch = ARCH_SMALL
+    R = 6
+    p = refresh_params(arch, 3)
+    grid = orc.prior_refresh(arch, p, R)
+    idx = np.stack(np.meshgrid(np.arange(R), np.arange(R), np.arange(R), indexing="ij"), -1).reshape(-1, 3)  # (i, j, k)
+    verts = (idx.astype(np.float64) / (R - 1)).astype(np.float32)
+    n = verts.shape[0]
+    ray_obj = np.concatenate([verts, np.tile(np.array([1.0, 0.0, 0.0], np.float32), (n, 1))], 1)
+    t = np.zeros((n, 1), np.float32)
+    dt = np.full((n, 1), 0.01, np.float32)
+    out = orc.render_fwd(arch, p, ray_obj, t, dt, np.zeros(n, np.uint8), want_samples=True)
+    sigma = out["samples"][:, 0, 0]
+    np.testing.assert_allclose(grid[idx[:, 2], idx[:, 1], idx[:, 0]], sigma, rtol=1e-14)
+    assert np.ptp(sigma) > 0.1 * np.abs(sigma).max()  # a varied field, so a transposed layout would fail
+
+
+def test_p16_prior_lookup_reproduces_refreshed_grid_at_vertices():
+    """The sampler's trilinear lookup (Eq. (4)) of a refreshed grid at its own
+    vertices returns the stored values: refresh and lookup share one vertex
+    alignment and one memory layout."""
+    arch = ARCH_SMALL
+    R = 7
+    grid = orc.prior_refresh(arch, refresh_params(arch, 5), R)
+    k, j, i = np.meshgrid(np.arange(R), np.arange(R), np.arange(R), indexing="ij")
+    pts = np.stack([i, j, k], -1).reshape(-1, 3).astype(np.float64) / (R - 1)
+    looked = orc.prior_lookup(grid.astype(np.float32), pts)
+    np.testing.assert_allclose(looked, grid.astype(np.float32).reshape(-1).astype(np.float64), rtol=1e-12)
