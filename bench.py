@@ -7,7 +7,9 @@ Workloads (--workload):
           hash grid 16 levels x 2^19 x 2 features, MLP 64 x 2 hidden, FP32,
           mean-squared colour loss, Adam.  A step is prenom_sample +
           prenom_render_fwd (fused loss) + prenom_render_bwd +
-          prenom_adam_step on resident inputs.
+          prenom_adam_step on resident inputs.  Also timed, outside the
+          step: the prior refresh over the 64^3 grid, which runs once every
+          50 steps.
   autograd the differentiation configuration: the prior scene at 2^18 rays
           x 64 samples, colour + 0.1 x depth MSE (1 cm depth noise) in torch
           on top of PrenomRender, Adam; store vs recompute, with peak memory.
@@ -68,6 +70,19 @@ def algorithmic_work(arch, n_rays, S, n_fine):
         SCATTER_GROUP: ("hbm", n_s * (pos + L * (8 * 8 + 8))),
         "k_adam": ("hbm", arch.n_params * (32 + (2 if getattr(arch, "table_dtype", "fp32") == "fp16" else 0))),
     }
+
+
+def refresh_work(arch, n):
+    """Algorithmic work of one prior refresh over n grid vertices: every
+    level's 8 corner rows and its 2 features written (the vertex comes from
+    the thread index, nothing else is read), the MLP forward, and the
+    density column (a 16-byte head row read, 4 bytes written)."""
+    L = arch.n_levels
+    in_dim, W, D = arch.in_dim, arch.width, arch.hidden
+    macs = W * in_dim + (D - 1) * W * W + 4 * W
+    return {"k_encode_grid": ("hbm", n * L * (8 * 8 + 8)),
+            "k_mlp_fwd": ("mfma", n * 2.0 * macs),
+            "k_density_grid": ("hbm", n * 20.0)}
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_prior_65536rays.md")
@@ -186,6 +201,25 @@ def copy_calibration():
     log("bench: copied 1 GiB device-to-device for counter calibration")
 
 
+def run_refresh(tr, arch, ms_per_step, R=64, reps=20, m=50):
+    """The prior refresh (the NeRF's density over the R^3 grid, recomputed
+    every m training steps) timed on its own, and its cost spread over the
+    m steps it serves."""
+    import torch
+    from paper_2503_01582_amd import api
+    tr.refresh_prior(R)
+    torch.cuda.synchronize()
+    log(f"bench: prior refresh, R = {R}, {reps} calls")
+    api.prenom_profile_begin()
+    ms = timed_loop(lambda: tr.refresh_prior(R), reps) / reps
+    kt = api.prenom_profile_end()
+    kern, roof = kernel_table(kt, reps, ms, refresh_work(arch, R ** 3), FP32_MFMA_PEAK_TFLOPS, log)
+    share = ms / (m * ms_per_step)
+    log(f"bench: refresh {ms:.3f} ms per call, {100 * share:.2f}% of the {m} steps it serves")
+    return dict(R=R, ms=round(ms, 4), vertices_per_s=round(R ** 3 / (ms * 1e-3), 1), every_m_steps=m,
+                amortised_share=round(share, 5), dominant=roof, kernels=kern)
+
+
 def run_prior(args):
     import torch
     from paper_2503_01582_amd import api
@@ -229,7 +263,8 @@ def run_prior(args):
                   samples_per_ray=S, n_coarse=batch.sample.n_coarse, n_fine=batch.sample.n_fine,
                   hash_levels=arch.n_levels, log2_table=arch.log2_table, mlp_width=arch.width,
                   mlp_hidden=arch.hidden, samples_per_s=round(value * S, 1))
-    return value, ms_per_step, "fp32", config, roofline, kern, cpu, {}
+    refresh = run_refresh(tr, arch, ms_per_step)
+    return value, ms_per_step, "fp32", config, roofline, kern, cpu, dict(prior_refresh=refresh)
 
 
 def held_between_passes(tr, db):

@@ -239,6 +239,32 @@ prenom_status prenom_adam_step(const prenom_model* model, const prenom_adam_cfg*
 prenom_status prenom_refresh_lowp(const prenom_model* model, void* stream);
 
 /* ------------------------------------------------------------------------
+ * prenom_prior_refresh -- the prior density grid recomputed from the NeRF.
+ * The category prior is the NeRF's density output over a cubic grid of
+ * resolution R (Sec. III-A, "Normalized mesh generation"); during online
+ * mapping it is recomputed from the object's current NeRF every m
+ * iterations so that sampling converges on the object even from an
+ * imprecise pose (Sec. III-B, "Probabilistic Ray Sampling"; m = 50 in
+ * Sec. IV-A).
+ * prior_out [R][R][R] (x fastest, the layout prenom_sample reads) receives
+ *   sigma = exp(o_0) at the vertices (i, j, k) / (R - 1) of the object
+ *   frame, each coordinate rounded from FP64 to FP32 like a sample position;
+ *   the forward reads the FP16 table copy when table_dtype is FP16.
+ * R in [2, PRENOM_MAX_PRIOR_RES]; workspace: >=
+ *   prenom_prior_refresh_workspace_size(arch, R) bytes (0 for an invalid
+ *   arch or R), 256-byte aligned, contents not preserved; the grid is
+ *   processed in chunks of at most 2^21 vertices, so the workspace stays
+ *   near (4 L F + 16) * 2^21 bytes (L levels, F features) whatever R is.  Errors:
+ *   PRENOM_ERR_SHAPE (R), PRENOM_ERR_INVALID_ARG, PRENOM_ERR_WORKSPACE,
+ *   PRENOM_ERR_UNSUPPORTED, checked before any launch.  Asynchronous on
+ *   stream; model->grads is not touched.
+ * ---------------------------------------------------------------------- */
+#define PRENOM_MAX_PRIOR_RES 512
+size_t prenom_prior_refresh_workspace_size(const prenom_arch* arch, int32_t R);
+prenom_status prenom_prior_refresh(const prenom_model* model, int32_t R, float* prior_out, void* workspace,
+                                   size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * prenom_encode -- the hash encoding alone (Sec. III-B "Object-level NeRFs"):
  * pos [n][3] in [0,1]^3 -> features [L][n][F] (level-major); corner_idx
  * [L][n][8] (int32 table row of each cell corner, corner e = (e&1, e>>1&1,

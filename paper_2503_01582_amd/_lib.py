@@ -107,6 +107,10 @@ def lib():
         L.prenom_refresh_lowp.argtypes = [C.POINTER(PrenomModel), _vp]
         L.prenom_encode.restype = C.c_int
         L.prenom_encode.argtypes = [C.POINTER(PrenomArch), _vp, _vp, C.c_int64, _vp, _vp, _vp]
+        L.prenom_prior_refresh_workspace_size.restype = C.c_size_t
+        L.prenom_prior_refresh_workspace_size.argtypes = [C.POINTER(PrenomArch), C.c_int32]
+        L.prenom_prior_refresh.restype = C.c_int
+        L.prenom_prior_refresh.argtypes = [C.POINTER(PrenomModel), C.c_int32, _vp, _vp, C.c_size_t, _vp]
         PB = C.POINTER(PrenomBatch)
         L.prenom_batch_param_count.restype = C.c_int64
         L.prenom_batch_param_count.argtypes = [C.POINTER(PrenomObject), C.c_int32]

@@ -253,6 +253,26 @@ def prenom_adam_step(model: Model, *, lr=1e-2, beta1=0.9, beta2=0.99, eps=1e-15,
     L.check(L.lib().prenom_adam_step(C.byref(mc), C.byref(c), _stream()), "prenom_adam_step")
 
 
+def prenom_prior_refresh(model: Model, R: int = 64, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """The model's density grid [R, R, R] (indexed [k][j][i], x fastest):
+    sigma at the vertices (i, j, k) / (R - 1), ready to pass to prenom_sample
+    as the prior."""
+    dev = model.params.device
+    c_arch = make_arch(model.arch)
+    need = L.lib().prenom_prior_refresh_workspace_size(C.byref(c_arch), R)
+    if need == 0:
+        raise ValueError(f"invalid architecture or R = {R}")
+    ws = torch.empty(need // 4 + 64, dtype=torch.float32, device=dev)
+    off = (-ws.data_ptr()) % 256
+    if out is None:
+        out = torch.empty((R, R, R), dtype=torch.float32, device=dev)
+    mc = model.c_struct()
+    st = L.lib().prenom_prior_refresh(C.byref(mc), R, _ptr(out), C.c_void_p(ws.data_ptr() + off),
+                                      need, _stream())
+    L.check(st, "prenom_prior_refresh")
+    return out
+
+
 def prenom_encode(arch, table: torch.Tensor, pos: torch.Tensor, with_corners=False):
     _dev(table, torch.float32, "table")
     _dev(pos, torch.float32, "pos")

@@ -301,6 +301,52 @@ size_t prenom_workspace_size(const prenom_arch* arch, int64_t n_rays, int32_t n_
     return ws_layout(arch, n_rays, n_samples).total;
 }
 
+// Workspace of prenom_prior_refresh, for one chunk of at most kPriorChunk
+// vertices: features [L][chunk][2], then head outputs [chunk][4].
+constexpr int64_t kPriorChunk = int64_t(1) << 21;
+
+size_t prior_refresh_ws(const prenom_arch* a, int32_t R, size_t* sc_off)
+{
+    const int64_t n = (int64_t)R * R * R;
+    const int64_t c = n < kPriorChunk ? n : kPriorChunk;
+    const size_t y = align_up((size_t)c * a->n_levels * a->n_features * sizeof(float));
+    if (sc_off) *sc_off = y;
+    return y + align_up((size_t)c * 4 * sizeof(float));
+}
+
+size_t prenom_prior_refresh_workspace_size(const prenom_arch* arch, int32_t R)
+{
+    if (check_arch(arch) != PRENOM_OK || R < 2 || R > PRENOM_MAX_PRIOR_RES) return 0;
+    return prior_refresh_ws(arch, R, nullptr);
+}
+
+prenom_status prenom_prior_refresh(const prenom_model* model, int32_t R, float* prior_out, void* workspace,
+                                   size_t ws_bytes, void* stream)
+{
+    prenom_status st = check_model(model, false);
+    if (st != PRENOM_OK) return st;
+    if (R < 2 || R > PRENOM_MAX_PRIOR_RES) return fail(PRENOM_ERR_SHAPE, "R %d outside [2, %d]", R, PRENOM_MAX_PRIOR_RES);
+    if (!prior_out) return fail(PRENOM_ERR_INVALID_ARG, "prior_out is NULL");
+    const prenom_arch* a = &model->arch;
+    size_t sc_off = 0;
+    const size_t need = prior_refresh_ws(a, R, &sc_off);
+    if (!workspace || !aligned(workspace, kAlign)) return fail(PRENOM_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
+    if (ws_bytes < need) return fail(PRENOM_ERR_WORKSPACE, "workspace %zu bytes < %zu", ws_bytes, need);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = (int64_t)R * R * R;
+    float* y = at<float>(workspace, 0);
+    float* sc = at<float>(workspace, sc_off);
+    const void* tlp = a->table_dtype == PRENOM_F16 ? model->table_lp : nullptr;
+    for (int64_t p0 = 0; p0 < n; p0 += kPriorChunk) {
+        const int64_t cnt = n - p0 < kPriorChunk ? n - p0 : kPriorChunk;
+        PRENOM_LAUNCH("k_encode_grid", s, launch_encode_grid(grid_info(a), model->params, tlp, R, p0, cnt, y, s));
+        PRENOM_LAUNCH("k_mlp_fwd", s,
+                      mlp_fwd_any(mlp_shape(a), model->params + table_params(a), y, cnt, sc, nullptr, s));
+        PRENOM_LAUNCH("k_density_grid", s, launch_density_grid(sc, cnt, prior_out + p0, s));
+    }
+    return PRENOM_OK;
+}
+
 prenom_status prenom_sample(const prenom_sample_cfg* cfg, const float* rays_o, const float* rays_d, const float* xi,
                             int64_t n_rays, float* ray_obj, float* t, float* dt, int32_t* bins, uint8_t* flags,
                             void* stream)

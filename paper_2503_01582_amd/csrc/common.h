@@ -128,6 +128,13 @@ struct SampleArgs {
 hipError_t launch_sample(const SampleArgs& a, hipStream_t s);
 hipError_t launch_sample_batch(const SampleArgs& a, const ObjDev* objs, int n_obj, hipStream_t s);
 
+// Encoding of the grid vertices p0 .. p0 + cnt - 1 of the R^3 grid, vertex
+// p = (k R + j) R + i at (i, j, k) / (R - 1): features [L][cnt][2]; and the
+// density column of head outputs sc [n][4] into out [n].
+hipError_t launch_encode_grid(const GridInfo& g, const float* table, const void* table_f16, int32_t R, int64_t p0,
+                              int64_t cnt, float* y, hipStream_t s);
+hipError_t launch_density_grid(const float* sc, int64_t n, float* out, hipStream_t s);
+
 // Encoding of explicit positions: features [L][n][2], optional corner rows.
 hipError_t launch_encode_points(const GridInfo& g, const float* table, const float* pos, int64_t n,
                                 float* features, int32_t* corner_idx, hipStream_t s);

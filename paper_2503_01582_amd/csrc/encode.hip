@@ -216,6 +216,32 @@ __global__ __launch_bounds__(kEncBlock) void k_encode_points(GridInfo g, const f
     }
 }
 
+// Encoding of the R^3 grid vertices (i, j, k) / (R - 1), vertex p = (k R + j) R + i
+// (x fastest); each coordinate is rounded from FP64 to FP32, like a sample
+// position.  Used to refresh the density prior from the NeRF.
+template <typename Row>
+__global__ __launch_bounds__(kEncBlock) void k_encode_grid(GridInfo g, const Row* __restrict__ table, int32_t R,
+                                                           int64_t p0, int64_t cnt, float2* __restrict__ y)
+{
+    const int64_t q = (int64_t)blockIdx.x * kEncBlock + threadIdx.x;
+    const int l = blockIdx.y;
+    if (q >= cnt) return;
+    const int64_t p = p0 + q;
+    const int64_t i = p % R, j = (p / R) % R, k = p / ((int64_t)R * R);
+    const double d = (double)(R - 1);  // correctly rounded FP64 quotients, then FP32
+    Corners c;
+    level_corners(g, l, (float)((double)i / d), (float)((double)j / d), (float)((double)k / d), c);
+    const Row* lt = table + ((int64_t)l << g.log2_table);
+    y[(int64_t)l * cnt + q] = gather_blend(lt, g, l, c);
+}
+
+// out[p] = sigma of head output p (sc rows are (sigma, r, g, b)).
+__global__ __launch_bounds__(256) void k_density_grid(const float4* __restrict__ sc, int64_t n, float* __restrict__ out)
+{
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p < n) out[p] = sc[p].x;
+}
+
 dim3 enc_grid(int64_t n, int L) { return dim3((uint32_t)((n + kEncBlock - 1) / kEncBlock), (uint32_t)L); }
 
 }  // namespace
@@ -232,6 +258,26 @@ hipError_t launch_encode_samples(const GridInfo& g, const float* table, const vo
     else
         hipLaunchKernelGGL(k_encode_samples<float2>, enc_grid(n_s, g.n_levels), dim3(kEncBlock), 0, s, g,
                            (const float2*)table, ray_obj, t, n_s, S, (float2*)y);
+    return hipGetLastError();
+}
+
+hipError_t launch_encode_grid(const GridInfo& g, const float* table, const void* table_f16, int32_t R, int64_t p0,
+                              int64_t cnt, float* y, hipStream_t s)
+{
+    if (cnt == 0) return hipSuccess;
+    if (table_f16)
+        hipLaunchKernelGGL(k_encode_grid<half2_t>, enc_grid(cnt, g.n_levels), dim3(kEncBlock), 0, s, g,
+                           (const half2_t*)table_f16, R, p0, cnt, (float2*)y);
+    else
+        hipLaunchKernelGGL(k_encode_grid<float2>, enc_grid(cnt, g.n_levels), dim3(kEncBlock), 0, s, g,
+                           (const float2*)table, R, p0, cnt, (float2*)y);
+    return hipGetLastError();
+}
+
+hipError_t launch_density_grid(const float* sc, int64_t n, float* out, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_density_grid, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, (const float4*)sc, n, out);
     return hipGetLastError();
 }
 

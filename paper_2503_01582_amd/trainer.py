@@ -33,7 +33,11 @@ def to_device(batch, device="cuda") -> DeviceBatch:
     """Copy a host batch (numpy arrays: rays_o, rays_d, xi, tgt_rgb, tgt_depth,
     mask, world_to_obj, prior, bg) to the device."""
     def t(a, dt=torch.float32):
-        return None if a is None else torch.as_tensor(np.ascontiguousarray(a)).to(device=device, dtype=dt)
+        if a is None:
+            return None
+        if isinstance(a, torch.Tensor):  # e.g. a prior refreshed on the device
+            return a.to(device=device, dtype=dt)
+        return torch.as_tensor(np.ascontiguousarray(a)).to(device=device, dtype=dt)
     return DeviceBatch(rays_o=t(batch.rays_o), rays_d=t(batch.rays_d), xi=t(batch.xi),
                        tgt_rgb=t(batch.tgt_rgb), tgt_depth=t(batch.tgt_depth),
                        mask=t(batch.mask, torch.uint8),
@@ -78,6 +82,11 @@ class Trainer:
         ws = self.ws.get(self.model.arch, b.n_rays, samp.n_samples)
         api.prenom_render_bwd(self.model, samp, self.loss_spec, ws, bg=b.bg, tgt_rgb=b.tgt_rgb,
                               tgt_depth=b.tgt_depth, mask=b.mask)
+
+    def refresh_prior(self, R: int = 64) -> torch.Tensor:
+        """The model's own density grid [R, R, R] at the vertices (i, j, k) /
+        (R - 1), for use as the sampling prior of later steps."""
+        return api.prenom_prior_refresh(self.model, R)
 
     def step(self, b: DeviceBatch):
         """One full training iteration; returns the forward outputs (device)."""
