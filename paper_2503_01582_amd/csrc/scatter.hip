@@ -111,25 +111,38 @@ __device__ __forceinline__ int level_of_tile(const ScatterObj& o, int lt)
 }
 
 // Adds 1 to hist[tile] for every active lane and returns the lane's rank
-// among the additions to that tile.  Lanes of the wave that share a tile are
-// combined into one LDS atomic issued by their first lane (same-address
-// atomics of one instruction would otherwise serialise).
+// among the additions to that tile.  Lanes of the wave that share the tile of
+// the first remaining lane are combined into one LDS atomic issued by that
+// lane (same-address atomics of one instruction would otherwise serialise);
+// after kAggregateRounds such rounds the lanes left use plain LDS atomics, so
+// a wave spread over many tiles does not pay one round per tile.  Every slot
+// comes from an atomic on the same counter, so ranks are distinct whichever
+// way a lane takes.
+constexpr int kAggregateRounds = 2;
+
 __device__ __forceinline__ uint32_t wave_aggregated_add(uint32_t* hist, uint32_t tile)
 {
     const int lane = threadIdx.x & 63;
     const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     uint64_t remaining = __ballot(1);
     uint32_t rank = 0;
-    while (remaining) {
+    bool placed = false;
+#pragma unroll
+    for (int round = 0; round < kAggregateRounds; ++round) {
+        if (remaining == 0) break;
         const int leader = __ffsll((unsigned long long)remaining) - 1;
         const uint32_t lt = __shfl(tile, leader);
         const uint64_t mask = __ballot(tile == lt);
         uint32_t base = 0;
         if (lane == leader) base = atomicAdd(&hist[lt], (uint32_t)__popcll(mask));
         base = __shfl(base, leader);
-        if (tile == lt) rank = base + (uint32_t)__popcll(mask & lane_lt);
+        if (tile == lt) {
+            rank = base + (uint32_t)__popcll(mask & lane_lt);
+            placed = true;
+        }
         remaining &= ~mask;
     }
+    if (!placed) rank = atomicAdd(&hist[tile], 1u);
     return rank;
 }
 
