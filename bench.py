@@ -21,6 +21,11 @@ Workloads (--workload):
   batch48 48 objects, 2^20 rays in all, MLP in BF16 (--mlp-dtype) on the
           matrix cores with FP32 accumulation, FP16 table copy, dynamic loss
           scaling from 2^12; otherwise as batch24.
+  reptile meta-training of a synthetic category's initial parameters: a
+          step is one meta-iteration, q = 8 inner gradient-descent steps of
+          8 tasks x 4096 rays x 32 uniform samples trained together (12
+          levels x 2^17, MLP 64 x 2), then the outer update; value = inner-
+          loop rays/s.
 
 Prints one JSON line: rays/s, the roofline position of the dominant kernel
 (per-kernel HIP-event timing) and, for the prior workload, the FP64 CPU
@@ -434,12 +439,75 @@ def run_batch(args, n_objects, total_rays, mlp_dtype, table_dtype, seed):
     return value, ms_per_step, mlp_dtype if lowp else "fp32", config, roofline, kern, None, extra
 
 
+def run_reptile(args):
+    """Meta-training (Reptile, Eq. (1)-(2)) of a synthetic category: a step is
+    one meta-iteration, q inner gradient-descent steps of B tasks trained
+    together, then the outer update."""
+    import torch
+    from paper_2503_01582_amd import api
+    from paper_2503_01582_amd.meta import ReptileTrainer
+    from synth.arch import Arch
+    from synth.category import category_pools, stratification
+    from synth.params import init_params
+    from synth.workloads import LossSpec, SampleSpec, nocs_affine
+
+    arch = Arch(n_levels=12, log2_table=17, width=64, hidden=2)
+    spec = SampleSpec(n_coarse=0, n_fine=32, include_coarse=False, uniform_only=True)
+    B, q, n, lr, beta = 8, 8, 4096, 80.0, 0.5
+    log(f"bench: {2 * B} instances of a synthetic category, {B} tasks per meta-iteration, q = {q}")
+    pools = category_pools(2, 2 * B, 8 * n)
+    dev = {f: torch.stack([torch.as_tensor(getattr(p, f)) for p in pools]).cuda()
+           for f in ("rays_o", "rays_d", "tgt_rgb", "tgt_depth", "mask")}
+    xi = torch.as_tensor(stratification(7, 0, 8 * n, spec.n_fine)).cuda()
+    tr = ReptileTrainer(arch, init_params(arch, 0), B, n, spec, LossSpec(), inner_lr=lr, beta=beta,
+                        world_to_obj=nocs_affine().reshape(3, 4))
+    ids_all = [torch.as_tensor([(i * B + b) % (2 * B) for b in range(B)]).cuda() for i in range(2)]
+    state = dict(i=0)
+
+    def meta_iteration():
+        i = state["i"]
+        ids = ids_all[i % 2]
+        for k in range(q):
+            sl = slice(k * n, (k + 1) * n)
+            tr.load_rays(dev["rays_o"][ids, sl].reshape(-1, 3), dev["rays_d"][ids, sl].reshape(-1, 3),
+                         xi[sl].repeat(B, 1), dev["tgt_rgb"][ids, sl].reshape(-1, 3),
+                         dev["tgt_depth"][ids, sl].reshape(-1), dev["mask"][ids, sl].reshape(-1))
+            tr.step()
+        tr.outer()
+        state["i"] = i + 1
+
+    for _ in range(args.warmup):
+        meta_iteration()
+    torch.cuda.synchronize()
+    steps = max(3, args.steps // 5)
+    log(f"bench: {steps} timed meta-iterations")
+    api.prenom_profile_begin()
+    ms = timed_loop(meta_iteration, steps)
+    kt = api.prenom_profile_end()
+    ms_per_step = ms / steps
+    rays = B * n * q
+    value = rays / (ms_per_step * 1e-3)
+    log(f"bench: {ms_per_step:.3f} ms per meta-iteration ({rays} inner-loop rays), "
+        f"last inner loss {float(tr.out['loss'].mean()):.4e}")
+    work = {k: (b, a * q) for k, (b, a) in summed_work([(arch, n, spec.n_samples, spec.n_fine)] * B).items()
+            if k != "k_adam"}
+    work["k_sgd"] = ("hbm", 16.0 * B * arch.n_params * q)
+    work["k_reptile"] = ("hbm", 8.0 * (B + 1) * arch.n_params)
+    kern, roofline = kernel_table(kt, steps, ms_per_step, work, FP32_MFMA_PEAK_TFLOPS, log)
+    config = dict(workload="Reptile meta-training of a synthetic category (one meta-iteration per step)",
+                  n_tasks=B, inner_steps=q, rays_per_task=n, samples_per_ray=spec.n_samples, inner_lr=lr,
+                  meta_step_size=beta, hash_levels=arch.n_levels, log2_table=arch.log2_table, mlp_width=arch.width,
+                  mlp_hidden=arch.hidden)
+    extra = dict(reptile_update=kern.get("k_reptile"))
+    return value, ms_per_step, "fp32", config, roofline, kern, None, extra
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", choices=("prior", "autograd", "batch24", "batch48"), default="prior")
+    ap.add_argument("--workload", choices=("prior", "autograd", "batch24", "batch48", "reptile"), default="prior")
     ap.add_argument("--mlp-dtype", choices=("bf16", "fp16"), default="bf16", help="batch48 only")
     ap.add_argument("--rays", type=int, default=65536, help="prior workload only")
     ap.add_argument("--cpu-rays", type=int, default=65536)
@@ -460,6 +528,8 @@ def main():
         res = run_prior(args)
     elif args.workload == "autograd":
         res = run_autograd(args)
+    elif args.workload == "reptile":
+        res = run_reptile(args)
     elif args.workload == "batch24":
         res = run_batch(args, 24, None, "fp32", "fp32", seed=4)
     else:

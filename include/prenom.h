@@ -388,6 +388,52 @@ prenom_status prenom_batch_adam_step(const prenom_batch* batch, const prenom_ada
 prenom_status prenom_batch_refresh_lowp(const prenom_batch* batch, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Meta-learning of the initial parameters (Sec. III-A, "Meta-learning",
+ * Eq. (1)-(2), Reptile).  A task is one object instance of a category,
+ * trained from the meta-parameters theta for q inner iterations of plain
+ * gradient descent (Eq. (1)); theta then moves towards the result (Eq. (2)).
+ * Tasks trained from the same theta can run together as the objects of one
+ * batch; the outer update then takes the mean of their differences.
+ * ---------------------------------------------------------------------- */
+typedef struct prenom_sgd_cfg {
+    float lr;                /* eta of Eq. (1), finite, >= 0 */
+    int32_t growth_interval; /* loss scaling as in prenom_adam_cfg */
+} prenom_sgd_cfg;
+
+/* Eq. (1): params -= lr * grads (unscaled by *loss_scale when the model has
+ * one; the whole update skipped after a non-finite gradient), then zeroes
+ * the gradients; rewrites the FP16 table copy when table_dtype is FP16.  No
+ * moments are read or written.  Errors as prenom_adam_step. */
+prenom_status prenom_sgd_step(const prenom_model* model, const prenom_sgd_cfg* cfg, void* stream);
+
+/* prenom_sgd_step over the whole parameter array of a batch; batch->step,
+ * when set, counts the applied steps; adam_m / adam_v are not used. */
+prenom_status prenom_batch_sgd_step(const prenom_batch* batch, const prenom_sgd_cfg* cfg, void* stream);
+
+/* Eq. (2) over n_tasks >= 1 tasks trained from theta:
+ *   theta += beta * (1 / n_tasks) * sum_b (task_b - theta)
+ * (n_tasks = 1: theta + beta (theta^(q) - theta), Eq. (2) itself), then
+ * every task slot is reset to the new theta for the next meta-iteration:
+ * task_b <- theta; its FP16 copy's first n_lp entries <- theta rounded to
+ * nearest (tasks_lp, or NULL); its Adam moments <- 0 (adam_m and adam_v,
+ * both or neither); *step <- 0 (a device step counter, or NULL).
+ *   theta   [n_params] device FP32, 16-byte aligned; must not overlap a task.
+ *   tasks   device FP32, task b at tasks + b * task_stride, 16-byte aligned;
+ *           task_stride >= n_params and a multiple of 4 (the batch layout
+ *           of prenom_batch_param_offset when every object has the same
+ *           architecture).
+ *   adam_m, adam_v: in the task layout, 16-byte aligned.
+ *   tasks_lp: FP16 in the task layout (in halves), 8-byte aligned;
+ *           0 <= n_lp <= n_params.
+ * n_tasks in [1, PRENOM_MAX_OBJECTS]; beta finite.  Errors: PRENOM_ERR_SHAPE,
+ * PRENOM_ERR_INVALID_ARG, checked before any launch.  One launch; tasks
+ * are read and written in place, so calls on the same tasks must not
+ * overlap. */
+prenom_status prenom_reptile_update(float* theta, float* tasks, int64_t n_params, int32_t n_tasks,
+                                    int64_t task_stride, float beta, float* adam_m, float* adam_v, void* tasks_lp,
+                                    int64_t n_lp, int64_t* step, void* stream);
+
+/* ------------------------------------------------------------------------
  * Kernel timing (instrumentation, not part of the method).  Between
  * prenom_profile_begin() and prenom_profile_end(), every kernel the library
  * launches is bracketed by a pair of HIP events on its stream.

@@ -352,3 +352,35 @@ def adam(params, grads, m, v, *, lr, beta1, beta2, eps, step):
                    float(np.float32(eps)), int(step), _p(p_out, _f64p), _p(m_out, _f64p),
                    _p(v_out, _f64p))
     return p_out, m_out, v_out
+
+
+# ---------------------------------------------------------------- meta-learning
+
+def sgd(params, grads, *, lr):
+    """Eq. (1): one gradient-descent step theta - eta grad, in FP64 (eta as
+    the FP32 value the device receives)."""
+    return _f64(params) - float(np.float32(lr)) * _f64(grads)
+
+
+def reptile_outer(theta, task_params, *, beta):
+    """Eq. (2): theta + beta (theta^(q) - theta).  For several tasks trained
+    from the same theta, the mean of their differences takes the place of
+    the one difference (one task: Eq. (2) itself).  FP64."""
+    theta = _f64(theta)
+    diffs = [_f64(p) - theta for p in task_params]
+    return theta + float(np.float32(beta)) * (np.sum(diffs, axis=0) / len(diffs))
+
+
+def reptile_meta_step(theta, tasks, *, q, lr, beta, grad, store=np.float32):
+    """One meta-iteration: every task trained from theta by q steps of
+    Eq. (1), grad(task, k, params) giving the task loss's gradient at inner
+    step k, then Eq. (2) over the tasks' results.  Between steps the
+    parameters are kept in `store` (FP32: the precision they are stored in
+    on the device; FP64 for closed-form checks)."""
+    finals = []
+    for task in tasks:
+        p = np.asarray(theta, store)
+        for k in range(q):
+            p = sgd(p, grad(task, k, p), lr=lr).astype(store)
+        finals.append(p)
+    return reptile_outer(theta, finals, beta=beta)

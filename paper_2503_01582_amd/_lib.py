@@ -48,6 +48,10 @@ class PrenomAdamCfg(C.Structure):
                 ("step", C.c_int64), ("growth_interval", C.c_int32)]
 
 
+class PrenomSgdCfg(C.Structure):
+    _fields_ = [("lr", C.c_float), ("growth_interval", C.c_int32)]
+
+
 class PrenomObject(C.Structure):
     _fields_ = [("arch", PrenomArch), ("n_rays", C.c_int64), ("prior", C.c_void_p),
                 ("prior_res", C.c_int32), ("world_to_obj", C.c_float * 12)]
@@ -133,6 +137,13 @@ def lib():
         L.prenom_batch_adam_step.argtypes = [PB, C.POINTER(PrenomAdamCfg), _vp]
         L.prenom_batch_refresh_lowp.restype = C.c_int
         L.prenom_batch_refresh_lowp.argtypes = [PB, _vp]
+        L.prenom_sgd_step.restype = C.c_int
+        L.prenom_sgd_step.argtypes = [C.POINTER(PrenomModel), C.POINTER(PrenomSgdCfg), _vp]
+        L.prenom_batch_sgd_step.restype = C.c_int
+        L.prenom_batch_sgd_step.argtypes = [PB, C.POINTER(PrenomSgdCfg), _vp]
+        L.prenom_reptile_update.restype = C.c_int
+        L.prenom_reptile_update.argtypes = [_vp, _vp, C.c_int64, C.c_int32, C.c_int64, C.c_float, _vp, _vp, _vp,
+                                            C.c_int64, _vp, _vp]
         L.prenom_profile_begin.restype = C.c_int
         L.prenom_profile_begin.argtypes = []
         L.prenom_profile_end.restype = C.c_int

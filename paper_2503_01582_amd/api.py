@@ -253,6 +253,36 @@ def prenom_adam_step(model: Model, *, lr=1e-2, beta1=0.9, beta2=0.99, eps=1e-15,
     L.check(L.lib().prenom_adam_step(C.byref(mc), C.byref(c), _stream()), "prenom_adam_step")
 
 
+def prenom_sgd_step(model: Model, *, lr: float, growth_interval=2000):
+    """Eq. (1): params -= lr * grads, gradients zeroed."""
+    c = L.PrenomSgdCfg()
+    c.lr, c.growth_interval = lr, growth_interval
+    mc = model.c_struct()
+    L.check(L.lib().prenom_sgd_step(C.byref(mc), C.byref(c), _stream()), "prenom_sgd_step")
+
+
+def prenom_reptile_update(theta: torch.Tensor, tasks: torch.Tensor, n_params: int, n_tasks: int, task_stride: int,
+                          beta: float, adam_m: Optional[torch.Tensor] = None, adam_v: Optional[torch.Tensor] = None,
+                          tasks_lp: Optional[torch.Tensor] = None, n_lp: int = 0,
+                          step: Optional[torch.Tensor] = None):
+    """Eq. (2) over n_tasks task vectors (task b at tasks[b * task_stride:]);
+    every task slot restarts from the new theta."""
+    _dev(theta, torch.float32, "theta")
+    _dev(tasks, torch.float32, "tasks")
+    if theta.numel() < n_params or tasks.numel() < (n_tasks - 1) * task_stride + n_params:
+        raise ValueError("theta or tasks smaller than the layout they are given")
+    for t, dt, name in ((adam_m, torch.float32, "adam_m"), (adam_v, torch.float32, "adam_v"),
+                        (tasks_lp, torch.float16, "tasks_lp")):
+        _dev(t, dt, name)
+        if t is not None and t.numel() < (n_tasks - 1) * task_stride + (n_lp if name == "tasks_lp" else n_params):
+            raise ValueError(f"{name} smaller than the task layout")
+    if step is not None and (step.dtype != torch.int64 or not step.is_cuda):
+        raise TypeError("step must be a device int64 tensor")
+    st = L.lib().prenom_reptile_update(_ptr(theta), _ptr(tasks), n_params, n_tasks, task_stride, beta, _ptr(adam_m),
+                                       _ptr(adam_v), _ptr(tasks_lp), n_lp, _ptr(step), _stream())
+    L.check(st, "prenom_reptile_update")
+
+
 def prenom_prior_refresh(model: Model, R: int = 64, out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """The model's density grid [R, R, R] (indexed [k][j][i], x fastest):
     sigma at the vertices (i, j, k) / (R - 1), ready to pass to prenom_sample

@@ -220,6 +220,13 @@ def prenom_batch_adam_step(bm: BatchModel, *, lr=1e-2, beta1=0.9, beta2=0.99, ep
     L.check(L.lib().prenom_batch_adam_step(C.byref(b), C.byref(c), _stream()), "prenom_batch_adam_step")
 
 
+def prenom_batch_sgd_step(bm: BatchModel, *, lr: float, growth_interval=2000):
+    c = L.PrenomSgdCfg()
+    c.lr, c.growth_interval = lr, growth_interval
+    b = bm.c_struct()
+    L.check(L.lib().prenom_batch_sgd_step(C.byref(b), C.byref(c), _stream()), "prenom_batch_sgd_step")
+
+
 def prenom_batch_refresh_lowp(bm: BatchModel):
     b = bm.c_struct()
     L.check(L.lib().prenom_batch_refresh_lowp(C.byref(b), _stream()), "prenom_batch_refresh_lowp")

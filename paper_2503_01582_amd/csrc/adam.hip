@@ -1,7 +1,9 @@
-// Adam over every parameter (Sec. III-B, last paragraph), fused with zeroing
-// the gradient it consumed and, when the tables are also kept in FP16, with
-// rewriting that copy.  Pure streaming: 4 loads + 4 stores of FP32 per
-// parameter, float4-vectorised.
+// The optimisers.  Adam over every parameter (Sec. III-B, last paragraph),
+// fused with zeroing the gradient it consumed and, when the tables are also
+// kept in FP16, with rewriting that copy: pure streaming, 4 loads + 4 stores
+// of FP32 per parameter, float4-vectorised.  Plain gradient descent, the
+// inner step of meta-learning (Sec. III-A, Eq. (1)), fused the same way:
+// 2 loads + 2 stores per parameter.
 //
 // With loss scaling the gradients arrive multiplied by the device scalar
 // `loss_scale`.  One pass flags any non-finite entry; the update then unscales
@@ -94,6 +96,41 @@ __global__ __launch_bounds__(kAdamBlock) void k_adam(AdamArgs a)
     }
 }
 
+__global__ __launch_bounds__(kAdamBlock) void k_sgd(AdamArgs a)
+{
+    const int64_t n4 = a.n >> 2;
+    const int64_t stride = (int64_t)gridDim.x * kAdamBlock;
+    const bool skip = a.loss_scale && a.scaler_state[0] != 0;
+    const float step = a.lr * (a.loss_scale ? 1.0f / *a.loss_scale : 1.0f);
+    for (int64_t i = (int64_t)blockIdx.x * kAdamBlock + threadIdx.x; i < n4; i += stride) {
+        float4* g4 = reinterpret_cast<float4*>(a.g) + i;
+        if (skip) {
+            *g4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            continue;
+        }
+        float4 p = reinterpret_cast<float4*>(a.p)[i];
+        const float4 g = *g4;
+        p.x -= step * g.x;
+        p.y -= step * g.y;
+        p.z -= step * g.z;
+        p.w -= step * g.w;
+        reinterpret_cast<float4*>(a.p)[i] = p;
+        *g4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (a.table_f16 && (i << 2) < a.n_table) {
+            half4_t h = {(_Float16)p.x, (_Float16)p.y, (_Float16)p.z, (_Float16)p.w};
+            reinterpret_cast<half4_t*>(a.table_f16)[i] = h;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x < (a.n & 3)) {
+        const int64_t i = (n4 << 2) + threadIdx.x;
+        if (!skip) {
+            a.p[i] -= step * a.g[i];
+            if (a.table_f16 && i < a.n_table) reinterpret_cast<_Float16*>(a.table_f16)[i] = (_Float16)a.p[i];
+        }
+        a.g[i] = 0.0f;
+    }
+}
+
 // After the update: advance the device step counter unless the step was
 // skipped, then adjust the loss scale.
 __global__ void k_finish_step(float* scale, int32_t* state, int32_t growth_interval, int64_t* step)
@@ -142,6 +179,25 @@ hipError_t launch_adam(const AdamArgs& a, hipStream_t s)
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_adam, grid, dim3(kAdamBlock), 0, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (a.loss_scale || a.step_dev) {
+        hipLaunchKernelGGL(k_finish_step, dim3(1), dim3(64), 0, s, a.loss_scale, a.scaler_state, a.growth_interval,
+                           a.step_dev);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+hipError_t launch_sgd(const AdamArgs& a, hipStream_t s)
+{
+    if (a.n == 0) return hipSuccess;
+    const dim3 grid((uint32_t)stream_blocks(a.n >> 2));
+    hipError_t e;
+    if (a.loss_scale) {
+        hipLaunchKernelGGL(k_adam_check, grid, dim3(kAdamBlock), 0, s, a);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_sgd, grid, dim3(kAdamBlock), 0, s, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (a.loss_scale || a.step_dev) {
         hipLaunchKernelGGL(k_finish_step, dim3(1), dim3(64), 0, s, a.loss_scale, a.scaler_state, a.growth_interval,

@@ -555,6 +555,64 @@ prenom_status prenom_adam_step(const prenom_model* model, const prenom_adam_cfg*
     return PRENOM_OK;
 }
 
+prenom_status prenom_sgd_step(const prenom_model* model, const prenom_sgd_cfg* cfg, void* stream)
+{
+    prenom_status st = check_model(model, true);
+    if (st != PRENOM_OK) return st;
+    if (!cfg) return fail(PRENOM_ERR_INVALID_ARG, "cfg is NULL");
+    if (!(cfg->lr >= 0.0f && std::isfinite(cfg->lr))) return fail(PRENOM_ERR_INVALID_ARG, "lr must be finite and >= 0");
+    if (cfg->growth_interval < 0) return fail(PRENOM_ERR_INVALID_ARG, "growth_interval < 0");
+    AdamArgs a{};
+    a.p = model->params;
+    a.g = model->grads;
+    a.n = table_params(&model->arch) + mlp_params(&model->arch);
+    a.lr = cfg->lr;
+    a.table_f16 = model->arch.table_dtype == PRENOM_F16 ? model->table_lp : nullptr;
+    a.n_table = table_params(&model->arch);
+    a.loss_scale = model->loss_scale;
+    a.scaler_state = model->scaler_state;
+    a.growth_interval = cfg->growth_interval;
+    PRENOM_LAUNCH("k_sgd", (hipStream_t)stream, launch_sgd(a, (hipStream_t)stream));
+    return PRENOM_OK;
+}
+
+prenom_status prenom_reptile_update(float* theta, float* tasks, int64_t n_params, int32_t n_tasks, int64_t task_stride,
+                                    float beta, float* adam_m, float* adam_v, void* tasks_lp, int64_t n_lp,
+                                    int64_t* step, void* stream)
+{
+    if (n_params < 0) return fail(PRENOM_ERR_SHAPE, "n_params < 0");
+    if (n_tasks < 1 || n_tasks > PRENOM_MAX_OBJECTS)
+        return fail(PRENOM_ERR_SHAPE, "n_tasks %d outside [1, %d]", n_tasks, PRENOM_MAX_OBJECTS);
+    if (task_stride < n_params || task_stride % 4 != 0)
+        return fail(PRENOM_ERR_SHAPE, "task_stride %lld must be >= n_params and a multiple of 4", (long long)task_stride);
+    if (!std::isfinite(beta)) return fail(PRENOM_ERR_INVALID_ARG, "beta is not finite");
+    if ((adam_m == nullptr) != (adam_v == nullptr)) return fail(PRENOM_ERR_INVALID_ARG, "adam_m and adam_v: both or neither");
+    if (tasks_lp && (n_lp < 0 || n_lp > n_params)) return fail(PRENOM_ERR_SHAPE, "n_lp outside [0, n_params]");
+    if (n_params > 0) {
+        if (!theta || !tasks || !aligned(theta, 16) || !aligned(tasks, 16))
+            return fail(PRENOM_ERR_INVALID_ARG, "theta / tasks NULL or not 16-byte aligned");
+        if ((adam_m && (!aligned(adam_m, 16) || !aligned(adam_v, 16))) || (tasks_lp && !aligned(tasks_lp, 8)))
+            return fail(PRENOM_ERR_INVALID_ARG, "adam moments not 16-byte or tasks_lp not 8-byte aligned");
+        const uintptr_t t0 = (uintptr_t)tasks, t1 = (uintptr_t)(tasks + (int64_t)(n_tasks - 1) * task_stride + n_params);
+        const uintptr_t h0 = (uintptr_t)theta, h1 = (uintptr_t)(theta + n_params);
+        if (h0 < t1 && t0 < h1) return fail(PRENOM_ERR_INVALID_ARG, "theta overlaps the task slots");
+    }
+    ReptileArgs a{};
+    a.theta = theta;
+    a.tasks = tasks;
+    a.m = adam_m;
+    a.v = adam_v;
+    a.tasks_f16 = tasks_lp;
+    a.n_f16 = tasks_lp ? n_lp : 0;
+    a.step = step;
+    a.n = n_params;
+    a.stride = task_stride;
+    a.n_tasks = n_tasks;
+    a.beta = beta;
+    PRENOM_LAUNCH("k_reptile", (hipStream_t)stream, launch_reptile(a, (hipStream_t)stream));
+    return PRENOM_OK;
+}
+
 prenom_status prenom_refresh_lowp(const prenom_model* model, void* stream)
 {
     prenom_status st = check_model(model, false);

@@ -607,6 +607,34 @@ prenom_status prenom_batch_adam_step(const prenom_batch* batch, const prenom_ada
     return PRENOM_OK;
 }
 
+prenom_status prenom_batch_sgd_step(const prenom_batch* batch, const prenom_sgd_cfg* cfg, void* stream)
+{
+    if (!batch) return fail(PRENOM_ERR_INVALID_ARG, "batch is NULL");
+    prenom_status st = check_objects(batch->objects, batch->n_objects);
+    if (st != PRENOM_OK) return st;
+    if (!cfg) return fail(PRENOM_ERR_INVALID_ARG, "cfg is NULL");
+    if (!(cfg->lr >= 0.0f && std::isfinite(cfg->lr))) return fail(PRENOM_ERR_INVALID_ARG, "lr must be finite and >= 0");
+    if (cfg->growth_interval < 0) return fail(PRENOM_ERR_INVALID_ARG, "growth_interval < 0");
+    bool any_f16 = false;
+    for (int i = 0; i < batch->n_objects; ++i) any_f16 = any_f16 || batch->objects[i].arch.table_dtype == PRENOM_F16;
+    Plan dummy;
+    dummy.any_f16_table = any_f16;
+    if ((st = check_params(batch, dummy, true)) != PRENOM_OK) return st;
+    AdamArgs a{};
+    a.p = batch->params;
+    a.g = batch->grads;
+    a.n = prenom_batch_param_count(batch->objects, batch->n_objects);
+    a.lr = cfg->lr;
+    a.table_f16 = any_f16 ? batch->params_lp : nullptr;
+    a.n_table = a.n;
+    a.loss_scale = batch->loss_scale;
+    a.scaler_state = batch->scaler_state;
+    a.growth_interval = cfg->growth_interval;
+    a.step_dev = batch->step;
+    PRENOM_LAUNCH("k_sgd", (hipStream_t)stream, launch_sgd(a, (hipStream_t)stream));
+    return PRENOM_OK;
+}
+
 prenom_status prenom_batch_refresh_lowp(const prenom_batch* batch, void* stream)
 {
     if (!batch) return fail(PRENOM_ERR_INVALID_ARG, "batch is NULL");

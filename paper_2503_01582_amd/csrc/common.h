@@ -328,6 +328,26 @@ struct AdamArgs {
                              // advanced after every applied (not skipped) step
 };
 hipError_t launch_adam(const AdamArgs& a, hipStream_t s);
+// Plain gradient descent p -= lr g on the same arguments (m, v, beta1, beta2,
+// eps and the bias corrections unused).
+hipError_t launch_sgd(const AdamArgs& a, hipStream_t s);
 hipError_t launch_to_f16(const float* src, void* dst, int64_t n, hipStream_t s);
+
+// Reptile's outer update over n_tasks parameter vectors trained from theta:
+// theta += beta * mean_b(task_b - theta), then every task slot (and its FP16
+// copy, and its Adam moments, when given) restarts from the new theta.
+struct ReptileArgs {
+    float* theta;
+    float* tasks;            // task b at tasks + b * stride
+    float* m;                // Adam moments in the task layout, or null
+    float* v;
+    void* tasks_f16;         // FP16 copy in the task layout (its first n_f16 entries), or null
+    int64_t* step;           // device step counter reset to 0, or null
+    int64_t n, stride;       // stride a multiple of 4
+    int64_t n_f16;
+    int32_t n_tasks;
+    float beta;
+};
+hipError_t launch_reptile(const ReptileArgs& a, hipStream_t s);
 
 }  // namespace prenom

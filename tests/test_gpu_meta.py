@@ -1,0 +1,291 @@
+"""Meta-learning of the initial parameters on the GPU (Sec. III-A, Eq. (1)-(2),
+Reptile): the inner gradient-descent step, the outer update over B tasks,
+one whole meta-iteration against the oracle, and the meta-learned versus the
+random initialisation (the ML row of the paper's ablation, Table IV)."""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from parity_util import assert_close
+from synth.arch import ARCH_SMALL, Arch
+from synth.category import category_pools, stratification
+from synth.params import init_params
+from synth.workloads import LossSpec, SampleSpec, eval_views, nocs_affine
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+UNIFORM = SampleSpec(n_coarse=0, n_fine=32, include_coarse=False, uniform_only=True)
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def sgd_bound(p, lr, g):
+    """FP32 rounding of p - lr g: at most two roundings of operands of these sizes."""
+    return 2.0 ** -22 * (np.abs(p) + np.abs(np.float32(lr) * g.astype(np.float64)))
+
+
+# ---------------------------------------------------------------- Eq. (1)
+
+@pytest.mark.parametrize("table_dtype", ["fp32", "fp16"])
+def test_sgd_step_matches_oracle(table_dtype):
+    say(f"test_sgd_step_matches_oracle[{table_dtype}]")
+    from paper_2503_01582_amd import api
+    arch = dataclasses.replace(ARCH_SMALL, table_dtype=table_dtype)
+    rng = np.random.default_rng(1)
+    p = init_params(arch, 2)
+    p[:arch.n_table_params] = rng.uniform(-0.3, 0.3, arch.n_table_params).astype(np.float32)
+    g = rng.normal(0, 1e-2, arch.n_params).astype(np.float32)
+    model = api.Model(arch, p)
+    model.grads.copy_(torch.as_tensor(g))
+    lr = 0.75
+    api.prenom_sgd_step(model, lr=lr)
+    torch.cuda.synchronize()
+    got = model.params.cpu().numpy().astype(np.float64)
+    ref = orc.sgd(p, g, lr=lr)
+    assert np.all(np.abs(got - ref) <= sgd_bound(p, lr, g))
+    assert float(model.grads.abs().max()) == 0.0
+    if table_dtype == "fp16":
+        lp = model.table_lp.float().cpu().numpy()
+        np.testing.assert_array_equal(lp, got[:arch.n_table_params].astype(np.float32).astype(np.float16))
+
+
+def test_sgd_step_loss_scaling():
+    """Gradients carrying a loss scale give the unscaled update; a non-finite
+    gradient skips the update, clears the gradients and halves the scale."""
+    say("test_sgd_step_loss_scaling")
+    from paper_2503_01582_amd import api
+    arch = ARCH_SMALL
+    rng = np.random.default_rng(3)
+    p = init_params(arch, 4)
+    g = rng.normal(0, 1e-2, arch.n_params).astype(np.float32)
+    model = api.Model(arch, p, loss_scale=1024.0)
+    model.grads.copy_(torch.as_tensor(g) * 1024.0)
+    api.prenom_sgd_step(model, lr=0.5)
+    torch.cuda.synchronize()
+    got = model.params.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - orc.sgd(p, g, lr=0.5)) <= sgd_bound(p, 0.5, g))
+    before = model.params.clone()
+    bad = torch.as_tensor(g).cuda()
+    bad[12345] = float("inf")
+    model.grads.copy_(bad)
+    api.prenom_sgd_step(model, lr=0.5)
+    torch.cuda.synchronize()
+    assert torch.equal(model.params, before)
+    assert float(model.grads.abs().max()) == 0.0
+    assert float(model.loss_scale.item()) == 512.0
+
+
+def test_batch_sgd_step_matches_oracle():
+    say("test_batch_sgd_step_matches_oracle")
+    from paper_2503_01582_amd.batch import BatchModel, BatchObject, prenom_batch_sgd_step
+    archs = [Arch(n_levels=8, log2_table=14, width=64, hidden=1), Arch(n_levels=12, log2_table=15, width=32, hidden=2),
+             Arch(n_levels=16, log2_table=14, width=128, hidden=1)]
+    objs = [BatchObject(a, 10, None, nocs_affine().reshape(3, 4)) for a in archs]
+    ps = [init_params(a, 10 + i) for i, a in enumerate(archs)]
+    bm = BatchModel(objs, ps)
+    rng = np.random.default_rng(5)
+    gs = [rng.normal(0, 1e-2, a.n_params).astype(np.float32) for a in archs]
+    for i, g in enumerate(gs):
+        bm.object_grads(i).copy_(torch.as_tensor(g))
+    prenom_batch_sgd_step(bm, lr=2.0)
+    torch.cuda.synchronize()
+    for i, (p, g) in enumerate(zip(ps, gs)):
+        got = bm.object_params(i).cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(got - orc.sgd(p, g, lr=2.0)) <= sgd_bound(p, 2.0, g)), f"object {i}"
+    assert float(bm.grads.abs().max()) == 0.0
+    assert int(bm.step.item()) == 1
+
+
+# ---------------------------------------------------------------- Eq. (2)
+
+@pytest.mark.parametrize("B,n", [(1, 1), (1, 4099), (3, 7), (8, 4099), (64, 100003)])
+def test_reptile_update_matches_oracle(B, n):
+    say(f"test_reptile_update_matches_oracle[B={B}, n={n}]")
+    from paper_2503_01582_amd import api
+    rng = np.random.default_rng(B * 7919 + n)
+    stride = (n + 63) // 64 * 64 + 64          # padding after every task
+    theta0 = rng.normal(size=n).astype(np.float32)
+    tasks0 = rng.normal(size=(B, stride)).astype(np.float32)
+    tasks0[:, :n] = theta0 + rng.normal(0, 0.1, (B, n)).astype(np.float32)
+    theta = torch.as_tensor(theta0).cuda()
+    tasks = torch.as_tensor(tasks0.reshape(-1)).cuda()
+    m = torch.full((B * stride,), 3.0, device="cuda")
+    v = torch.full((B * stride,), 4.0, device="cuda")
+    lp = torch.full((B * stride,), 5.0, dtype=torch.float16, device="cuda")
+    step = torch.full((1,), 77, dtype=torch.int64, device="cuda")
+    beta = 0.375
+    api.prenom_reptile_update(theta, tasks, n, B, stride, beta, adam_m=m, adam_v=v, tasks_lp=lp, n_lp=n, step=step)
+    torch.cuda.synchronize()
+    got = theta.cpu().numpy().astype(np.float64)
+    ref = orc.reptile_outer(theta0, list(tasks0[:, :n]), beta=beta)
+    # FP32 evaluation: B differences summed (B u sum|d_b|), the beta / B product,
+    # the final addition (u |theta'|); u = 2^-24, doubled for margin
+    dsum = np.abs(tasks0[:, :n].astype(np.float64) - theta0).sum(0)
+    bound = 2.0 ** -23 * (np.abs(ref) + beta * (B + 2) / B * dsum)
+    assert np.all(np.abs(got - ref) <= bound), f"max excess {np.max(np.abs(got - ref) / bound):.2f}"
+    assert_close(got, ref, 1e-6, "theta")
+    t = tasks.cpu().numpy().reshape(B, stride)
+    assert np.array_equal(t[:, :n], np.broadcast_to(got.astype(np.float32), (B, n)))
+    assert np.array_equal(t[:, n:], tasks0[:, n:])      # padding untouched
+    mm, vv = m.cpu().numpy().reshape(B, stride), v.cpu().numpy().reshape(B, stride)
+    assert np.all(mm[:, :n] == 0) and np.all(vv[:, :n] == 0) and np.all(mm[:, n:] == 3) and np.all(vv[:, n:] == 4)
+    ll = lp.cpu().numpy().reshape(B, stride)
+    assert np.array_equal(ll[:, :n], np.broadcast_to(got.astype(np.float32).astype(np.float16), (B, n)))
+    assert np.all(ll[:, n:] == 5)
+    assert int(step.item()) == 0
+
+
+def test_reptile_update_argument_errors():
+    say("test_reptile_update_argument_errors")
+    from paper_2503_01582_amd import api
+    from paper_2503_01582_amd._lib import PrenomError
+    theta = torch.zeros(64, device="cuda")
+    tasks = torch.zeros(4 * 64, device="cuda")
+    for kw in (dict(n_tasks=0, task_stride=64), dict(n_tasks=2, task_stride=62), dict(n_tasks=2, task_stride=30),
+               dict(n_tasks=5000, task_stride=64)):
+        with pytest.raises((PrenomError, ValueError)):
+            api.prenom_reptile_update(theta, tasks, 30, kw["n_tasks"], kw["task_stride"], 0.5)
+    with pytest.raises(PrenomError):
+        api.prenom_reptile_update(theta, tasks, 30, 2, 64, float("nan"))
+    with pytest.raises(PrenomError):   # theta inside the task slots
+        api.prenom_reptile_update(tasks[64:128], tasks, 30, 2, 64, 0.5)
+    with pytest.raises(PrenomError):   # moments: both or neither
+        api.prenom_reptile_update(theta, tasks, 30, 2, 64, 0.5, adam_m=torch.zeros(128, device="cuda"))
+
+
+# ---------------------------------------------------------------- one meta-iteration
+
+def device_rays(pools, ids, lo, n, seed, step, n_fine):
+    """Rays [lo, lo + n) of the pools `ids`, tasks one after another, on the device."""
+    cat = lambda f: torch.as_tensor(np.concatenate([getattr(pools[i], f)[lo:lo + n] for i in ids])).cuda()
+    xi = torch.as_tensor(np.concatenate([stratification(seed, step * 1000 + i, n, n_fine) for i in ids])).cuda()
+    return cat("rays_o"), cat("rays_d"), xi, cat("tgt_rgb"), cat("tgt_depth"), cat("mask")
+
+
+def test_meta_iteration_matches_oracle():
+    """B = 3 tasks of one category, q = 2 inner steps of Eq. (1) on 256 rays x
+    32 uniform samples each, then Eq. (2): theta's change within 1e-5 of the
+    oracle's (which samples, renders and differentiates on its own)."""
+    say("test_meta_iteration_matches_oracle")
+    from paper_2503_01582_amd.meta import ReptileTrainer
+    arch = ARCH_SMALL
+    B, q, n, lr, beta = 3, 2, 256, 4.0, 0.5
+    pools = category_pools(2, B, 2 * n)
+    rng = np.random.default_rng(9)
+    theta0 = init_params(arch, 3)
+    theta0[:arch.n_table_params] = rng.uniform(-0.3, 0.3, arch.n_table_params).astype(np.float32)
+    loss = LossSpec(lambda_d=0.1)
+    tr = ReptileTrainer(arch, theta0, B, n, UNIFORM, loss, inner_lr=lr, beta=beta,
+                        world_to_obj=nocs_affine().reshape(3, 4))
+    for k in range(q):
+        tr.load_rays(*device_rays(pools, range(B), k * n, n, 4, k, UNIFORM.n_fine))
+        tr.step()
+    tr.outer()
+    torch.cuda.synchronize()
+    got = tr.theta.cpu().numpy().astype(np.float64)
+    tasks = tr.model.params.cpu().numpy()
+    for b in range(B):
+        assert np.array_equal(tasks[tr.model.offsets[b]:tr.model.offsets[b] + arch.n_params], got.astype(np.float32))
+
+    def grad(b, k, p):
+        pool = pools[b]
+        sl = slice(k * n, (k + 1) * n)
+        xi = stratification(4, k * 1000 + b, n, UNIFORM.n_fine)
+        s = orc.sample(pool.rays_o[sl], pool.rays_d[sl], xi, n_coarse=0, n_fine=UNIFORM.n_fine, include_coarse=False,
+                       uniform_only=True, eps=UNIFORM.eps, near=UNIFORM.near, far=UNIFORM.far,
+                       world_to_obj=nocs_affine())
+        return orc.render_bwd(arch, p, s["ray_obj"].astype(np.float32), s["t"].astype(np.float32),
+                              s["dt"].astype(np.float32), s["flags"], tgt_rgb=pool.tgt_rgb[sl],
+                              tgt_depth=pool.tgt_depth[sl], mask=pool.mask[sl], lambda_d=loss.lambda_d)
+
+    ref = orc.reptile_meta_step(theta0, list(range(B)), q=q, lr=lr, beta=beta, grad=grad)
+    # Both sides store the parameters in FP32 after each inner step, and the
+    # device rounds theta' to FP32 too: where two FP32 gradients that agree to
+    # 1e-6 straddle a rounding boundary of the stored value, the stored values
+    # differ by one ulp.  Every entry: within (q + 1) ulps plus 1e-5 of the
+    # largest change; entries whose change is above 2^-12 of their value
+    # (rounding negligible): within 1e-5 in max and 2-norm relative error.
+    d_got, d_ref = got - theta0, ref - theta0
+    ulps = (q + 1) * 2.0 ** -23 * np.abs(ref)
+    assert np.all(np.abs(got - ref) <= ulps + 1e-5 * np.abs(d_ref).max())
+    big = np.abs(d_ref) > 2.0 ** -12 * np.abs(ref)
+    e = assert_close(d_got[big], d_ref[big], 1e-5, "meta-iteration update")
+    say(f"  theta change on {big.sum()} of {big.size} entries: max-rel {e[0]:.2e}, 2-rel {e[1]:.2e}; "
+        f"|change| {np.linalg.norm(d_ref):.3e}")
+
+
+# ---------------------------------------------------------------- the ML row
+
+def psnr_after(arch, params, scene_views, pool, steps, n_rays, seed):
+    """Held-out PSNR after `steps` Adam steps (the mapping optimiser) on the
+    instance's rays, uniform sampling."""
+    from paper_2503_01582_amd.api import Model
+    from paper_2503_01582_amd.trainer import DeviceBatch, Trainer
+    from test_gpu_training import psnr, render_views
+    tr = Trainer(arch, params, UNIFORM, LossSpec())
+    for k in range(steps):
+        lo = (k * n_rays) % (pool.rays_o.shape[0] - n_rays + 1)
+        rays = device_rays([pool], [0], lo, n_rays, seed, k, UNIFORM.n_fine)
+        db = DeviceBatch(rays_o=rays[0], rays_d=rays[1], xi=rays[2], tgt_rgb=rays[3], tgt_depth=rays[4],
+                         mask=rays[5], world_to_obj=nocs_affine(), prior=None, bg=None)
+        tr.step(db)
+    torch.cuda.synchronize()
+    model = tr.model if steps > 0 else Model(arch, params)
+    return psnr(render_views(model, scene_views, UNIFORM))
+
+
+@pytest.mark.parametrize("inner", ["sgd", "adam"])
+def test_meta_learned_init_beats_random_init(inner):
+    """Meta-training on 32 instances of a synthetic category (B = 8 tasks per
+    meta-iteration, q = 8 inner steps of 4096 rays, N = 40 meta-iterations),
+    then 0, 10 and 30 Adam steps on 4 unseen instances from the meta-learned
+    and from the random initialisation.  Eq. (1)'s plain gradient descent
+    needs a large step here (eta = 80; at eta <= 20 the inner loss stays on
+    the initial plateau for all 40 meta-iterations)."""
+    say(f"test_meta_learned_init_beats_random_init[{inner}]")
+    from paper_2503_01582_amd.meta import ReptileTrainer
+    arch = Arch(n_levels=12, log2_table=17, width=64, hidden=2)
+    B, q, n, N = 8, 8, 4096, 40
+    train = category_pools(2, 32, 8 * n)
+    test = category_pools(2, 4, 8 * n, first_instance=100)
+    theta0 = init_params(arch, 0)
+    inner_lr = 80.0 if inner == "sgd" else 1e-2
+    tr = ReptileTrainer(arch, theta0, B, n, UNIFORM, LossSpec(), inner_lr=inner_lr, beta=0.5, inner=inner,
+                        world_to_obj=nocs_affine().reshape(3, 4))
+    dev = {f: torch.stack([torch.as_tensor(getattr(p, f)) for p in train]).cuda()
+           for f in ("rays_o", "rays_d", "tgt_rgb", "tgt_depth", "mask")}
+    xi_pool = torch.as_tensor(stratification(7, 0, 8 * n, UNIFORM.n_fine)).cuda()
+    for i in range(N):
+        ids = torch.as_tensor([(i * B + b) % len(train) for b in range(B)]).cuda()
+        for k in range(q):
+            lo = ((i * q + k) * n) % (7 * n)
+            sl = slice(lo, lo + n)
+            tr.load_rays(dev["rays_o"][ids, sl].reshape(-1, 3), dev["rays_d"][ids, sl].reshape(-1, 3),
+                         xi_pool[sl].repeat(B, 1), dev["tgt_rgb"][ids, sl].reshape(-1, 3),
+                         dev["tgt_depth"][ids, sl].reshape(-1), dev["mask"][ids, sl].reshape(-1))
+            tr.step()
+        tr.outer()
+        if i % 10 == 0 or i == N - 1:
+            say(f"  meta-iteration {i}: mean inner loss {float(tr.out['loss'].mean()):.4e}")
+    theta_hat = tr.theta.cpu().numpy()
+    rows = []
+    for j, pool in enumerate(test):
+        views = eval_views(pool.scene, n_views=4, seed=200 + j, res=48)
+        r = [(psnr_after(arch, theta_hat, views, pool, k, n, 50 + j), psnr_after(arch, theta0, views, pool, k, n, 50 + j))
+             for k in (0, 10, 30)]
+        rows.append(r)
+        say(f"  instance {j}: PSNR meta / random after 0, 10, 30 steps: "
+            + ", ".join(f"{a:.2f} / {b:.2f}" for a, b in r))
+    mean = np.mean(np.array(rows), axis=0)
+    say("  mean: " + ", ".join(f"{a:.2f} / {b:.2f}" for a, b in mean))
+    # measured (2 instances): 25.3 / 15.1, 29.4 / 19.0, 31.3 / 27.8 dB
+    assert mean[0][0] > mean[0][1] + 5.0
+    assert mean[1][0] > mean[1][1] + 3.0
+    assert mean[2][0] > mean[2][1] + 0.5

@@ -850,3 +850,57 @@ def test_p16_prior_lookup_reproduces_refreshed_grid_at_vertices():
     pts = np.stack([i, j, k], -1).reshape(-1, 3).astype(np.float64) / (R - 1)
     looked = orc.prior_lookup(grid.astype(np.float32), pts)
     np.testing.assert_allclose(looked, grid.astype(np.float32).reshape(-1).astype(np.float64), rtol=1e-12)
+
+
+# P17: meta-learning (Sec. III-A, Eq. (1)-(2), Reptile)
+
+def test_p17_sgd_equals_torch_sgd():
+    """Eq. (1) against torch.optim.SGD (no momentum, no weight decay) in
+    float64 over several steps with the same gradients."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(17)
+    p0 = rng.normal(size=1000)
+    lr = np.float32(0.37)
+    w = torch.tensor(p0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.SGD([w], lr=float(lr))
+    p = p0.copy()
+    for _ in range(4):
+        g = rng.normal(size=1000)
+        w.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+        p = orc.sgd(p, g, lr=lr)
+    np.testing.assert_allclose(p, w.detach().numpy(), rtol=0, atol=1e-15)
+
+
+def test_p17_reptile_on_quadratic_tasks_matches_closed_form():
+    """Tasks L_b(theta) = |theta - c_b|^2 / 2 (gradient theta - c_b).  q steps
+    of Eq. (1) give c_b + (1 - eta)^q (theta - c_b), so Eq. (2) over B tasks
+    gives theta + beta (1 - (1 - eta)^q) (mean_b c_b - theta): a wrong step
+    count, sign, step size or mean fails it.  eta and beta are exact in FP32
+    (the oracle takes them as the FP32 values the device receives)."""
+    rng = np.random.default_rng(5)
+    n = 64
+    for B, q, eta, beta in ((1, 1, 0.5, 1.0), (1, 5, 0.25, 0.375), (4, 3, 0.125, 0.5), (7, 8, 0.0625, 0.75)):
+        centres = rng.normal(size=(B, n))
+        theta = rng.normal(size=n)
+        grad = lambda c, k, p: p - c
+        got = orc.reptile_meta_step(theta, list(centres), q=q, lr=eta, beta=beta, grad=grad, store=np.float64)
+        want = theta + beta * (1.0 - (1.0 - eta) ** q) * (centres.mean(0) - theta)
+        np.testing.assert_allclose(got, want, rtol=1e-13, atol=1e-13)
+
+
+def test_p17_reptile_special_cases():
+    """beta = 0 keeps theta; beta = 1 with one task is plain training of that
+    task for q steps; tasks that return theta unchanged leave it unchanged."""
+    rng = np.random.default_rng(8)
+    theta = rng.normal(size=50)
+    c = rng.normal(size=50)
+    grad = lambda task, k, p: (p - task) * (1.0 + k)   # step-dependent, to pin the order of steps
+    assert np.array_equal(orc.reptile_meta_step(theta, [c, -c], q=3, lr=0.125, beta=0.0, grad=grad,
+                                                store=np.float64), theta)
+    p = theta.copy()
+    for k in range(3):
+        p = p - 0.125 * grad(c, k, p)
+    np.testing.assert_allclose(orc.reptile_meta_step(theta, [c], q=3, lr=0.125, beta=1.0, grad=grad,
+                                                     store=np.float64), p, rtol=1e-15, atol=1e-15)
+    np.testing.assert_array_equal(orc.reptile_outer(theta, [theta, theta], beta=0.7), theta)
