@@ -80,6 +80,7 @@ def lib():
         L.orc_encode.argtypes = [C.POINTER(OrcArch), _f32p, _f32p, C.c_int64, _f64p, _i32p, _f64p]
         L.orc_mlp_fwd.argtypes = [C.POINTER(OrcArch), _f32p, _f64p, C.c_int64, _f64p]
         L.orc_prior_refresh.argtypes = [C.POINTER(OrcArch), _f32p, C.c_int32, _f64p]
+        L.orc_canonical_yaw.argtypes = [_f32p, C.c_int64, _f32p, C.c_int32, C.c_int32, _f64p, _f64p, _f64p, _i32p]
         L.orc_round16_array.argtypes = [_f64p, C.c_int64, C.c_int32, _f64p]
         L.orc_composite_fwd.argtypes = [C.c_int64, C.c_int32, _f64p, _f64p, _f64p, _f64p, _f64p,
                                         _f64p, _f64p, _f64p, _f64p, _f64p]
@@ -236,6 +237,19 @@ def prior_refresh(arch, params, R, emulate=False):
     out = np.empty((R, R, R), np.float64)
     lib().orc_prior_refresh(C.byref(make_arch(arch, emulate)), _p(params, _f32p), R, _p(out, _f64p))
     return out
+
+
+def canonical_yaw(points, prior, n_yaw):
+    """Eq. (3): scores [K] of the yaws 2 pi k / K, the extents and centres
+    [K, 3] of the rotated cloud, and the first index of largest score."""
+    points = _f32(points).reshape(-1, 3)
+    prior = _f32(prior)
+    K = int(n_yaw)
+    scores, ext, cen = np.empty(K), np.empty((K, 3)), np.empty((K, 3))
+    best = np.zeros(1, np.int32)
+    lib().orc_canonical_yaw(_p(points, _f32p), points.shape[0], _p(prior, _f32p), prior.shape[0], K,
+                            _p(scores, _f64p), _p(ext, _f64p), _p(cen, _f64p), _p(best, _i32p))
+    return dict(scores=scores, extents=ext, centers=cen, best=int(best[0]))
 
 
 def round16(x, dtype: str):

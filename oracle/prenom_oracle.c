@@ -522,6 +522,55 @@ void orc_prior_refresh(const orc_arch* a, const float* params, int32_t R, double
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Canonical yaw (Sec. III-B, "Object State Canonicalization", Eq. (3)).    */
+/* The object stands on the ground (z up), so only the yaw is searched.     */
+/* For K yaws gamma_k = 2 pi k / K the cloud is rotated about z,            */
+/* P_gamma = Rz(gamma) P; its extents S (max - min per axis) and their      */
+/* midpoint C normalise it into the unit cube, Pn = (P_gamma - C) / S + 1/2 */
+/* (an axis of zero extent maps to 1/2); the score of gamma_k is the sum of */
+/* the prior's trilinear density over the normalised points, and the       */
+/* search returns the first k of largest score.                             */
+/* ------------------------------------------------------------------------ */
+void orc_canonical_yaw(const float* pts, int64_t n, const float* F, int32_t R, int32_t K, double* scores,
+                       double* extents, double* centers, int32_t* best)
+{
+#pragma omp parallel for schedule(static)
+    for (int k = 0; k < K; ++k) {
+        const double g = 2.0 * 3.14159265358979323846 * (double)k / (double)K;
+        const double c = cos(g), s = sin(g);
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int64_t j = 0; j < n; ++j) {
+            const double x = pts[3 * j], y = pts[3 * j + 1];
+            const double q[3] = {c * x - s * y, s * x + c * y, (double)pts[3 * j + 2]};
+            for (int a = 0; a < 3; ++a) {
+                if (q[a] < lo[a]) lo[a] = q[a];
+                if (q[a] > hi[a]) hi[a] = q[a];
+            }
+        }
+        double S[3], C[3];
+        for (int a = 0; a < 3; ++a) {
+            S[a] = hi[a] - lo[a];
+            C[a] = 0.5 * (hi[a] + lo[a]);
+            extents[3 * k + a] = S[a];
+            centers[3 * k + a] = C[a];
+        }
+        double sum = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            const double x = pts[3 * j], y = pts[3 * j + 1];
+            const double q[3] = {c * x - s * y, s * x + c * y, (double)pts[3 * j + 2]};
+            double u[3];
+            for (int a = 0; a < 3; ++a) u[a] = S[a] > 0.0 ? (q[a] - C[a]) / S[a] + 0.5 : 0.5;
+            sum += orc_prior_at(F, R, u);
+        }
+        scores[k] = sum;
+    }
+    int b = 0;
+    for (int k = 1; k < K; ++k)
+        if (scores[k] > scores[b]) b = k;
+    *best = b;
+}
+
 static double orc_sigmoid(double z) { return 1.0 / (1.0 + exp(-z)); }
 
 /* ------------------------------------------------------------------------ */

@@ -904,3 +904,94 @@ def test_p17_reptile_special_cases():
     np.testing.assert_allclose(orc.reptile_meta_step(theta, [c], q=3, lr=0.125, beta=1.0, grad=grad,
                                                      store=np.float64), p, rtol=1e-15, atol=1e-15)
     np.testing.assert_array_equal(orc.reptile_outer(theta, [theta, theta], beta=0.7), theta)
+
+
+# P18: canonical yaw (Sec. III-B, "Object State Canonicalization", Eq. (3))
+
+def l_shape_points(rng, n):
+    """Uniform points in an L-shaped solid with no yaw symmetry: the bar
+    [-0.5, 0.5] x [-0.2, 0.2] x [-0.3, 0.3] plus the arm
+    [0.2, 0.5] x [0.2, 0.5] x [-0.3, 0.3]."""
+    out = []
+    while sum(len(o) for o in out) < n:
+        p = rng.uniform([-0.5, -0.2, -0.3], [0.5, 0.5, 0.3], (4 * n, 3))
+        keep = (p[:, 1] <= 0.2) | (p[:, 0] >= 0.2)
+        out.append(p[keep])
+    return np.concatenate(out)[:n]
+
+
+def l_shape_prior(R=32):
+    """Occupancy of the L-shape on the vertices of its own extents box mapped
+    onto the unit cube (u = (p - lo) / S), the normalisation Eq. (3) applies."""
+    lo, hi = np.array([-0.5, -0.2, -0.3]), np.array([0.5, 0.5, 0.3])
+    g = np.arange(R) / (R - 1)
+    z, y, x = np.meshgrid(g, g, g, indexing="ij")
+    p = lo + np.stack([x, y, z], -1) * (hi - lo)
+    occ = (p[..., 1] <= 0.2 + 1e-9) | (p[..., 0] >= 0.2 - 1e-9)
+    return occ.astype(np.float32)
+
+
+def rot_z(g):
+    c, s = math.cos(g), math.sin(g)
+    return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+
+
+@pytest.mark.parametrize("k0", [0, 7, 29, 50])
+def test_p18_recovers_a_known_yaw(k0):
+    """The L-shape's cloud turned by -gamma_k0, moved and scaled: the search
+    over K = 72 yaws returns k0 (rotating by gamma_k0 brings it back)."""
+    rng = np.random.default_rng(k0)
+    K = 72
+    P = l_shape_points(rng, 4000) @ rot_z(-2 * math.pi * k0 / K).T
+    P = (P * 1.7 + np.array([3.0, -2.0, 0.5])).astype(np.float32)
+    r = orc.canonical_yaw(P, l_shape_prior(), K)
+    assert r["best"] == k0
+    s = np.sort(r["scores"])
+    assert s[-1] > 1.01 * s[-2]            # a clear maximum (measured: 1.7% above the next)
+    np.testing.assert_allclose(r["extents"][k0], [1.7, 1.19, 1.02], rtol=2e-3)
+
+
+def test_p18_hand_worked_affine_prior():
+    """F[k][j][i] = i, so F(u) = (R - 1) u_x exactly.  Points x = 0, 1, 3 on
+    the x axis (y = z = 0: zero extents, normalised to 1/2).  gamma = 0:
+    u_x = 0, 1/3, 1, score (R - 1) 4/3.  gamma = pi: x' = 0, -1, -3,
+    u_x = 1, 2/3, 0, score (R - 1) 5/3.  K = 2, so the best index is 1."""
+    R = 9
+    F = np.broadcast_to(np.arange(R, dtype=np.float32), (R, R, R)).copy()
+    P = np.array([[0, 0, 0], [1, 0, 0], [3, 0, 0]], np.float32)
+    r = orc.canonical_yaw(P, F, 2)
+    np.testing.assert_allclose(r["scores"], [(R - 1) * 4 / 3, (R - 1) * 5 / 3], rtol=1e-14)
+    assert r["best"] == 1
+    np.testing.assert_allclose(r["extents"][0], [3, 0, 0], atol=1e-15)
+    np.testing.assert_allclose(r["centers"][0], [1.5, 0, 0], atol=1e-15)
+
+
+def test_p18_invariances():
+    """Scores do not change when the cloud is moved or scaled uniformly (by a
+    power of two: exact in FP32); an exact quarter turn of the cloud shifts
+    the score vector by K/4 indices; a constant prior c scores c |P| at every
+    yaw."""
+    rng = np.random.default_rng(4)
+    K = 48
+    P = rng.normal(size=(500, 3)).astype(np.float32) * np.float32([0.4, 0.2, 0.3])
+    F = rng.uniform(0, 1, (17, 17, 17)).astype(np.float32)
+    base = orc.canonical_yaw(P, F, K)["scores"]
+    np.testing.assert_allclose(orc.canonical_yaw(P * np.float32(4), F, K)["scores"], base, rtol=1e-12)
+    np.testing.assert_allclose(orc.canonical_yaw(P + np.float32([5, -3, 2]), F, K)["scores"], base, rtol=1e-6)
+    quarter = np.stack([-P[:, 1], P[:, 0], P[:, 2]], 1)       # exact 90 degree turn
+    # the turned cloud at gamma_k is the original at gamma_k + pi / 2
+    np.testing.assert_allclose(orc.canonical_yaw(quarter, F, K)["scores"], np.roll(base, -(K // 4)), rtol=1e-12)
+    const = orc.canonical_yaw(P, np.full((5, 5, 5), 0.75, np.float32), K)["scores"]
+    np.testing.assert_allclose(const, 0.75 * len(P), rtol=1e-14)
+
+
+def test_p18_degenerate_cloud_ties_to_first_yaw():
+    """One repeated point: every extent is 0, every point normalises to the
+    cube centre, all scores equal F(1/2, 1/2, 1/2) |P|, and the first yaw wins."""
+    F = np.random.default_rng(2).uniform(0, 1, (5, 5, 5)).astype(np.float32)
+    P = np.tile(np.float32([[0.3, -0.1, 0.2]]), (10, 1))
+    r = orc.canonical_yaw(P, F, 16)
+    centre = orc.prior_lookup(F, np.array([[0.5, 0.5, 0.5]]))[0]
+    np.testing.assert_allclose(r["scores"], 10 * centre, rtol=1e-15)
+    assert r["best"] == 0
+    assert np.all(r["extents"] == 0)
