@@ -9,7 +9,8 @@ Workloads (--workload):
           prenom_render_fwd (fused loss) + prenom_render_bwd +
           prenom_adam_step on resident inputs.  Also timed, outside the
           step: the prior refresh over the 64^3 grid, which runs once every
-          50 steps.
+          50 steps, and the canonical yaw search (360 yaws) of the object's
+          depth cloud, which runs once per object.
   autograd the differentiation configuration: the prior scene at 2^18 rays
           x 64 samples, colour + 0.1 x depth MSE (1 cm depth noise) in torch
           on top of PrenomRender, Adam; store vs recompute, with peak memory.
@@ -47,6 +48,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_MFMA_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix
 LOWP_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 / FP16 matrix
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 METRIC = "training rays/s (fwd+bwd) vs plain FP32 at equal PSNR; % HBM/MFMA roofline"
 # The hash-table gradient is one operation run as six dependent kernels
 # (k_scatter_count, _level_max, _scan_blocks, _scan_tiles, _place, _reduce);
@@ -225,6 +227,35 @@ def run_refresh(tr, arch, ms_per_step, R=64, reps=20, m=50):
                 amortised_share=round(share, 5), dominant=roof, kernels=kern)
 
 
+YAW_OPS = 71  # FP64 operations per (point, yaw): turn (x2), extents, normalise, trilinear weights and sum
+
+
+def run_canon(world, batch, K=360, reps=20):
+    """The canonical yaw search (Eq. (3)) on the object's depth cloud (the
+    batch's object rays at their true depth, in the object frame) against
+    the prior grid, timed on its own; FP64 ALU work counted as YAW_OPS per
+    (point, yaw)."""
+    import torch
+    from paper_2503_01582_amd import api
+    m = batch.mask == 1
+    P = (batch.rays_o[m] + batch.tgt_depth[m, None] * batch.rays_d[m]).astype(np.float32)
+    pts = torch.as_tensor(P).cuda()
+    prior = torch.as_tensor(world.prior).cuda()
+    api.prenom_canonical_yaw(pts, prior, K)
+    torch.cuda.synchronize()
+    log(f"bench: canonical yaw search, {P.shape[0]} points x {K} yaws, {reps} calls")
+    api.prenom_profile_begin()
+    ms = timed_loop(lambda: api.prenom_canonical_yaw(pts, prior, K), reps) / reps
+    kt = api.prenom_profile_end()
+    kms = kt["k_canonical_yaw"][1] / kt["k_canonical_yaw"][0]
+    tflops = YAW_OPS * P.shape[0] * K / (kms * 1e-3) / 1e12
+    log(f"bench: yaw search {ms:.3f} ms per call (kernels {kms:.3f} ms), {tflops:.2f} TFLOP/s FP64")
+    return dict(points=int(P.shape[0]), yaws=K, ms=round(ms, 4), kernel_ms=round(kms, 4),
+                lookups_per_s=round(P.shape[0] * K / (kms * 1e-3), 1),
+                roofline=dict(bound="alu", achieved=round(tflops, 3), peak=FP64_VECTOR_PEAK_TFLOPS, unit="TFLOP/s",
+                              frac=round(tflops / FP64_VECTOR_PEAK_TFLOPS, 4)))
+
+
 def run_prior(args):
     import torch
     from paper_2503_01582_amd import api
@@ -269,7 +300,8 @@ def run_prior(args):
                   hash_levels=arch.n_levels, log2_table=arch.log2_table, mlp_width=arch.width,
                   mlp_hidden=arch.hidden, samples_per_s=round(value * S, 1))
     refresh = run_refresh(tr, arch, ms_per_step)
-    return value, ms_per_step, "fp32", config, roofline, kern, cpu, dict(prior_refresh=refresh)
+    canon = run_canon(world, batch)
+    return value, ms_per_step, "fp32", config, roofline, kern, cpu, dict(prior_refresh=refresh, canonical_yaw=canon)
 
 
 def held_between_passes(tr, db):

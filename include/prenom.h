@@ -275,6 +275,34 @@ prenom_status prenom_encode(const prenom_arch* arch, const float* table, const f
                             float* features, int32_t* corner_idx, void* stream);
 
 /* ------------------------------------------------------------------------
+ * prenom_canonical_yaw -- the object's yaw in the category's canonical frame
+ * (Sec. III-B, "Object State Canonicalization", Eq. (3)).  Objects stand on
+ * the ground (z up), so only the yaw is searched: for each of the n_yaw
+ * yaws gamma_k = 2 pi k / n_yaw the cloud is turned about z, P_k = Rz(gamma_k) P,
+ * normalised into the unit cube by its extents,
+ *   Pn = (P_k - C_k) / S_k + 1/2   (S_k = max - min, C_k = (max + min) / 2
+ *                                   per axis; an axis with S_k = 0 maps to 1/2),
+ * and scored by the sum over its points of the prior's trilinear density
+ * (the lookup of prenom_sample).  best = the first k of largest score.
+ *   points  [n_points][3] device FP32, in the object's frame (any origin).
+ *   prior   [prior_res]^3 device FP32 density grid (x fastest).
+ *   scores  [n_yaw], extents and centers [n_yaw][3]: device FP64 outputs.
+ *   best    device int32.
+ * FP64 arithmetic; sums in a fixed order (results do not depend on
+ * scheduling).  1 <= n_points <= PRENOM_MAX_YAW_POINTS, 1 <= n_yaw <=
+ * PRENOM_MAX_YAWS, 2 <= prior_res <= PRENOM_MAX_PRIOR_RES; workspace: >=
+ * prenom_canonical_yaw_workspace_size bytes (0 for invalid sizes), 256-byte
+ * aligned.  Errors: PRENOM_ERR_SHAPE, PRENOM_ERR_INVALID_ARG,
+ * PRENOM_ERR_WORKSPACE, checked before any launch.
+ * ---------------------------------------------------------------------- */
+#define PRENOM_MAX_YAWS 4096
+#define PRENOM_MAX_YAW_POINTS (((int64_t)1) << 28)
+size_t prenom_canonical_yaw_workspace_size(int64_t n_points, int32_t n_yaw);
+prenom_status prenom_canonical_yaw(const float* points, int64_t n_points, const float* prior, int32_t prior_res,
+                                   int32_t n_yaw, double* scores, double* extents, double* centers, int32_t* best,
+                                   void* workspace, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batched training of many objects (Fig. 1 and Sec. IV-A: every object NeRF
  * of the map trains concurrently, each with its own category architecture
  * alpha, prior and pose).  Where the method gives each object its own host

@@ -137,6 +137,11 @@ def lib():
         L.prenom_batch_adam_step.argtypes = [PB, C.POINTER(PrenomAdamCfg), _vp]
         L.prenom_batch_refresh_lowp.restype = C.c_int
         L.prenom_batch_refresh_lowp.argtypes = [PB, _vp]
+        L.prenom_canonical_yaw_workspace_size.restype = C.c_size_t
+        L.prenom_canonical_yaw_workspace_size.argtypes = [C.c_int64, C.c_int32]
+        L.prenom_canonical_yaw.restype = C.c_int
+        L.prenom_canonical_yaw.argtypes = [_vp, C.c_int64, _vp, C.c_int32, C.c_int32, _vp, _vp, _vp, _vp, _vp,
+                                           C.c_size_t, _vp]
         L.prenom_sgd_step.restype = C.c_int
         L.prenom_sgd_step.argtypes = [C.POINTER(PrenomModel), C.POINTER(PrenomSgdCfg), _vp]
         L.prenom_batch_sgd_step.restype = C.c_int

@@ -283,6 +283,34 @@ def prenom_reptile_update(theta: torch.Tensor, tasks: torch.Tensor, n_params: in
     L.check(st, "prenom_reptile_update")
 
 
+def prenom_canonical_yaw(points: torch.Tensor, prior: torch.Tensor, n_yaw: int = 360) -> dict:
+    """Eq. (3): scores [n_yaw] of the yaws 2 pi k / n_yaw, the extents and
+    centres [n_yaw, 3] of the turned cloud (FP64, device) and the best index
+    (device int32 [1])."""
+    _dev(points, torch.float32, "points")
+    _dev(prior, torch.float32, "prior")
+    if points.dim() != 2 or points.shape[1] != 3:
+        raise ValueError("points must be [n, 3]")
+    if prior.dim() != 3 or not (prior.shape[0] == prior.shape[1] == prior.shape[2]):
+        raise ValueError("prior must be [R, R, R]")
+    n = points.shape[0]
+    need = L.lib().prenom_canonical_yaw_workspace_size(n, n_yaw)
+    if need == 0:
+        raise ValueError(f"invalid sizes: {n} points, {n_yaw} yaws")
+    dev = points.device
+    ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    off = (-ws.data_ptr()) % 256
+    out = dict(scores=torch.empty(n_yaw, dtype=torch.float64, device=dev),
+               extents=torch.empty((n_yaw, 3), dtype=torch.float64, device=dev),
+               centers=torch.empty((n_yaw, 3), dtype=torch.float64, device=dev),
+               best=torch.empty(1, dtype=torch.int32, device=dev))
+    st = L.lib().prenom_canonical_yaw(_ptr(points), n, _ptr(prior), prior.shape[0], n_yaw, _ptr(out["scores"]),
+                                      _ptr(out["extents"]), _ptr(out["centers"]), _ptr(out["best"]),
+                                      C.c_void_p(ws.data_ptr() + off), need, _stream())
+    L.check(st, "prenom_canonical_yaw")
+    return out
+
+
 def prenom_prior_refresh(model: Model, R: int = 64, out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """The model's density grid [R, R, R] (indexed [k][j][i], x fastest):
     sigma at the vertices (i, j, k) / (R - 1), ready to pass to prenom_sample

@@ -613,6 +613,45 @@ prenom_status prenom_reptile_update(float* theta, float* tasks, int64_t n_params
     return PRENOM_OK;
 }
 
+size_t prenom_canonical_yaw_workspace_size(int64_t n_points, int32_t n_yaw)
+{
+    if (n_points < 1 || n_points > PRENOM_MAX_YAW_POINTS || n_yaw < 1 || n_yaw > PRENOM_MAX_YAWS) return 0;
+    return align_up((size_t)n_yaw * (size_t)yaw_chunks(n_points) * 7 * sizeof(double));
+}
+
+prenom_status prenom_canonical_yaw(const float* points, int64_t n_points, const float* prior, int32_t prior_res,
+                                   int32_t n_yaw, double* scores, double* extents, double* centers, int32_t* best,
+                                   void* workspace, size_t ws_bytes, void* stream)
+{
+    if (n_points < 1 || n_points > PRENOM_MAX_YAW_POINTS)
+        return fail(PRENOM_ERR_SHAPE, "n_points %lld outside [1, %lld]", (long long)n_points,
+                    (long long)PRENOM_MAX_YAW_POINTS);
+    if (n_yaw < 1 || n_yaw > PRENOM_MAX_YAWS) return fail(PRENOM_ERR_SHAPE, "n_yaw %d outside [1, %d]", n_yaw, PRENOM_MAX_YAWS);
+    if (prior_res < 2 || prior_res > PRENOM_MAX_PRIOR_RES)
+        return fail(PRENOM_ERR_SHAPE, "prior_res %d outside [2, %d]", prior_res, PRENOM_MAX_PRIOR_RES);
+    if (!points || !prior || !scores || !extents || !centers || !best)
+        return fail(PRENOM_ERR_INVALID_ARG, "NULL array argument");
+    const int64_t C = yaw_chunks(n_points);
+    const size_t need = prenom_canonical_yaw_workspace_size(n_points, n_yaw);
+    if (!workspace || !aligned(workspace, kAlign)) return fail(PRENOM_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
+    if (ws_bytes < need) return fail(PRENOM_ERR_WORKSPACE, "workspace %zu bytes < %zu", ws_bytes, need);
+    YawArgs a{};
+    a.pts = points;
+    a.n = n_points;
+    a.F = prior;
+    a.R = prior_res;
+    a.K = n_yaw;
+    a.n_chunks = C;
+    a.part_ext = at<double>(workspace, 0);
+    a.part_sum = a.part_ext + (int64_t)n_yaw * C * 6;
+    a.scores = scores;
+    a.extents = extents;
+    a.centers = centers;
+    a.best = best;
+    PRENOM_LAUNCH("k_canonical_yaw", (hipStream_t)stream, launch_canonical_yaw(a, (hipStream_t)stream));
+    return PRENOM_OK;
+}
+
 prenom_status prenom_refresh_lowp(const prenom_model* model, void* stream)
 {
     prenom_status st = check_model(model, false);

@@ -350,4 +350,58 @@ struct ReptileArgs {
 };
 hipError_t launch_reptile(const ReptileArgs& a, hipStream_t s);
 
+// Trilinear, vertex-aligned lookup of a density grid F [R][R][R] (x fastest;
+// value F[i] at i/(R-1)), each coordinate clamped to [0, 1] (NaN to 0); FP64
+// without contraction, the sampler's prior lookup (Eq. (4)) and the canonical
+// yaw score (Eq. (3)).
+__device__ inline double prior_at(const float* __restrict__ F, int R, const double xin[3])
+{
+#pragma clang fp contract(off)
+    int i0[3];
+    double f[3];
+    for (int a = 0; a < 3; ++a) {
+        double x = xin[a];
+        x = x >= 0.0 ? x : 0.0;  // also maps NaN to 0
+        x = x > 1.0 ? 1.0 : x;
+        const double g = x * (double)(R - 1);
+        int i = (int)floor(g);
+        i = i > R - 2 ? R - 2 : i;
+        i0[a] = i;
+        f[a] = g - (double)i;
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+        for (int cy = 0; cy < 2; ++cy)
+#pragma unroll
+            for (int cx = 0; cx < 2; ++cx) {
+                const double wx = cx ? f[0] : 1.0 - f[0];
+                const double wy = cy ? f[1] : 1.0 - f[1];
+                const double wz = cz ? f[2] : 1.0 - f[2];
+                const double w = wx * wy * wz;
+                const int64_t idx = (int64_t)(i0[0] + cx) +
+                                    (int64_t)R * ((int64_t)(i0[1] + cy) + (int64_t)R * (i0[2] + cz));
+                s += w * (double)F[idx];
+            }
+    return s;
+}
+
+// Canonical yaw search (Eq. (3)); workspace: per (yaw, chunk) extents and sums.
+struct YawArgs {
+    const float* pts;   // [n][3]
+    int64_t n;
+    const float* F;     // [R][R][R]
+    int32_t R, K;
+    int64_t n_chunks;
+    double* part_ext;   // [K][n_chunks][6]: min xyz, max xyz
+    double* part_sum;   // [K][n_chunks]
+    double* scores;     // [K]
+    double* extents;    // [K][3]
+    double* centers;    // [K][3]
+    int32_t* best;
+};
+int64_t yaw_chunks(int64_t n);
+hipError_t launch_canonical_yaw(const YawArgs& a, hipStream_t s);
+
 }  // namespace prenom

@@ -28,39 +28,6 @@ namespace prenom {
 namespace {
 
 
-// Trilinear, vertex-aligned lookup (value F[i] at i/(R-1)), x clamped.
-__device__ double prior_at(const float* __restrict__ F, int R, const double xin[3])
-{
-    int i0[3];
-    double f[3];
-    for (int a = 0; a < 3; ++a) {
-        double x = xin[a];
-        x = x >= 0.0 ? x : 0.0;  // also maps NaN to 0
-        x = x > 1.0 ? 1.0 : x;
-        const double g = x * (double)(R - 1);
-        int i = (int)floor(g);
-        i = i > R - 2 ? R - 2 : i;
-        i0[a] = i;
-        f[a] = g - (double)i;
-    }
-    double s = 0.0;
-#pragma unroll
-    for (int cz = 0; cz < 2; ++cz)
-#pragma unroll
-        for (int cy = 0; cy < 2; ++cy)
-#pragma unroll
-            for (int cx = 0; cx < 2; ++cx) {
-                const double wx = cx ? f[0] : 1.0 - f[0];
-                const double wy = cy ? f[1] : 1.0 - f[1];
-                const double wz = cz ? f[2] : 1.0 - f[2];
-                const double w = wx * wy * wz;
-                const int64_t idx = (int64_t)(i0[0] + cx) +
-                                    (int64_t)R * ((int64_t)(i0[1] + cy) + (int64_t)R * (i0[2] + cz));
-                s += w * (double)F[idx];
-            }
-    return s;
-}
-
 struct RayFrame {
     double o[3], d[3];
     double tn, tf, len, delta;
