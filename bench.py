@@ -299,9 +299,10 @@ def run_prior(args):
                   samples_per_ray=S, n_coarse=batch.sample.n_coarse, n_fine=batch.sample.n_fine,
                   hash_levels=arch.n_levels, log2_table=arch.log2_table, mlp_width=arch.width,
                   mlp_hidden=arch.hidden, samples_per_s=round(value * S, 1))
-    refresh = run_refresh(tr, arch, ms_per_step)
-    canon = run_canon(world, batch)
-    return value, ms_per_step, "fp32", config, roofline, kern, cpu, dict(prior_refresh=refresh, canonical_yaw=canon)
+    extra = {}
+    if not args.no_extras:
+        extra = dict(prior_refresh=run_refresh(tr, arch, ms_per_step), canonical_yaw=run_canon(world, batch))
+    return value, ms_per_step, "fp32", config, roofline, kern, cpu, extra
 
 
 def held_between_passes(tr, db):
@@ -546,6 +547,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sequential", action="store_true", help="batch workloads: skip the sequential comparison")
     ap.add_argument("--no-tune", action="store_true", help="batch workloads: library default tiles if none cached")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="prior workload: skip the prior-refresh and yaw-search timings after the step (so that a "
+                         "counter run sees only the step's launches)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy 1 GiB device-to-device once (a kernel of known "
                          "traffic for scaling hardware byte counters)")
