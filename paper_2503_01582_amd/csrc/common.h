@@ -31,16 +31,19 @@ __device__ __forceinline__ uint32_t corner_row(bool dense, uint32_t side, uint32
 }
 
 // Cell of x on a lattice of resolution N: c = min(floor(x N), N - 1) of the
-// exact product (an FP32 x times an integer below 2^20 is exact in FP64), and
-// the local coordinate f = x N - c rounded to FP32.
+// exact product, and the local coordinate f = x N - c rounded to FP32.  In
+// FP32: N < 2^20 is exact, and rounding x N to nearest never takes it below
+// an integer it reaches, so floor of the rounded product is the exact floor
+// or one above it; fma(x, N, -c) is the exact x N - c rounded once, so its
+// sign tells which, and after the clamp it is f itself.
 __device__ __forceinline__ void lattice_cell(float x, int N, uint32_t& c, float& f)
 {
-    const double g = (double)x * (double)N;
-    int ci = (int)floor(g);
-    ci = ci > N - 1 ? N - 1 : ci;
-    ci = ci < 0 ? 0 : ci;
-    c = (uint32_t)ci;
-    f = (float)(g - (double)ci);
+    const float Nf = (float)N;
+    float cf = floorf(x * Nf);
+    if (fmaf(x, Nf, -cf) < 0.0f) cf -= 1.0f;
+    cf = fminf(fmaxf(cf, 0.0f), (float)(N - 1));
+    c = (uint32_t)cf;
+    f = fmaf(x, Nf, -cf);
 }
 
 // The 8 cell corners of x on level l: table rows and trilinear weights
@@ -67,10 +70,25 @@ __device__ __forceinline__ void level_corners(const GridInfo& g, int l, float x0
     lattice_cell(x0, N, cx, fx);
     lattice_cell(x1, N, cy, fy);
     lattice_cell(x2, N, cz, fz);
+    // Rows of the 8 corners from two products per level (corner_row of each
+    // corner, strength-reduced): (c + 1) P = c P + P modulo 2^32 for the hash,
+    // and the 1:1 row of a corner is the cell's row plus 1, side or side^2.
+    uint32_t r0 = 0, ry = 0, rz = 0, hy[2] = {0, 0}, hz[2] = {0, 0};
+    if (dense) {
+        r0 = cx + side * (cy + side * cz);
+        ry = side;
+        rz = side * side;
+    } else {
+        hy[0] = cy * 2654435761u;
+        hy[1] = hy[0] + 2654435761u;
+        hz[0] = cz * 805459861u;
+        hz[1] = hz[0] + 805459861u;
+    }
+    const uint32_t mask = (1u << g.log2_table) - 1u;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
         const uint32_t ex = e & 1, ey = (e >> 1) & 1, ez = (e >> 2) & 1;
-        c.row[e] = corner_row(dense, side, (uint32_t)g.log2_table, cx + ex, cy + ey, cz + ez);
+        c.row[e] = dense ? r0 + ex + (ey ? ry : 0u) + (ez ? rz : 0u) : ((cx + ex) ^ hy[ey] ^ hz[ez]) & mask;
         c.w[e] = (ex ? fx : 1.0f - fx) * (ey ? fy : 1.0f - fy) * (ez ? fz : 1.0f - fz);
     }
 }
