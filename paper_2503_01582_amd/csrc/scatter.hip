@@ -350,8 +350,7 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
     uint32_t* hist = reinterpret_cast<uint32_t*>(s_val + kRecordsPerBlock);
     uint32_t* seg = hist + nt_lds;
     uint32_t* p_total = seg + nt_lds;
-    uint16_t* s_key = reinterpret_cast<uint16_t*>(p_total + 4);
-    uint16_t* s_tile = s_key + kRecordsPerBlock;
+    uint32_t* s_kt = p_total + 4;  // row within the tile | local tile << 16
     const int64_t item = blockIdx.x;
     const ScatterObj& o = sobj<kMany>(a, obj_of_item<kMany>(a, item));
     int l, bx;
@@ -414,8 +413,7 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
         for (int e = 0; e < 8; ++e) {
             const uint32_t tt = c.row[e] >> kTileBits;
             const uint32_t p = seg[tt] + rank[e];
-            s_key[p] = (uint16_t)(c.row[e] & (kTileRows - 1));
-            s_tile[p] = (uint16_t)tt;
+            s_kt[p] = (c.row[e] & (kTileRows - 1)) | (tt << 16);
             s_val[p] = make_float2(c.w[e] * d.x, c.w[e] * d.y);
         }
     }
@@ -428,15 +426,14 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
 #pragma unroll
     for (int h = 0; h < kPer; h += kHalf) {
         if (h * kPlaceThreads >= (int)total) break;
-        uint32_t tt[kHalf];
+        uint32_t kt[kHalf];
 #pragma unroll
-        for (int k = 0; k < kHalf; ++k)
-            tt[k] = min((uint32_t)s_tile[threadIdx.x + (h + k) * kPlaceThreads], (uint32_t)nt - 1u);
+        for (int k = 0; k < kHalf; ++k) kt[k] = s_kt[threadIdx.x + (h + k) * kPlaceThreads];
 #pragma unroll
         for (int k = 0; k < kHalf; ++k) {
             const uint32_t p = threadIdx.x + (h + k) * kPlaceThreads;
-            const uint64_t dst = gbase[tt[k]] + p;
-            const uint16_t key = s_key[p];
+            const uint64_t dst = gbase[min(kt[k] >> 16, (uint32_t)nt - 1u)] + p;
+            const uint16_t key = (uint16_t)(kt[k] & 0xffffu);
             const float2 v = s_val[p];
             if (p < total) {
                 a.keys[dst] = key;
