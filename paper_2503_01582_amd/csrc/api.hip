@@ -279,6 +279,32 @@ prenom_status check_render(const prenom_model* model, const prenom_render_cfg* c
     return PRENOM_OK;
 }
 
+// Workspace of prenom_prior_refresh, for one chunk of at most kPriorChunk
+// vertices: features [L][chunk][2], then head outputs [chunk][4].
+constexpr int64_t kPriorChunk = int64_t(1) << 21;
+
+size_t prior_refresh_ws(const prenom_arch* a, int32_t R, size_t* sc_off)
+{
+    const int64_t n = (int64_t)R * R * R;
+    const int64_t c = n < kPriorChunk ? n : kPriorChunk;
+    const size_t y = align_up((size_t)c * a->n_levels * a->n_features * sizeof(float));
+    if (sc_off) *sc_off = y;
+    return y + align_up((size_t)c * 4 * sizeof(float));
+}
+
+// Tile histograms of the training forward, in the workspace's scatter counts.
+TileHist tile_hist(const WsLayout& w, void* workspace)
+{
+    TileHist h{};
+    h.counts = at<uint32_t>(workspace, w.counts);
+    h.n_blocks = w.plan.n_blocks;
+    for (int l = 0; l < w.plan.grid.n_levels; ++l) {
+        h.tiles[l] = w.plan.tiles[l];
+        h.tile_base[l] = w.plan.tile_base[l];
+    }
+    return h;
+}
+
 }  // namespace
 
 extern "C" {
@@ -299,19 +325,6 @@ size_t prenom_workspace_size(const prenom_arch* arch, int64_t n_rays, int32_t n_
 {
     if (check_arch(arch) != PRENOM_OK || n_rays < 0 || n_samples < 1) return 0;
     return ws_layout(arch, n_rays, n_samples).total;
-}
-
-// Workspace of prenom_prior_refresh, for one chunk of at most kPriorChunk
-// vertices: features [L][chunk][2], then head outputs [chunk][4].
-constexpr int64_t kPriorChunk = int64_t(1) << 21;
-
-size_t prior_refresh_ws(const prenom_arch* a, int32_t R, size_t* sc_off)
-{
-    const int64_t n = (int64_t)R * R * R;
-    const int64_t c = n < kPriorChunk ? n : kPriorChunk;
-    const size_t y = align_up((size_t)c * a->n_levels * a->n_features * sizeof(float));
-    if (sc_off) *sc_off = y;
-    return y + align_up((size_t)c * 4 * sizeof(float));
 }
 
 size_t prenom_prior_refresh_workspace_size(const prenom_arch* arch, int32_t R)
@@ -399,8 +412,9 @@ prenom_status prenom_render_fwd(const prenom_model* model, const prenom_render_c
     float* y = at<float>(workspace, w.y);
     float* sc = at<float>(workspace, w.sc);
     const void* tlp = a->table_dtype == PRENOM_F16 ? model->table_lp : nullptr;
+    const TileHist h = tile_hist(w, workspace);
     PRENOM_LAUNCH("k_encode_fwd", s,
-                  launch_encode_samples(g, model->params, tlp, ray_obj, t, n_rays, cfg->n_samples, y, s));
+                  launch_encode_samples(g, model->params, tlp, ray_obj, t, n_rays, cfg->n_samples, y, s, &h));
     const MlpShape m = mlp_shape(a);
     PRENOM_LAUNCH("k_mlp_fwd", s, mlp_fwd_any(m, model->params + table_params(a), y, n_s, sc, at<float>(workspace, w.act), s));
     CompositeArgs c{};
@@ -449,8 +463,9 @@ prenom_status prenom_render_bwd(const prenom_model* model, const prenom_render_c
         // rebuild the features, head outputs and per-ray results render_fwd would have left
         float* y = at<float>(workspace, w.y);
         const void* tlp = a->table_dtype == PRENOM_F16 ? model->table_lp : nullptr;
+        const TileHist h = tile_hist(w, workspace);
         PRENOM_LAUNCH("k_encode_fwd", s, launch_encode_samples(grid_info(a), model->params, tlp, ray_obj, t, n_rays,
-                                                               cfg->n_samples, y, s));
+                                                               cfg->n_samples, y, s, &h));
         PRENOM_LAUNCH("k_mlp_fwd", s, mlp_fwd_any(m, model->params + table_params(a), y, n_s,
                                                   at<float>(workspace, w.sc), at<float>(workspace, w.act), s));
         CompositeArgs f{};
@@ -517,8 +532,10 @@ prenom_status prenom_render_bwd(const prenom_model* model, const prenom_render_c
     sa.work_counter = at<unsigned long long>(workspace, w.work_counter);
     sa.keys = at<uint16_t>(workspace, w.keys);
     sa.vals = at<float2>(workspace, w.vals);
+    sa.n_records = scatter_records(w.plan);
+    sa.fwd_counts = 1;  // render_fwd (or the recompute above) wrote the tile histograms
     for (int ph = 0; ph < kScatterPhases; ++ph)
-        PRENOM_LAUNCH(kScatterPhaseNames[ph], s, launch_scatter_phase(sa, ph, s));
+        PRENOM_LAUNCH(ph == 0 ? "k_scatter_dymax" : kScatterPhaseNames[ph], s, launch_scatter_phase(sa, ph, s));
     return PRENOM_OK;
 }
 

@@ -333,6 +333,8 @@ ScatterArgs scatter_args(const Plan& p, void* ws, const float* ray_obj, const fl
     sa.work_counter = at<unsigned long long>(ws, p.work_counter);
     sa.keys = at<uint16_t>(ws, p.keys);
     sa.vals = at<float2>(ws, p.vals);
+    sa.n_records = p.records;
+    sa.fwd_counts = 0;
     return sa;
 }
 

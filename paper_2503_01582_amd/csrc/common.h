@@ -93,6 +93,64 @@ __device__ __forceinline__ void level_corners(const GridInfo& g, int l, float x0
     }
 }
 
+// ------------------------------------------------------------------ table tiles
+// The hash-table gradient buckets contributions by table tile (2^13 rows),
+// per (level, block of kScatterBlockSamples samples).  The training forward
+// writes the same per-block tile histograms as it encodes (TileHist).
+constexpr int kTileBits = 13;
+constexpr int kTileRows = 1 << kTileBits;
+constexpr int kMaxTilesPerLevel = 1 << (24 - kTileBits);  // T <= 2^24
+constexpr int kScatterBlockSamples = 512;
+// Levels with at most this many tiles have most lanes of a wave in the same
+// tile; their histogram atomics are combined per wave first.
+constexpr int kAggregateTiles = 16;
+
+// Adds 1 to hist[tile] for every active lane and returns the lane's rank
+// among the additions to that tile.  Lanes of the wave that share the tile of
+// the first remaining lane are combined into one LDS atomic issued by that
+// lane (same-address atomics of one instruction would otherwise serialise);
+// after kAggregateRounds such rounds the lanes left use plain LDS atomics, so
+// a wave spread over many tiles does not pay one round per tile.  Every slot
+// comes from an atomic on the same counter, so ranks are distinct whichever
+// way a lane takes.
+constexpr int kAggregateRounds = 2;
+
+__device__ __forceinline__ uint32_t wave_aggregated_add(uint32_t* hist, uint32_t tile)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint64_t remaining = __ballot(1);
+    uint32_t rank = 0;
+    bool placed = false;
+#pragma unroll
+    for (int round = 0; round < kAggregateRounds; ++round) {
+        if (remaining == 0) break;
+        const int leader = __ffsll((unsigned long long)remaining) - 1;
+        const uint32_t lt = __shfl(tile, leader);
+        const uint64_t mask = __ballot(tile == lt);
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&hist[lt], (uint32_t)__popcll(mask));
+        base = __shfl(base, leader);
+        if (tile == lt) {
+            rank = base + (uint32_t)__popcll(mask & lane_lt);
+            placed = true;
+        }
+        remaining &= ~mask;
+    }
+    if (!placed) rank = atomicAdd(&hist[tile], 1u);
+    return rank;
+}
+
+// Tile histograms of one object: counts[(tile_base[l] + i) * n_blocks + b]
+// = contributions of sample block b of level l to tile i of that level.
+struct TileHist {
+    uint32_t* counts;
+    int32_t n_blocks;
+    int32_t pad_;
+    int32_t tiles[PRENOM_MAX_LEVELS];
+    int32_t tile_base[PRENOM_MAX_LEVELS];
+};
+
 // ------------------------------------------------------------------ batches
 // Device descriptor of one object of a batch (offsets index the batch's
 // concatenated arrays; objects own consecutive rays).
@@ -166,9 +224,11 @@ int encode_block_samples();
 
 // Encoding of the rendered samples (positions from rays and t); reads the
 // FP16 table copy when table_f16 is not null, the FP32 tables otherwise.
+// hist (or null): also write the tile histograms of every (level, block of
+// kScatterBlockSamples samples), counting every sample, for the backward.
 hipError_t launch_encode_samples(const GridInfo& g, const float* table, const void* table_f16,
                                  const float* ray_obj, const float* t, int64_t n_rays, int32_t S, float* y,
-                                 hipStream_t s);
+                                 hipStream_t s, const TileHist* hist = nullptr);
 
 // Bucketed scatter-add of the feature gradients into the table gradient.
 // Geometry of one object's scatter: its table tiles and sample blocks, and
@@ -223,10 +283,19 @@ struct ScatterArgs {
     unsigned long long* work_counter;
     uint16_t* keys;         // [records]
     float2* vals;           // [records]
+    int64_t n_records;      // length of keys and vals
+    // 1: counts were written by the training forward over every sample
+    // (TileHist); the first phase then only takes the per-block max |dy|,
+    // place records every sample, and the scan checks that the histograms add
+    // up to n_records (else place and reduce do nothing).  0: the first phase
+    // counts the samples whose dy is not zero.
+    int32_t fwd_counts;
+    int32_t pad2_;
 };
 // The scatter runs as kScatterPhases dependent kernels, launched in order
-// (phase 0 .. kScatterPhases - 1): count, per-level max, scan over blocks,
-// scan over tiles, place, reduce.
+// (phase 0 .. kScatterPhases - 1): count (or, with fwd_counts, the block
+// maxima of |dy| alone), per-level max, scan over blocks, scan over tiles,
+// place, reduce.
 constexpr int kScatterPhases = 6;
 extern const char* const kScatterPhaseNames[kScatterPhases];
 hipError_t launch_scatter_phase(const ScatterArgs& a, int phase, hipStream_t s);

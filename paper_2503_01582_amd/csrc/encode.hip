@@ -156,6 +156,46 @@ __global__ __launch_bounds__(kEncBlock) void k_encode_samples(GridInfo g, const 
     y[(int64_t)l * n_s + s] = gather_blend(lt, g, l, c);
 }
 
+// The same, one block per (level, block of kScatterBlockSamples samples), also
+// counting each corner in an LDS histogram over the level's table tiles; the
+// histogram is the one the hash-table gradient's count pass would build from
+// the same corners, over every sample.
+template <typename Row>
+__global__ __launch_bounds__(kScatterBlockSamples) void k_encode_samples_hist(GridInfo g, const Row* __restrict__ table,
+                                                                          const float* __restrict__ ray_obj,
+                                                                          const float* __restrict__ t, int64_t n_s,
+                                                                          int32_t S, float2* __restrict__ y,
+                                                                          TileHist h)
+{
+    __shared__ uint32_t hist[kMaxTilesPerLevel];
+    const int l = blockIdx.y;
+    const int bx = blockIdx.x;
+    const int nt = h.tiles[l];
+    for (int i = threadIdx.x; i < nt; i += kScatterBlockSamples) hist[i] = 0;
+    __syncthreads();
+    const int64_t s = (int64_t)bx * kScatterBlockSamples + threadIdx.x;
+    if (s < n_s) {
+        const int64_t ray = s / S;
+        const float* ro = ray_obj + 6 * ray;
+        const float ts = t[s];
+        Corners c;
+        level_corners(g, l, sample_coord(ts, ro[3], ro[0]), sample_coord(ts, ro[4], ro[1]),
+                      sample_coord(ts, ro[5], ro[2]), c);
+        const Row* lt = table + ((int64_t)l << g.log2_table);
+        y[(int64_t)l * n_s + s] = gather_blend(lt, g, l, c);
+        if (nt <= kAggregateTiles) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) wave_aggregated_add(hist, c.row[e] >> kTileBits);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) atomicAdd(&hist[c.row[e] >> kTileBits], 1u);
+        }
+    }
+    __syncthreads();
+    uint32_t* out = h.counts + (int64_t)h.tile_base[l] * h.n_blocks + bx;
+    for (int i = threadIdx.x; i < nt; i += kScatterBlockSamples) out[(int64_t)i * h.n_blocks] = hist[i];
+}
+
 // Batched: block b is (object o, level l, sample block bx), object-major,
 // then level, then block (each level's table stays hot while its blocks run).
 __global__ __launch_bounds__(kEncBlock) void k_encode_batch(const ObjDev* __restrict__ objs, int n_obj,
@@ -248,10 +288,20 @@ dim3 enc_grid(int64_t n, int L) { return dim3((uint32_t)((n + kEncBlock - 1) / k
 
 hipError_t launch_encode_samples(const GridInfo& g, const float* table, const void* table_f16,
                                  const float* ray_obj, const float* t, int64_t n_rays, int32_t S, float* y,
-                                 hipStream_t s)
+                                 hipStream_t s, const TileHist* hist)
 {
     const int64_t n_s = n_rays * S;
     if (n_s == 0) return hipSuccess;
+    if (hist) {
+        const dim3 grid((uint32_t)((n_s + kScatterBlockSamples - 1) / kScatterBlockSamples), (uint32_t)g.n_levels);
+        if (table_f16)
+            hipLaunchKernelGGL(k_encode_samples_hist<half2_t>, grid, dim3(kScatterBlockSamples), 0, s, g,
+                               (const half2_t*)table_f16, ray_obj, t, n_s, S, (float2*)y, *hist);
+        else
+            hipLaunchKernelGGL(k_encode_samples_hist<float2>, grid, dim3(kScatterBlockSamples), 0, s, g,
+                               (const float2*)table, ray_obj, t, n_s, S, (float2*)y, *hist);
+        return hipGetLastError();
+    }
     if (table_f16)
         hipLaunchKernelGGL(k_encode_samples<half2_t>, enc_grid(n_s, g.n_levels), dim3(kEncBlock), 0, s, g,
                            (const half2_t*)table_f16, ray_obj, t, n_s, S, (float2*)y);

@@ -8,7 +8,10 @@
 // whose accumulators fill 128 KB of LDS):
 //
 //   count  : per (sample block, level) an LDS histogram of contributions per
-//            tile -> counts[tile][block], and the block's max |dy|
+//            tile -> counts[tile][block], and the block's max |dy|.  In the
+//            single-object training step the forward encoding has written
+//            the histograms already (it computes the same corners), so this
+//            phase only takes the block maxima of |dy| (k_scatter_dymax)
 //   scan   : exclusive prefix over blocks (per tile), then over tiles; the
 //            tile record ranges are cut into chunks of bounded length, and each
 //            tile gets a fixed-point scale 2^e
@@ -39,21 +42,15 @@
 namespace prenom {
 namespace {
 
-constexpr int kTileBits = 13;
-constexpr int kTileRows = 1 << kTileBits;
-constexpr int kPlaceThreads = 512;
+constexpr int kPlaceThreads = kScatterBlockSamples;
 constexpr int kSamplesPerBlock = kPlaceThreads;  // one sample per thread
 constexpr int kRecordsPerBlock = kSamplesPerBlock * 8;
-constexpr int kMaxTilesPerLevel = 1 << (24 - kTileBits);  // T <= 2^24
 constexpr int kScanThreads = 1024;
 constexpr int kReduceThreads = 1024;
 constexpr int kRun = 8;            // consecutive records per thread and load
 constexpr int kRunsPerThread = 2;  // runs in flight per thread
 constexpr int64_t kChunk = (int64_t)1 << 21;  // records per reduce work item
 
-// Levels with at most this many tiles have most lanes of a wave in the same
-// tile; their histogram atomics are combined per wave first.
-constexpr int kAggregateTiles = 16;
 
 // ---------------------------------------------------------------- object lookup
 // Index of the last object whose `field` is <= v (fields ascend with the index).
@@ -108,42 +105,6 @@ __device__ __forceinline__ int level_of_tile(const ScatterObj& o, int lt)
     int l = 0;
     while (l + 1 < o.grid.n_levels && o.tile_base[l + 1] <= lt) ++l;
     return l;
-}
-
-// Adds 1 to hist[tile] for every active lane and returns the lane's rank
-// among the additions to that tile.  Lanes of the wave that share the tile of
-// the first remaining lane are combined into one LDS atomic issued by that
-// lane (same-address atomics of one instruction would otherwise serialise);
-// after kAggregateRounds such rounds the lanes left use plain LDS atomics, so
-// a wave spread over many tiles does not pay one round per tile.  Every slot
-// comes from an atomic on the same counter, so ranks are distinct whichever
-// way a lane takes.
-constexpr int kAggregateRounds = 2;
-
-__device__ __forceinline__ uint32_t wave_aggregated_add(uint32_t* hist, uint32_t tile)
-{
-    const int lane = threadIdx.x & 63;
-    const uint64_t lane_lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    uint64_t remaining = __ballot(1);
-    uint32_t rank = 0;
-    bool placed = false;
-#pragma unroll
-    for (int round = 0; round < kAggregateRounds; ++round) {
-        if (remaining == 0) break;
-        const int leader = __ffsll((unsigned long long)remaining) - 1;
-        const uint32_t lt = __shfl(tile, leader);
-        const uint64_t mask = __ballot(tile == lt);
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(&hist[lt], (uint32_t)__popcll(mask));
-        base = __shfl(base, leader);
-        if (tile == lt) {
-            rank = base + (uint32_t)__popcll(mask & lane_lt);
-            placed = true;
-        }
-        remaining &= ~mask;
-    }
-    if (!placed) rank = atomicAdd(&hist[tile], 1u);
-    return rank;
 }
 
 // Ray of global sample gs (S samples per ray); 32-bit division when it fits.
@@ -217,6 +178,52 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_count(ScatterArgs a)
 }
 
 // Max |dy| of each (object, level) over its sample blocks; one block per pair.
+// With fwd_counts the histograms exist already: per (level, sample block)
+// only the max |dy| that fixes the fixed-point scale.  A workgroup takes
+// kDymaxItems consecutive items (consecutive blocks of one level lie next to
+// each other in dy), with all their loads in flight at once.
+constexpr int kDymaxItems = 8;
+
+template <bool kMany>
+__global__ __launch_bounds__(kPlaceThreads) void k_scatter_dymax(ScatterArgs a)
+{
+    __shared__ float wmax[kDymaxItems][kPlaceThreads / 64];
+    float m[kDymaxItems];
+#pragma unroll
+    for (int j = 0; j < kDymaxItems; ++j) {
+        const int64_t item = (int64_t)blockIdx.x * kDymaxItems + j;
+        m[j] = 0.0f;
+        if (item < a.n_items) {
+            const ScatterObj& o = sobj<kMany>(a, obj_of_item<kMany>(a, item));
+            int l, bx;
+            split_item(item - o.item_off, o.n_blocks, l, bx);
+            const int64_t s = (int64_t)bx * kSamplesPerBlock + threadIdx.x;
+            if (s < o.n_s) {
+                const float2 d = a.dy[o.dy_off + (int64_t)l * o.n_s + s];
+                m[j] = fmaxf(fabsf(d.x), fabsf(d.y));
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kDymaxItems; ++j) {
+#pragma unroll
+        for (int dd = 32; dd >= 1; dd >>= 1) m[j] = fmaxf(m[j], __shfl_xor(m[j], dd));
+        if ((threadIdx.x & 63) == 0) wmax[j][threadIdx.x >> 6] = m[j];
+    }
+    __syncthreads();
+    if (threadIdx.x < kDymaxItems) {
+        const int64_t item = (int64_t)blockIdx.x * kDymaxItems + threadIdx.x;
+        if (item < a.n_items) {
+            const ScatterObj& o = sobj<kMany>(a, obj_of_item<kMany>(a, item));
+            int l, bx;
+            split_item(item - o.item_off, o.n_blocks, l, bx);
+            float bm = 0.0f;
+            for (int w = 0; w < kPlaceThreads / 64; ++w) bm = fmaxf(bm, wmax[threadIdx.x][w]);
+            a.block_max[o.bmax_off + (int64_t)l * o.n_blocks + bx] = bm;
+        }
+    }
+}
+
 template <bool kMany>
 __global__ __launch_bounds__(256) void k_scatter_level_max(ScatterArgs a)
 {
@@ -328,8 +335,12 @@ __global__ __launch_bounds__(kScanThreads) void k_scatter_scan_tiles(ScatterArgs
         a.tile_exp[t] = e;
     }
     if (threadIdx.x == kScanThreads - 1) {
-        a.tile_start[n] = prec[kScanThreads - 1];
-        a.chunk_start[n] = pchk[kScanThreads - 1];
+        // Histograms from the forward must add up to one record per corner of
+        // every sample; otherwise (a backward given other rays than its
+        // forward) no chunk is handed out and place stops at once.
+        const bool ok = !a.fwd_counts || prec[kScanThreads - 1] == (uint64_t)a.n_records;
+        a.tile_start[n] = ok ? prec[kScanThreads - 1] : ~0ull;
+        a.chunk_start[n] = ok ? pchk[kScanThreads - 1] : 0ull;
         *a.work_counter = 0;
     }
 }
@@ -356,6 +367,7 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
     int l, bx;
     split_item(item - o.item_off, o.n_blocks, l, bx);
     const int nt = o.tiles[l];
+    if (a.fwd_counts && a.tile_start[a.n_tiles] != (uint64_t)a.n_records) return;  // uniform: the scan's verdict
     // Global start of this block's run in the thread's tile (thread i holds
     // tile i; threads past the level's tiles load tile nt - 1 and ignore it).
     // Loaded first, together with the contribution, so the block waits on
@@ -370,7 +382,7 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
     const int64_t s = (int64_t)bx * kSamplesPerBlock + threadIdx.x;
     float2 d;
     Corners c;
-    const bool has = s < o.n_s && load_contrib(a, o, l, s, d, c);
+    const bool has = s < o.n_s && (load_contrib(a, o, l, s, d, c) || a.fwd_counts);
     uint32_t rank[8];
     if (has) {
         if (nt <= kAggregateTiles) {
@@ -435,7 +447,7 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
             const uint64_t dst = gbase[min(kt[k] >> 16, (uint32_t)nt - 1u)] + p;
             const uint16_t key = (uint16_t)(kt[k] & 0xffffu);
             const float2 v = s_val[p];
-            if (p < total) {
+            if (p < total && dst < (uint64_t)a.n_records) {
                 a.keys[dst] = key;
                 a.vals[dst] = v;
             }
@@ -522,7 +534,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_scatter_reduce(ScatterArgs a
 #pragma unroll
                 for (int i = 0; i < kRun; ++i) {
                     const uint32_t w = i < 2 ? kw[u].x : i < 4 ? kw[u].y : i < 6 ? kw[u].z : kw[u].w;
-                    key[i] = (i & 1) ? (w >> 16) : (w & 0xffffu);
+                    key[i] = ((i & 1) ? (w >> 16) : w) & (kTileRows - 1);
                     const float vx = (i & 1) ? v4[u][i >> 1].z : v4[u][i >> 1].x;
                     const float vy = (i & 1) ? v4[u][i >> 1].w : v4[u][i >> 1].y;
                     const bool ok = q < q_end && rec0 + i >= r_begin && rec0 + i < r_end;
@@ -570,7 +582,11 @@ hipError_t scatter_phase_impl(const ScatterArgs& a, int phase, hipStream_t s)
 {
     switch (phase) {
         case 0:
-            hipLaunchKernelGGL(k_scatter_count<kMany>, dim3((uint32_t)a.n_items), dim3(kPlaceThreads), 0, s, a);
+            if (a.fwd_counts)
+                hipLaunchKernelGGL(k_scatter_dymax<kMany>, dim3((uint32_t)((a.n_items + kDymaxItems - 1) / kDymaxItems)),
+                                   dim3(kPlaceThreads), 0, s, a);
+            else
+                hipLaunchKernelGGL(k_scatter_count<kMany>, dim3((uint32_t)a.n_items), dim3(kPlaceThreads), 0, s, a);
             break;
         case 1:
             hipLaunchKernelGGL(k_scatter_level_max<kMany>, dim3((uint32_t)a.n_levels_total), dim3(256), 0, s, a);

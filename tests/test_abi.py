@@ -91,3 +91,18 @@ def test_product_path_never_touches_the_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"\boracle\b", txt.replace("oracle-free", "")), f
+
+
+def test_no_stray_c_exports():
+    """Every exported symbol with C linkage is part of the ABI (prenom_*);
+    helpers stay internal (C++ names, or file-local)."""
+    import shutil
+    import subprocess
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm not available")
+    from paper_2503_01582_amd import _lib
+    out = subprocess.run([nm, "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True, check=True)
+    names = [ln.split()[-1] for ln in out.stdout.splitlines() if ln.strip()]
+    stray = [n for n in names if not n.startswith(("prenom_", "_Z", "__hip_cuid"))]
+    assert stray == []
