@@ -235,11 +235,18 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_batch(const MlpWork* __restrict
                             wk.tile_begin + wave, wk.tile_end, n_waves);
 }
 
+constexpr int kStagePadF32 = 10;
+
 template <int IN, int W, int D>
 struct BwdLds {
     static constexpr int IP = 16 * Net<IN, W, D>::IT;           // input dim padded to 16
-    static constexpr int HW = (W > IP ? W : IP) + kStagePad;    // H row pitch
-    static constexpr int DW = W + kStagePad;                    // Delta row pitch
+    // Row pitches padded by 10 floats: the staging stores (lane (q, j) at
+    // row j, column 4 q + r) and the accumulation loads (row 4 ks + q, column
+    // j) then spread over the LDS banks with at most 3-way conflicts on the
+    // stores and 2-way on the loads for the 32- and 64-wide networks (a pad
+    // of 4 gave 4-way on both).
+    static constexpr int HW = (W > IP ? W : IP) + kStagePadF32;  // H row pitch
+    static constexpr int DW = W + kStagePadF32;                  // Delta row pitch
     static constexpr int PER_WAVE = 16 * (HW + DW);
 };
 
