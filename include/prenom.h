@@ -188,9 +188,10 @@ size_t prenom_workspace_size(const prenom_arch* arch, int64_t n_rays, int32_t n_
  * Outputs: rgb [n][3], depth [n], opacity [n]; loss [1] (device scalar, or
  *   NULL); sample_out [n][S][4] = (sigma, r, g, b) per sample, or NULL.
  * workspace: >= prenom_workspace_size bytes, 256-byte aligned.  It also
- *   receives the per-tile histograms of the hash-table corners (every
- *   sample, per level and block of 512 samples) that the backward's
- *   table-gradient scatter starts from.  Unless cfg->recompute is set, it
+ *   receives the per-tile histograms of the hash-table gradient's records
+ *   (per level and block of 512 samples: one per corner of every sample,
+ *   a corner that repeats the previous sample's row joining its record)
+ *   that the backward's table-gradient scatter starts from.  Unless cfg->recompute is set, it
  *   carries the per-sample features and per-ray results that
  *   prenom_render_bwd reads: pass the same workspace and unchanged inputs to
  *   the matching bwd call.
@@ -213,9 +214,10 @@ prenom_status prenom_render_fwd(const prenom_model* model, const prenom_render_c
  * Without cfg->recompute it must follow render_fwd on the same stream with the
  * same workspace and inputs; with it, only the inputs must match.  A call
  * that breaks this gives a wrong gradient but stays within its arrays: the
- * scatter checks that the forward's histograms account for every corner of
- * every sample, else it adds nothing to the table gradient, and every record
- * it writes or reads is bounded by the workspace's record arrays.
+ * scatter checks that the forward's histograms hold no more records than
+ * there are corners of samples, else it adds nothing to the table gradient,
+ * and every record it writes or reads is bounded by the workspace's record
+ * arrays.
  * The table gradient is accumulated per 2^13-row tile in 64-bit fixed point
  * (order independent); tiles that receive more than 2^21 contributions are
  * split and their partial sums added with FP32 atomics, so only those may

@@ -141,8 +141,68 @@ __device__ __forceinline__ uint32_t wave_aggregated_add(uint32_t* hist, uint32_t
     return rank;
 }
 
+// Lane exchange within a row of 16 lanes (DPP): kCtrl = 0x100 + n (row_shl:
+// lane i reads lane i + n, 0 past the row end) or 0x110 + n (row_shr: lane i
+// reads lane i - n, 0 before the row start).  All lanes must be active.
+template <int kCtrl>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kCtrl, 0xf, 0xf, true);
+}
+
+template <int kCtrl>
+__device__ __forceinline__ float dpp_f32(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, 0xf, 0xf, true));
+}
+
+// Merging repeated corners.  Consecutive samples of a ray often share a cell
+// on the coarser levels, so the same corner row repeats on neighbouring
+// lanes; such a run becomes one record (the sum of its contributions).  Runs
+// stay inside groups of 8 lanes.  Bit e of the result is set when the lane's
+// corner e starts a run: the lane holds a sample and is the first of its
+// group of 8, or lane - 1's corner e has another row.  Lanes with samples
+// must form a prefix of the wave (then lane - 1 holds one whenever the lane
+// does).  Every lane of the wave must call it.
+__device__ __forceinline__ uint32_t run_heads(const Corners& c, bool has)
+{
+    const bool first = (threadIdx.x & 7) == 0;
+    uint32_t m = 0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const uint32_t prev = dpp_u32<0x111>(c.row[e]);
+        if (has && (first || prev != c.row[e])) m |= 1u << e;
+    }
+    return m;
+}
+
+// Per lane that starts a run (boundary set): the sum of v over its run (the
+// lane and the following lanes of its group of 8 up to the next boundary); a
+// segmented suffix scan in three steps, in a fixed order.  Lanes without a
+// sample pass v = 0 and boundary = true.  Every lane of the wave must call it.
+__device__ __forceinline__ float2 run_sum(float2 v, bool boundary)
+{
+    const int g = threadIdx.x & 7;
+    const int lane = threadIdx.x & 63;
+    const uint64_t B = __ballot(boundary);
+    // lane + 1 .. lane + d continue this lane's run (they lie in its group)
+    const bool c1 = g + 1 < 8 && ((B >> (lane + 1)) & 1ull) == 0;
+    const bool c2 = g + 2 < 8 && ((B >> (lane + 1)) & 3ull) == 0;
+    const bool c4 = g + 4 < 8 && ((B >> (lane + 1)) & 15ull) == 0;
+    float ox = dpp_f32<0x101>(v.x), oy = dpp_f32<0x101>(v.y);
+    if (c1) { v.x += ox; v.y += oy; }
+    ox = dpp_f32<0x102>(v.x);
+    oy = dpp_f32<0x102>(v.y);
+    if (c2) { v.x += ox; v.y += oy; }
+    ox = dpp_f32<0x104>(v.x);
+    oy = dpp_f32<0x104>(v.y);
+    if (c4) { v.x += ox; v.y += oy; }
+    return v;
+}
+
 // Tile histograms of one object: counts[(tile_base[l] + i) * n_blocks + b]
-// = contributions of sample block b of level l to tile i of that level.
+// = records (runs of repeated corners, run_heads) of sample block b of level
+// l in tile i of that level.
 struct TileHist {
     uint32_t* counts;
     int32_t n_blocks;
@@ -284,11 +344,12 @@ struct ScatterArgs {
     uint16_t* keys;         // [records]
     float2* vals;           // [records]
     int64_t n_records;      // length of keys and vals
-    // 1: counts were written by the training forward over every sample
-    // (TileHist); the first phase then only takes the per-block max |dy|,
-    // place records every sample, and the scan checks that the histograms add
-    // up to n_records (else place and reduce do nothing).  0: the first phase
-    // counts the samples whose dy is not zero.
+    // 1: counts were written by the training forward (TileHist: every
+    // sample, repeated corners merged); the first phase then only takes the
+    // per-block max |dy|, place records every sample and merges the same
+    // runs, and the scan checks the histograms hold at most n_records (else
+    // place and reduce do nothing).  0: the first phase counts one record
+    // per corner of every sample whose dy is not zero.
     int32_t fwd_counts;
     int32_t pad2_;
 };

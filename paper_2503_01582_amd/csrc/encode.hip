@@ -157,9 +157,10 @@ __global__ __launch_bounds__(kEncBlock) void k_encode_samples(GridInfo g, const 
 }
 
 // The same, one block per (level, block of kScatterBlockSamples samples), also
-// counting each corner in an LDS histogram over the level's table tiles; the
-// histogram is the one the hash-table gradient's count pass would build from
-// the same corners, over every sample.
+// counting the records of the hash-table gradient in an LDS histogram over
+// the level's table tiles: one per corner of every sample, except that a
+// corner repeating the previous lane's row joins that lane's record
+// (run_heads); place applies the same rule to the same corners.
 template <typename Row>
 __global__ __launch_bounds__(kScatterBlockSamples) void k_encode_samples_hist(GridInfo g, const Row* __restrict__ table,
                                                                           const float* __restrict__ ray_obj,
@@ -174,21 +175,25 @@ __global__ __launch_bounds__(kScatterBlockSamples) void k_encode_samples_hist(Gr
     for (int i = threadIdx.x; i < nt; i += kScatterBlockSamples) hist[i] = 0;
     __syncthreads();
     const int64_t s = (int64_t)bx * kScatterBlockSamples + threadIdx.x;
-    if (s < n_s) {
-        const int64_t ray = s / S;
-        const float* ro = ray_obj + 6 * ray;
-        const float ts = t[s];
-        Corners c;
-        level_corners(g, l, sample_coord(ts, ro[3], ro[0]), sample_coord(ts, ro[4], ro[1]),
-                      sample_coord(ts, ro[5], ro[2]), c);
+    const bool has = s < n_s;  // a prefix of every wave
+    const int64_t sc = has ? s : n_s - 1;
+    const float* ro = ray_obj + 6 * (sc / S);
+    const float ts = t[sc];
+    Corners c;
+    level_corners(g, l, sample_coord(ts, ro[3], ro[0]), sample_coord(ts, ro[4], ro[1]),
+                  sample_coord(ts, ro[5], ro[2]), c);
+    const uint32_t heads = run_heads(c, has);  // one record per run of a repeated corner
+    if (has) {
         const Row* lt = table + ((int64_t)l << g.log2_table);
         y[(int64_t)l * n_s + s] = gather_blend(lt, g, l, c);
         if (nt <= kAggregateTiles) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) wave_aggregated_add(hist, c.row[e] >> kTileBits);
+            for (int e = 0; e < 8; ++e)
+                if ((heads >> e) & 1u) wave_aggregated_add(hist, c.row[e] >> kTileBits);
         } else {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) atomicAdd(&hist[c.row[e] >> kTileBits], 1u);
+            for (int e = 0; e < 8; ++e)
+                if ((heads >> e) & 1u) atomicAdd(&hist[c.row[e] >> kTileBits], 1u);
         }
     }
     __syncthreads();

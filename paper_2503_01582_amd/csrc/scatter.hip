@@ -318,12 +318,14 @@ __global__ __launch_bounds__(kScanThreads) void k_scatter_scan_tiles(ScatterArgs
         a.chunk_start[t] = ck;
         r += a.tile_total[t];
         ck += (a.tile_total[t] + kChunk - 1) / kChunk;
-        // largest e with max|dy| * records * 2^e < 2^62 (bound on any row's
-        // |sum| * 2^e) and max|dy| * 2^e < 2^50 (bound on one contribution,
-        // for the reduce's FP64 rounding)
+        // largest e with vmax * records * 2^e < 2^62 (bound on any row's
+        // |sum| * 2^e) and vmax * 2^e < 2^50 (bound on one record, for the
+        // reduce's FP64 rounding), vmax the largest record: max|dy|, or 64
+        // max|dy| when repeated corners are merged
         const ScatterObj& o = sobj<kMany>(a, obj_of_tile<kMany>(a, t));
         const int l = level_of_tile(o, (int)(t - o.tile_off));
-        const double vmax = (double)a.level_max[o.lev_off + l];
+        // (a merged record sums at most 64 contributions, one per lane)
+        const double vmax = (double)a.level_max[o.lev_off + l] * (a.fwd_counts ? 64.0 : 1.0);
         const double bound = vmax * (double)a.tile_total[t];
         int e = 0;
         if (bound > 0.0) {
@@ -335,10 +337,11 @@ __global__ __launch_bounds__(kScanThreads) void k_scatter_scan_tiles(ScatterArgs
         a.tile_exp[t] = e;
     }
     if (threadIdx.x == kScanThreads - 1) {
-        // Histograms from the forward must add up to one record per corner of
-        // every sample; otherwise (a backward given other rays than its
-        // forward) no chunk is handed out and place stops at once.
-        const bool ok = !a.fwd_counts || prec[kScanThreads - 1] == (uint64_t)a.n_records;
+        // Histograms from the forward cannot hold more records than there
+        // are corners of samples; if they do (a backward whose workspace
+        // holds no forward of these rays), no chunk is handed out and place
+        // stops at once.
+        const bool ok = !a.fwd_counts || prec[kScanThreads - 1] <= (uint64_t)a.n_records;
         a.tile_start[n] = ok ? prec[kScanThreads - 1] : ~0ull;
         a.chunk_start[n] = ok ? pchk[kScanThreads - 1] : 0ull;
         *a.work_counter = 0;
@@ -367,7 +370,7 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
     int l, bx;
     split_item(item - o.item_off, o.n_blocks, l, bx);
     const int nt = o.tiles[l];
-    if (a.fwd_counts && a.tile_start[a.n_tiles] != (uint64_t)a.n_records) return;  // uniform: the scan's verdict
+    if (a.fwd_counts && a.tile_start[a.n_tiles] > (uint64_t)a.n_records) return;  // uniform: the scan's verdict
     // Global start of this block's run in the thread's tile (thread i holds
     // tile i; threads past the level's tiles load tile nt - 1 and ignore it).
     // Loaded first, together with the contribution, so the block waits on
@@ -382,15 +385,36 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
     const int64_t s = (int64_t)bx * kSamplesPerBlock + threadIdx.x;
     float2 d;
     Corners c;
-    const bool has = s < o.n_s && (load_contrib(a, o, l, s, d, c) || a.fwd_counts);
+    bool has;
+    uint32_t heads = 0xffu;  // corners that start a record
+    float2 val[8];
+    if (a.fwd_counts) {
+        // every sample counted, repeated corners merged as the forward did:
+        // samples are a prefix of the wave, every lane takes part
+        has = s < o.n_s;
+        load_contrib(a, o, l, has ? s : o.n_s - 1, d, c);
+        heads = run_heads(c, has);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            val[e] = has ? make_float2(c.w[e] * d.x, c.w[e] * d.y) : make_float2(0.0f, 0.0f);
+            const bool head = (heads >> e) & 1u;
+            if (__ballot(has && !head)) val[e] = run_sum(val[e], head || !has);
+        }
+    } else {
+        has = s < o.n_s && load_contrib(a, o, l, s, d, c);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) val[e] = make_float2(c.w[e] * d.x, c.w[e] * d.y);
+    }
     uint32_t rank[8];
     if (has) {
         if (nt <= kAggregateTiles) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) rank[e] = wave_aggregated_add(hist, c.row[e] >> kTileBits);
+            for (int e = 0; e < 8; ++e)
+                if ((heads >> e) & 1u) rank[e] = wave_aggregated_add(hist, c.row[e] >> kTileBits);
         } else {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) rank[e] = atomicAdd(&hist[c.row[e] >> kTileBits], 1u);
+            for (int e = 0; e < 8; ++e)
+                if ((heads >> e) & 1u) rank[e] = atomicAdd(&hist[c.row[e] >> kTileBits], 1u);
         }
     }
     __syncthreads();
@@ -423,10 +447,11 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
     if (has) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
+            if (!((heads >> e) & 1u)) continue;
             const uint32_t tt = c.row[e] >> kTileBits;
             const uint32_t p = seg[tt] + rank[e];
             s_kt[p] = (c.row[e] & (kTileRows - 1)) | (tt << 16);
-            s_val[p] = make_float2(c.w[e] * d.x, c.w[e] * d.y);
+            s_val[p] = val[e];
         }
     }
     __syncthreads();
