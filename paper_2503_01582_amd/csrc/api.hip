@@ -534,6 +534,7 @@ prenom_status prenom_render_bwd(const prenom_model* model, const prenom_render_c
     sa.vals = at<float2>(workspace, w.vals);
     sa.n_records = scatter_records(w.plan);
     sa.fwd_counts = 1;  // render_fwd (or the recompute above) wrote the tile histograms
+    sa.merge_runs = 1;
     for (int ph = 0; ph < kScatterPhases; ++ph)
         PRENOM_LAUNCH(ph == 0 ? "k_scatter_dymax" : kScatterPhaseNames[ph], s, launch_scatter_phase(sa, ph, s));
     return PRENOM_OK;

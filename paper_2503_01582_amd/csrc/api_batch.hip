@@ -335,6 +335,7 @@ ScatterArgs scatter_args(const Plan& p, void* ws, const float* ray_obj, const fl
     sa.vals = at<float2>(ws, p.vals);
     sa.n_records = p.records;
     sa.fwd_counts = 0;
+    sa.merge_runs = 1;
     return sa;
 }
 

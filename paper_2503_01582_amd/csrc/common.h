@@ -344,14 +344,15 @@ struct ScatterArgs {
     uint16_t* keys;         // [records]
     float2* vals;           // [records]
     int64_t n_records;      // length of keys and vals
-    // 1: counts were written by the training forward (TileHist: every
-    // sample, repeated corners merged); the first phase then only takes the
-    // per-block max |dy|, place records every sample and merges the same
-    // runs, and the scan checks the histograms hold at most n_records (else
-    // place and reduce do nothing).  0: the first phase counts one record
-    // per corner of every sample whose dy is not zero.
+    // 1: counts were written by the training forward (TileHist); the first
+    // phase then only takes the per-block max |dy|, and the scan checks the
+    // histograms hold at most n_records (else place and reduce do nothing).
+    // 0: the first phase counts.
     int32_t fwd_counts;
-    int32_t pad2_;
+    // 1: every sample counted, a corner repeating the previous lane's row
+    // joining its record (run_heads; the rule the forward's histograms
+    // follow).  0: one record per corner of every sample whose dy is not zero.
+    int32_t merge_runs;
 };
 // The scatter runs as kScatterPhases dependent kernels, launched in order
 // (phase 0 .. kScatterPhases - 1): count (or, with fwd_counts, the block

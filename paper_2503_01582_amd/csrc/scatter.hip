@@ -154,14 +154,25 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_count(ScatterArgs a)
     const int64_t s = (int64_t)bx * kSamplesPerBlock + threadIdx.x;
     float2 d;
     Corners c;
-    if (s < o.n_s && load_contrib(a, o, l, s, d, c)) {
+    bool has;
+    uint32_t heads = 0xffu;
+    if (a.merge_runs) {  // every sample, runs of a repeated corner as one record
+        has = s < o.n_s;
+        load_contrib(a, o, l, has ? s : o.n_s - 1, d, c);
+        heads = run_heads(c, has);
+    } else {
+        has = s < o.n_s && load_contrib(a, o, l, s, d, c);
+    }
+    if (has) {
         m = fmaxf(fabsf(d.x), fabsf(d.y));
         if (nt <= kAggregateTiles) {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) wave_aggregated_add(hist, c.row[e] >> kTileBits);
+            for (int e = 0; e < 8; ++e)
+                if ((heads >> e) & 1u) wave_aggregated_add(hist, c.row[e] >> kTileBits);
         } else {
 #pragma unroll
-            for (int e = 0; e < 8; ++e) atomicAdd(&hist[c.row[e] >> kTileBits], 1u);
+            for (int e = 0; e < 8; ++e)
+                if ((heads >> e) & 1u) atomicAdd(&hist[c.row[e] >> kTileBits], 1u);
         }
     }
 #pragma unroll
@@ -320,12 +331,12 @@ __global__ __launch_bounds__(kScanThreads) void k_scatter_scan_tiles(ScatterArgs
         ck += (a.tile_total[t] + kChunk - 1) / kChunk;
         // largest e with vmax * records * 2^e < 2^62 (bound on any row's
         // |sum| * 2^e) and vmax * 2^e < 2^50 (bound on one record, for the
-        // reduce's FP64 rounding), vmax the largest record: max|dy|, or 64
+        // reduce's FP64 rounding), vmax the largest record: max|dy|, or 8
         // max|dy| when repeated corners are merged
         const ScatterObj& o = sobj<kMany>(a, obj_of_tile<kMany>(a, t));
         const int l = level_of_tile(o, (int)(t - o.tile_off));
-        // (a merged record sums at most 64 contributions, one per lane)
-        const double vmax = (double)a.level_max[o.lev_off + l] * (a.fwd_counts ? 64.0 : 1.0);
+        // (a merged record sums at most 8 contributions, one per lane of a group)
+        const double vmax = (double)a.level_max[o.lev_off + l] * (a.merge_runs ? 8.0 : 1.0);
         const double bound = vmax * (double)a.tile_total[t];
         int e = 0;
         if (bound > 0.0) {
@@ -388,9 +399,9 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
     bool has;
     uint32_t heads = 0xffu;  // corners that start a record
     float2 val[8];
-    if (a.fwd_counts) {
-        // every sample counted, repeated corners merged as the forward did:
-        // samples are a prefix of the wave, every lane takes part
+    if (a.merge_runs) {
+        // every sample counted, repeated corners merged as the count (or the
+        // forward) did: samples are a prefix of the wave, every lane takes part
         has = s < o.n_s;
         load_contrib(a, o, l, has ? s : o.n_s - 1, d, c);
         heads = run_heads(c, has);
