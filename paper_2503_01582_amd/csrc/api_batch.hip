@@ -45,7 +45,7 @@ struct Plan {
     std::vector<MlpRed> red;
     std::vector<MlpWork> fwd, bwd;
     std::vector<Group> groups;
-    int64_t n_rays = 0, n_params = 0, n_mlp_total = 0, enc_blocks = 0, n_tiles = 0, n_items = 0, records = 0;
+    int64_t n_rays = 0, n_params = 0, n_mlp_total = 0, n_tiles = 0, n_items = 0, records = 0;
     int64_t y_floats = 0, partial_floats = 0, counts = 0, bmax = 0, act_floats = 0;
     int32_t n_levels_total = 0, tiles_max = 1;
     bool any_f16_table = false;
@@ -118,9 +118,8 @@ prenom_status build_plan(const prenom_batch* b, int32_t S, Plan& p)
     h = fnv(h, &n, sizeof n);
     h = fnv(h, &S, sizeof S);
 
-    int64_t ray = 0, param = 0, yoff = 0, eblk = 0, tile = 0, item = 0, cnt = 0, bmax = 0, mlp = 0;
+    int64_t ray = 0, param = 0, yoff = 0, tile = 0, item = 0, cnt = 0, bmax = 0, mlp = 0;
     int32_t lev = 0;
-    const int enc_bs = encode_block_samples();
     for (int i = 0; i < n; ++i) {
         const prenom_object& o = b->objects[i];
         const prenom_arch* a = &o.arch;
@@ -135,12 +134,10 @@ prenom_status build_plan(const prenom_batch* b, int32_t S, Plan& p)
         d.grid = grid_info(a);
         d.table_dtype = a->table_dtype;
         d.prior_res = o.prior ? o.prior_res : 0;
-        d.enc_blocks = (int32_t)((n_s + enc_bs - 1) / enc_bs);
         d.param_off = param;
         d.ray_begin = ray;
         d.n_rays = o.n_rays;
         d.y_off = yoff;
-        d.eblock_off = eblk;
         d.prior = o.prior;
         for (int k = 0; k < 12; ++k) d.A[k] = (double)o.world_to_obj[k];
         p.any_f16_table = p.any_f16_table || a->table_dtype == PRENOM_F16;
@@ -165,7 +162,6 @@ prenom_status build_plan(const prenom_batch* b, int32_t S, Plan& p)
         ray += o.n_rays;
         param += round_up(obj_params(a), kParamAlign);
         yoff += (int64_t)a->n_levels * n_s * 2;
-        eblk += (int64_t)a->n_levels * d.enc_blocks;
         tile += so.n_tiles;
         item += scatter_items(so);
         cnt += (int64_t)so.n_tiles * so.n_blocks;
@@ -178,14 +174,13 @@ prenom_status build_plan(const prenom_batch* b, int32_t S, Plan& p)
     p.n_rays = ray;
     p.n_params = param;
     p.y_floats = yoff;
-    p.enc_blocks = eblk;
     p.n_tiles = tile;
     p.n_items = item;
     p.counts = cnt;
     p.bmax = bmax;
     p.n_levels_total = lev;
     p.n_mlp_total = mlp;
-    if (eblk >= ((int64_t)1 << 31) || item >= ((int64_t)1 << 31) || tile >= ((int64_t)1 << 31))
+    if (item >= ((int64_t)1 << 31) || tile >= ((int64_t)1 << 31))
         return fail(PRENOM_ERR_SHAPE, "batch grid too large");
 
     // MLP groups, in order of first appearance; work items object by object
@@ -334,7 +329,7 @@ ScatterArgs scatter_args(const Plan& p, void* ws, const float* ray_obj, const fl
     sa.keys = at<uint16_t>(ws, p.keys);
     sa.vals = at<float2>(ws, p.vals);
     sa.n_records = p.records;
-    sa.fwd_counts = 0;
+    sa.fwd_counts = 1;  // fwd_features (render_fwd, or the recompute in render_bwd) wrote the histograms
     sa.merge_runs = 1;
     return sa;
 }
@@ -345,9 +340,11 @@ prenom_status fwd_features(const prenom_batch* b, const Plan& p, const float* ra
 {
     const ObjDev* dev = at<const ObjDev>(ws, p.o_dev);
     float* y = at<float>(ws, p.y);
+    // the encoding also writes the tile histograms the backward's scatter starts from
     PRENOM_LAUNCH("k_encode_fwd", s,
-                  launch_encode_batch(dev, p.n_obj, p.enc_blocks, b->params, p.any_f16_table ? b->params_lp : nullptr,
-                                      ray_obj, t, p.S, y, s));
+                  launch_encode_batch_hist(dev, at<const ScatterObj>(ws, p.o_sc), p.n_obj, p.n_items, b->params,
+                                           p.any_f16_table ? b->params_lp : nullptr, ray_obj, t, p.S, y,
+                                           at<uint32_t>(ws, p.cnt), s));
     for (const Group& g : p.groups) {
         const MlpWork* work = at<const MlpWork>(ws, p.o_fwd) + g.fwd_first;
         float* sc = at<float>(ws, p.sc_out);
@@ -564,7 +561,7 @@ prenom_status prenom_batch_render_bwd(const prenom_batch* batch, const prenom_re
     {
         const ScatterArgs sa = scatter_args(p, workspace, ray_obj, t, batch->grads);
         for (int ph = 0; ph < kScatterPhases; ++ph)
-            PRENOM_LAUNCH(kScatterPhaseNames[ph], s, launch_scatter_phase(sa, ph, s));
+            PRENOM_LAUNCH(ph == 0 ? "k_scatter_dymax" : kScatterPhaseNames[ph], s, launch_scatter_phase(sa, ph, s));
     }
     return PRENOM_OK;
 }

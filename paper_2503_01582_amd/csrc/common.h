@@ -218,12 +218,10 @@ struct ObjDev {
     GridInfo grid;
     int32_t table_dtype;  // PRENOM_F32 or PRENOM_F16 (read the FP16 parameter copy)
     int32_t prior_res;
-    int32_t enc_blocks;   // encode blocks per level
-    int32_t pad_;
+    int32_t pad_[2];
     int64_t param_off;    // floats: first parameter (the tables) of the object
     int64_t ray_begin, n_rays;
     int64_t y_off;        // floats: the object's features [L][n_s][2] (and their gradient)
-    int64_t eblock_off;   // first block of the object in the batched encode grid
     const float* prior;   // [R^3] or null (uniform sampling)
     double A[12];         // world -> object frame
 };
@@ -275,12 +273,14 @@ hipError_t launch_density_grid(const float* sc, int64_t n, float* out, hipStream
 hipError_t launch_encode_points(const GridInfo& g, const float* table, const float* pos, int64_t n,
                                 float* features, int32_t* corner_idx, hipStream_t s);
 
-// Encoding of the rendered samples of every object of a batch: one block per
-// (object, level, sample block); FP16 tables come from params_f16.
-hipError_t launch_encode_batch(const ObjDev* objs, int n_obj, int64_t n_blocks, const float* params,
-                               const void* params_f16, const float* ray_obj, const float* t, int32_t S, float* y,
-                               hipStream_t s);
-int encode_block_samples();
+struct ScatterObj;
+// Encoding of the rendered samples of every object of a batch, which also
+// writes the tile histograms of its hash-table gradient: one block per
+// scatter item (object, level, sample block) of sobjs, counts laid out as the
+// scatter reads them; FP16 tables come from params_f16.
+hipError_t launch_encode_batch_hist(const ObjDev* objs, const ScatterObj* sobjs, int n_obj, int64_t n_items,
+                                    const float* params, const void* params_f16, const float* ray_obj, const float* t,
+                                    int32_t S, float* y, uint32_t* counts, hipStream_t s);
 
 // Encoding of the rendered samples (positions from rays and t); reads the
 // FP16 table copy when table_f16 is not null, the FP32 tables otherwise.

@@ -201,43 +201,68 @@ __global__ __launch_bounds__(kScatterBlockSamples) void k_encode_samples_hist(Gr
     for (int i = threadIdx.x; i < nt; i += kScatterBlockSamples) out[(int64_t)i * h.n_blocks] = hist[i];
 }
 
-// Batched: block b is (object o, level l, sample block bx), object-major,
-// then level, then block (each level's table stays hot while its blocks run).
-__global__ __launch_bounds__(kEncBlock) void k_encode_batch(const ObjDev* __restrict__ objs, int n_obj,
-                                                            const float* __restrict__ params,
-                                                            const half2_t* __restrict__ params_f16,
-                                                            const float* __restrict__ ray_obj,
-                                                            const float* __restrict__ t, int32_t S,
-                                                            float2* __restrict__ y)
+// Batched, with the tile histograms: one block per item (object, level,
+// block of kScatterBlockSamples samples) of the batch's hash-table gradient,
+// numbered as its scatter numbers them (sobjs[i] and objs[i] describe object
+// i); the same run rule as k_encode_samples_hist.
+__global__ __launch_bounds__(kScatterBlockSamples) void k_encode_batch_hist(const ObjDev* __restrict__ objs,
+                                                                        const ScatterObj* __restrict__ sobjs,
+                                                                        int n_obj, const float* __restrict__ params,
+                                                                        const half2_t* __restrict__ params_f16,
+                                                                        const float* __restrict__ ray_obj,
+                                                                        const float* __restrict__ t, int32_t S,
+                                                                        float2* __restrict__ y,
+                                                                        uint32_t* __restrict__ counts)
 {
-    const int64_t b = blockIdx.x;
+    __shared__ uint32_t hist[kMaxTilesPerLevel];
+    const int64_t item = blockIdx.x;
     int lo = 0, hi = n_obj - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (objs[mid].eblock_off <= b)
+        if (sobjs[mid].item_off <= item)
             lo = mid;
         else
             hi = mid - 1;
     }
+    const ScatterObj& so = sobjs[lo];
     const ObjDev& o = objs[lo];
-    const int64_t rem = b - o.eblock_off;
-    const int l = (int)(rem / o.enc_blocks);
-    const int64_t s = (rem % o.enc_blocks) * kEncBlock + threadIdx.x;
-    const int64_t n_s = o.n_rays * S;
-    if (s >= n_s) return;
-    const int64_t gs = o.ray_begin * S + s;
+    const uint32_t rem = (uint32_t)(item - so.item_off);
+    const int l = (int)(rem / (uint32_t)so.n_blocks);
+    const int bx = (int)(rem - (uint32_t)l * (uint32_t)so.n_blocks);
+    const int nt = so.tiles[l];
+    for (int i = threadIdx.x; i < nt; i += kScatterBlockSamples) hist[i] = 0;
+    __syncthreads();
+    const int64_t n_s = so.n_s;
+    const int64_t s = (int64_t)bx * kScatterBlockSamples + threadIdx.x;
+    const bool has = s < n_s;  // a prefix of every wave
+    const int64_t gs = so.s_begin + (has ? s : n_s - 1);
     const float* ro = ray_obj + 6 * (gs / S);
     const float ts = t[gs];
     Corners c;
     level_corners(o.grid, l, sample_coord(ts, ro[3], ro[0]), sample_coord(ts, ro[4], ro[1]),
                   sample_coord(ts, ro[5], ro[2]), c);
-    const int64_t row0 = (int64_t)l << o.grid.log2_table;  // rows of float2 / half2
-    float2 v;
-    if (o.table_dtype == PRENOM_F16)
-        v = gather_blend_rows(params_f16 + o.param_off / 2 + row0, c);
-    else
-        v = gather_blend_rows(reinterpret_cast<const float2*>(params + o.param_off) + row0, c);
-    reinterpret_cast<float2*>(y)[o.y_off / 2 + (int64_t)l * n_s + s] = v;
+    const uint32_t heads = run_heads(c, has);
+    if (has) {
+        const int64_t row0 = (int64_t)l << o.grid.log2_table;  // rows of float2 / half2
+        float2 v;
+        if (o.table_dtype == PRENOM_F16)
+            v = gather_blend_rows(params_f16 + o.param_off / 2 + row0, c);
+        else
+            v = gather_blend_rows(reinterpret_cast<const float2*>(params + o.param_off) + row0, c);
+        y[o.y_off / 2 + (int64_t)l * n_s + s] = v;
+        if (nt <= kAggregateTiles) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                if ((heads >> e) & 1u) wave_aggregated_add(hist, c.row[e] >> kTileBits);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                if ((heads >> e) & 1u) atomicAdd(&hist[c.row[e] >> kTileBits], 1u);
+        }
+    }
+    __syncthreads();
+    uint32_t* out = counts + so.count_off + (int64_t)so.tile_base[l] * so.n_blocks + bx;
+    for (int i = threadIdx.x; i < nt; i += kScatterBlockSamples) out[(int64_t)i * so.n_blocks] = hist[i];
 }
 
 __global__ __launch_bounds__(kEncBlock) void k_encode_points(GridInfo g, const float2* __restrict__ table,
@@ -336,17 +361,16 @@ hipError_t launch_density_grid(const float* sc, int64_t n, float* out, hipStream
     return hipGetLastError();
 }
 
-int encode_block_samples() { return kEncBlock; }
-
-hipError_t launch_encode_batch(const ObjDev* objs, int n_obj, int64_t n_blocks, const float* params,
-                               const void* params_f16, const float* ray_obj, const float* t, int32_t S, float* y,
-                               hipStream_t s)
+hipError_t launch_encode_batch_hist(const ObjDev* objs, const ScatterObj* sobjs, int n_obj, int64_t n_items,
+                                    const float* params, const void* params_f16, const float* ray_obj, const float* t,
+                                    int32_t S, float* y, uint32_t* counts, hipStream_t s)
 {
-    if (n_blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_encode_batch, dim3((uint32_t)n_blocks), dim3(kEncBlock), 0, s, objs, n_obj, params,
-                       (const half2_t*)params_f16, ray_obj, t, S, (float2*)y);
+    if (n_items == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_encode_batch_hist, dim3((uint32_t)n_items), dim3(kScatterBlockSamples), 0, s, objs, sobjs,
+                       n_obj, params, (const half2_t*)params_f16, ray_obj, t, S, (float2*)y, counts);
     return hipGetLastError();
 }
+
 
 hipError_t launch_encode_points(const GridInfo& g, const float* table, const float* pos, int64_t n,
                                 float* features, int32_t* corner_idx, hipStream_t s)

@@ -200,12 +200,18 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_dymax(ScatterArgs a)
 {
     __shared__ float wmax[kDymaxItems][kPlaceThreads / 64];
     float m[kDymaxItems];
+    // object of the first item by search; the next items follow it (consecutive
+    // items belong to the same object or to the ones after it)
+    const int64_t item0 = (int64_t)blockIdx.x * kDymaxItems;
+    int oi = obj_of_item<kMany>(a, item0 < a.n_items ? item0 : a.n_items - 1);
 #pragma unroll
     for (int j = 0; j < kDymaxItems; ++j) {
-        const int64_t item = (int64_t)blockIdx.x * kDymaxItems + j;
+        const int64_t item = item0 + j;
         m[j] = 0.0f;
         if (item < a.n_items) {
-            const ScatterObj& o = sobj<kMany>(a, obj_of_item<kMany>(a, item));
+            if constexpr (kMany)
+                while (oi + 1 < a.n_obj && a.objs[oi + 1].item_off <= item) ++oi;
+            const ScatterObj& o = sobj<kMany>(a, oi);
             int l, bx;
             split_item(item - o.item_off, o.n_blocks, l, bx);
             const int64_t s = (int64_t)bx * kSamplesPerBlock + threadIdx.x;
@@ -223,7 +229,7 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_dymax(ScatterArgs a)
     }
     __syncthreads();
     if (threadIdx.x < kDymaxItems) {
-        const int64_t item = (int64_t)blockIdx.x * kDymaxItems + threadIdx.x;
+        const int64_t item = item0 + threadIdx.x;
         if (item < a.n_items) {
             const ScatterObj& o = sobj<kMany>(a, obj_of_item<kMany>(a, item));
             int l, bx;
