@@ -212,7 +212,9 @@ prenom_status prenom_render_fwd(const prenom_model* model, const prenom_render_c
  * product an outer autograd needs; with d_rgb == NULL it is the gradient of
  * the fused loss of render_fwd (targets required).
  * Without cfg->recompute it must follow render_fwd on the same stream with the
- * same workspace and inputs; with it, only the inputs must match.  A call
+ * same workspace and inputs; with it, only the inputs must match.  The
+ * backward leaves what the forward wrote unchanged, so several backward calls
+ * (for instance with different upstream gradients) may follow one forward.  A call
  * that breaks this gives a wrong gradient but stays within its arrays: the
  * scatter checks that the forward's histograms hold no more records than
  * there are corners of samples, else it adds nothing to the table gradient,

@@ -192,7 +192,7 @@ using namespace prenom::host;
 
 struct WsLayout {
     size_t y, sc, dout, dy, ray_state, loss_partial, mlp_partial, act;
-    size_t counts, block_max, level_max, tile_exp, tile_total, tile_start, chunk_start, work_counter, keys, vals, total;
+    size_t counts, offsets, block_max, level_max, tile_exp, tile_total, tile_start, chunk_start, work_counter, keys, vals, total;
     int n_loss_blocks, n_mlp_slots;
     ScatterObj plan;
 };
@@ -223,6 +223,8 @@ WsLayout ws_layout(const prenom_arch* a, int64_t n_rays, int32_t S)
     w.plan = scatter_obj(grid_info(a), (int64_t)n_s);
     const size_t nt = (size_t)w.plan.n_tiles;
     w.counts = off;
+    off = align_up(off + nt * (size_t)w.plan.n_blocks * sizeof(uint32_t));
+    w.offsets = off;
     off = align_up(off + nt * (size_t)w.plan.n_blocks * sizeof(uint32_t));
     w.block_max = off;
     off = align_up(off + (size_t)a->n_levels * (size_t)w.plan.n_blocks * sizeof(float));
@@ -523,6 +525,7 @@ prenom_status prenom_render_bwd(const prenom_model* model, const prenom_render_c
     sa.dy = reinterpret_cast<const float2*>(dy);
     sa.g_table = model->grads;
     sa.counts = at<uint32_t>(workspace, w.counts);
+    sa.offsets = at<uint32_t>(workspace, w.offsets);
     sa.block_max = at<float>(workspace, w.block_max);
     sa.level_max = at<float>(workspace, w.level_max);
     sa.tile_exp = at<int32_t>(workspace, w.tile_exp);

@@ -51,7 +51,7 @@ struct Plan {
     bool any_f16_table = false;
     // workspace offsets (bytes)
     size_t o_dev, o_sc, o_red, o_fwd, o_bwd;
-    size_t y, sc_out, dout, dy, ray_state, ray_loss, partial, act, cnt, block_max, level_max, tile_exp, tile_total,
+    size_t y, sc_out, dout, dy, ray_state, ray_loss, partial, act, cnt, offs, block_max, level_max, tile_exp, tile_total,
         tile_start, chunk_start, work_counter, keys, vals, total;
     uint64_t fingerprint = 0;
 };
@@ -264,6 +264,7 @@ prenom_status build_plan(const prenom_batch* b, int32_t S, Plan& p)
     p.partial = take(sizeof(float) * (size_t)p.partial_floats);
     p.act = take(sizeof(float) * (size_t)p.act_floats);
     p.cnt = take(sizeof(uint32_t) * (size_t)p.counts);
+    p.offs = take(sizeof(uint32_t) * (size_t)p.counts);
     p.block_max = take(sizeof(float) * (size_t)p.bmax);
     p.level_max = take(sizeof(float) * (size_t)p.n_levels_total);
     p.tile_exp = take(sizeof(int32_t) * (size_t)p.n_tiles);
@@ -319,6 +320,7 @@ ScatterArgs scatter_args(const Plan& p, void* ws, const float* ray_obj, const fl
     sa.dy = at<const float2>(ws, p.dy);
     sa.g_table = grads;
     sa.counts = at<uint32_t>(ws, p.cnt);
+    sa.offsets = at<uint32_t>(ws, p.offs);
     sa.block_max = at<float>(ws, p.block_max);
     sa.level_max = at<float>(ws, p.level_max);
     sa.tile_exp = at<int32_t>(ws, p.tile_exp);

@@ -333,7 +333,8 @@ struct ScatterArgs {
     const float* t;
     const float2* dy;
     float* g_table;
-    uint32_t* counts;       // per object [n_tiles][n_blocks]
+    uint32_t* counts;       // per object [n_tiles][n_blocks], read only after the first phase
+    uint32_t* offsets;      // same layout: per block, its first record within the tile
     float* block_max;       // per object [L][n_blocks] max |dy| per sample block
     float* level_max;       // [n_levels_total]
     int32_t* tile_exp;      // [n_tiles] fixed-point exponent

@@ -269,7 +269,8 @@ __device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v, int lane)
     return v;
 }
 
-// Per tile: exclusive prefix of the per-block counts (in place) and the total.
+// Per tile: exclusive prefix of the per-block counts (into offsets, so the
+// forward's histograms survive for another backward) and the total.
 // Thread t owns a contiguous run of blocks; the runs' sums are scanned within
 // each wave, then across the block's waves.
 template <bool kMany>
@@ -280,7 +281,9 @@ __global__ __launch_bounds__(kScanThreads) void k_scatter_scan_blocks(ScatterArg
     const int64_t tile = blockIdx.x;
     const ScatterObj& o = sobj<kMany>(a, obj_of_tile<kMany>(a, tile));
     const int nb = o.n_blocks;
-    uint32_t* row = a.counts + o.count_off + (tile - o.tile_off) * nb;
+    const int64_t row0 = o.count_off + (tile - o.tile_off) * nb;
+    const uint32_t* row = a.counts + row0;
+    uint32_t* orow = a.offsets + row0;
     const int per = (nb + kScanThreads - 1) / kScanThreads;
     const int b0 = min((int)threadIdx.x * per, nb), b1 = min(b0 + per, nb);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -298,9 +301,8 @@ __global__ __launch_bounds__(kScanThreads) void k_scatter_scan_blocks(ScatterArg
     __syncthreads();
     uint64_t run = wave_tot[wave] + incl - sum;
     for (int b = b0; b < b1; ++b) {
-        const uint32_t c = row[b];
-        row[b] = (uint32_t)run;  // offsets within a tile fit 32 bits
-        run += c;
+        orow[b] = (uint32_t)run;  // offsets within a tile fit 32 bits
+        run += row[b];
     }
 }
 
@@ -395,7 +397,7 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
     const int tb = o.tile_base[l];
     const int own = min((int)threadIdx.x, nt - 1);
     const uint64_t own_start = a.tile_start[o.tile_off + tb + own];
-    const uint32_t own_off = a.counts[o.count_off + (int64_t)(tb + own) * o.n_blocks + bx];
+    const uint32_t own_off = a.offsets[o.count_off + (int64_t)(tb + own) * o.n_blocks + bx];
     for (int i = threadIdx.x; i < nt; i += kPlaceThreads) hist[i] = 0;
     __syncthreads();
     // pass 1: rank of each contribution within its tile (LDS atomics)
@@ -455,7 +457,7 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
     __syncthreads();
     // global position of record p of local tile tt: gbase[tt] + p
     {
-        const uint32_t* cnt = a.counts + o.count_off;
+        const uint32_t* cnt = a.offsets + o.count_off;
         if ((int)threadIdx.x < nt) gbase[threadIdx.x] = own_start + own_off - seg[threadIdx.x];
         for (int i = threadIdx.x + kPlaceThreads; i < nt; i += kPlaceThreads)
             gbase[i] = a.tile_start[o.tile_off + tb + i] + cnt[(int64_t)(tb + i) * o.n_blocks + bx] - seg[i];

@@ -218,6 +218,44 @@ def test_batch_equals_single_object_calls():
         say(f"  tiles {'default' if tl is None else 'fwd 12 / bwd 40'}: batch == single-object calls")
 
 
+def test_backward_repeats_after_one_forward():
+    """The backward only reads what the forward left in the workspace (the
+    tile histograms of the table gradient included): two backward calls after
+    one forward add the same gradient twice, batched and single-object."""
+    say("test_backward_repeats_after_one_forward")
+    from paper_2503_01582_amd import api
+    objs = make_objects(counts=[900, 0, 400, 777, 3, 1100, 65])
+    params = object_params(objs)
+    b = multi_batch(objs, step=3)
+    geo = oracle_geometry(objs, b)
+    loss = LossSpec(lambda_d=0.1)
+    run = BatchRun(objs, params, b, geo, loss)
+    run.fwd()
+    g1 = run.bwd()
+    run.B.prenom_batch_render_bwd(run.bm, run.samp, run.loss, run.ws, **run.kw)
+    torch.cuda.synchronize()
+    for i, o in enumerate(objs):
+        if o.n_rays:
+            assert_close(run.bm.object_grads(i).cpu().numpy(), 2 * g1[i], tol=1e-6, name=f"object {i} grads")
+    i = 5
+    sl = b.slice(i)
+    m = api.Model(objs[i].arch, params[i])
+    samp = api.SampleOut(*(dev(x[sl]) for x in geo[:3]),
+                         bins=torch.zeros((objs[i].n_rays, 1), dtype=torch.int32, device="cuda"),
+                         flags=dev(geo[3][sl]))
+    ws = api.Workspace().get(objs[i].arch, objs[i].n_rays, 64)
+    kw = dict(tgt_rgb=dev(b.tgt_rgb[sl]), tgt_depth=dev(b.tgt_depth[sl]), mask=dev(b.mask[sl]))
+    api.prenom_render_fwd(m, samp, loss, ws, **kw)
+    api.prenom_render_bwd(m, samp, loss, ws, **kw)
+    torch.cuda.synchronize()
+    one = m.grads.cpu().numpy().copy()
+    assert np.any(one[:objs[i].arch.n_table_params])
+    api.prenom_render_bwd(m, samp, loss, ws, **kw)
+    torch.cuda.synchronize()
+    assert_close(m.grads.cpu().numpy(), 2 * one, tol=1e-6, name="single-object grads")
+    say("  second backward after one forward: gradient added twice")
+
+
 def test_batch_adam_device_step():
     """One Adam launch over the batch; bias corrections from the device step
     counter match the oracle's host-step Adam on every object."""

@@ -1,0 +1,170 @@
+"""The batched step at the sizes it is benchmarked at, in the same launch
+configuration (the bench's objects, rays, priors and tile shapes):
+
+* 24 objects, FP32, each with its own architecture, prior, pose and a
+  log-uniform ray count;
+* 48 objects sharing 2^20 rays, BF16 MLP and FP16 table copy, loss scale
+  2^12.
+
+Checked where the oracle can follow: the sampler's bins and flags of every
+ray bit-exact; colour, depth and opacity on 256 sampled rays of every object;
+the loss of the three objects with the fewest rays, and their whole table
+and MLP gradient (an object's gradient depends on its own rays only).  FP32
+at 1e-5; the reduced-precision form against the oracle that emulates it, at
+2e-3 (gradients in the 2-norm).
+
+The gradient is compared as a vector-Jacobian product with random upstream
+gradients on every ray of the object; in FP32, except those near a ReLU
+kink (the reduced-precision tolerance already allows for kinks: an operand at
+a 16-bit rounding boundary moves pre-activations by far more).  With
+10^7 pre-activations per object, a few lie within FP32 rounding of zero;
+there the FP32 and FP64 forwards switch the unit differently and that
+sample's feature gradient changes by O(1), a difference of arithmetic, not
+of the method.  A ray counts as near a kink when the oracle's ReLU pattern
+of the ray changes under any of four perturbations of every parameter by
+1e-5 of itself with an independent random sign, which moves a
+pre-activation well beyond its FP32 rounding."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle as orc
+from parity_util import TOL_FP32, rel_errors
+from test_gpu_batch import dev
+from test_gpu_precision import lowp_ok
+from synth.multi import multi_batch, multi_objects
+from synth.params import init_params
+from synth.workloads import PRIOR_SAMPLE, LossSpec
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def full_case(n_objects, total_rays, mlp_dtype, table_dtype, seed):
+    from paper_2503_01582_amd import autotune
+    from paper_2503_01582_amd.batch import BatchObject
+    objs = multi_objects(seed, n_objects, total_rays=total_rays, mlp_dtype=mlp_dtype, table_dtype=table_dtype)
+    b = multi_batch(objs, step=0)
+    params = [init_params(o.arch, i) for i, o in enumerate(objs)]
+    for i, (o, p) in enumerate(zip(objs, params)):  # a varied field, so colours and gradients are not trivial
+        p[:o.arch.n_table_params] = np.random.default_rng(100 + i).uniform(-0.3, 0.3, o.arch.n_table_params)
+    priors = [torch.as_tensor(o.prior).cuda() for o in objs]
+    bobjs = [BatchObject(o.arch, o.n_rays, pr, o.world_to_obj) for o, pr in zip(objs, priors)]
+    return objs, b, params, bobjs, autotune.tiles_for([o.arch for o in objs])
+
+
+def oracle_sample(o, b, sl):
+    s = PRIOR_SAMPLE
+    return orc.sample(b.rays_o[sl], b.rays_d[sl], b.xi[sl], n_coarse=s.n_coarse, n_fine=s.n_fine,
+                      include_coarse=s.include_coarse, uniform_only=s.uniform_only, eps=s.eps, near=s.near,
+                      far=s.far, world_to_obj=o.world_to_obj, prior=o.prior)
+
+
+def run_full(n_objects, total_rays, mlp_dtype, table_dtype, seed):
+    from paper_2503_01582_amd import api
+    from paper_2503_01582_amd import batch as B
+    lowp = mlp_dtype != "fp32"
+    scale = 4096.0 if lowp else None
+    objs, b, params, bobjs, tiles = full_case(n_objects, total_rays, mlp_dtype, table_dtype, seed)
+    n = sum(o.n_rays for o in objs)
+    say(f"  {len(objs)} objects, {n} rays, {len(tiles)} tuned MLP shapes")
+    bm = B.BatchModel(bobjs, params, tiles=tiles, loss_scale=scale)
+    ws = B.alloc_workspace(bm, PRIOR_SAMPLE.n_samples)
+    samp = B.prenom_batch_sample(bm, PRIOR_SAMPLE, dev(b.rays_o), dev(b.rays_d), dev(b.xi), ws)
+    torch.cuda.synchronize()
+    bins, flags = samp.bins.cpu().numpy(), samp.flags.cpu().numpy()
+    geo = []
+    for i, o in enumerate(objs):
+        sl = b.slice(i)
+        if o.n_rays == 0:
+            continue
+        ref = oracle_sample(o, b, sl)
+        np.testing.assert_array_equal(flags[sl], ref["flags"], err_msg=f"object {i} flags")
+        np.testing.assert_array_equal(bins[sl], ref["bins"], err_msg=f"object {i} bins")
+        geo.append(ref)
+    say(f"  sampler: bins and flags of all {n} rays exact")
+    cat = lambda k, dt: np.concatenate([g[k] for g in geo]).astype(dt)
+    g_all = (cat("ray_obj", np.float32).reshape(-1, 6), cat("t", np.float32), cat("dt", np.float32),
+             cat("flags", np.uint8))
+    loss = LossSpec(lambda_d=0.1)
+    s2 = api.SampleOut(ray_obj=dev(g_all[0]), t=dev(g_all[1]), dt=dev(g_all[2]),
+                       bins=torch.zeros((n, 1), dtype=torch.int32, device="cuda"), flags=dev(g_all[3]))
+    kw = dict(tgt_rgb=dev(b.tgt_rgb), tgt_depth=dev(b.tgt_depth), mask=dev(b.mask))
+    out = B.prenom_batch_render_fwd(bm, s2, loss, ws, **kw)
+    bm.grads.zero_()
+    B.prenom_batch_render_bwd(bm, s2, loss, ws, **kw)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in out.items()}
+    rng = np.random.default_rng(seed)
+    worst = {}
+    small = sorted((o.n_rays, i) for i, o in enumerate(objs) if o.n_rays > 0)[:3]
+    checks = []
+    for i, o in enumerate(objs):
+        if o.n_rays == 0:
+            continue
+        sl = b.slice(i)
+        g = tuple(x[sl] for x in g_all)
+        okw = dict(lambda_d=np.float32(0.1), emulate=lowp)
+        pick = np.unique(np.concatenate([np.arange(min(128, o.n_rays)), rng.integers(0, o.n_rays, 128)]))
+        gp = tuple(x[pick] for x in g)
+        ref = orc.render_fwd(o.arch, params[i], *gp, **okw)
+        for k in ("rgb", "depth", "opacity"):
+            e = rel_errors(got[k][sl][pick], ref[k])
+            worst[k] = max(worst.get(k, 0.0), e[0])
+            assert (lowp_ok(k, e) if lowp else max(e) <= TOL_FP32), (i, k, e)
+        if (o.n_rays, i) in small:
+            tk = dict(tgt_rgb=b.tgt_rgb[sl], tgt_depth=b.tgt_depth[sl], mask=b.mask[sl])
+            rf = orc.render_fwd(o.arch, params[i], *g, **tk, **okw)
+            el = rel_errors([got["loss"][i]], [rf["loss"]])
+            assert (lowp_ok("loss", el) if lowp else max(el) <= TOL_FP32), (i, el)
+            checks.append((i, sl, g, okw, el))
+    say("  worst max-rel error on sampled rays: " + ", ".join(f"{k} {v:.1e}" for k, v in worst.items()))
+    # gradients: upstream on the rays of the three smallest objects only (FP32: away from kinks)
+    d_rgb = np.zeros((n, 3), np.float32)
+    d_depth = np.zeros(n, np.float32)
+    for i, sl, g, okw, _ in checks:
+        o = objs[i]
+        if not lowp:
+            sig = orc.render_fwd(o.arch, params[i], *g, want_relu_signature=True, **okw)["relu_signature"]
+        keep = np.ones(o.n_rays, bool)
+        for _ in range(0 if lowp else 4):  # the reduced-precision tolerance already allows for kinks
+            sgn = rng.choice([-1.0, 1.0], params[i].size)
+            pp = params[i].astype(np.float64) * (1.0 + 1e-5 * sgn * rng.uniform(0.5, 1.0, params[i].size))
+            keep &= orc.render_fwd(o.arch, pp.astype(np.float32), *g, want_relu_signature=True,
+                                   **okw)["relu_signature"] == sig
+        d_rgb[sl][keep] = rng.normal(size=(int(keep.sum()), 3))
+        d_depth[sl][keep] = rng.normal(size=int(keep.sum()))
+        if not lowp:
+            say(f"  object {i}: {o.n_rays - keep.sum()} of {o.n_rays} rays near a ReLU kink left out of the gradient")
+    bm.grads.zero_()
+    B.prenom_batch_render_bwd(bm, s2, loss, ws, d_rgb=dev(d_rgb), d_depth=dev(d_depth), **kw)
+    torch.cuda.synchronize()
+    for i, sl, g, okw, el in checks:
+        o = objs[i]
+        gr = orc.render_bwd(o.arch, params[i], *g, d_rgb=d_rgb[sl], d_depth=d_depth[sl], **okw,
+                            **(dict(loss_scale=scale) if lowp else {}))
+        gi = bm.object_grads(i).cpu().numpy().astype(np.float64) / (scale or 1.0)
+        nt = o.arch.n_table_params
+        et, em = rel_errors(gi[:nt], gr[:nt]), rel_errors(gi[nt:], gr[nt:])
+        if lowp:
+            assert lowp_ok("g_table", et) and lowp_ok("g_mlp", em), (i, et, em)
+        else:
+            assert max(et) <= TOL_FP32 and max(em) <= TOL_FP32, (i, et, em)
+        say(f"  object {i} ({o.n_rays} rays, L{o.arch.n_levels} 2^{o.arch.log2_table} W{o.arch.width} "
+            f"D{o.arch.hidden}): loss {el[0]:.1e}, table grad {et[0]:.1e}/{et[1]:.1e}, "
+            f"MLP grad {em[0]:.1e}/{em[1]:.1e}")
+
+
+def test_batch24_full_size_fp32():
+    say("test_batch24_full_size_fp32")
+    run_full(24, None, "fp32", "fp32", seed=4)
+
+
+def test_batch48_full_size_reduced_precision():
+    say("test_batch48_full_size_reduced_precision")
+    run_full(48, 1 << 20, "bf16", "fp16", seed=5)
