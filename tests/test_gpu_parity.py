@@ -281,6 +281,26 @@ def test_render_upstream_gradients():
                 oracle_bwd(arch, params, geo, b, d_rgb=d_rgb, d_depth=d_depth))
 
 
+def test_backward_without_its_forward_adds_no_table_gradient():
+    """A backward whose workspace holds no forward of these rays (here: every
+    byte 0xff, so the tile histograms claim far more records than there are
+    corners) must stay within its arrays: the scatter's check refuses the
+    histograms and leaves the table gradient untouched.  A forward and
+    backward afterwards give the gradient of a fresh workspace, bit for bit."""
+    say("test_backward_without_its_forward_adds_no_table_gradient")
+    arch, params, b, geo = render_case("small", 300)
+    gr = GpuRender(arch, params, geo)
+    gr.ws.fill_(0xFF)
+    g = gr.bwd(b)
+    assert not np.any(g[:arch.n_table_params]), "table gradient written from histograms no forward made"
+    gr.fwd(b)
+    g1 = gr.bwd(b)
+    fresh = GpuRender(arch, params, geo)
+    fresh.fwd(b)
+    np.testing.assert_array_equal(g1, fresh.bwd(b))
+    assert np.any(g1[:arch.n_table_params])
+
+
 @pytest.mark.parametrize("nc,nr,n_rays", [(40, 60, 333), (128, 128, 96), (7, 17, 1037)])
 def test_render_long_and_ragged_rays(nc, nr, n_rays):
     say(f"test_render_long_and_ragged_rays: S = {nc}+{nr}, {n_rays} rays")
