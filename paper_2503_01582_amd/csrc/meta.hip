@@ -39,7 +39,10 @@ __global__ __launch_bounds__(kReptileBlock) void k_reptile(ReptileArgs a)
         }
         const float4 nw = make_float4(t.x + scale * d.x, t.y + scale * d.y, t.z + scale * d.z, t.w + scale * d.w);
         theta[i] = nw;
-        const bool f16 = a.tasks_f16 && (i << 2) < a.n_f16;
+        // FP16 copy of the first n_f16 entries only: whole groups of 4 as one
+        // store, a group that n_f16 cuts entry by entry
+        const int64_t e0 = i << 2;
+        const int lp = !a.tasks_f16 || e0 >= a.n_f16 ? 0 : (e0 + 4 <= a.n_f16 ? 4 : (int)(a.n_f16 - e0));
         const half4_t h = {(_Float16)nw.x, (_Float16)nw.y, (_Float16)nw.z, (_Float16)nw.w};
         for (int b = 0; b < a.n_tasks; ++b) {
             const int64_t j = b * s4 + i;
@@ -48,7 +51,11 @@ __global__ __launch_bounds__(kReptileBlock) void k_reptile(ReptileArgs a)
                 reinterpret_cast<float4*>(a.m)[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 reinterpret_cast<float4*>(a.v)[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             }
-            if (f16) reinterpret_cast<half4_t*>(a.tasks_f16)[j] = h;
+            if (lp == 4) {
+                reinterpret_cast<half4_t*>(a.tasks_f16)[j] = h;
+            } else {
+                for (int e = 0; e < lp; ++e) reinterpret_cast<_Float16*>(a.tasks_f16)[4 * j + e] = h[e];
+            }
         }
     }
     // tail (n not a multiple of 4): the first threads of block 0

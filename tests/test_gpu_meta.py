@@ -142,6 +142,25 @@ def test_reptile_update_matches_oracle(B, n):
     assert int(step.item()) == 0
 
 
+@pytest.mark.parametrize("n_lp", [0, 4, 4094, 4097, 4099])
+def test_reptile_update_fp16_copy_stops_at_n_lp(n_lp):
+    """Only the first n_lp entries of each task's FP16 copy are written, also
+    when n_lp ends inside a group of four that the vector path covers."""
+    say(f"test_reptile_update_fp16_copy_stops_at_n_lp[{n_lp}]")
+    from paper_2503_01582_amd import api
+    B, n, stride = 3, 4099, 4160
+    rng = np.random.default_rng(n_lp)
+    theta = torch.as_tensor(rng.normal(size=n).astype(np.float32)).cuda()
+    tasks = torch.as_tensor(rng.normal(size=B * stride).astype(np.float32)).cuda()
+    lp = torch.full((B * stride,), 5.0, dtype=torch.float16, device="cuda")
+    api.prenom_reptile_update(theta, tasks, n, B, stride, 0.5, tasks_lp=lp, n_lp=n_lp)
+    torch.cuda.synchronize()
+    want = theta.cpu().numpy().astype(np.float16)
+    ll = lp.cpu().numpy().reshape(B, stride)
+    assert np.array_equal(ll[:, :n_lp], np.broadcast_to(want[:n_lp], (B, n_lp)))
+    assert np.all(ll[:, n_lp:] == 5)
+
+
 def test_reptile_update_argument_errors():
     say("test_reptile_update_argument_errors")
     from paper_2503_01582_amd import api
