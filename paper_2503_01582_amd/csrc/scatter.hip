@@ -48,7 +48,7 @@ constexpr int kRecordsPerBlock = kSamplesPerBlock * 8;
 constexpr int kScanThreads = 1024;
 constexpr int kReduceThreads = 1024;
 constexpr int kRun = 8;            // consecutive records per thread and load
-constexpr int kRunsPerThread = 2;  // runs in flight per thread
+constexpr int kRunsPerThread = 3;  // runs in flight per thread
 constexpr int64_t kChunk = (int64_t)1 << 21;  // records per reduce work item
 
 
