@@ -22,6 +22,23 @@ def _stream() -> C.c_void_p:
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _check_rays(samp: "SampleOut", n: int, **arrays):
+    """The library takes plain pointers and cannot check sizes: every per-ray
+    array (the samples' own and the optional ones given by keyword) must be a
+    contiguous device tensor of the expected dtype holding exactly n rays."""
+    S = samp.t.shape[1] if samp.t.dim() == 2 else -1
+    per = dict(ray_obj=(torch.float32, 6), t=(torch.float32, S), dt=(torch.float32, S),
+               flags=(torch.uint8, 1), bg=(torch.float32, 3), tgt_rgb=(torch.float32, 3),
+               tgt_depth=(torch.float32, 1), mask=(torch.uint8, 1), d_rgb=(torch.float32, 3),
+               d_depth=(torch.float32, 1), d_opacity=(torch.float32, 1), sample_out=(torch.float32, 4 * S))
+    given = dict(ray_obj=samp.ray_obj, t=samp.t, dt=samp.dt, flags=samp.flags, **arrays)
+    for name, t in given.items():
+        dtype, k = per[name]
+        _dev(t, dtype, name)
+        if t is not None and (k < 0 or t.numel() != n * k):
+            raise ValueError(f"{name} holds {t.numel()} values, expected {n} rays x {k}")
+
+
 def _dev(t: Optional[torch.Tensor], dtype, name: str):
     if t is None:
         return None
@@ -204,11 +221,7 @@ def prenom_render_fwd(model: Model, samp: SampleOut, loss_spec, ws: torch.Tensor
                    depth=torch.empty((n,), dtype=torch.float32, device=dev),
                    opacity=torch.empty((n,), dtype=torch.float32, device=dev),
                    loss=torch.zeros((1,), dtype=torch.float32, device=dev))
-    _dev(bg, torch.float32, "bg")
-    _dev(tgt_rgb, torch.float32, "tgt_rgb")
-    _dev(tgt_depth, torch.float32, "tgt_depth")
-    _dev(mask, torch.uint8, "mask")
-    _dev(sample_out, torch.float32, "sample_out")
+    _check_rays(samp, n, bg=bg, tgt_rgb=tgt_rgb, tgt_depth=tgt_depth, mask=mask, sample_out=sample_out)
     cfg = render_cfg(S, loss_spec)
     mc = model.c_struct()
     st = L.lib().prenom_render_fwd(
@@ -224,9 +237,8 @@ def prenom_render_bwd(model: Model, samp: SampleOut, loss_spec, ws: torch.Tensor
                       tgt_rgb=None, tgt_depth=None, mask=None, d_rgb=None, d_depth=None,
                       d_opacity=None, grads: Optional[torch.Tensor] = None, recompute=False):
     n, S = samp.t.shape
-    _dev(d_rgb, torch.float32, "d_rgb")
-    _dev(d_depth, torch.float32, "d_depth")
-    _dev(d_opacity, torch.float32, "d_opacity")
+    _check_rays(samp, n, bg=bg, tgt_rgb=tgt_rgb, tgt_depth=tgt_depth, mask=mask, d_rgb=d_rgb, d_depth=d_depth,
+                d_opacity=d_opacity)
     cfg = render_cfg(S, loss_spec, recompute)
     mc = model.c_struct(grads)
     st = L.lib().prenom_render_bwd(

@@ -14,7 +14,7 @@ import numpy as np
 import torch
 
 from . import _lib as L
-from .api import SampleOut, _dev, _ptr, _stream, alloc_sample_out, make_arch, render_cfg, sample_cfg
+from .api import SampleOut, _check_rays, _dev, _ptr, _stream, alloc_sample_out, make_arch, render_cfg, sample_cfg
 
 
 @dataclass
@@ -176,10 +176,7 @@ def prenom_batch_render_fwd(bm: BatchModel, samp: SampleOut, loss_spec, ws: torc
                             tgt_rgb=None, tgt_depth=None, mask=None, want_loss=True, out=None, recompute=False):
     if out is None:
         out = alloc_render_out(bm, samp.t.device)
-    _dev(bg, torch.float32, "bg")
-    _dev(tgt_rgb, torch.float32, "tgt_rgb")
-    _dev(tgt_depth, torch.float32, "tgt_depth")
-    _dev(mask, torch.uint8, "mask")
+    _check_rays(samp, bm.n_rays, bg=bg, tgt_rgb=tgt_rgb, tgt_depth=tgt_depth, mask=mask)
     cfg = render_cfg(samp.n_samples, loss_spec, recompute)
     b = bm.c_struct()
     st = L.lib().prenom_batch_render_fwd(
@@ -193,9 +190,8 @@ def prenom_batch_render_fwd(bm: BatchModel, samp: SampleOut, loss_spec, ws: torc
 def prenom_batch_render_bwd(bm: BatchModel, samp: SampleOut, loss_spec, ws: torch.Tensor, *, bg=None,
                             tgt_rgb=None, tgt_depth=None, mask=None, d_rgb=None, d_depth=None, d_opacity=None,
                             recompute=False):
-    _dev(d_rgb, torch.float32, "d_rgb")
-    _dev(d_depth, torch.float32, "d_depth")
-    _dev(d_opacity, torch.float32, "d_opacity")
+    _check_rays(samp, bm.n_rays, bg=bg, tgt_rgb=tgt_rgb, tgt_depth=tgt_depth, mask=mask, d_rgb=d_rgb,
+                d_depth=d_depth, d_opacity=d_opacity)
     cfg = render_cfg(samp.n_samples, loss_spec, recompute)
     b = bm.c_struct()
     st = L.lib().prenom_batch_render_bwd(

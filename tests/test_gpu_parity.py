@@ -281,6 +281,25 @@ def test_render_upstream_gradients():
                 oracle_bwd(arch, params, geo, b, d_rgb=d_rgb, d_depth=d_depth))
 
 
+def test_bindings_reject_per_ray_arrays_of_the_wrong_size():
+    """The C ABI takes plain pointers; the Python binding checks every
+    per-ray array against the ray and sample counts before any launch."""
+    say("test_bindings_reject_per_ray_arrays_of_the_wrong_size")
+    arch, params, b, geo = render_case("small")
+    gr = GpuRender(arch, params, geo)
+    A, n = gr.A, geo[1].shape[0]
+    z = lambda *shape, dtype=torch.float32: torch.zeros(shape, dtype=dtype, device="cuda")
+    with pytest.raises(ValueError):
+        A.prenom_render_bwd(gr.model, gr.samp, gr.loss, gr.ws, d_rgb=z(n - 1, 3))
+    with pytest.raises(ValueError):
+        A.prenom_render_fwd(gr.model, gr.samp, gr.loss, gr.ws, tgt_rgb=z(n, 2))
+    with pytest.raises(ValueError):
+        A.prenom_render_fwd(gr.model, gr.samp, gr.loss, gr.ws, sample_out=z(n, geo[1].shape[1], 3))
+    with pytest.raises(TypeError):
+        A.prenom_render_fwd(gr.model, gr.samp, gr.loss, gr.ws, tgt_rgb=z(n, 3), mask=z(n))
+    gr.fwd(b)  # the right sizes still go through
+
+
 def test_backward_without_its_forward_adds_no_table_gradient():
     """A backward whose workspace holds no forward of these rays (here: every
     byte 0xff, so the tile histograms claim far more records than there are
