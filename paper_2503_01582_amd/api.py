@@ -161,6 +161,8 @@ def sample_cfg(spec, world_to_obj, prior: Optional[torch.Tensor]) -> L.PrenomSam
         c.world_to_obj[i] = float(A[i])
     if prior is not None:
         _dev(prior, torch.float32, "prior")
+        if prior.dim() != 3 or len(set(prior.shape)) != 1:
+            raise ValueError(f"prior must be an [R, R, R] grid, got {tuple(prior.shape)}")
         c.prior = prior.data_ptr()
         c.prior_res = prior.shape[0]
     else:
@@ -179,6 +181,13 @@ def prenom_sample(spec, rays_o: torch.Tensor, rays_d: torch.Tensor, xi: torch.Te
         raise ValueError("rays_o, rays_d must be [n, 3] and xi [n, n_fine]")
     if out is None:
         out = alloc_sample_out(n, spec.n_fine, spec.n_samples, rays_o.device)
+    else:
+        if out.t.dim() != 2 or out.t.shape != (n, spec.n_samples):
+            raise ValueError(f"out.t must be [{n}, {spec.n_samples}]")
+        _check_rays(out, n)
+        _dev(out.bins, torch.int32, "bins")
+        if out.bins.numel() != n * spec.n_fine:
+            raise ValueError(f"out.bins must hold {n} x {spec.n_fine} values")
     cfg = sample_cfg(spec, world_to_obj, prior)
     st = L.lib().prenom_sample(C.byref(cfg), _ptr(rays_o), _ptr(rays_d), _ptr(xi), n,
                                _ptr(out.ray_obj), _ptr(out.t), _ptr(out.dt), _ptr(out.bins),

@@ -32,6 +32,8 @@ def _c_objects(objs: Sequence[BatchObject]):
         arr[i].n_rays = int(o.n_rays)
         if o.prior is not None:
             _dev(o.prior, torch.float32, "prior")
+            if o.prior.dim() != 3 or len(set(o.prior.shape)) != 1:
+                raise ValueError(f"object {i}: prior must be an [R, R, R] grid, got {tuple(o.prior.shape)}")
             arr[i].prior = o.prior.data_ptr()
             arr[i].prior_res = int(o.prior.shape[0])
         else:
