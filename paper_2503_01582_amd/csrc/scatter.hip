@@ -198,7 +198,8 @@ constexpr int kDymaxItems = 8;
 template <bool kMany>
 __global__ __launch_bounds__(kPlaceThreads) void k_scatter_dymax(ScatterArgs a)
 {
-    __shared__ float wmax[kDymaxItems][kPlaceThreads / 64];
+    constexpr int kRows = kPlaceThreads / 16;  // 16-lane DPP rows per workgroup
+    __shared__ float wmax[kDymaxItems][kRows];
     float m[kDymaxItems];
     // object of the first item by search; the next items follow it (consecutive
     // items belong to the same object or to the ones after it)
@@ -221,11 +222,15 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_dymax(ScatterArgs a)
             }
         }
     }
+    // Row maxima by DPP row shifts: lanes past the row's end read 0, the
+    // identity of a maximum of |dy| values; the row's first lane ends with it.
 #pragma unroll
     for (int j = 0; j < kDymaxItems; ++j) {
-#pragma unroll
-        for (int dd = 32; dd >= 1; dd >>= 1) m[j] = fmaxf(m[j], __shfl_xor(m[j], dd));
-        if ((threadIdx.x & 63) == 0) wmax[j][threadIdx.x >> 6] = m[j];
+        m[j] = fmaxf(m[j], dpp_f32<0x101>(m[j]));
+        m[j] = fmaxf(m[j], dpp_f32<0x102>(m[j]));
+        m[j] = fmaxf(m[j], dpp_f32<0x104>(m[j]));
+        m[j] = fmaxf(m[j], dpp_f32<0x108>(m[j]));
+        if ((threadIdx.x & 15) == 0) wmax[j][threadIdx.x >> 4] = m[j];
     }
     __syncthreads();
     if (threadIdx.x < kDymaxItems) {
@@ -235,7 +240,7 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_dymax(ScatterArgs a)
             int l, bx;
             split_item(item - o.item_off, o.n_blocks, l, bx);
             float bm = 0.0f;
-            for (int w = 0; w < kPlaceThreads / 64; ++w) bm = fmaxf(bm, wmax[threadIdx.x][w]);
+            for (int w = 0; w < kRows; ++w) bm = fmaxf(bm, wmax[threadIdx.x][w]);
             a.block_max[o.bmax_off + (int64_t)l * o.n_blocks + bx] = bm;
         }
     }
