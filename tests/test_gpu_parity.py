@@ -12,10 +12,10 @@ import numpy as np
 import pytest
 
 import oracle as orc
-from parity_util import TOL_FP32, assert_close, rel_errors
+from parity_util import TOL_FP32, assert_close
 from synth.arch import ARCH_LARGE, ARCH_SMALL, Arch
 from synth.params import init_params
-from synth.workloads import (PRIOR_SAMPLE, LossSpec, SampleSpec, prior_batch, prior_world,
+from synth.workloads import (LossSpec, SampleSpec, prior_batch, prior_world,
                              small_batch, uniform_xi)
 
 pytestmark = pytest.mark.gpu
