@@ -299,6 +299,66 @@ def test_p7_draws_follow_termination_pmf():
     assert chi2 < dof + 3 * math.sqrt(2 * dof), (chi2, dof)
 
 
+def _edge_cdf(prior, pts, delta_nocs):
+    """Eq. (6) CDF at the N_c + 1 bin edges, from the product form of Eq. (4)
+    and (5) on the prior values at the bin midpoints (not the telescoped
+    exponential form the oracle evaluates)."""
+    sig = orc.prior_lookup(prior, pts)
+    occ = 1.0 - np.exp(-sig * delta_nocs)
+    surv = np.concatenate([[1.0], np.cumprod(1.0 - occ)[:-1]])
+    term = occ * surv
+    return np.concatenate([[0.0], np.cumsum(term) / term.sum()])
+
+
+@pytest.mark.parametrize("dscale", [1.0, 3.0])
+def test_p7_draw_position_inverts_piecewise_linear_cdf(dscale):
+    """Inverse transform sampling on the discrete CDF (Sec. III-B), read as
+    linear inside a bin: each draw t_k is the point where the piecewise-linear
+    interpolation of the edge CDF reaches u_k = (k + xi_k)/N_r, so
+    interp(t_k; edges, CDF) = u_k.  A bin midpoint, swapped bin endpoints or
+    a shifted bin all fail this."""
+    rng = np.random.default_rng(21)
+    R, Nc, Nr, n = 16, 12, 40, 96
+    prior = rng.uniform(0.0, 12.0, (R, R, R)).astype(np.float32)
+    prior[:, :, : R // 3] = 0.0            # empty stretches: zero-mass bins
+    o, d = axis_rays(n, rng)
+    d = (d * np.float32(dscale)).astype(np.float32)
+    xi = uniform_xi(rng, n, Nr)
+    out = run_sampler(o, d, xi, prior, Nc, Nr)
+    assert np.all(out["flags"] == 0)
+    u = (np.arange(Nr)[None, :] + xi.astype(np.float64)) / Nr
+    # world distance: the ray meets x_nocs = 0 at t = 1/(2|d|) and leaves at 3/(2|d|)
+    tn, tf = 0.5 / dscale, 1.5 / dscale
+    edges = tn + (tf - tn) * np.arange(Nc + 1) / Nc
+    worst = 0.0
+    for r in range(n):
+        yz = o[r, 1:].astype(np.float64) + 0.5
+        pts = np.stack([(np.arange(Nc) + 0.5) / Nc, np.full(Nc, yz[0]), np.full(Nc, yz[1])], 1)
+        cdf = _edge_cdf(prior, pts, 1.0 / Nc)
+        got = np.interp(out["t"][r], edges, cdf)
+        worst = max(worst, float(np.abs(got - u[r]).max()))
+    assert worst < 1e-12, worst
+
+
+def test_p7_draw_position_small_prior_limit():
+    """As a constant prior s -> 0 the CDF becomes i/N_c and the draws tend to
+    the stratified uniform ones, t_k -> t_n + u_k (t_f - t_n), with an error
+    of order s."""
+    rng = np.random.default_rng(22)
+    n, Nc, Nr = 64, 16, 48
+    o, d = axis_rays(n, rng)
+    xi = uniform_xi(rng, n, Nr)
+    u = (np.arange(Nr)[None, :] + xi.astype(np.float64)) / Nr
+    errs = []
+    for s in (1e-2, 1e-3):
+        out = run_sampler(o, d, xi, np.full((4, 4, 4), s, np.float32), Nc, Nr, eps=1e-6)
+        assert np.all(out["flags"] == 0)
+        e = np.abs(out["t"] - (0.5 + u)).max()
+        assert e < s, (s, e)
+        errs.append(e)
+    assert errs[1] < errs[0] / 5  # the error shrinks with s
+
+
 def test_sampler_merge_includes_coarse_midpoints():
     """With the coarse samples rendered, the sorted union of the N_c bin
     midpoints and the N_r draws is returned, with delta = next gap * |d|."""
