@@ -276,6 +276,26 @@ prenom_status prenom_prior_refresh(const prenom_model* model, int32_t R, float* 
                                    size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * prenom_prior_refresh_noalloc -- prenom_prior_refresh for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight mapping
+ * loops, harnesses that forbid hipMalloc).  Same arguments, result and errors
+ * as prenom_prior_refresh, without the workspace: the per-vertex features
+ * and head outputs of each chunk live in a fixed array of
+ * PRENOM_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on
+ * until the process ends.  The grid is processed in chunks sized to that
+ * array (any R in [2, PRENOM_MAX_PRIOR_RES]); an architecture whose features
+ * of 1024 vertices do not fit returns PRENOM_ERR_WORKSPACE before any launch.
+ * Nothing is allocated or freed: the array's device address is looked up
+ * once per device, on the first call with that device current (make that
+ * first call outside graph capture).  Every call on a GPU shares that GPU's
+ * array, so calls that overlap on one GPU (different streams without
+ * ordering) race; calls on one stream are ordered and safe.
+ * ---------------------------------------------------------------------- */
+#define PRENOM_NOALLOC_SCRATCH_BYTES (((size_t)16) << 20)
+size_t prenom_noalloc_scratch_bytes(void);
+prenom_status prenom_prior_refresh_noalloc(const prenom_model* model, int32_t R, float* prior_out, void* stream);
+
+/* ------------------------------------------------------------------------
  * prenom_encode -- the hash encoding alone (Sec. III-B "Object-level NeRFs"):
  * pos [n][3] in [0,1]^3 -> features [L][n][F] (level-major); corner_idx
  * [L][n][8] (int32 table row of each cell corner, corner e = (e&1, e>>1&1,

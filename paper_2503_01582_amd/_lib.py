@@ -115,6 +115,10 @@ def lib():
         L.prenom_prior_refresh_workspace_size.argtypes = [C.POINTER(PrenomArch), C.c_int32]
         L.prenom_prior_refresh.restype = C.c_int
         L.prenom_prior_refresh.argtypes = [C.POINTER(PrenomModel), C.c_int32, _vp, _vp, C.c_size_t, _vp]
+        L.prenom_noalloc_scratch_bytes.restype = C.c_size_t
+        L.prenom_noalloc_scratch_bytes.argtypes = []
+        L.prenom_prior_refresh_noalloc.restype = C.c_int
+        L.prenom_prior_refresh_noalloc.argtypes = [C.POINTER(PrenomModel), C.c_int32, _vp, _vp]
         PB = C.POINTER(PrenomBatch)
         L.prenom_batch_param_count.restype = C.c_int64
         L.prenom_batch_param_count.argtypes = [C.POINTER(PrenomObject), C.c_int32]

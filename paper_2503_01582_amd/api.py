@@ -352,6 +352,21 @@ def prenom_prior_refresh(model: Model, R: int = 64, out: Optional[torch.Tensor] 
     return out
 
 
+def prenom_prior_refresh_noalloc(model: Model, R: int = 64, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """prenom_prior_refresh without a workspace: the library's fixed scratch
+    array holds the per-chunk intermediates, so nothing is allocated on the
+    device by the call (`out` is the caller's; pass one to allocate nothing)."""
+    if out is None:
+        out = torch.empty((R, R, R), dtype=torch.float32, device=model.params.device)
+    _dev(out, torch.float32, "out")
+    if out.numel() != R * R * R:
+        raise ValueError(f"out holds {out.numel()} floats, not R^3 = {R ** 3}")
+    mc = model.c_struct()
+    st = L.lib().prenom_prior_refresh_noalloc(C.byref(mc), R, _ptr(out), _stream())
+    L.check(st, "prenom_prior_refresh_noalloc")
+    return out
+
+
 def prenom_encode(arch, table: torch.Tensor, pos: torch.Tensor, with_corners=False):
     _dev(table, torch.float32, "table")
     _dev(pos, torch.float32, "pos")

@@ -181,6 +181,36 @@ prenom_status check_render_cfg(const prenom_render_cfg* cfg)
     return PRENOM_OK;
 }
 
+prenom_status check_model(const prenom_model* m, bool need_grads)
+{
+    if (!m) return fail(PRENOM_ERR_INVALID_ARG, "model is NULL");
+    const prenom_status st = check_supported(&m->arch);
+    if (st != PRENOM_OK) return st;
+    if (!m->params || !aligned(m->params, 16)) return fail(PRENOM_ERR_INVALID_ARG, "params NULL or not 16-byte aligned");
+    if (need_grads && (!m->grads || !aligned(m->grads, 16)))
+        return fail(PRENOM_ERR_INVALID_ARG, "grads NULL or not 16-byte aligned");
+    if (m->arch.table_dtype == PRENOM_F16 && (!m->table_lp || !aligned(m->table_lp, 8)))
+        return fail(PRENOM_ERR_INVALID_ARG, "table_dtype FP16 needs an 8-byte aligned table_lp");
+    if (m->loss_scale && !m->scaler_state) return fail(PRENOM_ERR_INVALID_ARG, "loss_scale needs scaler_state");
+    return PRENOM_OK;
+}
+
+prenom_status prior_refresh_chunks(const prenom_model* model, int32_t R, float* prior_out, float* y, float* sc,
+                                   int64_t chunk, hipStream_t s)
+{
+    const prenom_arch* a = &model->arch;
+    const int64_t n = (int64_t)R * R * R;
+    const void* tlp = a->table_dtype == PRENOM_F16 ? model->table_lp : nullptr;
+    for (int64_t p0 = 0; p0 < n; p0 += chunk) {
+        const int64_t cnt = n - p0 < chunk ? n - p0 : chunk;
+        PRENOM_LAUNCH("k_encode_grid", s, launch_encode_grid(grid_info(a), model->params, tlp, R, p0, cnt, y, s));
+        PRENOM_LAUNCH("k_mlp_fwd", s,
+                      mlp_fwd_any(mlp_shape(a), model->params + table_params(a), y, cnt, sc, nullptr, s));
+        PRENOM_LAUNCH("k_density_grid", s, launch_density_grid(sc, cnt, prior_out + p0, s));
+    }
+    return PRENOM_OK;
+}
+
 }  // namespace host
 }  // namespace prenom
 
@@ -248,19 +278,6 @@ WsLayout ws_layout(const prenom_arch* a, int64_t n_rays, int32_t S)
     return w;
 }
 
-prenom_status check_model(const prenom_model* m, bool need_grads)
-{
-    if (!m) return fail(PRENOM_ERR_INVALID_ARG, "model is NULL");
-    const prenom_status st = check_supported(&m->arch);
-    if (st != PRENOM_OK) return st;
-    if (!m->params || !aligned(m->params, 16)) return fail(PRENOM_ERR_INVALID_ARG, "params NULL or not 16-byte aligned");
-    if (need_grads && (!m->grads || !aligned(m->grads, 16)))
-        return fail(PRENOM_ERR_INVALID_ARG, "grads NULL or not 16-byte aligned");
-    if (m->arch.table_dtype == PRENOM_F16 && (!m->table_lp || !aligned(m->table_lp, 8)))
-        return fail(PRENOM_ERR_INVALID_ARG, "table_dtype FP16 needs an 8-byte aligned table_lp");
-    if (m->loss_scale && !m->scaler_state) return fail(PRENOM_ERR_INVALID_ARG, "loss_scale needs scaler_state");
-    return PRENOM_OK;
-}
 
 prenom_status check_render(const prenom_model* model, const prenom_render_cfg* cfg, const float* ray_obj,
                            const float* t, const float* dt, const uint8_t* flags, int64_t n_rays, void* ws,
@@ -347,19 +364,8 @@ prenom_status prenom_prior_refresh(const prenom_model* model, int32_t R, float* 
     const size_t need = prior_refresh_ws(a, R, &sc_off);
     if (!workspace || !aligned(workspace, kAlign)) return fail(PRENOM_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
     if (ws_bytes < need) return fail(PRENOM_ERR_WORKSPACE, "workspace %zu bytes < %zu", ws_bytes, need);
-    hipStream_t s = (hipStream_t)stream;
-    const int64_t n = (int64_t)R * R * R;
-    float* y = at<float>(workspace, 0);
-    float* sc = at<float>(workspace, sc_off);
-    const void* tlp = a->table_dtype == PRENOM_F16 ? model->table_lp : nullptr;
-    for (int64_t p0 = 0; p0 < n; p0 += kPriorChunk) {
-        const int64_t cnt = n - p0 < kPriorChunk ? n - p0 : kPriorChunk;
-        PRENOM_LAUNCH("k_encode_grid", s, launch_encode_grid(grid_info(a), model->params, tlp, R, p0, cnt, y, s));
-        PRENOM_LAUNCH("k_mlp_fwd", s,
-                      mlp_fwd_any(mlp_shape(a), model->params + table_params(a), y, cnt, sc, nullptr, s));
-        PRENOM_LAUNCH("k_density_grid", s, launch_density_grid(sc, cnt, prior_out + p0, s));
-    }
-    return PRENOM_OK;
+    return prior_refresh_chunks(model, R, prior_out, at<float>(workspace, 0), at<float>(workspace, sc_off), kPriorChunk,
+                                (hipStream_t)stream);
 }
 
 prenom_status prenom_sample(const prenom_sample_cfg* cfg, const float* rays_o, const float* rays_d, const float* xi,

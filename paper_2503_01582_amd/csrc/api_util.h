@@ -49,6 +49,11 @@ int64_t mlp_params_of(const MlpShape& m);
 GridInfo grid_info(const prenom_arch* a);
 prenom_status check_sample_cfg(const prenom_sample_cfg* cfg, bool need_prior_fields);
 prenom_status check_render_cfg(const prenom_render_cfg* cfg);
+prenom_status check_model(const prenom_model* m, bool need_grads);
+// Prior refresh of R^3 vertices in chunks of `chunk`: features into y
+// ([L][chunk][2]), head outputs into sc ([chunk][4]), densities into prior_out.
+prenom_status prior_refresh_chunks(const prenom_model* model, int32_t R, float* prior_out, float* y, float* sc,
+                                   int64_t chunk, hipStream_t s);
 
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
