@@ -1,7 +1,13 @@
 """Training-step throughput of the per-object NeRF step on one MI355X.
 
 Workloads (--workload):
-  prior   (default) one object, prior-based sampling: 65536 rays per step
+  headline (default) the target comparison: batch48 with the MLP in BF16
+          (graph-replayed) against prior (FP32, one object), both timed in
+          the same run; value = batch48 rays/s, the ratio in
+          config.speedup_vs_fp32_single_object, and the held-out PSNR of the
+          reduced-precision forms against FP32 after 500 steps (three seeds,
+          from the committed summary of that test run) beside it.
+  prior   one object, prior-based sampling: 65536 rays per step
           drawn from 16 cameras at 640x480 around a random 3-ellipsoid
           object, 16 coarse + 48 inverse-CDF samples per ray (64 rendered),
           hash grid 16 levels x 2^19 x 2 features, MLP 64 x 2 hidden, FP32,
@@ -29,8 +35,12 @@ Workloads (--workload):
           loop rays/s.
 
 Prints one JSON line: rays/s, the roofline position of the dominant kernel
-(per-kernel HIP-event timing) and, for the prior workload, the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+and, for the headline and prior workloads, the FP64 CPU oracle timed on a
+bounded sample (single thread and every host CPU).  The timed steps run
+without instrumentation; per-kernel times come from a separate pass of the
+same steps in which every launch sits between two HIP events on its stream
+(eager steps for the batched workloads, whose timed steps are graph
+replays).
 """
 from __future__ import annotations
 
@@ -95,13 +105,13 @@ def refresh_work(arch, n):
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_prior_65536rays.md")
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per step of `kernel` from the committed counter summary (the
-    fenced json block of profiles/hbm_traffic_prior_65536rays.md), or None
-    when there is none or a source it was measured with has changed since."""
+def measured_traffic(kernel: str, summary: str = TRAFFIC_SUMMARY):
+    """HBM bytes per step of `kernel` from a committed counter summary (the
+    fenced json block of a profiles/hbm_traffic_*.md file), or None when there
+    is none or a source it was measured with has changed since."""
     import hashlib
     try:
-        text = open(TRAFFIC_SUMMARY).read()
+        text = open(summary).read()
         block = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
     except (OSError, IndexError, ValueError):
         return None
@@ -156,8 +166,23 @@ def kernel_table(kt, steps, ms_per_step, work, mlp_peak, log):
     return kern, roofline
 
 
-def cpu_baseline(batch, params, n_sample_rays):
-    """FP64 oracle, one full step on a bounded sample of the batch's rays."""
+def cpu_model():
+    """Host CPU model name and the number of CPUs this process may use."""
+    name = "unknown"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                name = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return name, len(os.sched_getaffinity(0))
+
+
+def oracle_step_seconds(batch, params, n_sample_rays):
+    """FP64 oracle on the first n_sample_rays rays of the batch: (seconds of
+    the per-ray work -- sample, forward + loss, backward --, seconds of Adam
+    over every parameter)."""
     import oracle as orc
     s = batch.sample
     sel = slice(0, n_sample_rays)
@@ -171,13 +196,37 @@ def cpu_baseline(batch, params, n_sample_rays):
     kw = dict(tgt_rgb=batch.tgt_rgb[sel], tgt_depth=batch.tgt_depth[sel], mask=batch.mask[sel])
     orc.render_fwd(batch.arch, params, *geo, **kw)
     g = orc.render_bwd(batch.arch, params, *geo, **kw)
+    t1 = time.perf_counter()
     z = np.zeros_like(params)
     orc.adam(params, g.astype(np.float32), z, z, lr=1e-2, beta1=0.9, beta2=0.99, eps=1e-15, step=1)
-    dt = time.perf_counter() - t0
-    return dict(value=n_sample_rays / dt, unit="rays/s", cores=orc.max_threads(), kind="oracle",
-                sample=f"{n_sample_rays} of the {batch.n_rays} rays of one batch, one full step "
-                       f"(sample, fwd + loss, bwd, Adam over all {batch.arch.n_params} parameters), "
-                       f"FP64, {dt:.1f} s")
+    return t1 - t0, time.perf_counter() - t1
+
+
+def cpu_baseline(batch, params, n_sample_rays):
+    """The FP64 oracle (untuned) on the host cores: the per-ray work of a
+    sub-batch of n_sample_rays rays of the single-object prior workload, plus
+    Adam over all its parameters, once on one thread and once on every CPU
+    this process may use.  Rays/s of a whole batch, extrapolated linearly in
+    rays (the per-ray work is linear in rays; Adam is counted once)."""
+    import oracle as orc
+    model, ncpu = cpu_model()
+    res = {}
+    for threads in (1, ncpu):
+        orc.set_threads(threads)
+        log(f"bench: CPU oracle, {n_sample_rays} rays, {threads} thread(s)")
+        t_rays, t_adam = oracle_step_seconds(batch, params, n_sample_rays)
+        step_s = t_rays * batch.n_rays / n_sample_rays + t_adam
+        res[threads] = (batch.n_rays / step_s, t_rays, t_adam)
+        log(f"bench:   {t_rays:.2f} s per-ray work, {t_adam:.2f} s Adam -> {batch.n_rays / step_s:.1f} rays/s")
+    orc.set_threads(ncpu)
+    v1, r1, a1 = res[1]
+    vn, rn, an = res[ncpu]
+    return dict(value=round(vn, 1), unit="rays/s", cores=orc.max_threads(), kind="oracle",
+                single_thread_value=round(v1, 1), cpu_model=model, nproc=ncpu,
+                sample=f"{n_sample_rays} of the {batch.n_rays} rays of one batch of the single-object prior "
+                       f"workload (sample, forward + loss, backward: {rn:.2f} s on {ncpu} threads, {r1:.2f} s on "
+                       f"one), plus Adam over all {batch.arch.n_params} parameters ({an:.2f} s / {a1:.2f} s), "
+                       f"FP64; rays/s of the whole {batch.n_rays}-ray step, extrapolated linearly in rays")
 
 
 def log(*a):
@@ -276,24 +325,27 @@ def run_prior(args):
         tr.step(db)
     torch.cuda.synchronize()
     log(f"bench: {args.steps} timed steps")
-    api.prenom_profile_begin()
     t0 = time.perf_counter()
     ms = timed_loop(lambda: tr.step(db), args.steps)
     wall = time.perf_counter() - t0
-    kt = api.prenom_profile_end()
-    if args.copy_calibration:
-        copy_calibration()
     ms_per_step = ms / args.steps
     value = args.rays * args.steps / (ms / 1e3)
     log(f"bench: {ms_per_step:.3f} ms/step ({wall / args.steps * 1e3:.3f} ms wall), "
         f"loss {float(tr._out['loss'].item()):.4e}")
-    kern, roofline = kernel_table(kt, args.steps, ms_per_step, algorithmic_work(arch, args.rays, S, batch.sample.n_fine),
-                                  FP32_MFMA_PEAK_TFLOPS, log)
+    # per-kernel times: the same steps again, each launch between two HIP events
+    prof_steps = max(3, min(args.steps, 20))
+    api.prenom_profile_begin()
+    ms_prof = timed_loop(lambda: tr.step(db), prof_steps)
+    kt = api.prenom_profile_end()
+    if args.copy_calibration:
+        copy_calibration()
+    log(f"bench: {ms_prof / prof_steps:.3f} ms/step with per-launch events ({prof_steps} steps)")
+    kern, roofline = kernel_table(kt, prof_steps, ms_prof / prof_steps,
+                                  algorithmic_work(arch, args.rays, S, batch.sample.n_fine), FP32_MFMA_PEAK_TFLOPS, log)
     if args.rays == 65536:
         roofline["traffic"] = measured_traffic(roofline["kernel"])
     cpu = None
     if not args.no_cpu_baseline:
-        log(f"bench: CPU oracle on {args.cpu_rays} rays")
         cpu = cpu_baseline(batch, params, args.cpu_rays)
     config = dict(workload="prior-sampled object NeRF training step", n_rays=args.rays,
                   samples_per_ray=S, n_coarse=batch.sample.n_coarse, n_fine=batch.sample.n_fine,
@@ -535,15 +587,55 @@ def run_reptile(args):
     return value, ms_per_step, "fp32", config, roofline, kern, None, extra
 
 
+PSNR_SUMMARY = os.path.join(ROOT, "profiles", "psnr_batch48_2p20rays_500steps.md")
+HEADLINE_TRAFFIC = os.path.join(ROOT, "profiles", "hbm_traffic_batch48_2p20rays.md")
+
+
+def held_psnr_delta():
+    """Mean held-out PSNR of the 48-object reduced-precision forms minus the
+    FP32 form after 500 steps, three seeds (fenced json block of the
+    committed summary of that test's run), or None."""
+    try:
+        text = open(PSNR_SUMMARY).read()
+        return json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+
+
+def run_headline(args):
+    """The target comparison: the 48-object batched step with the MLP in
+    BF16 (FP16 table copy, FP32 gradients and masters, loss scaling),
+    graph-replayed, against the plain FP32 single-object step of the prior
+    workload, both timed in this run without per-launch instrumentation."""
+    import torch
+    args.no_sequential = True
+    value, ms, dtype, config, roofline, kern, _, extra = run_batch(args, 48, 1 << 20, args.mlp_dtype, "fp16", seed=5)
+    roofline["traffic"] = measured_traffic(roofline["kernel"], HEADLINE_TRAFFIC)
+    torch.cuda.empty_cache()
+    args.no_extras = True
+    v32, ms32, _, cfg32, roof32, _, cpu, _ = run_prior(args)
+    ratio = value / v32
+    log(f"bench: batched {args.mlp_dtype} {value / 1e6:.2f} M rays/s vs FP32 single object {v32 / 1e6:.2f} M rays/s: "
+        f"{ratio:.3f}x")
+    config["compared_with"] = dict(workload=cfg32["workload"] + " (FP32, one object)", n_rays=cfg32["n_rays"],
+                                   ms_per_step=round(ms32, 4), rays_per_s=round(v32, 1),
+                                   dominant=roof32)
+    config["speedup_vs_fp32_single_object"] = round(ratio, 4)
+    config["psnr_vs_fp32_after_500_steps"] = held_psnr_delta()
+    extra = dict(extra, speedup_vs_fp32_single_object=round(ratio, 4))
+    return value, ms, dtype, config, roofline, kern, cpu, extra
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", choices=("prior", "autograd", "batch24", "batch48", "reptile"), default="prior")
-    ap.add_argument("--mlp-dtype", choices=("bf16", "fp16"), default="bf16", help="batch48 only")
+    ap.add_argument("--workload", choices=("headline", "prior", "autograd", "batch24", "batch48", "reptile"),
+                    default="headline")
+    ap.add_argument("--mlp-dtype", choices=("bf16", "fp16"), default="bf16", help="headline and batch48")
     ap.add_argument("--rays", type=int, default=65536, help="prior workload only")
-    ap.add_argument("--cpu-rays", type=int, default=65536)
+    ap.add_argument("--cpu-rays", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sequential", action="store_true", help="batch workloads: skip the sequential comparison")
     ap.add_argument("--no-tune", action="store_true", help="batch workloads: library default tiles if none cached")
@@ -560,7 +652,9 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
-    if args.workload == "prior":
+    if args.workload == "headline":
+        res = run_headline(args)
+    elif args.workload == "prior":
         res = run_prior(args)
     elif args.workload == "autograd":
         res = run_autograd(args)

@@ -96,6 +96,7 @@ def lib():
                                C.c_double, C.c_double, C.c_int64, _f64p, _f64p, _f64p]
         L.orc_positions.argtypes = [_f32p, _f32p, C.c_int64, C.c_int32, _f32p]
         L.orc_max_threads.restype = C.c_int32
+        L.orc_set_threads.argtypes = [C.c_int32]
         _lib = L
     return _lib
 
@@ -144,6 +145,11 @@ def param_count(arch) -> int:
 
 def max_threads() -> int:
     return int(lib().orc_max_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's per-ray loops from now on (timing only)."""
+    lib().orc_set_threads(int(n))
 
 
 # ---------------------------------------------------------------- sampler

@@ -1018,6 +1018,17 @@ void orc_round16_array(const double* x, int64_t n, int32_t dtype, double* out)
     for (int64_t i = 0; i < n; ++i) out[i] = orc_round16(x[i], dtype);
 }
 
+/* Thread count of the per-ray parallel loops (timing only; results do not
+ * depend on it). */
+void orc_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int32_t orc_max_threads(void)
 {
 #ifdef _OPENMP
