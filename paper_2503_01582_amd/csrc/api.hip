@@ -222,7 +222,7 @@ using namespace prenom::host;
 
 struct WsLayout {
     size_t y, sc, dout, dy, ray_state, loss_partial, mlp_partial, act;
-    size_t counts, offsets, block_max, level_max, tile_exp, tile_total, tile_start, chunk_start, work_counter, keys, vals, total;
+    size_t counts, offsets, block_max, level_max, tile_exp, tile_total, tile_start, chunk_start, work_counter, recs, total;
     int n_loss_blocks, n_mlp_slots;
     ScatterObj plan;
 };
@@ -270,10 +270,8 @@ WsLayout ws_layout(const prenom_arch* a, int64_t n_rays, int32_t S)
     off = align_up(off + (nt + 1) * sizeof(uint64_t));
     w.work_counter = off;
     off = align_up(off + sizeof(uint64_t));
-    w.keys = off;
-    off = align_up(off + (size_t)scatter_records(w.plan) * sizeof(uint16_t));
-    w.vals = off;
-    off = align_up(off + (size_t)scatter_records(w.plan) * 2 * sizeof(float));
+    w.recs = off;
+    off = align_up(off + (size_t)scatter_records(w.plan) * sizeof(uint64_t));
     w.total = off;
     return w;
 }
@@ -539,9 +537,9 @@ prenom_status prenom_render_bwd(const prenom_model* model, const prenom_render_c
     sa.tile_start = at<uint64_t>(workspace, w.tile_start);
     sa.chunk_start = at<uint64_t>(workspace, w.chunk_start);
     sa.work_counter = at<unsigned long long>(workspace, w.work_counter);
-    sa.keys = at<uint16_t>(workspace, w.keys);
-    sa.vals = at<float2>(workspace, w.vals);
+    sa.recs = at<uint64_t>(workspace, w.recs);
     sa.n_records = scatter_records(w.plan);
+    sa.nonfinite = model->loss_scale ? model->scaler_state : nullptr;
     sa.fwd_counts = 1;  // render_fwd (or the recompute above) wrote the tile histograms
     sa.merge_runs = 1;
     for (int ph = 0; ph < kScatterPhases; ++ph)

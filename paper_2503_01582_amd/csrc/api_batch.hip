@@ -52,7 +52,7 @@ struct Plan {
     // workspace offsets (bytes)
     size_t o_dev, o_sc, o_red, o_fwd, o_bwd;
     size_t y, sc_out, dout, dy, ray_state, ray_loss, partial, act, cnt, offs, block_max, level_max, tile_exp, tile_total,
-        tile_start, chunk_start, work_counter, keys, vals, total;
+        tile_start, chunk_start, work_counter, recs, total;
     uint64_t fingerprint = 0;
 };
 
@@ -272,8 +272,7 @@ prenom_status build_plan(const prenom_batch* b, int32_t S, Plan& p)
     p.tile_start = take(sizeof(uint64_t) * (size_t)(p.n_tiles + 1));
     p.chunk_start = take(sizeof(uint64_t) * (size_t)(p.n_tiles + 1));
     p.work_counter = take(sizeof(uint64_t));
-    p.keys = take(sizeof(uint16_t) * (size_t)p.records);
-    p.vals = take(sizeof(float) * 2 * (size_t)p.records);
+    p.recs = take(sizeof(uint64_t) * (size_t)p.records);
     p.total = off;
     return PRENOM_OK;
 }
@@ -304,7 +303,8 @@ prenom_status check_params(const prenom_batch* b, const Plan& p, bool need_grads
     return PRENOM_OK;
 }
 
-ScatterArgs scatter_args(const Plan& p, void* ws, const float* ray_obj, const float* t, float* grads)
+ScatterArgs scatter_args(const Plan& p, void* ws, const float* ray_obj, const float* t, float* grads,
+                         int32_t* nonfinite)
 {
     ScatterArgs sa{};
     sa.S = p.S;
@@ -328,9 +328,9 @@ ScatterArgs scatter_args(const Plan& p, void* ws, const float* ray_obj, const fl
     sa.tile_start = at<uint64_t>(ws, p.tile_start);
     sa.chunk_start = at<uint64_t>(ws, p.chunk_start);
     sa.work_counter = at<unsigned long long>(ws, p.work_counter);
-    sa.keys = at<uint16_t>(ws, p.keys);
-    sa.vals = at<float2>(ws, p.vals);
+    sa.recs = at<uint64_t>(ws, p.recs);
     sa.n_records = p.records;
+    sa.nonfinite = nonfinite;
     sa.fwd_counts = 1;  // fwd_features (render_fwd, or the recompute in render_bwd) wrote the histograms
     sa.merge_runs = 1;
     return sa;
@@ -561,7 +561,8 @@ prenom_status prenom_batch_render_bwd(const prenom_batch* batch, const prenom_re
                   launch_reduce_partials_batch(at<const MlpRed>(workspace, p.o_red), p.n_obj, p.n_mlp_total, partial,
                                                batch->grads, s));
     {
-        const ScatterArgs sa = scatter_args(p, workspace, ray_obj, t, batch->grads);
+        const ScatterArgs sa = scatter_args(p, workspace, ray_obj, t, batch->grads,
+                                            batch->loss_scale ? batch->scaler_state : nullptr);
         for (int ph = 0; ph < kScatterPhases; ++ph)
             PRENOM_LAUNCH(ph == 0 ? "k_scatter_dymax" : kScatterPhaseNames[ph], s, launch_scatter_phase(sa, ph, s));
     }

@@ -342,9 +342,9 @@ struct ScatterArgs {
     uint64_t* tile_start;   // [n_tiles + 1]
     uint64_t* chunk_start;  // [n_tiles + 1]
     unsigned long long* work_counter;
-    uint16_t* keys;         // [records]
-    float2* vals;           // [records]
-    int64_t n_records;      // length of keys and vals
+    uint64_t* recs;         // [records] packed records (scatter.hip: row, shared exponent, two mantissas)
+    int64_t n_records;      // length of recs
+    int32_t* nonfinite;     // set to 1 when a dy entry is not finite (loss scaling), or null
     // 1: counts were written by the training forward (TileHist); the first
     // phase then only takes the per-block max |dy|, and the scan checks the
     // histograms hold at most n_records (else place and reduce do nothing).

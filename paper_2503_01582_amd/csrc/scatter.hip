@@ -16,8 +16,9 @@
 //            tile record ranges are cut into chunks of bounded length, and each
 //            tile gets a fixed-point scale 2^e
 //   place  : the block recomputes its contributions, sorts them by tile in LDS
-//            and writes each tile's run contiguously (coalesced) as records
-//            (row within tile: u16, contribution: float2)
+//            and writes each tile's run contiguously (coalesced) as 8-byte
+//            records (row within the tile, and the contribution's two
+//            features as 22-bit mantissas under one shared exponent)
 //   reduce : a persistent grid takes chunks from a counter; each chunk is
 //            accumulated in LDS and added to the gradient rows -- plain
 //            read-modify-write when the tile has one chunk (the block owns it),
@@ -29,6 +30,11 @@
 // contribution is rounded by at most 2^-(e+1) <= 2^-51 max|dy|, far below FP32
 // resolution of the result.  Integer sums do not depend on order, so a tile
 // with one chunk gets a bit-reproducible gradient.
+//
+// A record keeps 21 significant bits of the larger of its two features (an
+// FP32 value has 24): each feature is within 2^-21 of the larger one's
+// magnitude; the sum over records is then exact up to the fixed-point
+// rounding.
 //
 // Corner rows and weights are computed by the same function as the forward
 // encoding, so count and place agree exactly.
@@ -50,6 +56,55 @@ constexpr int kReduceThreads = 1024;
 constexpr int kRun = 8;            // consecutive records per thread and load
 constexpr int kRunsPerThread = 3;  // runs in flight per thread
 constexpr int64_t kChunk = (int64_t)1 << 21;  // records per reduce work item
+
+// ---------------------------------------------------------------- records
+// One 64-bit word per record: bits 0-12 the row within the tile, bits 13-19
+// an exponent offset r, bits 20-41 and 42-63 the two's-complement mantissas
+// qx, qy; the record's value is (qx, qy) * 2^(E - r - 21), E being the
+// level's record exponent.  A record whose larger feature lies below
+// 2^(E - 128) (r beyond 7 bits) is dropped.
+constexpr int kRecExpBits = 7;
+constexpr int kRecMantBits = 22;
+
+// Record exponent E of a level whose largest |dy| is lm: a record sums at most
+// 8 contributions w dy with 0 <= w <= 1, so |record| <= 8 lm < 2^(E - 1).
+__device__ __forceinline__ int level_rec_exp(float lm)
+{
+    int e = 0;
+    frexpf(lm, &e);  // lm < 2^e
+    return e + 4;
+}
+
+__device__ __forceinline__ uint64_t encode_record(float2 v, int E, uint32_t row)
+{
+    const float m = fmaxf(fabsf(v.x), fabsf(v.y));
+    uint64_t rec = row;
+    if (m > 0.0f) {
+        int k = 0;
+        frexpf(m, &k);  // 2^(k-1) <= m < 2^k
+        float rx = rintf(ldexpf(v.x, 21 - k)), ry = rintf(ldexpf(v.y, 21 - k));
+        if (fmaxf(fabsf(rx), fabsf(ry)) >= 2097152.0f) {  // the larger one rounded up to 2^21
+            ++k;
+            rx = rintf(ldexpf(v.x, 21 - k));
+            ry = rintf(ldexpf(v.y, 21 - k));
+        }
+        const int r = E - k;
+        constexpr uint32_t kMant = (1u << kRecMantBits) - 1u;
+        if (r >= 0 && r < (1 << kRecExpBits))
+            rec |= (uint64_t)r << kTileBits | (uint64_t)((uint32_t)(int32_t)rx & kMant) << (kTileBits + kRecExpBits) |
+                   (uint64_t)((uint32_t)(int32_t)ry & kMant) << (kTileBits + kRecExpBits + kRecMantBits);
+    }
+    return rec;
+}
+
+// q * 2^sh rounded to an integer (halves upward), for |q| <= 2^21, sh <= 33.
+__device__ __forceinline__ long long scale_mantissa(long long q, int sh)
+{
+    if (sh >= 0) return q * (1ll << sh);
+    const int d = -sh;
+    return d > 62 ? 0ll : (q + (1ll << (d - 1))) >> d;
+}
+static_assert(kTileBits + kRecExpBits + 2 * kRecMantBits == 64, "record fields fill one word");
 
 
 // ---------------------------------------------------------------- object lookup
@@ -163,6 +218,7 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_count(ScatterArgs a)
     } else {
         has = s < o.n_s && load_contrib(a, o, l, s, d, c);
     }
+    if (a.nonfinite && s < o.n_s && !(isfinite(d.x) && isfinite(d.y))) a.nonfinite[0] = 1;
     if (has) {
         m = fmaxf(fabsf(d.x), fabsf(d.y));
         if (nt <= kAggregateTiles) {
@@ -201,6 +257,7 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_dymax(ScatterArgs a)
     constexpr int kRows = kPlaceThreads / 16;  // 16-lane DPP rows per workgroup
     __shared__ float wmax[kDymaxItems][kRows];
     float m[kDymaxItems];
+    bool bad = false;
     // object of the first item by search; the next items follow it (consecutive
     // items belong to the same object or to the ones after it)
     const int64_t item0 = (int64_t)blockIdx.x * kDymaxItems;
@@ -219,9 +276,13 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_dymax(ScatterArgs a)
             if (s < o.n_s) {
                 const float2 d = a.dy[o.dy_off + (int64_t)l * o.n_s + s];
                 m[j] = fmaxf(fabsf(d.x), fabsf(d.y));
+                bad |= !(isfinite(d.x) && isfinite(d.y));
             }
         }
     }
+    // a non-finite feature gradient (fmaxf would drop a NaN) marks the step
+    // for the loss scaler, which then skips the update
+    if (a.nonfinite && bad) a.nonfinite[0] = 1;
     // Row maxima by DPP row shifts: lanes past the row's end read 0, the
     // identity of a maximum of |dy| values; the row's first lane ends with it.
 #pragma unroll
@@ -343,9 +404,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scatter_scan_tiles(ScatterArgs
         r += a.tile_total[t];
         ck += (a.tile_total[t] + kChunk - 1) / kChunk;
         // largest e with vmax * records * 2^e < 2^62 (bound on any row's
-        // |sum| * 2^e) and vmax * 2^e < 2^50 (bound on one record, for the
-        // reduce's FP64 rounding), vmax the largest record: max|dy|, or 8
-        // max|dy| when repeated corners are merged
+        // |sum| * 2^e) and vmax * 2^e < 2^50 (bound on one record's fixed-point
+        // value, so a record's mantissa is shifted by at most 33 bits), vmax
+        // the largest record: max|dy|, or 8 max|dy| when repeated corners are
+        // merged
         const ScatterObj& o = sobj<kMany>(a, obj_of_tile<kMany>(a, t));
         const int l = level_of_tile(o, (int)(t - o.tile_off));
         // (a merged record sums at most 8 contributions, one per lane of a group)
@@ -372,23 +434,27 @@ __global__ __launch_bounds__(kScanThreads) void k_scatter_scan_tiles(ScatterArgs
     }
 }
 
-// Dynamic LDS of the place kernel for nt tiles of one level.
-__host__ __device__ constexpr size_t place_lds_bytes(int nt)
+// Dynamic LDS of the place kernel for nt tiles of one level, with staged tile
+// ids of tile_bytes bytes: record bases, staged records, histogram, block
+// segments, the total, staged tile ids.
+__host__ __device__ constexpr size_t place_lds_bytes(int nt, int tile_bytes)
 {
-    return (size_t)nt * 8 + (size_t)kRecordsPerBlock * 8 + (size_t)nt * 8 + 16 + (size_t)kRecordsPerBlock * 4;
+    return (size_t)nt * 8 + (size_t)kRecordsPerBlock * 8 + (size_t)nt * 8 + 16 + (size_t)kRecordsPerBlock * tile_bytes;
 }
 
-template <bool kMany>
+// TileT: type of the staged local tile ids (uint8_t when a level has at most
+// 256 tiles, which keeps the block's LDS under 40 KB: four blocks per CU).
+template <bool kMany, typename TileT>
 __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int nt_lds = a.tiles_max;
     uint64_t* gbase = reinterpret_cast<uint64_t*>(smem);
-    float2* s_val = reinterpret_cast<float2*>(gbase + nt_lds);
-    uint32_t* hist = reinterpret_cast<uint32_t*>(s_val + kRecordsPerBlock);
+    uint64_t* s_rec = gbase + nt_lds;
+    uint32_t* hist = reinterpret_cast<uint32_t*>(s_rec + kRecordsPerBlock);
     uint32_t* seg = hist + nt_lds;
     uint32_t* p_total = seg + nt_lds;
-    uint32_t* s_kt = p_total + 4;  // row within the tile | local tile << 16
+    TileT* s_tile = reinterpret_cast<TileT*>(p_total + 4);
     const int64_t item = blockIdx.x;
     const ScatterObj& o = sobj<kMany>(a, obj_of_item<kMany>(a, item));
     int l, bx;
@@ -403,6 +469,7 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
     const int own = min((int)threadIdx.x, nt - 1);
     const uint64_t own_start = a.tile_start[o.tile_off + tb + own];
     const uint32_t own_off = a.offsets[o.count_off + (int64_t)(tb + own) * o.n_blocks + bx];
+    const int E = level_rec_exp(a.level_max[o.lev_off + l]);
     for (int i = threadIdx.x; i < nt; i += kPlaceThreads) hist[i] = 0;
     __syncthreads();
     // pass 1: rank of each contribution within its tile (LDS atomics)
@@ -467,15 +534,15 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
         for (int i = threadIdx.x + kPlaceThreads; i < nt; i += kPlaceThreads)
             gbase[i] = a.tile_start[o.tile_off + tb + i] + cnt[(int64_t)(tb + i) * o.n_blocks + bx] - seg[i];
     }
-    // pass 2: stage the records sorted by tile (corners kept from pass 1)
+    // pass 2: stage the encoded records sorted by tile (corners kept from pass 1)
     if (has) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             if (!((heads >> e) & 1u)) continue;
             const uint32_t tt = c.row[e] >> kTileBits;
             const uint32_t p = seg[tt] + rank[e];
-            s_kt[p] = (c.row[e] & (kTileRows - 1)) | (tt << 16);
-            s_val[p] = val[e];
+            s_rec[p] = encode_record(val[e], E, c.row[e] & (kTileRows - 1));
+            s_tile[p] = (TileT)tt;
         }
     }
     __syncthreads();
@@ -487,32 +554,21 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
 #pragma unroll
     for (int h = 0; h < kPer; h += kHalf) {
         if (h * kPlaceThreads >= (int)total) break;
-        uint32_t kt[kHalf];
-#pragma unroll
-        for (int k = 0; k < kHalf; ++k) kt[k] = s_kt[threadIdx.x + (h + k) * kPlaceThreads];
+        uint32_t tt[kHalf];
+        uint64_t rec[kHalf];
 #pragma unroll
         for (int k = 0; k < kHalf; ++k) {
             const uint32_t p = threadIdx.x + (h + k) * kPlaceThreads;
-            const uint64_t dst = gbase[min(kt[k] >> 16, (uint32_t)nt - 1u)] + p;
-            const uint16_t key = (uint16_t)(kt[k] & 0xffffu);
-            const float2 v = s_val[p];
-            if (p < total && dst < (uint64_t)a.n_records) {
-                a.keys[dst] = key;
-                a.vals[dst] = v;
-            }
+            tt[k] = s_tile[p];
+            rec[k] = s_rec[p];
+        }
+#pragma unroll
+        for (int k = 0; k < kHalf; ++k) {
+            const uint32_t p = threadIdx.x + (h + k) * kPlaceThreads;
+            const uint64_t dst = gbase[min(tt[k], (uint32_t)nt - 1u)] + p;
+            if (p < total && dst < (uint64_t)a.n_records) a.recs[dst] = rec[k];
         }
     }
-}
-
-// round(v * 2^ex) as an integer, for |v * 2^ex| < 2^51 (the tile exponent
-// guarantees it).  v * 2^ex is exact in FP64; adding 1.5 * 2^52 rounds it to an
-// integer (to nearest, ties to even, as rintf) held in the low mantissa bits,
-// and subtracting the constant's bit pattern leaves that integer.
-__device__ __forceinline__ long long quantize(float v, int ex)
-{
-    constexpr double kMagic = 6755399441055744.0;  // 1.5 * 2^52
-    const double q = ldexp((double)v, ex) + kMagic;
-    return (long long)(__double_as_longlong(q) - __double_as_longlong(kMagic));
 }
 
 template <bool kMany>
@@ -548,31 +604,31 @@ __global__ __launch_bounds__(kReduceThreads) void k_scatter_reduce(ScatterArgs a
         const uint64_t r_end = min(r_begin + (uint64_t)kChunk, a.tile_start[tile + 1]);
         const bool owner = (a.chunk_start[tile + 1] - a.chunk_start[tile]) == 1;
         const int ex = a.tile_exp[tile];
+        // a record (qx, qy, r) is worth (qx, qy) 2^(E - r - 21); in fixed point
+        // at 2^ex that is (qx, qy) 2^(sh0 - r)
+        const int sh0 = level_rec_exp(a.level_max[o.lev_off + l]) - 21 + ex;
         for (int i = threadIdx.x; i < n_rows; i += kReduceThreads) {
             acc[i] = 0ull;
             acc[kTileRows + i] = 0ull;
         }
         __syncthreads();
-        // Each thread takes runs of kRun consecutive records (one 16-byte key
-        // load, four 16-byte value loads; runs start at multiples of kRun, so
-        // the loads are aligned and stay inside the record arrays, whose
-        // length is a multiple of kRun).  Records of a run outside
-        // [r_begin, r_end) add zero.  Consecutive records often carry the same
-        // row (neighbouring samples of one ray on a coarse level); such
-        // repeats are summed in registers first, so one LDS atomic per row
-        // and run is issued instead of one per record.
+        // Each thread takes runs of kRun consecutive records (four 16-byte
+        // loads; runs start at multiples of kRun, so the loads are aligned and
+        // stay inside the record array, whose length is a multiple of kRun).
+        // Records of a run outside [r_begin, r_end) add zero.  Consecutive
+        // records often carry the same row (neighbouring samples of one ray on
+        // a coarse level); such repeats are summed in registers first, so one
+        // LDS atomic per row and run is issued instead of one per record.
         const uint64_t q_begin = r_begin / kRun, q_end = (r_end + kRun - 1) / kRun;
         for (uint64_t q0 = q_begin + threadIdx.x; q0 < q_end; q0 += (uint64_t)kReduceThreads * kRunsPerThread) {
-            uint4 kw[kRunsPerThread];
-            float4 v4[kRunsPerThread][kRun / 2];
+            uint4 rw[kRunsPerThread][kRun / 2];
 #pragma unroll
             for (int u = 0; u < kRunsPerThread; ++u) {
                 const uint64_t q = q0 + (uint64_t)u * kReduceThreads;
                 const uint64_t qc = q < q_end ? q : q_begin;
-                kw[u] = *reinterpret_cast<const uint4*>(a.keys + qc * kRun);
-                const float4* vp = reinterpret_cast<const float4*>(a.vals + qc * kRun);
+                const uint4* rp = reinterpret_cast<const uint4*>(a.recs + qc * kRun);
 #pragma unroll
-                for (int i = 0; i < kRun / 2; ++i) v4[u][i] = vp[i];
+                for (int i = 0; i < kRun / 2; ++i) rw[u][i] = rp[i];
             }
 #pragma unroll
             for (int u = 0; u < kRunsPerThread; ++u) {
@@ -582,13 +638,16 @@ __global__ __launch_bounds__(kReduceThreads) void k_scatter_reduce(ScatterArgs a
                 long long sx[kRun], sy[kRun];
 #pragma unroll
                 for (int i = 0; i < kRun; ++i) {
-                    const uint32_t w = i < 2 ? kw[u].x : i < 4 ? kw[u].y : i < 6 ? kw[u].z : kw[u].w;
-                    key[i] = ((i & 1) ? (w >> 16) : w) & (kTileRows - 1);
-                    const float vx = (i & 1) ? v4[u][i >> 1].z : v4[u][i >> 1].x;
-                    const float vy = (i & 1) ? v4[u][i >> 1].w : v4[u][i >> 1].y;
+                    const uint32_t lo = (i & 1) ? rw[u][i >> 1].z : rw[u][i >> 1].x;
+                    const uint32_t hi = (i & 1) ? rw[u][i >> 1].w : rw[u][i >> 1].y;
+                    const uint64_t w = (uint64_t)hi << 32 | lo;
+                    key[i] = lo & (kTileRows - 1);
+                    const int sh = sh0 - (int)((lo >> kTileBits) & ((1u << kRecExpBits) - 1u));
+                    const long long qx = (long long)(w << (64 - kTileBits - kRecExpBits - kRecMantBits)) >> (64 - kRecMantBits);
+                    const long long qy = (long long)w >> (64 - kRecMantBits);
                     const bool ok = q < q_end && rec0 + i >= r_begin && rec0 + i < r_end;
-                    sx[i] = ok ? quantize(vx, ex) : 0ll;
-                    sy[i] = ok ? quantize(vy, ex) : 0ll;
+                    sx[i] = ok ? scale_mantissa(qx, sh) : 0ll;
+                    sy[i] = ok ? scale_mantissa(qy, sh) : 0ll;
                 }
 #pragma unroll
                 for (int i = 1; i < kRun; ++i) {
@@ -647,13 +706,19 @@ hipError_t scatter_phase_impl(const ScatterArgs& a, int phase, hipStream_t s)
             hipLaunchKernelGGL(k_scatter_scan_tiles<kMany>, dim3(1), dim3(kScanThreads), 0, s, a);
             break;
         case 4: {
-            const size_t place_lds = place_lds_bytes(a.tiles_max);
+            const bool narrow = a.tiles_max <= 256;
+            const size_t place_lds = place_lds_bytes(a.tiles_max, narrow ? 1 : 2);
+            const void* fn = narrow ? (const void*)k_scatter_place<kMany, uint8_t> : (const void*)k_scatter_place<kMany, uint16_t>;
             hipError_t e;
             if (place_lds > 65536 &&
-                (e = hipFuncSetAttribute((const void*)k_scatter_place<kMany>,
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)place_lds)) != hipSuccess)
+                (e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)place_lds)) != hipSuccess)
                 return e;
-            hipLaunchKernelGGL(k_scatter_place<kMany>, dim3((uint32_t)a.n_items), dim3(kPlaceThreads), place_lds, s, a);
+            if (narrow)
+                hipLaunchKernelGGL((k_scatter_place<kMany, uint8_t>), dim3((uint32_t)a.n_items), dim3(kPlaceThreads),
+                                   place_lds, s, a);
+            else
+                hipLaunchKernelGGL((k_scatter_place<kMany, uint16_t>), dim3((uint32_t)a.n_items), dim3(kPlaceThreads),
+                                   place_lds, s, a);
             break;
         }
         case 5:
