@@ -59,6 +59,9 @@ class OrcRenderCfg(C.Structure):
         ("lambda_d", C.c_double),
         ("lambda_sigma", C.c_double),
         ("grad_scale", C.c_double),
+        ("jitter", C.c_double),
+        ("jitter_features", C.c_double),
+        ("jitter_seed", C.c_uint64),
     ]
 
 
@@ -292,8 +295,12 @@ def composite_bwd(sigma, rgb, t, dt, bg, gC, gD, gA=None):
 
 # ---------------------------------------------------------------- render
 
-def _render_cfg(arch, n_samples, loss_mode, lambda_d, lambda_sigma, emulate=False, grad_scale=1.0):
+def _render_cfg(arch, n_samples, loss_mode, lambda_d, lambda_sigma, emulate=False, grad_scale=1.0,
+                jitter=0.0, jitter_features=None, jitter_seed=0):
     c = OrcRenderCfg()
+    c.jitter = float(jitter)
+    c.jitter_features = float(jitter if jitter_features is None else jitter_features)
+    c.jitter_seed = int(jitter_seed)
     c.arch = make_arch(arch, emulate)
     c.n_samples = n_samples
     c.loss_mode = loss_mode
@@ -305,7 +312,14 @@ def _render_cfg(arch, n_samples, loss_mode, lambda_d, lambda_sigma, emulate=Fals
 
 def render_fwd(arch, params, ray_obj, t, dt, flags, *, bg=None, tgt_rgb=None, tgt_depth=None,
                mask=None, loss_mode=0, lambda_d=0.0, lambda_sigma=0.0, want_samples=False,
-               want_relu_signature=False, emulate=False):
+               want_relu_signature=False, emulate=False, jitter=0.0, jitter_features=None, jitter_seed=0):
+    """Per-ray colour, depth, opacity (and loss terms with targets).  jitter
+    (diagnostic, 0 = off): every encoded feature and MLP pre-activation is
+    moved by a pseudo-random amount of up to `jitter` times the sum of the
+    absolute terms that formed it, before it is rounded or its ReLU decided,
+    so that want_relu_signature can reveal the rays whose ReLU pattern
+    arithmetic at that scale could change; jitter_features (default: jitter)
+    sets the scale for the encoded features alone."""
     params = _f32(params)
     ray_obj = _f32(ray_obj).reshape(-1, 6)
     n = ray_obj.shape[0]
@@ -314,7 +328,8 @@ def render_fwd(arch, params, ray_obj, t, dt, flags, *, bg=None, tgt_rgb=None, tg
     dt = _f32(dt).reshape(n, S)
     flags = _u8(flags)
     bg, tgt_rgb, tgt_depth, mask = _f32(bg), _f32(tgt_rgb), _f32(tgt_depth), _u8(mask)
-    cfg = _render_cfg(arch, S, loss_mode, lambda_d, lambda_sigma, emulate)
+    cfg = _render_cfg(arch, S, loss_mode, lambda_d, lambda_sigma, emulate, jitter=jitter,
+                      jitter_features=jitter_features, jitter_seed=jitter_seed)
     out = dict(rgb=np.empty((n, 3)), depth=np.empty(n), opacity=np.empty(n))
     ray_loss = np.empty(n) if tgt_rgb is not None else None
     loss = np.zeros(1) if tgt_rgb is not None else None

@@ -116,6 +116,9 @@ typedef struct {
     double lambda_d;
     double lambda_sigma;
     double grad_scale;  /* emulation: gradients carry this loss scale (a power of two) when rounded */
+    double jitter;          /* diagnostic, 0 = off: jitter of MLP pre-activations (orc_jitter) */
+    double jitter_features; /* diagnostic, 0 = off: jitter of encoded features (orc_jitter) */
+    uint64_t jitter_seed;
 } orc_render_cfg;
 
 /* ------------------------------------------------------------------------ */
@@ -383,7 +386,27 @@ static void orc_level_corners(int32_t N, int32_t log2T, const float x[3], uint32
 /* A table value as the forward gathers read it. */
 static double orc_table_value(const orc_arch* a, float v) { return orc_round16((double)v, a->table_dtype); }
 
-static void orc_encode_point(const orc_arch* a, const float* table, const float x[3], double* y)
+/* Diagnostic only (jitter = 0 leaves x as it is): x + jitter u A, with
+ * u = +-[1/2, 1) from a hash of x's bits and the seed, and A the sum of the
+ * absolute terms that formed x.  Applied to every encoded feature and every
+ * MLP pre-activation before it is rounded or its ReLU decided, it moves each
+ * by about what the same sum computed in FP32 instead of FP64 could differ
+ * by, so a ReLU signature reveals the decisions such arithmetic could change. */
+static double orc_jitter(double jitter, uint64_t seed, double x, double A)
+{
+    if (!(jitter > 0.0)) return x;
+    uint64_t b;
+    memcpy(&b, &x, sizeof b);
+    uint64_t h = (b ^ seed) * 0x9E3779B97F4A7C15ull;
+    h ^= h >> 29;
+    h *= 0xBF58476D1CE4E5B9ull;
+    h ^= h >> 32;
+    const double u = 0.5 + 0.5 * (double)(h >> 11) * 0x1.0p-53;
+    return x + ((h & 1u) ? u : -u) * jitter * A;
+}
+
+static void orc_encode_point(const orc_arch* a, const float* table, const float x[3], double* y, double jitter,
+                             uint64_t seed)
 {
     const int64_t T = (int64_t)1 << a->log2_table;
     const int F = a->n_features;
@@ -392,9 +415,13 @@ static void orc_encode_point(const orc_arch* a, const float* table, const float 
         double w[8];
         orc_level_corners(a->res[l], a->log2_table, x, idx, w);
         for (int p = 0; p < F; ++p) {
-            double s = 0.0;
-            for (int e = 0; e < 8; ++e) s += w[e] * orc_table_value(a, table[((int64_t)l * T + idx[e]) * F + p]);
-            y[l * F + p] = s;
+            double s = 0.0, A = 0.0;
+            for (int e = 0; e < 8; ++e) {
+                const double term = w[e] * orc_table_value(a, table[((int64_t)l * T + idx[e]) * F + p]);
+                s += term;
+                A += fabs(term);
+            }
+            y[l * F + p] = orc_jitter(jitter, seed, s, A);
         }
     }
 }
@@ -437,6 +464,9 @@ typedef struct {
     int out_dim[8];
     int n_layers;
     int dtype;         /* operand type of the products (orc_round16) */
+    double jitter;          /* diagnostic jitter of pre-activations (orc_jitter), 0 = off */
+    double jitter_features; /* diagnostic jitter of encoded features, 0 = off */
+    uint64_t jitter_seed;
 } orc_mlp_view;
 
 static orc_mlp_view orc_mlp_layers(const orc_arch* a, const float* mlp)
@@ -446,6 +476,9 @@ static orc_mlp_view orc_mlp_layers(const orc_arch* a, const float* mlp)
     int64_t off = 0;
     v.n_layers = a->hidden + 1;
     v.dtype = a->mlp_dtype;
+    v.jitter = 0.0;
+    v.jitter_features = 0.0;
+    v.jitter_seed = 0;
     for (int k = 0; k < v.n_layers; ++k) {
         v.in_dim[k] = (k == 0) ? in : a->width;
         v.out_dim[k] = (k == a->hidden) ? ORC_N_OUT : a->width;
@@ -465,9 +498,14 @@ static void orc_mlp_point(const orc_mlp_view* v, const double* y, double* h /* [
         double* hout = (k + 1 < v->n_layers) ? h + (size_t)(k + 1) * maxw : o;
         const float* W = v->W[k];
         for (int i = 0; i < v->out_dim[k]; ++i) {
-            double s = 0.0;
-            for (int j = 0; j < v->in_dim[k]; ++j)
-                s += orc_round16((double)W[(int64_t)i * v->in_dim[k] + j], v->dtype) * orc_round16(hin[j], v->dtype);
+            double s = 0.0, A = 0.0;
+            for (int j = 0; j < v->in_dim[k]; ++j) {
+                const double term =
+                    orc_round16((double)W[(int64_t)i * v->in_dim[k] + j], v->dtype) * orc_round16(hin[j], v->dtype);
+                s += term;
+                A += fabs(term);
+            }
+            s = orc_jitter(v->jitter, v->jitter_seed, s, A);
             hout[i] = (k + 1 < v->n_layers) ? (s > 0.0 ? s : 0.0) : s;
         }
     }
@@ -513,7 +551,7 @@ void orc_prior_refresh(const orc_arch* a, const float* params, int32_t R, double
             float x[3];
             for (int k = 0; k < 3; ++k) x[k] = (float)((double)idx[k] / (double)(R - 1));
             double o[ORC_N_OUT];
-            orc_encode_point(a, params, x, y);
+            orc_encode_point(a, params, x, y, 0.0, 0);
             orc_mlp_point(&v, y, h, maxw, o);
             out[p] = exp(o[0]);
         }
@@ -776,7 +814,8 @@ static void orc_ray_forward(const orc_render_cfg* c, const float* params, const 
     const int S = s->S;
     for (int j = 0; j < S; ++j) {
         orc_position(ro, t[j], s->x + 3 * j);
-        orc_encode_point(&c->arch, params, s->x + 3 * j, s->y + (size_t)j * s->in_dim);
+        orc_encode_point(&c->arch, params, s->x + 3 * j, s->y + (size_t)j * s->in_dim, mv->jitter_features,
+                         mv->jitter_seed);
         orc_mlp_point(mv, s->y + (size_t)j * s->in_dim, s->h + (size_t)j * (s->n_layers + 1) * s->maxw,
                       s->maxw, s->o + 4 * j);
         s->sigma[j] = exp(s->o[4 * j]);
@@ -810,7 +849,10 @@ void orc_render_fwd(const orc_render_cfg* c, const float* params, const float* r
                     uint64_t* relu_sig)
 {
     const int S = c->n_samples;
-    const orc_mlp_view mv = orc_mlp_layers(&c->arch, params + orc_table_params(&c->arch));
+    orc_mlp_view mv = orc_mlp_layers(&c->arch, params + orc_table_params(&c->arch));
+    mv.jitter = c->jitter;
+    mv.jitter_features = c->jitter_features;
+    mv.jitter_seed = c->jitter_seed;
     double* per_ray = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
 #pragma omp parallel
     {
