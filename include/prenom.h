@@ -165,12 +165,16 @@ typedef struct prenom_render_cfg {
     float lambda_sigma;
     int32_t recompute; /* 0: render_bwd reads what render_fwd stored in the workspace
                           (per-sample features, head outputs, per-ray results);
-                          1: render_bwd recomputes them, so the workspace need not
-                          survive between the two calls (activations are not kept) */
+                          1: both calls run pass by pass over chunks of about 2^21
+                          samples and render_bwd recomputes each pass's features,
+                          head outputs and per-ray results, so the workspace holds
+                          one pass (not the batch) and need not survive between
+                          the two calls (activations are not kept) */
 } prenom_render_cfg;
 
-/* Bytes of device workspace render_fwd/render_bwd need for this batch. */
-size_t prenom_workspace_size(const prenom_arch* arch, int64_t n_rays, int32_t n_samples);
+/* Bytes of device workspace render_fwd/render_bwd need for this batch, in the
+ * stored (recompute = 0) or the recompute (1) form; 0 on invalid input. */
+size_t prenom_workspace_size(const prenom_arch* arch, int64_t n_rays, int32_t n_samples, int32_t recompute);
 
 /* ------------------------------------------------------------------------
  * prenom_render_fwd -- Sec. III-B "Volume Rendering", Eq. (7)-(9).
@@ -187,7 +191,8 @@ size_t prenom_workspace_size(const prenom_arch* arch, int64_t n_rays, int32_t n_
  *   mask [n] (uint8, 1 = object ray) may all be NULL (no loss).
  * Outputs: rgb [n][3], depth [n], opacity [n]; loss [1] (device scalar, or
  *   NULL); sample_out [n][S][4] = (sigma, r, g, b) per sample, or NULL.
- * workspace: >= prenom_workspace_size bytes, 256-byte aligned.  It also
+ * workspace: >= prenom_workspace_size(arch, n, S, cfg->recompute) bytes,
+ *   256-byte aligned.  In the stored form it also
  *   receives the per-tile histograms of the hash-table gradient's records
  *   (per level and block of 512 samples: one per corner of every sample,
  *   a corner that repeats the previous sample's row joining its record)

@@ -93,7 +93,7 @@ def lib():
         L.prenom_table_param_count.restype = C.c_int64
         L.prenom_table_param_count.argtypes = [C.POINTER(PrenomArch)]
         L.prenom_workspace_size.restype = C.c_size_t
-        L.prenom_workspace_size.argtypes = [C.POINTER(PrenomArch), C.c_int64, C.c_int32]
+        L.prenom_workspace_size.argtypes = [C.POINTER(PrenomArch), C.c_int64, C.c_int32, C.c_int32]
         L.prenom_sample.restype = C.c_int
         L.prenom_sample.argtypes = [C.POINTER(PrenomSampleCfg), _vp, _vp, _vp, C.c_int64,
                                     _vp, _vp, _vp, _vp, _vp, _vp]

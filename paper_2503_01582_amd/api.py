@@ -74,8 +74,8 @@ def prenom_table_param_count(arch) -> int:
     return int(L.lib().prenom_table_param_count(C.byref(make_arch(arch))))
 
 
-def prenom_workspace_size(arch, n_rays: int, n_samples: int) -> int:
-    return int(L.lib().prenom_workspace_size(C.byref(make_arch(arch)), n_rays, n_samples))
+def prenom_workspace_size(arch, n_rays: int, n_samples: int, recompute: bool = False) -> int:
+    return int(L.lib().prenom_workspace_size(C.byref(make_arch(arch)), n_rays, n_samples, int(bool(recompute))))
 
 
 class Model:
@@ -213,8 +213,8 @@ class Workspace:
         self.device = device
         self.buf: Optional[torch.Tensor] = None
 
-    def get(self, arch, n_rays: int, n_samples: int) -> torch.Tensor:
-        need = prenom_workspace_size(arch, n_rays, n_samples)
+    def get(self, arch, n_rays: int, n_samples: int, recompute: bool = False) -> torch.Tensor:
+        need = prenom_workspace_size(arch, n_rays, n_samples, recompute)
         if self.buf is None or self.buf.numel() < need:
             self.buf = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
         return self.buf
@@ -222,7 +222,7 @@ class Workspace:
 
 def prenom_render_fwd(model: Model, samp: SampleOut, loss_spec, ws: torch.Tensor, *, bg=None,
                       tgt_rgb=None, tgt_depth=None, mask=None, want_loss=True, sample_out=None,
-                      out=None):
+                      out=None, recompute=False):
     n, S = samp.t.shape
     dev = samp.t.device
     if out is None:
@@ -231,7 +231,7 @@ def prenom_render_fwd(model: Model, samp: SampleOut, loss_spec, ws: torch.Tensor
                    opacity=torch.empty((n,), dtype=torch.float32, device=dev),
                    loss=torch.zeros((1,), dtype=torch.float32, device=dev))
     _check_rays(samp, n, bg=bg, tgt_rgb=tgt_rgb, tgt_depth=tgt_depth, mask=mask, sample_out=sample_out)
-    cfg = render_cfg(S, loss_spec)
+    cfg = render_cfg(S, loss_spec, recompute)
     mc = model.c_struct()
     st = L.lib().prenom_render_fwd(
         C.byref(mc), C.byref(cfg), _ptr(samp.ray_obj), _ptr(samp.t), _ptr(samp.dt), _ptr(samp.flags), n,

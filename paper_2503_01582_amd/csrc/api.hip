@@ -227,9 +227,31 @@ struct WsLayout {
     ScatterObj plan;
 };
 
-WsLayout ws_layout(const prenom_arch* a, int64_t n_rays, int32_t S)
+// Rays per pass of the recompute form: about 2^21 samples, a multiple of the
+// compositing kernels' rays per block (so each pass's loss partials continue
+// those of the pass before).
+constexpr int64_t kRecomputeSamples = int64_t(1) << 21;
+
+int64_t recompute_chunk_rays(int32_t S)
+{
+    const int64_t rpb = composite_rays_per_block();
+    const int64_t c = kRecomputeSamples / S / rpb * rpb;
+    return c < rpb ? rpb : c;
+}
+
+// Rays whose per-sample buffers the workspace holds at once: all of them, or
+// one pass of the recompute form.
+int64_t buffered_rays(int64_t n_rays, int32_t S, bool recompute)
+{
+    if (!recompute) return n_rays;
+    const int64_t c = recompute_chunk_rays(S);
+    return n_rays < c ? n_rays : c;
+}
+
+WsLayout ws_layout(const prenom_arch* a, int64_t n_rays_all, int32_t S, bool recompute)
 {
     WsLayout w{};
+    const int64_t n_rays = buffered_rays(n_rays_all, S, recompute);
     const size_t n_s = (size_t)n_rays * (size_t)S, L = (size_t)a->n_levels;
     size_t off = 0;
     w.y = off;
@@ -242,7 +264,7 @@ WsLayout ws_layout(const prenom_arch* a, int64_t n_rays, int32_t S)
     off = align_up(off + L * n_s * 2 * sizeof(float));
     w.ray_state = off;
     off = align_up(off + (size_t)n_rays * 8 * sizeof(float));
-    w.n_loss_blocks = composite_loss_blocks(n_rays);
+    w.n_loss_blocks = composite_loss_blocks(n_rays_all);
     w.loss_partial = off;
     off = align_up(off + (size_t)(w.n_loss_blocks > 0 ? w.n_loss_blocks : 1) * sizeof(double));
     w.n_mlp_slots = mlp_bwd_waves((int64_t)n_s);
@@ -289,7 +311,7 @@ prenom_status check_render(const prenom_model* model, const prenom_render_cfg* c
     if ((double)n_rays * cfg->n_samples > 536870912.0) return fail(PRENOM_ERR_SHAPE, "n_rays * n_samples > 2^29");
     if (n_rays > 0 && (!ray_obj || !t || !dt || !flags))
         return fail(PRENOM_ERR_INVALID_ARG, "ray_obj, t, dt and flags are required");
-    const WsLayout w = ws_layout(&model->arch, n_rays, cfg->n_samples);
+    const WsLayout w = ws_layout(&model->arch, n_rays, cfg->n_samples, cfg->recompute != 0);
     if (!ws || !aligned(ws, kAlign)) return fail(PRENOM_ERR_WORKSPACE, "workspace NULL or not 256-byte aligned");
     if (ws_bytes < w.total)
         return fail(PRENOM_ERR_WORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, w.total);
@@ -309,15 +331,16 @@ size_t prior_refresh_ws(const prenom_arch* a, int32_t R, size_t* sc_off)
     return y + align_up((size_t)c * 4 * sizeof(float));
 }
 
-// Tile histograms of the training forward, in the workspace's scatter counts.
-TileHist tile_hist(const WsLayout& w, void* workspace)
+// Tile histograms of the training forward, in the workspace's scatter counts,
+// laid out for the scatter plan of the samples encoded.
+TileHist tile_hist(const WsLayout& w, const ScatterObj& plan, void* workspace)
 {
     TileHist h{};
     h.counts = at<uint32_t>(workspace, w.counts);
-    h.n_blocks = w.plan.n_blocks;
-    for (int l = 0; l < w.plan.grid.n_levels; ++l) {
-        h.tiles[l] = w.plan.tiles[l];
-        h.tile_base[l] = w.plan.tile_base[l];
+    h.n_blocks = plan.n_blocks;
+    for (int l = 0; l < plan.grid.n_levels; ++l) {
+        h.tiles[l] = plan.tiles[l];
+        h.tile_base[l] = plan.tile_base[l];
     }
     return h;
 }
@@ -338,10 +361,10 @@ int64_t prenom_table_param_count(const prenom_arch* arch)
     return table_params(arch);
 }
 
-size_t prenom_workspace_size(const prenom_arch* arch, int64_t n_rays, int32_t n_samples)
+size_t prenom_workspace_size(const prenom_arch* arch, int64_t n_rays, int32_t n_samples, int32_t recompute)
 {
-    if (check_arch(arch) != PRENOM_OK || n_rays < 0 || n_samples < 1) return 0;
-    return ws_layout(arch, n_rays, n_samples).total;
+    if (check_arch(arch) != PRENOM_OK || n_rays < 0 || n_samples < 1 || (recompute != 0 && recompute != 1)) return 0;
+    return ws_layout(arch, n_rays, n_samples, recompute != 0).total;
 }
 
 size_t prenom_prior_refresh_workspace_size(const prenom_arch* arch, int32_t R)
@@ -412,41 +435,56 @@ prenom_status prenom_render_fwd(const prenom_model* model, const prenom_render_c
     if (loss && !tgt_rgb && n_rays > 0) return fail(PRENOM_ERR_INVALID_ARG, "loss requested without tgt_rgb");
     hipStream_t s = (hipStream_t)stream;
     const prenom_arch* a = &model->arch;
-    const WsLayout w = ws_layout(a, n_rays, cfg->n_samples);
-    const int64_t n_s = n_rays * cfg->n_samples;
+    const bool recompute = cfg->recompute != 0;
+    const int32_t S = cfg->n_samples;
+    const WsLayout w = ws_layout(a, n_rays, S, recompute);
     const GridInfo g = grid_info(a);
+    const MlpShape m = mlp_shape(a);
     float* y = at<float>(workspace, w.y);
     float* sc = at<float>(workspace, w.sc);
     const void* tlp = a->table_dtype == PRENOM_F16 ? model->table_lp : nullptr;
-    const TileHist h = tile_hist(w, workspace);
-    PRENOM_LAUNCH("k_encode_fwd", s,
-                  launch_encode_samples(g, model->params, tlp, ray_obj, t, n_rays, cfg->n_samples, y, s, &h));
-    const MlpShape m = mlp_shape(a);
-    PRENOM_LAUNCH("k_mlp_fwd", s, mlp_fwd_any(m, model->params + table_params(a), y, n_s, sc, at<float>(workspace, w.act), s));
-    CompositeArgs c{};
-    c.n_rays = n_rays;
-    c.S = cfg->n_samples;
-    c.loss_mode = cfg->loss_mode;
-    c.lambda_d = cfg->lambda_d;
-    c.lambda_sigma = cfg->lambda_sigma;
-    c.sc = sc;
-    c.t = t;
-    c.dt = dt;
-    c.flags = flags;
-    c.bg = bg;
-    c.tgt_rgb = tgt_rgb;
-    c.tgt_depth = tgt_depth;
-    c.mask = mask;
-    c.rgb = rgb;
-    c.depth = depth;
-    c.opacity = opacity;
-    c.ray_state = at<float>(workspace, w.ray_state);
-    c.loss_partial = loss ? at<double>(workspace, w.loss_partial) : nullptr;
-    PRENOM_LAUNCH("k_composite_fwd", s, launch_composite_fwd(c, s));
-    if (loss) PRENOM_LAUNCH("k_loss_finalize", s, launch_loss_finalize(c.loss_partial, w.n_loss_blocks, loss, s));
-    if (sample_out && n_s > 0)
-        PRENOM_TRY_HIP(hipMemcpyAsync(sample_out, sc, (size_t)n_s * 4 * sizeof(float), hipMemcpyDeviceToDevice, s),
-                       "copy sample_out");
+    double* loss_partial = loss ? at<double>(workspace, w.loss_partial) : nullptr;
+    // The stored form runs once over all rays and keeps features, head outputs
+    // and per-ray results (and the scatter's histograms) for render_bwd; the
+    // recompute form runs pass by pass over chunks of rays and keeps nothing.
+    const int64_t chunk = recompute ? recompute_chunk_rays(S) : (n_rays > 0 ? n_rays : 1);
+    for (int64_t r0 = 0; r0 < n_rays; r0 += chunk) {
+        const int64_t nr = n_rays - r0 < chunk ? n_rays - r0 : chunk;
+        const int64_t n_s = nr * S;
+        const ScatterObj plan = scatter_obj(g, n_s);
+        const TileHist h = tile_hist(w, plan, workspace);
+        PRENOM_LAUNCH("k_encode_fwd", s,
+                      launch_encode_samples(g, model->params, tlp, ray_obj + 6 * r0, t + S * r0, nr, S, y, s,
+                                            recompute ? nullptr : &h));
+        PRENOM_LAUNCH("k_mlp_fwd", s,
+                      mlp_fwd_any(m, model->params + table_params(a), y, n_s, sc, at<float>(workspace, w.act), s));
+        CompositeArgs c{};
+        c.n_rays = nr;
+        c.norm_rays = n_rays;
+        c.S = S;
+        c.loss_mode = cfg->loss_mode;
+        c.lambda_d = cfg->lambda_d;
+        c.lambda_sigma = cfg->lambda_sigma;
+        c.sc = sc;
+        c.t = t + S * r0;
+        c.dt = dt + S * r0;
+        c.flags = flags + r0;
+        c.bg = bg ? bg + 3 * r0 : nullptr;
+        c.tgt_rgb = tgt_rgb ? tgt_rgb + 3 * r0 : nullptr;
+        c.tgt_depth = tgt_depth ? tgt_depth + r0 : nullptr;
+        c.mask = mask ? mask + r0 : nullptr;
+        c.rgb = rgb + 3 * r0;
+        c.depth = depth + r0;
+        c.opacity = opacity + r0;
+        c.ray_state = at<float>(workspace, w.ray_state);
+        c.loss_partial = loss_partial ? loss_partial + r0 / composite_rays_per_block() : nullptr;
+        PRENOM_LAUNCH("k_composite_fwd", s, launch_composite_fwd(c, s));
+        if (sample_out && n_s > 0)
+            PRENOM_TRY_HIP(hipMemcpyAsync(sample_out + 4 * S * r0, sc, (size_t)n_s * 4 * sizeof(float),
+                                          hipMemcpyDeviceToDevice, s),
+                           "copy sample_out");
+    }
+    if (loss) PRENOM_LAUNCH("k_loss_finalize", s, launch_loss_finalize(loss_partial, w.n_loss_blocks, loss, s));
     return PRENOM_OK;
 }
 
@@ -462,88 +500,93 @@ prenom_status prenom_render_bwd(const prenom_model* model, const prenom_render_c
         return fail(PRENOM_ERR_INVALID_ARG, "either d_rgb or the loss targets are required");
     hipStream_t s = (hipStream_t)stream;
     const prenom_arch* a = &model->arch;
-    const WsLayout w = ws_layout(a, n_rays, cfg->n_samples);
-    const int64_t n_s = n_rays * cfg->n_samples;
+    const bool recompute = cfg->recompute != 0;
+    const int32_t S = cfg->n_samples;
+    const WsLayout w = ws_layout(a, n_rays, S, recompute);
+    const GridInfo g = grid_info(a);
     const MlpShape m = mlp_shape(a);
-    if (cfg->recompute) {
-        // rebuild the features, head outputs and per-ray results render_fwd would have left
-        float* y = at<float>(workspace, w.y);
-        const void* tlp = a->table_dtype == PRENOM_F16 ? model->table_lp : nullptr;
-        const TileHist h = tile_hist(w, workspace);
-        PRENOM_LAUNCH("k_encode_fwd", s, launch_encode_samples(grid_info(a), model->params, tlp, ray_obj, t, n_rays,
-                                                               cfg->n_samples, y, s, &h));
-        PRENOM_LAUNCH("k_mlp_fwd", s, mlp_fwd_any(m, model->params + table_params(a), y, n_s,
-                                                  at<float>(workspace, w.sc), at<float>(workspace, w.act), s));
-        CompositeArgs f{};
-        f.n_rays = n_rays;
-        f.S = cfg->n_samples;
-        f.sc = at<float>(workspace, w.sc);
-        f.t = t;
-        f.dt = dt;
-        f.flags = flags;
-        f.bg = bg;
-        f.ray_state = at<float>(workspace, w.ray_state);
-        PRENOM_LAUNCH("k_composite_fwd", s, launch_composite_fwd(f, s));
+    const void* tlp = a->table_dtype == PRENOM_F16 ? model->table_lp : nullptr;
+    const int64_t chunk = recompute ? recompute_chunk_rays(S) : (n_rays > 0 ? n_rays : 1);
+    for (int64_t r0 = 0; r0 < n_rays; r0 += chunk) {
+        const int64_t nr = n_rays - r0 < chunk ? n_rays - r0 : chunk;
+        const int64_t n_s = nr * S;
+        const ScatterObj plan = scatter_obj(g, n_s);
+        const float* ro = ray_obj + 6 * r0;
+        const float* tc = t + S * r0;
+        CompositeArgs c{};
+        c.n_rays = nr;
+        c.norm_rays = n_rays;
+        c.S = S;
+        c.loss_mode = cfg->loss_mode;
+        c.lambda_d = cfg->lambda_d;
+        c.lambda_sigma = cfg->lambda_sigma;
+        c.sc = at<float>(workspace, w.sc);
+        c.t = tc;
+        c.dt = dt + S * r0;
+        c.flags = flags + r0;
+        c.bg = bg ? bg + 3 * r0 : nullptr;
+        c.tgt_rgb = tgt_rgb ? tgt_rgb + 3 * r0 : nullptr;
+        c.tgt_depth = tgt_depth ? tgt_depth + r0 : nullptr;
+        c.mask = mask ? mask + r0 : nullptr;
+        c.ray_state = at<float>(workspace, w.ray_state);
+        if (recompute) {
+            // rebuild this pass's features, head outputs and per-ray results
+            // (and the scatter's tile histograms) as render_fwd would have left them
+            const TileHist h = tile_hist(w, plan, workspace);
+            PRENOM_LAUNCH("k_encode_fwd", s,
+                          launch_encode_samples(g, model->params, tlp, ro, tc, nr, S, at<float>(workspace, w.y), s, &h));
+            PRENOM_LAUNCH("k_mlp_fwd", s, mlp_fwd_any(m, model->params + table_params(a), at<float>(workspace, w.y),
+                                                      n_s, at<float>(workspace, w.sc), at<float>(workspace, w.act), s));
+            CompositeArgs f = c;
+            f.tgt_rgb = nullptr;  // per-ray results only, no loss
+            PRENOM_LAUNCH("k_composite_fwd", s, launch_composite_fwd(f, s));
+        }
+        c.d_rgb = d_rgb ? d_rgb + 3 * r0 : nullptr;
+        c.d_depth = d_depth ? d_depth + r0 : nullptr;
+        c.d_opacity = d_opacity ? d_opacity + r0 : nullptr;
+        c.loss_scale = model->loss_scale;
+        c.dout = at<float>(workspace, w.dout);
+        PRENOM_LAUNCH("k_composite_bwd", s, launch_composite_bwd(c, s));
+        float* partial = at<float>(workspace, w.mlp_partial);
+        float* dy = at<float>(workspace, w.dy);
+        PRENOM_LAUNCH("k_mlp_bwd", s,
+                      mlp_bwd_any(m, model->params + table_params(a), at<float>(workspace, w.y), c.dout,
+                                  at<float>(workspace, w.sc), n_s, dy, partial, at<float>(workspace, w.act), s));
+        if (n_s > 0)
+            PRENOM_LAUNCH("k_reduce_partials", s,
+                          launch_reduce_partials(partial, mlp_bwd_waves(n_s), mlp_params(a),
+                                                 model->grads + table_params(a), s));
+        ScatterArgs sa{};
+        sa.S = S;
+        sa.n_obj = 1;
+        sa.one = plan;
+        sa.objs = nullptr;
+        sa.tiles_max = scatter_tiles_max(plan);
+        sa.reduce_blocks = device_cus();
+        sa.n_tiles = plan.n_tiles;
+        sa.n_items = scatter_items(plan);
+        sa.n_levels_total = a->n_levels;
+        sa.ray_obj = ro;
+        sa.t = tc;
+        sa.dy = reinterpret_cast<const float2*>(dy);
+        sa.g_table = model->grads;
+        sa.counts = at<uint32_t>(workspace, w.counts);
+        sa.offsets = at<uint32_t>(workspace, w.offsets);
+        sa.block_max = at<float>(workspace, w.block_max);
+        sa.level_max = at<float>(workspace, w.level_max);
+        sa.tile_exp = at<int32_t>(workspace, w.tile_exp);
+        sa.tile_total = at<uint64_t>(workspace, w.tile_total);
+        sa.tile_start = at<uint64_t>(workspace, w.tile_start);
+        sa.chunk_start = at<uint64_t>(workspace, w.chunk_start);
+        sa.work_counter = at<unsigned long long>(workspace, w.work_counter);
+        sa.recs = at<uint64_t>(workspace, w.recs);
+        sa.n_records = scatter_records(plan);
+        sa.nonfinite = model->loss_scale ? model->scaler_state : nullptr;
+        sa.fwd_counts = 1;  // render_fwd (or the recompute above) wrote the tile histograms
+        sa.merge_runs = 1;
+        for (int ph = 0; ph < kScatterPhases; ++ph)
+            PRENOM_LAUNCH(ph == 0 ? "k_scatter_dymax" : kScatterPhaseNames[ph], s, launch_scatter_phase(sa, ph, s));
     }
-    CompositeArgs c{};
-    c.n_rays = n_rays;
-    c.S = cfg->n_samples;
-    c.loss_mode = cfg->loss_mode;
-    c.lambda_d = cfg->lambda_d;
-    c.lambda_sigma = cfg->lambda_sigma;
-    c.sc = at<float>(workspace, w.sc);
-    c.t = t;
-    c.dt = dt;
-    c.flags = flags;
-    c.bg = bg;
-    c.tgt_rgb = tgt_rgb;
-    c.tgt_depth = tgt_depth;
-    c.mask = mask;
-    c.ray_state = at<float>(workspace, w.ray_state);
-    c.d_rgb = d_rgb;
-    c.d_depth = d_depth;
-    c.d_opacity = d_opacity;
-    c.loss_scale = model->loss_scale;
-    c.dout = at<float>(workspace, w.dout);
-    PRENOM_LAUNCH("k_composite_bwd", s, launch_composite_bwd(c, s));
-    float* partial = at<float>(workspace, w.mlp_partial);
-    float* dy = at<float>(workspace, w.dy);
-    PRENOM_LAUNCH("k_mlp_bwd", s,
-                  mlp_bwd_any(m, model->params + table_params(a), at<float>(workspace, w.y), c.dout,
-                              at<float>(workspace, w.sc), n_s, dy, partial, at<float>(workspace, w.act), s));
-    if (n_s > 0)
-        PRENOM_LAUNCH("k_reduce_partials", s,
-                      launch_reduce_partials(partial, w.n_mlp_slots, mlp_params(a), model->grads + table_params(a), s));
-    ScatterArgs sa{};
-    sa.S = cfg->n_samples;
-    sa.n_obj = 1;
-    sa.one = w.plan;
-    sa.objs = nullptr;
-    sa.tiles_max = scatter_tiles_max(w.plan);
-    sa.reduce_blocks = device_cus();
-    sa.n_tiles = w.plan.n_tiles;
-    sa.n_items = scatter_items(w.plan);
-    sa.n_levels_total = a->n_levels;
-    sa.ray_obj = ray_obj;
-    sa.t = t;
-    sa.dy = reinterpret_cast<const float2*>(dy);
-    sa.g_table = model->grads;
-    sa.counts = at<uint32_t>(workspace, w.counts);
-    sa.offsets = at<uint32_t>(workspace, w.offsets);
-    sa.block_max = at<float>(workspace, w.block_max);
-    sa.level_max = at<float>(workspace, w.level_max);
-    sa.tile_exp = at<int32_t>(workspace, w.tile_exp);
-    sa.tile_total = at<uint64_t>(workspace, w.tile_total);
-    sa.tile_start = at<uint64_t>(workspace, w.tile_start);
-    sa.chunk_start = at<uint64_t>(workspace, w.chunk_start);
-    sa.work_counter = at<unsigned long long>(workspace, w.work_counter);
-    sa.recs = at<uint64_t>(workspace, w.recs);
-    sa.n_records = scatter_records(w.plan);
-    sa.nonfinite = model->loss_scale ? model->scaler_state : nullptr;
-    sa.fwd_counts = 1;  // render_fwd (or the recompute above) wrote the tile histograms
-    sa.merge_runs = 1;
-    for (int ph = 0; ph < kScatterPhases; ++ph)
-        PRENOM_LAUNCH(ph == 0 ? "k_scatter_dymax" : kScatterPhaseNames[ph], s, launch_scatter_phase(sa, ph, s));
     return PRENOM_OK;
 }
 

@@ -430,6 +430,7 @@ hipError_t launch_reduce_partials_batch(const MlpRed* reds, int n_obj, int64_t n
 // Compositing and loss.
 struct CompositeArgs {
     int64_t n_rays;
+    int64_t norm_rays;    // single object: rays the loss is averaged over (0: n_rays), for calls over a part of them
     int32_t S;
     int32_t loss_mode;
     float lambda_d, lambda_sigma;
@@ -456,6 +457,7 @@ struct CompositeArgs {
     float* dout;          // bwd: [n_s][4] (dsigma, dr, dg, db)
 };
 int composite_loss_blocks(int64_t n_rays);
+int composite_rays_per_block();  // rays of one compositing block (its loss partial)
 hipError_t launch_composite_fwd(const CompositeArgs& a, hipStream_t s);
 hipError_t launch_loss_finalize(const double* partial, int n_blocks, float* loss, hipStream_t s);
 hipError_t launch_composite_bwd(const CompositeArgs& a, hipStream_t s);

@@ -76,7 +76,7 @@ __device__ __forceinline__ double wave_sum_d(double v)
 // ray's object in a batch.
 __device__ __forceinline__ int64_t norm_rays(const CompositeArgs& a, int64_t r)
 {
-    if (!a.objs) return a.n_rays;
+    if (!a.objs) return a.norm_rays > 0 ? a.norm_rays : a.n_rays;
     int lo = 0, hi = a.n_obj - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -395,6 +395,7 @@ __global__ __launch_bounds__(64 * kWaves) void k_composite_bwd(CompositeArgs a)
 
 // Forward blocks (one loss partial each): kWaves waves of 64 / kRow rays.
 int composite_loss_blocks(int64_t n_rays) { return (int)((n_rays + kRaysPerBlock - 1) / kRaysPerBlock); }
+int composite_rays_per_block() { return kRaysPerBlock; }
 
 hipError_t launch_composite_fwd(const CompositeArgs& a, hipStream_t s)
 {

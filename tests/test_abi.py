@@ -42,6 +42,10 @@ def test_param_and_workspace_sizes(L):
         a = api.prenom_workspace_size(arch, 1000, 64)
         b = api.prenom_workspace_size(arch, 2000, 64)
         assert 0 < a < b and a % 256 == 0
+        # the recompute form holds one pass of about 2^21 samples, whatever the batch
+        r1 = api.prenom_workspace_size(arch, 1 << 16, 64, recompute=True)
+        r2 = api.prenom_workspace_size(arch, 1 << 20, 64, recompute=True)
+        assert 0 < r1 <= r2 < 1.01 * r1 and r2 < api.prenom_workspace_size(arch, 1 << 16, 64) / 1.5
     bad = Arch(n_levels=4, log2_table=8, width=16, hidden=1)  # log2_table below 10
     assert api.prenom_param_count(bad) == -1
 
