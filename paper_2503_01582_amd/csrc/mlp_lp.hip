@@ -68,6 +68,21 @@ __device__ __forceinline__ floatx4 unpack(typename P::vec v)
     return {P::back(v[0]), P::back(v[1]), P::back(v[2]), P::back(v[3])};
 }
 
+// Stored 16-bit activations carry the ReLU decision in their sign: a unit
+// switched off is stored as -0, one switched on as its value, which may round
+// to +0 (FP16 underflow) and still passes its delta in the backward.
+__device__ __forceinline__ floatx4 relu_sign_coded(floatx4 h)
+{
+    return {h[0] > 0.0f ? h[0] : -0.0f, h[1] > 0.0f ? h[1] : -0.0f, h[2] > 0.0f ? h[2] : -0.0f,
+            h[3] > 0.0f ? h[3] : -0.0f};
+}
+
+__device__ __forceinline__ floatx4 mask_sign_coded(floatx4 g, floatx4 h)
+{
+    return {signbit(h[0]) ? 0.0f : g[0], signbit(h[1]) ? 0.0f : g[1], signbit(h[2]) ? 0.0f : g[2],
+            signbit(h[3]) ? 0.0f : g[3]};
+}
+
 template <int IN, int W, int D>
 struct NetLp {
     static constexpr int KB1 = (IN + 15) / 16;  // 16-feature K-blocks of layer 1 (zero-padded)
@@ -234,7 +249,7 @@ __device__ __forceinline__ void mlp_fwd_tiles_lp(const typename P::vec* __restri
 #pragma unroll
             for (int k = 0; k < D; ++k)
 #pragma unroll
-                for (int to = 0; to < N::OT; ++to) a16[(((int64_t)k * n_s + s) * W + 16 * to + 4 * q) / 4] = pack<P>(hs[k][to]);
+                for (int to = 0; to < N::OT; ++to) a16[(((int64_t)k * n_s + s) * W + 16 * to + 4 * q) / 4] = pack<P>(relu_sign_coded(hs[k][to]));
         }
     }
 }
@@ -450,11 +465,12 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_bwd_lp_batch(const MlpWo
 }
 
 // ---------------------------------------------------------------- 128 wide
-// As in the FP32 form: the forward stores the hidden activations (FP32); a
-// chain kernel with only the transposed fragments writes every layer's delta
-// (FP32) and dy; a weight-gradient kernel contracts deltas with activations
-// over the block's samples (operands rounded to the MFMA type, FP32
-// accumulation), the 4 waves splitting the output rows.
+// As in the FP32 form: the forward stores the hidden activations (in the
+// MFMA type, each unit's ReLU decision in the sign: relu_sign_coded); a chain
+// kernel with only the transposed fragments writes every layer's delta and
+// dy; a weight-gradient kernel contracts deltas with activations over the
+// block's samples (operands rounded to the MFMA type, FP32 accumulation),
+// the 4 waves splitting the output rows.
 constexpr int kWideWavesLp = 4;
 
 // act16 / dlt16: [D][n_s][W] 16-bit values, indexed in groups of 4 (P::vec).
@@ -485,7 +501,7 @@ __device__ __forceinline__ void mlp_chain_bwd_tiles_lp(const typename P::vec* __
         for (int to = 0; to < N::OT; ++to) {
             floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
             acc = P::mma(bfrag[(BO + to) * 64 + lane], dOp, acc);
-            delta[to] = mask_pos(acc, hk[to]);
+            delta[to] = mask_sign_coded(acc, hk[to]);
             if (valid) dlt16[vi(D - 1, to)] = pack<P>(delta[to]);
         }
 #pragma unroll
@@ -500,7 +516,7 @@ __device__ __forceinline__ void mlp_chain_bwd_tiles_lp(const typename P::vec* __
             layer_lp_ks_outer<P, N::OT, N::OT>(bfrag, lane, BH + (k - 1) * N::OT * N::OT, N::OT, dp, nd);
 #pragma unroll
             for (int to = 0; to < N::OT; ++to) {
-                delta[to] = mask_pos(nd[to], hk[to]);
+                delta[to] = mask_sign_coded(nd[to], hk[to]);
                 if (valid) dlt16[vi(k - 1, to)] = pack<P>(delta[to]);
             }
         }

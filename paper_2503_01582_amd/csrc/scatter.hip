@@ -100,7 +100,7 @@ __device__ __forceinline__ uint64_t encode_record(float2 v, int E, uint32_t row)
 // q * 2^sh rounded to an integer (halves upward), for |q| <= 2^21, sh <= 33.
 __device__ __forceinline__ long long scale_mantissa(long long q, int sh)
 {
-    if (sh >= 0) return q * (1ll << sh);
+    if (sh >= 0) return q * (1ll << min(sh, 40));  // (the clamp only matters for non-finite gradients)
     const int d = -sh;
     return d > 62 ? 0ll : (q + (1ll << (d - 1))) >> d;
 }

@@ -17,7 +17,7 @@ import numpy as np
 import pytest
 
 import oracle as orc
-from parity_util import TOL_FP32, assert_close, rel_errors
+from parity_util import MAX_KINK_SHARE, TOL_FP32, assert_close, rel_errors, relu_stable_rays
 from test_gpu_precision import lowp_ok
 from synth.arch import Arch
 from synth.multi import multi_batch, multi_objects
@@ -135,9 +135,10 @@ class BatchRun:
         torch.cuda.synchronize()
         return {k: v.cpu().numpy() for k, v in out.items()}
 
-    def bwd(self, recompute=False):
+    def bwd(self, recompute=False, d_rgb=None, d_depth=None):
         self.bm.grads.zero_()
-        self.B.prenom_batch_render_bwd(self.bm, self.samp, self.loss, self.ws, recompute=recompute, **self.kw)
+        up = {} if d_rgb is None else dict(d_rgb=dev(d_rgb), d_depth=dev(d_depth))
+        self.B.prenom_batch_render_bwd(self.bm, self.samp, self.loss, self.ws, recompute=recompute, **self.kw, **up)
         torch.cuda.synchronize()
         return [self.bm.object_grads(i).cpu().numpy() for i in range(len(self.bm.objs))]
 
@@ -323,8 +324,10 @@ def test_batch_graph_replay_matches_eager():
 def test_batch_reduced_precision(mlp_dtype, table_dtype):
     """Objects in the reduced-precision form: bit-exact against the
     single-object reduced-precision calls, within 2e-3 of the oracle that
-    emulates the reduced-precision method (the plain FP64 comparison is
-    reported by test_gpu_precision)."""
+    emulates the reduced-precision method in both norms (the plain FP64
+    comparison is reported by test_gpu_precision); gradients through random
+    upstream gradients on each object's ReLU-stable rays
+    (parity_util.relu_stable_rays)."""
     say(f"test_batch_reduced_precision[{mlp_dtype}, table {table_dtype}]")
     from paper_2503_01582_amd import api
     objs = make_objects(mlp_dtype=mlp_dtype, table_dtype=table_dtype, counts=[600, 0, 200, 500, 5, 900, 80])
@@ -335,7 +338,18 @@ def test_batch_reduced_precision(mlp_dtype, table_dtype):
     scale = 4096.0
     run = BatchRun(objs, params, b, geo, loss, loss_scale=scale)
     got = run.fwd()
-    grads = run.bwd()
+    rng = np.random.default_rng(17)
+    n = b.tgt_rgb.shape[0]
+    d_rgb, d_depth = np.zeros((n, 3), np.float32), np.zeros(n, np.float32)
+    for i, o in enumerate(objs):
+        if o.n_rays == 0:
+            continue
+        sl = b.slice(i)
+        keep = relu_stable_rays(o.arch, params[i], tuple(x[sl] for x in geo), rng, emulate=True)
+        assert o.n_rays - keep.sum() <= max(1, MAX_KINK_SHARE * o.n_rays), (i, o.n_rays - keep.sum())
+        d_rgb[sl][keep] = rng.normal(size=(int(keep.sum()), 3))
+        d_depth[sl][keep] = rng.normal(size=int(keep.sum()))
+    grads = run.bwd(d_rgb=d_rgb, d_depth=d_depth)
     worst = {}
     for i, o in enumerate(objs):
         if o.n_rays == 0:
@@ -354,7 +368,7 @@ def test_batch_reduced_precision(mlp_dtype, table_dtype):
         kw = dict(tgt_rgb=b.tgt_rgb[sl], tgt_depth=b.tgt_depth[sl], mask=b.mask[sl], lambda_d=np.float32(0.1),
                   emulate=True)
         ref = orc.render_fwd(o.arch, params[i], *g, **kw)
-        g_ref = orc.render_bwd(o.arch, params[i], *g, loss_scale=scale, **kw)
+        g_ref = orc.render_bwd(o.arch, params[i], *g, loss_scale=scale, d_rgb=d_rgb[sl], d_depth=d_depth[sl], **kw)
         nt = o.arch.n_table_params
         gi = grads[i].astype(np.float64) / scale
         errs = {"rgb": rel_errors(got["rgb"][sl], ref["rgb"]), "depth": rel_errors(got["depth"][sl], ref["depth"]),

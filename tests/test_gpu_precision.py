@@ -2,17 +2,29 @@
 with FP32 accumulation, FP16 table storage read by the forward gathers, FP32
 master weights and table-gradient accumulation, dynamic loss scaling.
 
-Two comparisons per output (colour, depth, opacity, loss, table and MLP
-gradients), both reported:
-  * against the oracle emulating the reduced-precision method (the same
-    operands rounded at the same points, FP64 elsewhere): held to 2e-3
-    (gradients in the 2-norm; see lowp_ok);
-  * against the plain FP64 method: reported.  Forward outputs stay within
-    2e-3 of it; gradients do not, because operand rounding moves ReLU
-    pre-activations across zero for ~eps of the units and each such flip
-    changes that unit's delta by O(1), so gradients differ by O(sqrt(eps))
-    (about 5% for BF16, 1.5% for FP16); they are held to 10%.
-The loss-scaling state machine is driven from the host."""
+Every output (colour, depth, opacity, loss, table and MLP gradients) is
+held to 2e-3 in both the max-norm and the 2-norm relative error against the
+oracle running the reduced-precision method itself (the same 16-bit
+operands rounded at the same points, FP64 elsewhere).  The kernel and that
+oracle then differ only by FP32 against FP64 accumulation, about 1e-7
+relative, so a ReLU decision can differ only where a pre-activation lies
+that close to zero.  Gradients are taken through upstream gradients on the
+rays whose oracle ReLU pattern survives eight perturbations moving every
+parameter and pre-activation by up to 2e-8 and every encoded feature by up
+to 3e-7 of the sum of its absolute terms, the sizes of FP32 against FP64
+arithmetic (ReLU-stable rays, parity_util.relu_stable_rays); the rest get
+zero upstream gradient, and their share is bounded (10%: a ray holds 2048
+16-bit-rounded features and 4096-16384 pre-activations, so 2-7% of the rays
+hold one whose rounding or ReLU decision FP32 arithmetic can flip).  A
+perturbation of one 16-bit ulp would change the pattern of every ray, which
+is why the criterion sits at the accumulation scale.
+
+Against the plain FP64 method the errors are reported (forward outputs also
+held to 2e-3 in the 2-norm): operand rounding moves ReLU pre-activations
+across zero for about eps of the units, and each such flip changes that
+unit's delta by O(1), so gradients differ from the FP64 method by O(sqrt(eps)).
+The loss-scaling state machine is driven from the host, and an overflow
+inside the FP16 backward is made to happen with an oversized loss scale."""
 from __future__ import annotations
 
 import dataclasses
@@ -21,7 +33,7 @@ import numpy as np
 import pytest
 
 import oracle as orc
-from parity_util import rel_errors
+from parity_util import MAX_KINK_SHARE, rel_errors, relu_stable_rays
 from synth.arch import ARCH_LARGE
 from synth.params import init_params
 from synth.workloads import LossSpec, prior_batch, prior_world
@@ -29,19 +41,11 @@ from synth.workloads import LossSpec, prior_batch, prior_world
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 TOL_LOWP = 2e-3
-TOL_LOWP_GRAD_MAX = 2e-2
 
 
 def lowp_ok(name, errs):
-    """Against the emulating oracle: forward outputs within 2e-3 in max and
-    2-norm relative error; gradients within 2e-3 in the 2-norm.  A gradient
-    entry's max error is held to 2e-2 only: where an operand sits at a 16-bit
-    rounding boundary, the kernel's FP32 sum and the oracle's FP64 sum round
-    to neighbouring values (one 16-bit ulp), and such a difference can now
-    and then move a ReLU pre-activation across zero."""
+    """Against the emulating oracle: 2e-3 in max and 2-norm relative error."""
     e_max, e_2 = errs
-    if name.startswith("g_"):
-        return e_2 <= TOL_LOWP and e_max <= TOL_LOWP_GRAD_MAX
     return e_max <= TOL_LOWP and e_2 <= TOL_LOWP
 
 _world = None
@@ -67,9 +71,22 @@ def geometry(b):
                                                    ("bf16", "fp16"), ("fp16", "fp16")])
 def test_reduced_precision_against_oracle(mlp_dtype, table_dtype):
     print(f"test_reduced_precision_against_oracle[{mlp_dtype}, table {table_dtype}]", flush=True)
+    run_case(dataclasses.replace(ARCH_LARGE, mlp_dtype=mlp_dtype, table_dtype=table_dtype), 1024)
+
+
+@pytest.mark.parametrize("hidden,mlp_dtype", [(1, "bf16"), (2, "bf16"), (2, "fp16")])
+def test_reduced_precision_wide_mlp(hidden, mlp_dtype):
+    """The 128-wide MLP (forward storing 16-bit activations; backward fusing
+    the delta chain with the weight gradient chunk by chunk) on a ragged ray
+    count that leaves a partial chunk."""
+    print(f"test_reduced_precision_wide_mlp[hidden={hidden}, {mlp_dtype}]", flush=True)
+    arch = dataclasses.replace(ARCH_LARGE, width=128, hidden=hidden, mlp_dtype=mlp_dtype, table_dtype="fp16")
+    run_case(arch, 777)
+
+
+def run_case(arch, n_rays):
     from paper_2503_01582_amd import api
-    arch = dataclasses.replace(ARCH_LARGE, mlp_dtype=mlp_dtype, table_dtype=table_dtype)
-    b = prior_batch(world(), 1024, step=31, loss=LossSpec(lambda_d=0.1))
+    b = prior_batch(world(), n_rays, step=31, loss=LossSpec(lambda_d=0.1))
     params = init_params(arch, 5)
     params[:arch.n_table_params] = np.random.default_rng(6).uniform(
         -0.3, 0.3, arch.n_table_params).astype(np.float32)
@@ -83,32 +100,78 @@ def test_reduced_precision_against_oracle(mlp_dtype, table_dtype):
     kw = dict(tgt_rgb=dev(b.tgt_rgb), tgt_depth=dev(b.tgt_depth), mask=dev(b.mask))
     ws = api.Workspace().get(arch, b.n_rays, samp.t.shape[1])
     out = api.prenom_render_fwd(model, samp, b.loss, ws, **kw)
-    api.prenom_render_bwd(model, samp, b.loss, ws, **kw)
+    # gradients through upstream gradients on the ReLU-stable rays
+    rng = np.random.default_rng(3)
+    keep = relu_stable_rays(arch, params, geo, rng, emulate=True)
+    share = 1.0 - keep.mean()
+    d_rgb = (rng.normal(size=(b.n_rays, 3)) * keep[:, None]).astype(np.float32)
+    d_depth = (rng.normal(size=b.n_rays) * keep).astype(np.float32)
+    api.prenom_render_bwd(model, samp, b.loss, ws, d_rgb=dev(d_rgb), d_depth=dev(d_depth), **kw)
     torch.cuda.synchronize()
     got = {"rgb": out["rgb"].cpu().numpy(), "depth": out["depth"].cpu().numpy(),
            "opacity": out["opacity"].cpu().numpy(), "loss": out["loss"].cpu().numpy()}
     g = model.grads.cpu().numpy().astype(np.float64) / scale
     nt = arch.n_table_params
-    kw = dict(tgt_rgb=b.tgt_rgb, tgt_depth=b.tgt_depth, mask=b.mask, lambda_d=np.float32(0.1))
+    fkw = dict(tgt_rgb=b.tgt_rgb, tgt_depth=b.tgt_depth, mask=b.mask, lambda_d=np.float32(0.1))
     report = {}
     for emulate in (True, False):
-        ref = orc.render_fwd(arch, params, *geo, emulate=emulate, **kw)
-        g_ref = orc.render_bwd(arch, params, *geo, emulate=emulate, loss_scale=scale, **kw)
+        ref = orc.render_fwd(arch, params, *geo, emulate=emulate, **fkw)
+        g_ref = orc.render_bwd(arch, params, *geo, d_rgb=d_rgb, d_depth=d_depth, emulate=emulate,
+                               loss_scale=scale)
         errs = {k: rel_errors(got[k], ref[k] if k != "loss" else [ref["loss"]])
                 for k in ("rgb", "depth", "opacity", "loss")}
         errs["g_table"] = rel_errors(g[:nt], g_ref[:nt])
         errs["g_mlp"] = rel_errors(g[nt:], g_ref[nt:])
         report[emulate] = errs
+    print(f"  {100 * share:.2f}% of the rays change ReLU pattern under FP32-sized perturbations "
+          f"(left out of the gradient)", flush=True)
     print("  output    vs emulated method (max-rel / 2-rel)   vs plain FP64 method", flush=True)
     for k in report[True]:
         e, p_ = report[True][k], report[False][k]
         print(f"  {k:8s}  {e[0]:.2e} / {e[1]:.2e}               {p_[0]:.2e} / {p_[1]:.2e}", flush=True)
+    assert share <= MAX_KINK_SHARE, share
     bad = {k: v for k, v in report[True].items() if not lowp_ok(k, v)}
     assert not bad, bad
     for k in ("rgb", "depth", "opacity", "loss"):
         assert report[False][k][1] <= TOL_LOWP, (k, report[False][k])
-    for k in ("g_table", "g_mlp"):
-        assert report[False][k][1] <= 0.1, (k, report[False][k])
+
+
+def test_fp16_backward_overflow_skips_the_update():
+    """An oversized loss scale makes the FP16 backward overflow inside
+    render_bwd (the head adjoint, then every feature gradient, leaves the FP16
+    range): the scatter and the check pass flag it, Adam skips the update,
+    clears the gradients and halves the scale."""
+    print("test_fp16_backward_overflow_skips_the_update", flush=True)
+    from paper_2503_01582_amd import api
+    arch = dataclasses.replace(ARCH_LARGE, mlp_dtype="fp16", table_dtype="fp16")
+    b = prior_batch(world(), 1024, step=32)
+    params = init_params(arch, 7)
+    geo = geometry(b)
+    dev = lambda a: torch.as_tensor(a).cuda()
+    samp = api.SampleOut(*(dev(g) for g in geo[:3]),
+                         bins=torch.zeros((b.n_rays, 1), dtype=torch.int32, device="cuda"),
+                         flags=dev(geo[3]))
+    kw = dict(tgt_rgb=dev(b.tgt_rgb), tgt_depth=dev(b.tgt_depth), mask=dev(b.mask))
+    ws = api.Workspace().get(arch, b.n_rays, samp.t.shape[1])
+    for scale, overflow in ((2.0 ** 12, False), (2.0 ** 40, True)):
+        m = api.Model(arch, params, loss_scale=scale)
+        p0 = m.params.clone()
+        api.prenom_render_fwd(m, samp, b.loss, ws, **kw)
+        api.prenom_render_bwd(m, samp, b.loss, ws, **kw)
+        torch.cuda.synchronize()
+        g = m.grads.cpu().numpy()
+        print(f"  scale 2^{int(np.log2(scale))}: finite gradient entries {np.isfinite(g).mean():.4f}, "
+              f"scaler state {m.scaler_state.cpu().tolist()}", flush=True)
+        api.prenom_adam_step(m, growth_interval=1000)
+        torch.cuda.synchronize()
+        assert float(m.grads.abs().max()) == 0.0
+        if overflow:
+            assert torch.equal(m.params, p0), "the overflowing step must not move the parameters"
+            assert float(m.loss_scale.item()) == scale / 2
+        else:
+            assert not torch.equal(m.params, p0)
+            assert float(m.loss_scale.item()) == scale
+        assert m.scaler_state.cpu().tolist()[0] == 0
 
 
 def test_loss_scaling_skips_non_finite_steps_and_adapts():
