@@ -68,19 +68,33 @@ __device__ __forceinline__ floatx4 unpack(typename P::vec v)
     return {P::back(v[0]), P::back(v[1]), P::back(v[2]), P::back(v[3])};
 }
 
-// Stored 16-bit activations carry the ReLU decision in their sign: a unit
-// switched off is stored as -0, one switched on as its value, which may round
-// to +0 (FP16 underflow) and still passes its delta in the backward.
-__device__ __forceinline__ floatx4 relu_sign_coded(floatx4 h)
+// ReLU masks of the 128-wide MLP, kept beside its stored activations as bits
+// (the decision of the FP32 pre-activation, whatever the 16-bit activation
+// rounds to): one 32-bit word per (layer, sample, lane group q), bit 4 to + r
+// for neuron 16 to + 4 q + r.  The backward chain reads these 16 bytes per
+// sample and layer instead of the 256-byte activation row.
+__device__ __forceinline__ uint32_t relu_mask_bits(const floatx4* h, int n_tiles)
 {
-    return {h[0] > 0.0f ? h[0] : -0.0f, h[1] > 0.0f ? h[1] : -0.0f, h[2] > 0.0f ? h[2] : -0.0f,
-            h[3] > 0.0f ? h[3] : -0.0f};
+    uint32_t m = 0;
+    for (int to = 0; to < n_tiles; ++to)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) m |= (h[to][r] > 0.0f ? 1u : 0u) << (4 * to + r);
+    return m;
 }
 
-__device__ __forceinline__ floatx4 mask_sign_coded(floatx4 g, floatx4 h)
+__device__ __forceinline__ floatx4 mask_by_bits(floatx4 g, uint32_t m, int to)
 {
-    return {signbit(h[0]) ? 0.0f : g[0], signbit(h[1]) ? 0.0f : g[1], signbit(h[2]) ? 0.0f : g[2],
-            signbit(h[3]) ? 0.0f : g[3]};
+    return {(m >> (4 * to)) & 1u ? g[0] : 0.0f, (m >> (4 * to + 1)) & 1u ? g[1] : 0.0f,
+            (m >> (4 * to + 2)) & 1u ? g[2] : 0.0f, (m >> (4 * to + 3)) & 1u ? g[3] : 0.0f};
+}
+
+// Layout of the 128-wide MLP's activation buffer (mlp_act_floats floats):
+// activations [D][n_s][W] and deltas [D][n_s][W] in the MFMA type, then the
+// ReLU mask words [D][n_s][4].
+template <int W, int D, class P>
+__device__ __forceinline__ uint32_t* wide_masks(typename P::vec* a16, int64_t n_s)
+{
+    return reinterpret_cast<uint32_t*>(a16 + (int64_t)2 * D * n_s * W / 4);
 }
 
 template <int IN, int W, int D>
@@ -246,10 +260,13 @@ __device__ __forceinline__ void mlp_fwd_tiles_lp(const typename P::vec* __restri
         if (q == 0 && valid) sc[s] = make_float4(__expf(o[0]), sigmoidf_(o[1]), sigmoidf_(o[2]), sigmoidf_(o[3]));
         if (act && valid) {  // stored already rounded: the values every later use sees
             typename P::vec* a16 = reinterpret_cast<typename P::vec*>(act);
+            uint32_t* masks = wide_masks<W, D, P>(a16, n_s);
 #pragma unroll
-            for (int k = 0; k < D; ++k)
+            for (int k = 0; k < D; ++k) {
 #pragma unroll
-                for (int to = 0; to < N::OT; ++to) a16[(((int64_t)k * n_s + s) * W + 16 * to + 4 * q) / 4] = pack<P>(relu_sign_coded(hs[k][to]));
+                for (int to = 0; to < N::OT; ++to) a16[(((int64_t)k * n_s + s) * W + 16 * to + 4 * q) / 4] = pack<P>(hs[k][to]);
+                masks[((int64_t)k * n_s + s) * 4 + q] = relu_mask_bits(hs[k], N::OT);
+            }
         }
     }
 }
@@ -466,7 +483,7 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_bwd_lp_batch(const MlpWo
 
 // ---------------------------------------------------------------- 128 wide
 // As in the FP32 form: the forward stores the hidden activations (in the
-// MFMA type, each unit's ReLU decision in the sign: relu_sign_coded); a chain
+// MFMA type, each unit's ReLU decision beside them as bits: relu_mask_bits); a chain
 // kernel with only the transposed fragments writes every layer's delta and
 // dy; a weight-gradient kernel contracts deltas with activations over the
 // block's samples (operands rounded to the MFMA type, FP32 accumulation),
@@ -492,23 +509,22 @@ __device__ __forceinline__ void mlp_chain_bwd_tiles_lp(const typename P::vec* __
             dO = {g.x * v.x, g.y * v.y * (1.0f - v.y), g.z * v.z * (1.0f - v.z), g.w * v.w * (1.0f - v.w)};
         }
         const typename P::vec dOp = pack<P>(dO);
-        floatx4 hk[N::OT], delta[N::OT];
+        static_assert(N::OT * 4 <= 32, "mask bits per lane");
+        const uint32_t* masks = wide_masks<W, D, P>(const_cast<typename P::vec*>(act16), n_s);
+        floatx4 delta[N::OT];
         auto vi = [&](int k, int to) { return (((int64_t)k * n_s + s) * W + 16 * to + 4 * q) / 4; };
-#pragma unroll
-        for (int to = 0; to < N::OT; ++to)
-            hk[to] = valid ? unpack<P>(act16[vi(D - 1, to)]) : floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+        auto mask_of = [&](int k) { return valid ? masks[((int64_t)k * n_s + s) * 4 + q] : 0u; };
+        uint32_t mk = mask_of(D - 1);
 #pragma unroll
         for (int to = 0; to < N::OT; ++to) {
             floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
             acc = P::mma(bfrag[(BO + to) * 64 + lane], dOp, acc);
-            delta[to] = mask_sign_coded(acc, hk[to]);
+            delta[to] = mask_by_bits(acc, mk, to);
             if (valid) dlt16[vi(D - 1, to)] = pack<P>(delta[to]);
         }
 #pragma unroll
         for (int k = D - 1; k >= 1; --k) {
-#pragma unroll
-            for (int to = 0; to < N::OT; ++to)
-                hk[to] = valid ? unpack<P>(act16[vi(k - 1, to)]) : floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+            mk = mask_of(k - 1);
             typename P::vec dp[N::OT];
 #pragma unroll
             for (int ti = 0; ti < N::OT; ++ti) dp[ti] = pack<P>(delta[ti]);
@@ -516,7 +532,7 @@ __device__ __forceinline__ void mlp_chain_bwd_tiles_lp(const typename P::vec* __
             layer_lp_ks_outer<P, N::OT, N::OT>(bfrag, lane, BH + (k - 1) * N::OT * N::OT, N::OT, dp, nd);
 #pragma unroll
             for (int to = 0; to < N::OT; ++to) {
-                delta[to] = mask_sign_coded(nd[to], hk[to]);
+                delta[to] = mask_by_bits(nd[to], mk, to);
                 if (valid) dlt16[vi(k - 1, to)] = pack<P>(delta[to]);
             }
         }
