@@ -383,7 +383,15 @@ typedef struct prenom_mlp_tiles {
  * step: device int64 Adam step counter or NULL.  With it the bias corrections
  *   use *step + 1 and the counter advances on the device after each applied
  *   update, so a captured step graph can be replayed without host arguments
- *   (the caller zeroes it once). */
+ *   (the caller zeroes it once).
+ * record_budget: bytes of hash-table gradient records one scatter pass may
+ *   hold, 0 for PRENOM_RECORD_BUDGET.  The backward's scatter (Eq. (3)'s
+ *   table gradient) runs over groups of consecutive whole objects whose
+ *   worst-case records (64 bytes per sample and level) fit the budget; an
+ *   object above it is a group of its own.  The workspace holds the largest
+ *   group's records, so a smaller budget trades a smaller workspace for more
+ *   launches (six per group); the gradients do not depend on the grouping. */
+#define PRENOM_RECORD_BUDGET ((int64_t)4 << 30)
 typedef struct prenom_batch {
     int32_t n_objects;
     const prenom_object* objects;
@@ -397,6 +405,7 @@ typedef struct prenom_batch {
     float* loss_scale;
     int32_t* scaler_state;
     int64_t* step;
+    int64_t record_budget;
 } prenom_batch;
 
 #define PRENOM_MAX_OBJECTS 4096

@@ -66,7 +66,8 @@ class PrenomBatch(C.Structure):
     _fields_ = [("n_objects", C.c_int32), ("objects", C.POINTER(PrenomObject)), ("n_tiles", C.c_int32),
                 ("tiles", C.POINTER(PrenomMlpTiles)), ("params", C.c_void_p), ("grads", C.c_void_p),
                 ("adam_m", C.c_void_p), ("adam_v", C.c_void_p), ("params_lp", C.c_void_p),
-                ("loss_scale", C.c_void_p), ("scaler_state", C.c_void_p), ("step", C.c_void_p)]
+                ("loss_scale", C.c_void_p), ("scaler_state", C.c_void_p), ("step", C.c_void_p),
+                ("record_budget", C.c_int64)]
 
 
 class PrenomKernelTime(C.Structure):

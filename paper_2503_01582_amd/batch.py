@@ -71,8 +71,9 @@ class BatchModel:
     the batch layout (object i at its 64-float aligned offset)."""
 
     def __init__(self, objs: Sequence[BatchObject], params: Sequence, device="cuda", loss_scale=None,
-                 tiles=None, device_step: bool = True):
+                 tiles=None, device_step: bool = True, record_budget: int = 0):
         self.objs = list(objs)
+        self.record_budget = int(record_budget)
         self._c_objs = _c_objects(self.objs)
         n_obj = len(self.objs)
         n = int(L.lib().prenom_batch_param_count(self._c_objs, n_obj))
@@ -124,6 +125,7 @@ class BatchModel:
         b.loss_scale = None if self.loss_scale is None else self.loss_scale.data_ptr()
         b.scaler_state = None if self.scaler_state is None else self.scaler_state.data_ptr()
         b.step = None if self.step is None else self.step.data_ptr()
+        b.record_budget = self.record_budget
         return b
 
 
@@ -236,8 +238,9 @@ class BatchTrainer:
 
     def __init__(self, objs: Sequence[BatchObject], params: Sequence, sample_spec, loss_spec, lr=1e-2,
                  beta1=0.9, beta2=0.99, eps=1e-15, device="cuda", loss_scale=None, growth_interval=2000,
-                 tiles=None, recompute=False):
-        self.model = BatchModel(objs, params, device, loss_scale=loss_scale, tiles=tiles, device_step=True)
+                 tiles=None, recompute=False, record_budget=0):
+        self.model = BatchModel(objs, params, device, loss_scale=loss_scale, tiles=tiles, device_step=True,
+                                record_budget=record_budget)
         self.sample_spec = sample_spec
         self.loss_spec = loss_spec
         self.recompute = recompute

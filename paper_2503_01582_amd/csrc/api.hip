@@ -289,7 +289,7 @@ WsLayout ws_layout(const prenom_arch* a, int64_t n_rays_all, int32_t S, bool rec
     w.tile_start = off;
     off = align_up(off + (nt + 1) * sizeof(uint64_t));
     w.chunk_start = off;
-    off = align_up(off + (nt + 1) * sizeof(uint64_t));
+    off = align_up(off + (nt + 2) * sizeof(uint64_t));
     w.work_counter = off;
     off = align_up(off + sizeof(uint64_t));
     w.recs = off;
@@ -584,6 +584,7 @@ prenom_status prenom_render_bwd(const prenom_model* model, const prenom_render_c
         sa.nonfinite = model->loss_scale ? model->scaler_state : nullptr;
         sa.fwd_counts = 1;  // render_fwd (or the recompute above) wrote the tile histograms
         sa.merge_runs = 1;
+        sa.chunk_min_bits = 21;  // one pass over one object: items of 2^21 records keep the CUs busy
         for (int ph = 0; ph < kScatterPhases; ++ph)
             PRENOM_LAUNCH(ph == 0 ? "k_scatter_dymax" : kScatterPhaseNames[ph], s, launch_scatter_phase(sa, ph, s));
     }

@@ -38,10 +38,22 @@ struct Group {
     int64_t partial_off;       // floats
 };
 
+// One pass of the table-gradient scatter: consecutive whole objects
+// [first, first + count), with their scatter geometry re-based so the pass's
+// items, tiles and levels count from 0 (counts, block maxima, dy and the
+// gradient keep the batch's offsets).
+struct ScatterGroup {
+    int first = 0, count = 0;
+    int64_t n_items = 0, n_tiles = 0, records = 0;
+    int32_t n_levels = 0;
+};
+
 struct Plan {
     int n_obj = 0, S = 0;
     std::vector<ObjDev> dev;
     std::vector<ScatterObj> sc;
+    std::vector<ScatterObj> sc_pass;  // sc re-based per scatter group
+    std::vector<ScatterGroup> sgroups;
     std::vector<MlpRed> red;
     std::vector<MlpWork> fwd, bwd;
     std::vector<Group> groups;
@@ -50,7 +62,7 @@ struct Plan {
     int32_t n_levels_total = 0, tiles_max = 1;
     bool any_f16_table = false;
     // workspace offsets (bytes)
-    size_t o_dev, o_sc, o_red, o_fwd, o_bwd;
+    size_t o_dev, o_sc, o_sc_pass, o_red, o_fwd, o_bwd;
     size_t y, sc_out, dout, dy, ray_state, ray_loss, partial, act, cnt, offs, block_max, level_max, tile_exp, tile_total,
         tile_start, chunk_start, work_counter, recs, total;
     uint64_t fingerprint = 0;
@@ -100,6 +112,7 @@ prenom_status build_plan(const prenom_batch* b, int32_t S, Plan& p)
     if (st != PRENOM_OK) return st;
     if (S < 1 || S > 256) return fail(PRENOM_ERR_SHAPE, "n_samples %d outside [1, 256]", S);
     if (b->n_tiles < 0 || (b->n_tiles > 0 && !b->tiles)) return fail(PRENOM_ERR_INVALID_ARG, "tiles");
+    if (b->record_budget < 0) return fail(PRENOM_ERR_INVALID_ARG, "record_budget < 0");
     for (int i = 0; i < b->n_tiles; ++i) {
         const prenom_mlp_tiles& t = b->tiles[i];
         if (t.fwd_tiles != 0 && (t.fwd_tiles < 4 || t.fwd_tiles > 4096 || t.fwd_tiles % 4))
@@ -168,7 +181,6 @@ prenom_status build_plan(const prenom_batch* b, int32_t S, Plan& p)
         bmax += (int64_t)a->n_levels * so.n_blocks;
         lev += a->n_levels;
         mlp += r.n_mlp;
-        p.records += scatter_records(so);
     }
     if ((double)ray * S > 536870912.0) return fail(PRENOM_ERR_SHAPE, "batch rays * n_samples > 2^29");
     p.n_rays = ray;
@@ -182,6 +194,30 @@ prenom_status build_plan(const prenom_batch* b, int32_t S, Plan& p)
     p.n_mlp_total = mlp;
     if (item >= ((int64_t)1 << 31) || tile >= ((int64_t)1 << 31))
         return fail(PRENOM_ERR_SHAPE, "batch grid too large");
+
+    // scatter passes: greedy runs of whole objects within the record budget
+    const int64_t budget = (b->record_budget > 0 ? b->record_budget : PRENOM_RECORD_BUDGET) / (int64_t)sizeof(uint64_t);
+    h = fnv(h, &budget, sizeof budget);
+    p.sc_pass = p.sc;
+    p.records = 0;
+    for (int i = 0; i < n;) {
+        ScatterGroup g{};
+        g.first = i;
+        do {
+            ScatterObj& lo = p.sc_pass[i];
+            lo.item_off = g.n_items;
+            lo.tile_off = g.n_tiles;
+            lo.lev_off = g.n_levels;
+            g.n_items += scatter_items(p.sc[i]);
+            g.n_tiles += p.sc[i].n_tiles;
+            g.n_levels += p.sc[i].grid.n_levels;
+            g.records += scatter_records(p.sc[i]);
+            ++i;
+        } while (i < n && g.records + scatter_records(p.sc[i]) <= budget);
+        g.count = i - g.first;
+        p.records = g.records > p.records ? g.records : p.records;
+        p.sgroups.push_back(g);
+    }
 
     // MLP groups, in order of first appearance; work items object by object
     for (int i = 0; i < n; ++i) {
@@ -252,6 +288,7 @@ prenom_status build_plan(const prenom_batch* b, int32_t S, Plan& p)
     const size_t n_s = (size_t)p.n_rays * (size_t)S;
     p.o_dev = take(sizeof(ObjDev) * n);
     p.o_sc = take(sizeof(ScatterObj) * n);
+    p.o_sc_pass = take(sizeof(ScatterObj) * n);
     p.o_red = take(sizeof(MlpRed) * n);
     p.o_fwd = take(sizeof(MlpWork) * p.fwd.size());
     p.o_bwd = take(sizeof(MlpWork) * p.bwd.size());
@@ -270,7 +307,7 @@ prenom_status build_plan(const prenom_batch* b, int32_t S, Plan& p)
     p.tile_exp = take(sizeof(int32_t) * (size_t)p.n_tiles);
     p.tile_total = take(sizeof(uint64_t) * (size_t)p.n_tiles);
     p.tile_start = take(sizeof(uint64_t) * (size_t)(p.n_tiles + 1));
-    p.chunk_start = take(sizeof(uint64_t) * (size_t)(p.n_tiles + 1));
+    p.chunk_start = take(sizeof(uint64_t) * (size_t)(p.n_tiles + 2));
     p.work_counter = take(sizeof(uint64_t));
     p.recs = take(sizeof(uint64_t) * (size_t)p.records);
     p.total = off;
@@ -303,18 +340,20 @@ prenom_status check_params(const prenom_batch* b, const Plan& p, bool need_grads
     return PRENOM_OK;
 }
 
-ScatterArgs scatter_args(const Plan& p, void* ws, const float* ray_obj, const float* t, float* grads,
-                         int32_t* nonfinite)
+// Scatter of group g's objects; the per-tile and per-level arrays are reused
+// from their start by every pass.
+ScatterArgs scatter_args(const Plan& p, const ScatterGroup& g, void* ws, const float* ray_obj, const float* t,
+                         float* grads, int32_t* nonfinite)
 {
     ScatterArgs sa{};
     sa.S = p.S;
-    sa.n_obj = p.n_obj;
-    sa.objs = at<ScatterObj>(ws, p.o_sc);
+    sa.n_obj = g.count;
+    sa.objs = at<ScatterObj>(ws, p.o_sc_pass) + g.first;
     sa.tiles_max = p.tiles_max;
     sa.reduce_blocks = device_cus();
-    sa.n_tiles = p.n_tiles;
-    sa.n_items = p.n_items;
-    sa.n_levels_total = p.n_levels_total;
+    sa.n_tiles = g.n_tiles;
+    sa.n_items = g.n_items;
+    sa.n_levels_total = g.n_levels;
     sa.ray_obj = ray_obj;
     sa.t = t;
     sa.dy = at<const float2>(ws, p.dy);
@@ -333,6 +372,7 @@ ScatterArgs scatter_args(const Plan& p, void* ws, const float* ray_obj, const fl
     sa.nonfinite = nonfinite;
     sa.fwd_counts = 1;  // fwd_features (render_fwd, or the recompute in render_bwd) wrote the histograms
     sa.merge_runs = 1;
+    sa.chunk_min_bits = 18;  // a pass of a few objects needs smaller items to fill the CUs
     return sa;
 }
 
@@ -438,6 +478,8 @@ prenom_status prenom_batch_prepare(const prenom_batch* batch, int32_t n_samples,
     };
     PRENOM_TRY_HIP(put(p.o_dev, p.dev.data(), sizeof(ObjDev) * p.dev.size()), "upload objects");
     PRENOM_TRY_HIP(put(p.o_sc, p.sc.data(), sizeof(ScatterObj) * p.sc.size()), "upload scatter geometry");
+    PRENOM_TRY_HIP(put(p.o_sc_pass, p.sc_pass.data(), sizeof(ScatterObj) * p.sc_pass.size()),
+                   "upload scatter passes");
     PRENOM_TRY_HIP(put(p.o_red, p.red.data(), sizeof(MlpRed) * p.red.size()), "upload reductions");
     PRENOM_TRY_HIP(put(p.o_fwd, p.fwd.data(), sizeof(MlpWork) * p.fwd.size()), "upload forward work");
     PRENOM_TRY_HIP(put(p.o_bwd, p.bwd.data(), sizeof(MlpWork) * p.bwd.size()), "upload backward work");
@@ -560,8 +602,8 @@ prenom_status prenom_batch_render_bwd(const prenom_batch* batch, const prenom_re
     PRENOM_LAUNCH("k_reduce_partials", s,
                   launch_reduce_partials_batch(at<const MlpRed>(workspace, p.o_red), p.n_obj, p.n_mlp_total, partial,
                                                batch->grads, s));
-    {
-        const ScatterArgs sa = scatter_args(p, workspace, ray_obj, t, batch->grads,
+    for (const ScatterGroup& g : p.sgroups) {
+        const ScatterArgs sa = scatter_args(p, g, workspace, ray_obj, t, batch->grads,
                                             batch->loss_scale ? batch->scaler_state : nullptr);
         for (int ph = 0; ph < kScatterPhases; ++ph)
             PRENOM_LAUNCH(ph == 0 ? "k_scatter_dymax" : kScatterPhaseNames[ph], s, launch_scatter_phase(sa, ph, s));

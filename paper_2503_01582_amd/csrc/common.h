@@ -340,7 +340,7 @@ struct ScatterArgs {
     int32_t* tile_exp;      // [n_tiles] fixed-point exponent
     uint64_t* tile_total;   // [n_tiles]
     uint64_t* tile_start;   // [n_tiles + 1]
-    uint64_t* chunk_start;  // [n_tiles + 1]
+    uint64_t* chunk_start;  // [n_tiles + 2]: chunk bases, their total, the chunk size's log2
     unsigned long long* work_counter;
     uint64_t* recs;         // [records] packed records (scatter.hip: row, shared exponent, two mantissas)
     int64_t n_records;      // length of recs
@@ -354,6 +354,11 @@ struct ScatterArgs {
     // joining its record (run_heads; the rule the forward's histograms
     // follow).  0: one record per corner of every sample whose dy is not zero.
     int32_t merge_runs;
+    // log2 of the smallest reduce work item in records (18..21; the scan picks
+    // a size from the pass's records).  A tile longer than one item is summed
+    // by several workgroups whose FP32 partials meet in atomics, in an order
+    // that can change the last bits; 21 keeps most tiles to one item.
+    int32_t chunk_min_bits;
 };
 // The scatter runs as kScatterPhases dependent kernels, launched in order
 // (phase 0 .. kScatterPhases - 1): count (or, with fwd_counts, the block

@@ -55,7 +55,12 @@ constexpr int kScanThreads = 1024;
 constexpr int kReduceThreads = 1024;
 constexpr int kRun = 8;            // consecutive records per thread and load
 constexpr int kRunsPerThread = 3;  // runs in flight per thread
-constexpr int64_t kChunk = (int64_t)1 << 21;  // records per reduce work item
+// Records per reduce work item: a power of two between 2^chunk_min_bits and
+// 2^kChunkMaxBits, the smallest that gives at most kChunksPerBlock items per
+// reduce block (few large items leave blocks idle at the end of a pass; each
+// item also zeroes and writes out its whole tile).
+constexpr int kChunkMinBits = 18, kChunkMaxBits = 21;
+constexpr uint64_t kChunksPerBlock = 4;
 
 // ---------------------------------------------------------------- records
 // One 64-bit word per record: bits 0-12 the row within the tile, bits 13-19
@@ -382,18 +387,26 @@ __global__ __launch_bounds__(kScanThreads) void k_scatter_scan_tiles(ScatterArgs
     const int64_t per = (n + kScanThreads - 1) / kScanThreads;
     const int64_t t0 = threadIdx.x * per, t1 = min(t0 + per, n);
     uint64_t rs = 0, cs = 0;
-    for (int64_t t = t0; t < t1; ++t) {
-        rs += a.tile_total[t];
-        cs += (a.tile_total[t] + kChunk - 1) / kChunk;
-    }
+    for (int64_t t = t0; t < t1; ++t) rs += a.tile_total[t];
     prec[threadIdx.x] = rs;
-    pchk[threadIdx.x] = cs;
     __syncthreads();
     for (int d = 1; d < kScanThreads; d <<= 1) {
         const uint64_t v = threadIdx.x >= d ? prec[threadIdx.x - d] : 0;
-        const uint64_t w = threadIdx.x >= d ? pchk[threadIdx.x - d] : 0;
         __syncthreads();
         prec[threadIdx.x] += v;
+        __syncthreads();
+    }
+    // chunk size from the pass's record total
+    const uint64_t per_item = prec[kScanThreads - 1] / ((uint64_t)a.reduce_blocks * kChunksPerBlock);
+    int cb = min(max(a.chunk_min_bits, kChunkMinBits), kChunkMaxBits);
+    while (cb < kChunkMaxBits && ((uint64_t)1 << cb) < per_item) ++cb;
+    const uint64_t chunk = (uint64_t)1 << cb;
+    for (int64_t t = t0; t < t1; ++t) cs += (a.tile_total[t] + chunk - 1) >> cb;
+    pchk[threadIdx.x] = cs;
+    __syncthreads();
+    for (int d = 1; d < kScanThreads; d <<= 1) {
+        const uint64_t w = threadIdx.x >= d ? pchk[threadIdx.x - d] : 0;
+        __syncthreads();
         pchk[threadIdx.x] += w;
         __syncthreads();
     }
@@ -402,7 +415,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scatter_scan_tiles(ScatterArgs
         a.tile_start[t] = r;
         a.chunk_start[t] = ck;
         r += a.tile_total[t];
-        ck += (a.tile_total[t] + kChunk - 1) / kChunk;
+        ck += (a.tile_total[t] + chunk - 1) >> cb;
         // largest e with vmax * records * 2^e < 2^62 (bound on any row's
         // |sum| * 2^e) and vmax * 2^e < 2^50 (bound on one record's fixed-point
         // value, so a record's mantissa is shifted by at most 33 bits), vmax
@@ -430,6 +443,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scatter_scan_tiles(ScatterArgs
         const bool ok = !a.fwd_counts || prec[kScanThreads - 1] <= (uint64_t)a.n_records;
         a.tile_start[n] = ok ? prec[kScanThreads - 1] : ~0ull;
         a.chunk_start[n] = ok ? pchk[kScanThreads - 1] : 0ull;
+        a.chunk_start[n + 1] = (uint64_t)cb;
         *a.work_counter = 0;
     }
 }
@@ -577,6 +591,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_scatter_reduce(ScatterArgs a
     __shared__ unsigned long long acc[2 * kTileRows];  // fixed point: feature 0 rows, then feature 1 rows
     __shared__ int64_t s_chunk;
     const uint64_t n_chunks = a.chunk_start[a.n_tiles];
+    const int cb = (int)a.chunk_start[a.n_tiles + 1];
     for (;;) {
         if (threadIdx.x == 0) s_chunk = (int64_t)atomicAdd(a.work_counter, 1ull);
         __syncthreads();
@@ -600,8 +615,8 @@ __global__ __launch_bounds__(kReduceThreads) void k_scatter_reduce(ScatterArgs a
         const int64_t row0 = (int64_t)tt << kTileBits;
         const int n_rows = (int)min((int64_t)kTileRows, o.level_rows[l] - row0);
         const uint64_t k0 = chunk - a.chunk_start[tile];
-        const uint64_t r_begin = a.tile_start[tile] + k0 * kChunk;
-        const uint64_t r_end = min(r_begin + (uint64_t)kChunk, a.tile_start[tile + 1]);
+        const uint64_t r_begin = a.tile_start[tile] + (k0 << cb);
+        const uint64_t r_end = min(r_begin + ((uint64_t)1 << cb), a.tile_start[tile + 1]);
         const bool owner = (a.chunk_start[tile + 1] - a.chunk_start[tile]) == 1;
         const int ex = a.tile_exp[tile];
         // a record (qx, qy, r) is worth (qx, qy) 2^(E - r - 21); in fixed point

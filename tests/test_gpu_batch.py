@@ -118,11 +118,12 @@ def oracle_geometry(objs, b):
 
 
 class BatchRun:
-    def __init__(self, objs, params, b, geo, loss, tiles=None, loss_scale=None):
+    def __init__(self, objs, params, b, geo, loss, tiles=None, loss_scale=None, record_budget=0):
         from paper_2503_01582_amd import api
         from paper_2503_01582_amd import batch as B
         self.B = B
-        self.bm = B.BatchModel(batch_objects(objs), params, tiles=tiles, loss_scale=loss_scale)
+        self.bm = B.BatchModel(batch_objects(objs), params, tiles=tiles, loss_scale=loss_scale,
+                               record_budget=record_budget)
         self.ws = B.alloc_workspace(self.bm, geo[1].shape[1])
         self.samp = api.SampleOut(ray_obj=dev(geo[0]), t=dev(geo[1]), dt=dev(geo[2]),
                                   bins=torch.zeros((geo[1].shape[0], 1), dtype=torch.int32, device="cuda"),
@@ -143,15 +144,17 @@ class BatchRun:
         return [self.bm.object_grads(i).cpu().numpy() for i in range(len(self.bm.objs))]
 
 
-@pytest.mark.parametrize("recompute", [False, True])
-def test_batch_render_matches_oracle(recompute):
-    say(f"test_batch_render_matches_oracle[recompute={recompute}]")
+# record budgets: one scatter pass over all objects; one pass per object (1
+# byte); two passes, objects 0-4 and 5-6 (64 MiB)
+@pytest.mark.parametrize("recompute,record_budget", [(False, 0), (True, 0), (False, 1), (True, 64 << 20)])
+def test_batch_render_matches_oracle(recompute, record_budget):
+    say(f"test_batch_render_matches_oracle[recompute={recompute}, record_budget={record_budget}]")
     objs = make_objects()
     params = object_params(objs)
     b = multi_batch(objs, step=5, depth_noise=0.01)
     geo = oracle_geometry(objs, b)
     loss = LossSpec(lambda_d=0.1, lambda_sigma=0.01)
-    run = BatchRun(objs, params, b, geo, loss)
+    run = BatchRun(objs, params, b, geo, loss, record_budget=record_budget)
     got = run.fwd()
     if recompute:  # the workspace must not be needed between the calls
         run.ws[:] = 0
