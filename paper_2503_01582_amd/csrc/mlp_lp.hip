@@ -500,20 +500,37 @@ __device__ __forceinline__ void mlp_chain_bwd_tiles_lp(const typename P::vec* __
     using N = NetLp<IN, W, D>;
     constexpr int BO = 0, BH = N::BH - N::N_FWD, B1 = N::B1 - N::N_FWD;
     const int lane = threadIdx.x & 63, q = lane >> 4, j = lane & 15;
+    static_assert(N::OT * 4 <= 32, "mask bits per lane");
+    const uint32_t* masks = wide_masks<W, D, P>(const_cast<typename P::vec*>(act16), n_s);
+    // a tile's loads (head adjoint inputs on lanes q == 0, every layer's mask
+    // word), issued one tile ahead so they overlap the current tile's work
+    float4 gn = make_float4(0.0f, 0.0f, 0.0f, 0.0f), vn = gn;
+    uint32_t mn[D];
+    auto load_tile = [&](int64_t t) {
+        const int64_t st = t * 16 + j;
+        const bool ok = t < end && st < n_s;
+        gn = vn = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (ok && q == 0) {
+            gn = dout[st];
+            vn = sc[st];
+        }
+#pragma unroll
+        for (int k = 0; k < D; ++k) mn[k] = ok ? masks[((int64_t)k * n_s + st) * 4 + q] : 0u;
+    };
+    load_tile(tile0);
     for (int64_t tile = tile0; tile < end; tile += step) {
         const int64_t s = tile * 16 + j;
         const bool valid = s < n_s;
-        floatx4 dO = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (q == 0 && valid) {
-            const float4 g = dout[s], v = sc[s];
-            dO = {g.x * v.x, g.y * v.y * (1.0f - v.y), g.z * v.z * (1.0f - v.z), g.w * v.w * (1.0f - v.w)};
-        }
+        const float4 g = gn, v = vn;
+        uint32_t mc[D];
+#pragma unroll
+        for (int k = 0; k < D; ++k) mc[k] = mn[k];
+        load_tile(tile + step);
+        const floatx4 dO = {g.x * v.x, g.y * v.y * (1.0f - v.y), g.z * v.z * (1.0f - v.z), g.w * v.w * (1.0f - v.w)};
         const typename P::vec dOp = pack<P>(dO);
-        static_assert(N::OT * 4 <= 32, "mask bits per lane");
-        const uint32_t* masks = wide_masks<W, D, P>(const_cast<typename P::vec*>(act16), n_s);
         floatx4 delta[N::OT];
         auto vi = [&](int k, int to) { return (((int64_t)k * n_s + s) * W + 16 * to + 4 * q) / 4; };
-        auto mask_of = [&](int k) { return valid ? masks[((int64_t)k * n_s + s) * 4 + q] : 0u; };
+        auto mask_of = [&](int k) { return mc[k]; };
         uint32_t mk = mask_of(D - 1);
 #pragma unroll
         for (int to = 0; to < N::OT; ++to) {
@@ -590,70 +607,93 @@ __device__ __forceinline__ uint2 bits(typename P::vec v)
     return __builtin_bit_cast(uint2, v);
 }
 
-// Stage samples [s0, min(s0 + kDwChunk, s_end)) (zeros past the end).
-// act16 / dlt16: [D][n_s][W] 16-bit rows; y: level-major [L][n_s][2].
+// Staging of samples [s0, min(s0 + kDwChunk, s_end)) (zeros past the end),
+// in two halves so the next chunk's global loads overlap the current chunk's
+// MFMAs: dw_load_lp reads a thread's share into registers, dw_store_lp
+// writes it to LDS.  act16 / dlt16: [D][n_s][W] 16-bit rows; y: level-major
+// [L][n_s][2].  256 threads.
+template <int W, int D>
+struct DwRegsLp {
+    static constexpr int SG = kDwChunk / 4;              // 4-sample groups per chunk
+    static constexpr int V = W / 4;                      // 4-neuron groups per row
+    static constexpr int N_AD = 2 * D * SG * V;          // 4 x 4 blocks of deltas and activations
+    static constexpr int PER = (N_AD + 255) / 256;
+    uint2 ad[PER][4];  // rows r = 0..3 (samples) of each block
+    float2 yv[4];      // features 2l, 2l + 1 of 4 samples (threads < 16 SG)
+    float4 g, v;       // head adjoint inputs of one sample (threads < kDwChunk)
+};
+
 template <int IN, int W, int D, class P>
-__device__ __forceinline__ void dw_stage_lp(uint16_t* __restrict__ lds, const float* __restrict__ y,
-                                            const float4* __restrict__ sc, const float4* __restrict__ dout,
-                                            const typename P::vec* __restrict__ act16,
-                                            const typename P::vec* __restrict__ dlt16, int64_t n_s, int64_t s0,
-                                            int64_t s_end)
+__device__ __forceinline__ void dw_load_lp(DwRegsLp<W, D>& R, const float* __restrict__ y,
+                                           const float4* __restrict__ sc, const float4* __restrict__ dout,
+                                           const typename P::vec* __restrict__ act16,
+                                           const typename P::vec* __restrict__ dlt16, int64_t n_s, int64_t s0,
+                                           int64_t s_end)
+{
+    using Rg = DwRegsLp<W, D>;
+#pragma unroll
+    for (int u = 0; u < Rg::PER; ++u) {
+        const int i = threadIdx.x + 256 * u;
+        const int arr = i / (D * Rg::SG * Rg::V), rem = i % (D * Rg::SG * Rg::V);
+        const int k = rem / (Rg::SG * Rg::V), r2 = rem % (Rg::SG * Rg::V), sg = r2 / Rg::V, c = r2 % Rg::V;
+        const typename P::vec* src = arr == 0 ? dlt16 : act16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t s = s0 + 4 * sg + r;
+            R.ad[u][r] = i < Rg::N_AD && s < s_end ? bits<P>(src[((int64_t)k * n_s + s) * Rg::V + c]) : make_uint2(0u, 0u);
+        }
+    }
+    {
+        const int l = threadIdx.x / Rg::SG, sg = threadIdx.x % Rg::SG;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t s = s0 + 4 * sg + r;
+            R.yv[r] = threadIdx.x < 16 * Rg::SG && s < s_end && 2 * l < IN
+                          ? reinterpret_cast<const float2*>(y)[(int64_t)l * n_s + s]
+                          : make_float2(0.0f, 0.0f);
+        }
+    }
+    {
+        const int64_t s = s0 + threadIdx.x;
+        const bool ok = threadIdx.x < kDwChunk && s < s_end;
+        R.g = ok ? dout[s] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        R.v = ok ? sc[s] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+}
+
+template <int IN, int W, int D, class P>
+__device__ __forceinline__ void dw_store_lp(uint16_t* __restrict__ lds, const DwRegsLp<W, D>& R)
 {
     using St = DwStageLp<W, D>;
-    constexpr int V = W / 4;                 // 4-neuron groups per row
-    constexpr int SG = kDwChunk / 4;         // 4-sample groups per chunk
+    using Rg = DwRegsLp<W, D>;
     // activations and deltas: one 4 x 4 block (4 samples x 4 neurons) per item
-    for (int i = threadIdx.x; i < 2 * D * SG * V; i += blockDim.x) {
-        const int arr = i / (D * SG * V), rem = i % (D * SG * V);
-        const int k = rem / (SG * V), r2 = rem % (SG * V), sg = r2 / V, c = r2 % V;
-        const typename P::vec* src = arr == 0 ? dlt16 : act16;
-        uint2 in[4], out[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t s = s0 + 4 * sg + r;
-            in[r] = s < s_end ? bits<P>(src[((int64_t)k * n_s + s) * V + c]) : make_uint2(0u, 0u);
+    for (int u = 0; u < Rg::PER; ++u) {
+        const int i = threadIdx.x + 256 * u;
+        if (i < Rg::N_AD) {
+            const int arr = i / (D * Rg::SG * Rg::V), rem = i % (D * Rg::SG * Rg::V);
+            const int k = rem / (Rg::SG * Rg::V), r2 = rem % (Rg::SG * Rg::V), sg = r2 / Rg::V, c = r2 % Rg::V;
+            uint2 out[4];
+            transpose4x4_16(R.ad[u], out);
+            uint16_t* base = lds + (arr == 0 ? St::DL : St::AC) + (k * W + 4 * c) * kDwRowLp + 4 * sg;
+#pragma unroll
+            for (int n = 0; n < 4; ++n) *reinterpret_cast<uint2*>(base + n * kDwRowLp) = out[n];
         }
-        transpose4x4_16(in, out);
-        uint16_t* base = lds + (arr == 0 ? St::DL : St::AC) + (k * W + 4 * c) * kDwRowLp + 4 * sg;
-#pragma unroll
-        for (int n = 0; n < 4; ++n) *reinterpret_cast<uint2*>(base + n * kDwRowLp) = out[n];
     }
     // inputs: features 2l, 2l + 1 of 4 samples per item (rounded to P)
-    for (int i = threadIdx.x; i < 16 * SG; i += blockDim.x) {
-        const int l = i / SG, sg = i % SG;
-        float f0[4], f1[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t s = s0 + 4 * sg + r;
-            float2 v = make_float2(0.0f, 0.0f);
-            if (s < s_end && 2 * l < IN) v = reinterpret_cast<const float2*>(y)[(int64_t)l * n_s + s];
-            f0[r] = v.x;
-            f1[r] = v.y;
-        }
+    if (threadIdx.x < 16 * Rg::SG) {
+        const int l = threadIdx.x / Rg::SG, sg = threadIdx.x % Rg::SG;
         uint16_t* base = lds + St::Y + (2 * l) * kDwRowLp + 4 * sg;
-        *reinterpret_cast<uint2*>(base) = bits<P>(pack<P>(f0[0], f0[1], f0[2], f0[3]));
-        *reinterpret_cast<uint2*>(base + kDwRowLp) = bits<P>(pack<P>(f1[0], f1[1], f1[2], f1[3]));
+        *reinterpret_cast<uint2*>(base) = bits<P>(pack<P>(R.yv[0].x, R.yv[1].x, R.yv[2].x, R.yv[3].x));
+        *reinterpret_cast<uint2*>(base + kDwRowLp) = bits<P>(pack<P>(R.yv[0].y, R.yv[1].y, R.yv[2].y, R.yv[3].y));
     }
-    // head adjoint (d sigma / d o0 = sigma, d c / d o = c (1 - c)) of 4 samples per item
-    for (int sg = threadIdx.x; sg < SG; sg += blockDim.x) {
-        float o[4][4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t s = s0 + 4 * sg + r;
-            float4 g = make_float4(0.0f, 0.0f, 0.0f, 0.0f), v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (s < s_end) {
-                g = dout[s];
-                v = sc[s];
-            }
-            o[0][r] = g.x * v.x;
-            o[1][r] = g.y * v.y * (1.0f - v.y);
-            o[2][r] = g.z * v.z * (1.0f - v.z);
-            o[3][r] = g.w * v.w * (1.0f - v.w);
-        }
+    // head adjoint (d sigma / d o0 = sigma, d c / d o = c (1 - c)) of one sample
+    if (threadIdx.x < kDwChunk) {
+        const float4 g = R.g, v = R.v;
+        const float o[4] = {g.x * v.x, g.y * v.y * (1.0f - v.y), g.z * v.z * (1.0f - v.z), g.w * v.w * (1.0f - v.w)};
 #pragma unroll
         for (int n = 0; n < 4; ++n)
-            *reinterpret_cast<uint2*>(lds + St::DO + n * kDwRowLp + 4 * sg) =
-                bits<P>(pack<P>(o[n][0], o[n][1], o[n][2], o[n][3]));
+            lds[St::DO + n * kDwRowLp + threadIdx.x] = __builtin_bit_cast(uint16_t, P::cvt(o[n]));
     }
 }
 
@@ -690,9 +730,13 @@ __device__ __forceinline__ void mlp_dw_range_lp(uint16_t* __restrict__ lds, cons
     auto op = [&](int base, int row, int k0) {
         return __builtin_bit_cast(typename P::vec, *reinterpret_cast<const uint2*>(lds + base + row * kDwRowLp + k0));
     };
+    static_assert(64 * kWideWavesLp == 256, "staging assumes 256 threads");
+    DwRegsLp<W, D> R;
+    if (s_begin < s_end) dw_load_lp<IN, W, D, P>(R, y, sc, dout, act16, dlt16, n_s, s_begin, s_end);
     for (int64_t c0 = s_begin; c0 < s_end; c0 += kDwChunk) {
-        dw_stage_lp<IN, W, D, P>(lds, y, sc, dout, act16, dlt16, n_s, c0, s_end);
+        dw_store_lp<IN, W, D, P>(lds, R);
         __syncthreads();
+        if (c0 + kDwChunk < s_end) dw_load_lp<IN, W, D, P>(R, y, sc, dout, act16, dlt16, n_s, c0 + kDwChunk, s_end);
 #pragma unroll 1
         for (int ks = 0; ks < kDwChunk / 16; ++ks) {  // not unrolled: bounds the operands in flight
             const int k0 = 16 * ks + 4 * q;
