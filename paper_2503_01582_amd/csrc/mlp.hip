@@ -298,11 +298,24 @@ __device__ __forceinline__ void mlp_bwd_tiles(float* __restrict__ lds, const flo
         dWo[0][a] = {0.0f, 0.0f, 0.0f, 0.0f};
     }
 
+    // the next tile's inputs and upstream gradient, loaded while the current tile runs
+    float yn[N::KT1];
+    float4 gn = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    auto load_tile = [&](int64_t t) {
+        const int64_t st = t * 16 + j;
+        const bool ok = t < end && st < n_s;
+        load_inputs<N::KT1>(y, n_s, st, ok, q, yn);
+        gn = ok && q == 0 ? dout[st] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    };
+    load_tile(tile0);
     for (int64_t tile = tile0; tile < end; tile += step) {
         const int64_t s = tile * 16 + j;
         const bool valid = s < n_s;
         float yb[N::KT1];
-        load_inputs<N::KT1>(y, n_s, s, valid, q, yb);
+#pragma unroll
+        for (int kk = 0; kk < N::KT1; ++kk) yb[kk] = yn[kk];
+        const float4 gc = gn;
+        load_tile(tile + step);
         floatx4 hs[D][N::OT];
         floatx4 o;
         mlp_chain<IN, W, D>(frag, lane, yb, hs, o);
@@ -310,7 +323,7 @@ __device__ __forceinline__ void mlp_bwd_tiles(float* __restrict__ lds, const flo
         // head adjoint: lanes with q == 0 hold the 4 outputs of sample j
         float dq0 = 0.0f, dq1 = 0.0f, dq2 = 0.0f, dq3 = 0.0f;
         if (q == 0 && valid) {
-            const float4 g = dout[s];
+            const float4 g = gc;
             const float sig = __expf(o[0]);
             const float c1 = sigmoidf_(o[1]), c2 = sigmoidf_(o[2]), c3 = sigmoidf_(o[3]);
             dq0 = g.x * sig;
@@ -494,12 +507,23 @@ __device__ __forceinline__ void mlp_chain_bwd_tiles(const float* __restrict__ bf
     using N = Net<IN, W, D>;
     constexpr int BO = 0, BH = N::BH - N::N_FWD, B1 = N::B1 - N::N_FWD;  // fragments rebased to the transposed set
     const int lane = threadIdx.x & 63, q = lane >> 4, j = lane & 15;
+    // the next tile's upstream gradient and head outputs, loaded while the current tile runs
+    float4 gn = make_float4(0.0f, 0.0f, 0.0f, 0.0f), vn = gn;
+    auto load_tile = [&](int64_t t) {
+        const int64_t st = t * 16 + j;
+        const bool ok = t < end && st < n_s && q == 0;
+        gn = ok ? dout[st] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        vn = ok ? sc[st] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    };
+    load_tile(tile0);
     for (int64_t tile = tile0; tile < end; tile += step) {
         const int64_t s = tile * 16 + j;
         const bool valid = s < n_s;
+        const float4 gc = gn, vc = vn;
+        load_tile(tile + step);
         float dq0 = 0.0f, dq1 = 0.0f, dq2 = 0.0f, dq3 = 0.0f;
         if (q == 0 && valid) {  // d sigma / d o0 = sigma, d c / d o = c (1 - c)
-            const float4 g = dout[s], v = sc[s];
+            const float4 g = gc, v = vc;
             dq0 = g.x * v.x;
             dq1 = g.y * v.y * (1.0f - v.y);
             dq2 = g.z * v.z * (1.0f - v.z);

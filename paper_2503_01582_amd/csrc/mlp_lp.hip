@@ -357,11 +357,24 @@ __device__ __forceinline__ void mlp_bwd_tiles_lp(unsigned char* __restrict__ sme
         dWo[0][a] = {0.0f, 0.0f, 0.0f, 0.0f};
     }
 
+    // the next tile's inputs and upstream gradient, loaded while the current tile runs
+    floatx4 yn[N::KB1];
+    float4 gn = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    auto load_tile = [&](int64_t t) {
+        const int64_t st = t * 16 + j;
+        const bool ok = t < end && st < n_s;
+        load_inputs_lp<IN, N::KB1>(y, n_s, st, ok, q, yn);
+        gn = ok && q == 0 ? dout[st] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    };
+    load_tile(tile0);
     for (int64_t tile = tile0; tile < end; tile += step) {
         const int64_t s = tile * 16 + j;
         const bool valid = s < n_s;
         floatx4 yf[N::KB1];
-        load_inputs_lp<IN, N::KB1>(y, n_s, s, valid, q, yf);
+#pragma unroll
+        for (int m = 0; m < N::KB1; ++m) yf[m] = yn[m];
+        const float4 gc = gn;
+        load_tile(tile + step);
         floatx4 hs[D][N::OT];
         floatx4 o;
         chain_lp<IN, W, D, P>(frag, lane, yf, hs, o);
@@ -369,7 +382,7 @@ __device__ __forceinline__ void mlp_bwd_tiles_lp(unsigned char* __restrict__ sme
         // head adjoint in the output tile's own layout (rows 4q + r; only q == 0 is real)
         floatx4 dO[1] = {{0.0f, 0.0f, 0.0f, 0.0f}};
         if (q == 0 && valid) {
-            const float4 g = dout[s];
+            const float4 g = gc;
             const float c1 = sigmoidf_(o[1]), c2 = sigmoidf_(o[2]), c3 = sigmoidf_(o[3]);
             dO[0] = {g.x * __expf(o[0]), g.y * c1 * (1.0f - c1), g.z * c2 * (1.0f - c2), g.w * c3 * (1.0f - c3)};
         }
