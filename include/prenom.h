@@ -368,8 +368,9 @@ typedef struct prenom_object {
 /* Tile shape of the batched MLP launches for one MLP shape (chosen by an
  * autotuner; shapes without an entry use defaults).  fwd_tiles: 16-sample
  * tiles per forward block, a multiple of 4 in [4, 4096]; bwd_tiles: per
- * backward block (each writes one partial weight gradient), a multiple of 8
- * in [8, 65536]. */
+ * backward block (each writes one partial weight gradient and the maxima of
+ * |dy| of its 512-sample blocks, which the table gradient's fixed-point scale
+ * needs), a multiple of 32 in [32, 1024]. */
 typedef struct prenom_mlp_tiles {
     int32_t in_dim, width, hidden, dtype;
     int32_t fwd_tiles, bwd_tiles;

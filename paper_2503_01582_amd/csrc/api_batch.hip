@@ -117,7 +117,7 @@ prenom_status build_plan(const prenom_batch* b, int32_t S, Plan& p)
         const prenom_mlp_tiles& t = b->tiles[i];
         if (t.fwd_tiles != 0 && (t.fwd_tiles < 4 || t.fwd_tiles > 4096 || t.fwd_tiles % 4))
             return fail(PRENOM_ERR_INVALID_ARG, "tiles[%d].fwd_tiles %d", i, t.fwd_tiles);
-        if (t.bwd_tiles != 0 && (t.bwd_tiles < 8 || t.bwd_tiles > 65536 || t.bwd_tiles % 8))
+        if (t.bwd_tiles != 0 && (t.bwd_tiles < 32 || t.bwd_tiles > 1024 || t.bwd_tiles % 32))
             return fail(PRENOM_ERR_INVALID_ARG, "tiles[%d].bwd_tiles %d", i, t.bwd_tiles);
     }
     const int n = b->n_objects;
@@ -250,6 +250,8 @@ prenom_status build_plan(const prenom_batch* b, int32_t S, Plan& p)
             w.s_off = p.dev[i].ray_begin * S;
             w.n_s = n_s;
             w.a_off = act;
+            w.bmax_off = p.sc[i].bmax_off;
+            w.n_sblocks = p.sc[i].n_blocks;
             act += mlp_act_floats(m, n_s);
             for (int64_t t0 = 0; t0 < n_t; t0 += g.fwd_tiles) {
                 w.tile_begin = t0;
@@ -587,6 +589,11 @@ prenom_status prenom_batch_render_bwd(const prenom_batch* batch, const prenom_re
     c.dout = at<float>(workspace, p.dout);
     PRENOM_LAUNCH("k_composite_bwd", s, launch_composite_bwd(c, s));
     float* partial = at<float>(workspace, p.partial);
+    // the MLP backward also writes the maxima of |dy| per (object, level,
+    // scatter block) and flags a non-finite dy, so the scatter starts at its
+    // level maxima (phase 1)
+    float* block_max = at<float>(workspace, p.block_max);
+    int32_t* nonfinite = batch->loss_scale ? batch->scaler_state : nullptr;
     for (const Group& g : p.groups) {
         const MlpWork* work = at<const MlpWork>(workspace, p.o_bwd) + g.bwd_first;
         const int64_t n_mlp = mlp_params_of(g.shape);
@@ -595,18 +602,19 @@ prenom_status prenom_batch_render_bwd(const prenom_batch* batch, const prenom_re
         PRENOM_LAUNCH("k_mlp_bwd", s,
                       g.shape.dtype == PRENOM_F32
                           ? launch_mlp_bwd_batch(g.shape, work, (int)g.n_bwd, batch->params, y, c.dout, c.sc, dy,
-                                                 partial + g.partial_off, n_mlp, at<float>(workspace, p.act), s)
+                                                 partial + g.partial_off, n_mlp, at<float>(workspace, p.act),
+                                                 block_max, nonfinite, s)
                           : launch_mlp_bwd_lp_batch(g.shape, work, (int)g.n_bwd, batch->params, y, c.dout, c.sc, dy,
-                                                    partial + g.partial_off, n_mlp, at<float>(workspace, p.act), s));
+                                                    partial + g.partial_off, n_mlp, at<float>(workspace, p.act),
+                                                    block_max, nonfinite, s));
     }
     PRENOM_LAUNCH("k_reduce_partials", s,
                   launch_reduce_partials_batch(at<const MlpRed>(workspace, p.o_red), p.n_obj, p.n_mlp_total, partial,
                                                batch->grads, s));
     for (const ScatterGroup& g : p.sgroups) {
-        const ScatterArgs sa = scatter_args(p, g, workspace, ray_obj, t, batch->grads,
-                                            batch->loss_scale ? batch->scaler_state : nullptr);
-        for (int ph = 0; ph < kScatterPhases; ++ph)
-            PRENOM_LAUNCH(ph == 0 ? "k_scatter_dymax" : kScatterPhaseNames[ph], s, launch_scatter_phase(sa, ph, s));
+        const ScatterArgs sa = scatter_args(p, g, workspace, ray_obj, t, batch->grads, nonfinite);
+        for (int ph = 1; ph < kScatterPhases; ++ph)
+            PRENOM_LAUNCH(kScatterPhaseNames[ph], s, launch_scatter_phase(sa, ph, s));
     }
     return PRENOM_OK;
 }

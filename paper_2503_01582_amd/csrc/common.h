@@ -384,6 +384,8 @@ struct MlpWork {
     int64_t w_off, y_off, s_off, n_s;
     int64_t tile_begin, tile_end;
     int64_t a_off;
+    int64_t bmax_off;   // the object's [L][n_blocks] maxima of |dy| (scatter blocks), written by the backward
+    int64_t n_sblocks;  // its scatter blocks (kScatterBlockSamples samples each)
 };
 
 // The 128-wide MLP stores its hidden activations in the forward and runs its
@@ -412,14 +414,20 @@ hipError_t launch_mlp_bwd_lp(const MlpShape& m, const float* w, const float* y, 
                              int64_t n_s, float* dy, float* partial, float* act, hipStream_t s);
 hipError_t launch_mlp_fwd_batch(const MlpShape& m, const MlpWork* work, int n_blocks, const float* params,
                                 const float* y, float* sc, float* act, hipStream_t s);
+// Batched backward: besides dy and the partial weight gradients, every work
+// item writes its maxima of |dy| into block_max (MlpWork::bmax_off) and sets
+// *nonfinite (when not null) on a non-finite dy; work items start at a
+// multiple of kScatterBlockSamples / 16 tiles and span at most 1024 tiles.
 hipError_t launch_mlp_bwd_batch(const MlpShape& m, const MlpWork* work, int n_blocks, const float* params,
                                 const float* y, const float* dout, const float* sc, float* dy, float* partial,
-                                int64_t slot_stride, float* act, hipStream_t s);
+                                int64_t slot_stride, float* act, float* block_max, int32_t* nonfinite,
+                                hipStream_t s);
 hipError_t launch_mlp_fwd_lp_batch(const MlpShape& m, const MlpWork* work, int n_blocks, const float* params,
                                    const float* y, float* sc, float* act, hipStream_t s);
 hipError_t launch_mlp_bwd_lp_batch(const MlpShape& m, const MlpWork* work, int n_blocks, const float* params,
                                    const float* y, const float* dout, const float* sc, float* dy, float* partial,
-                                   int64_t slot_stride, float* act, hipStream_t s);
+                                   int64_t slot_stride, float* act, float* block_max, int32_t* nonfinite,
+                                   hipStream_t s);
 hipError_t launch_reduce_partials(const float* partial, int n_slots, int64_t n_mlp, float* g_mlp,
                                   hipStream_t s);
 

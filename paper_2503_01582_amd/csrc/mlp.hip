@@ -271,10 +271,13 @@ __device__ __forceinline__ void accumulate_dw(const float* __restrict__ sD, cons
 // Backward over tiles tile0, tile0 + step, ... < end (per wave) of one object
 // whose fragments are in LDS (lds[0 .. N_ALL*64)); writes dy and the block's
 // merged dW to dst.  Called by every thread of the block.
+// bm (or null): also note the maxima of |dy| of the work item starting at tile
+// tile_begin; bad: set on a non-finite dy.
 template <int IN, int W, int D>
 __device__ __forceinline__ void mlp_bwd_tiles(float* __restrict__ lds, const float* __restrict__ y, const float4* __restrict__ dout,
                               int64_t n_s, float2* __restrict__ dy, float* __restrict__ dst, int64_t tile0,
-                              int64_t end, int64_t step)
+                              int64_t end, int64_t step, DyMaxLds* bm = nullptr, int64_t tile_begin = 0,
+                              bool* bad = nullptr)
 {
     using N = Net<IN, W, D>;
     using B = BwdLds<IN, W, D>;
@@ -397,6 +400,7 @@ __device__ __forceinline__ void mlp_bwd_tiles(float* __restrict__ lds, const flo
                 dy[(int64_t)(f >> 1) * n_s + s] = make_float2(acc[0], acc[1]);
                 dy[(int64_t)((f >> 1) + 1) * n_s + s] = make_float2(acc[2], acc[3]);
             }
+            if (bm) dymax_note(*bm, tile, tile_begin, f >> 1, acc, valid && f < IN, j, *bad);
         }
     }
 
@@ -441,16 +445,24 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_bwd_batch(const MlpWork*
                                                                   const float* __restrict__ y,
                                                                   const float4* __restrict__ dout,
                                                                   float2* __restrict__ dy, float* __restrict__ partial,
-                                                                  int64_t slot_stride)
+                                                                  int64_t slot_stride, float* __restrict__ block_max,
+                                                                  int32_t* __restrict__ nonfinite)
 {
     using N = Net<IN, W, D>;
+    static_assert(IN / 2 <= kBmLevels, "levels");
     extern __shared__ float lds[];
+    __shared__ DyMaxLds bm;
     const MlpWork wk = work[blockIdx.x];
+    dymax_clear(bm);
     load_fragments<IN, W, D>(params + wk.w_off, lds, N::N_ALL);
     __syncthreads();
+    bool bad = false;
     mlp_bwd_tiles<IN, W, D>(lds, y + wk.y_off, dout + wk.s_off, wk.n_s, dy + wk.y_off / 2,
                             partial + (int64_t)blockIdx.x * slot_stride, wk.tile_begin + (threadIdx.x >> 6),
-                            wk.tile_end, kBwdWaves);
+                            wk.tile_end, kBwdWaves, &bm, wk.tile_begin, &bad);
+    if (bad && nonfinite) *nonfinite = 1;
+    __syncthreads();
+    dymax_flush(bm, block_max + wk.bmax_off, wk.n_sblocks, IN / 2, wk.tile_begin, wk.tile_end);
 }
 
 // Sum of the per-block partial weight gradients.  A block takes kRedParams
@@ -502,7 +514,8 @@ template <int IN, int W, int D>
 __device__ __forceinline__ void mlp_chain_bwd_tiles(const float* __restrict__ bfrag, const float4* __restrict__ sc,
                                     const float4* __restrict__ dout, const float* __restrict__ act,
                                     float* __restrict__ dlt, int64_t n_s, float2* __restrict__ dy, int64_t tile0,
-                                    int64_t end, int64_t step)
+                                    int64_t end, int64_t step, DyMaxLds* bm = nullptr, int64_t tile_begin = 0,
+                                    bool* bad = nullptr)
 {
     using N = Net<IN, W, D>;
     constexpr int BO = 0, BH = N::BH - N::N_FWD, B1 = N::B1 - N::N_FWD;  // fragments rebased to the transposed set
@@ -567,6 +580,7 @@ __device__ __forceinline__ void mlp_chain_bwd_tiles(const float* __restrict__ bf
                 dy[(int64_t)(f >> 1) * n_s + s] = make_float2(acc[0], acc[1]);
                 dy[(int64_t)((f >> 1) + 1) * n_s + s] = make_float2(acc[2], acc[3]);
             }
+            if (bm) dymax_note(*bm, tile, tile_begin, f >> 1, acc, valid && f < IN, j, *bad);
         }
     }
 }
@@ -687,17 +701,25 @@ __global__ __launch_bounds__(256) void k_mlp_chain_bwd_batch(const MlpWork* __re
                                                              const float* __restrict__ params,
                                                              const float4* __restrict__ sc,
                                                              const float4* __restrict__ dout, float* __restrict__ act,
-                                                             float2* __restrict__ dy)
+                                                             float2* __restrict__ dy, float* __restrict__ block_max,
+                                                             int32_t* __restrict__ nonfinite)
 {
     using N = Net<IN, W, D>;
+    static_assert(IN / 2 <= kBmLevels, "levels");
     extern __shared__ float frag[];
+    __shared__ DyMaxLds bm;
     const MlpWork wk = work[blockIdx.x];
+    dymax_clear(bm);
     load_fragments<IN, W, D>(params + wk.w_off, frag, N::N_ALL - N::N_FWD, N::N_FWD);
     __syncthreads();
     const float* a = act + wk.a_off;
+    bool bad = false;
     mlp_chain_bwd_tiles<IN, W, D>(frag, sc + wk.s_off, dout + wk.s_off, a, act + wk.a_off + (int64_t)D * wk.n_s * W,
                                   wk.n_s, dy + wk.y_off / 2, wk.tile_begin + (threadIdx.x >> 6), wk.tile_end,
-                                  blockDim.x / 64);
+                                  blockDim.x / 64, &bm, wk.tile_begin, &bad);
+    if (bad && nonfinite) *nonfinite = 1;
+    __syncthreads();
+    dymax_flush(bm, block_max + wk.bmax_off, wk.n_sblocks, IN / 2, wk.tile_begin, wk.tile_end);
 }
 
 template <int IN, int W, int D>
@@ -840,14 +862,15 @@ hipError_t fwd_batch_impl(const MlpWork* work, int n_blocks, const float* params
 
 template <int IN, int W, int D>
 hipError_t bwd_batch_impl(const MlpWork* work, int n_blocks, const float* params, const float* y, const float* dout,
-                          const float* sc, float* dy, float* partial, int64_t slot_stride, float* act, hipStream_t s)
+                          const float* sc, float* dy, float* partial, int64_t slot_stride, float* act,
+                          float* block_max, int32_t* nonfinite, hipStream_t s)
 {
     if constexpr (W >= kWideWidth) {
         const size_t lds = chain_bwd_lds_bytes<IN, W, D>();
         hipError_t e = set_lds(k_mlp_chain_bwd_batch<IN, W, D>, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_mlp_chain_bwd_batch<IN, W, D>), dim3((uint32_t)n_blocks), dim3(256), lds, s, work,
-                           params, (const float4*)sc, (const float4*)dout, act, (float2*)dy);
+                           params, (const float4*)sc, (const float4*)dout, act, (float2*)dy, block_max, nonfinite);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const size_t dwl = dw_lds_bytes<IN, W, D>();
         if ((e = set_lds(k_mlp_dw_batch<IN, W, D>, dwl)) != hipSuccess) return e;
@@ -860,7 +883,7 @@ hipError_t bwd_batch_impl(const MlpWork* work, int n_blocks, const float* params
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(kern, dim3((uint32_t)n_blocks), dim3(64 * kBwdWaves), lds, s, work, params, y,
-                           (const float4*)dout, (float2*)dy, partial, slot_stride);
+                           (const float4*)dout, (float2*)dy, partial, slot_stride, block_max, nonfinite);
         return hipGetLastError();
     }
 }
@@ -933,12 +956,14 @@ hipError_t launch_mlp_fwd_batch(const MlpShape& m, const MlpWork* work, int n_bl
 
 hipError_t launch_mlp_bwd_batch(const MlpShape& m, const MlpWork* work, int n_blocks, const float* params,
                                 const float* y, const float* dout, const float* sc, float* dy, float* partial,
-                                int64_t slot_stride, float* act, hipStream_t s)
+                                int64_t slot_stride, float* act, float* block_max, int32_t* nonfinite,
+                                hipStream_t s)
 {
     if (n_blocks == 0) return hipSuccess;
-#define X(I, Wd, Dp)                                        \
-    if (m.in_dim == I && m.width == Wd && m.hidden == Dp) \
-        return bwd_batch_impl<I, Wd, Dp>(work, n_blocks, params, y, dout, sc, dy, partial, slot_stride, act, s);
+#define X(I, Wd, Dp)                                                                                   \
+    if (m.in_dim == I && m.width == Wd && m.hidden == Dp)                                            \
+        return bwd_batch_impl<I, Wd, Dp>(work, n_blocks, params, y, dout, sc, dy, partial, slot_stride, act, \
+                                         block_max, nonfinite, s);
     PRENOM_FOR_EACH_MLP(X)
 #undef X
     return hipErrorInvalidValue;

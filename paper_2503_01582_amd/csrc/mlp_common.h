@@ -37,6 +37,64 @@ __device__ __forceinline__ void wave_lds_sync()
 
 __device__ __forceinline__ float sigmoidf_(float z) { return 1.0f / (1.0f + __expf(-z)); }
 
+// Maxima of |dy| per (level, block of kScatterBlockSamples samples), which fix
+// the hash-table gradient's fixed-point scale, taken by the batched MLP
+// backward as it writes dy: per wave and tile a DPP row maximum over the 16
+// samples, one LDS atomic max per (tile, level) on the bit pattern (non-
+// negative floats order as unsigned integers; NaN is dropped by fmaxf, as
+// the scatter's own pass drops it), then one store per (block, level) when
+// the work item ends.  A work item starts at a multiple of kBmTiles tiles of
+// its object and spans at most kBmSlots blocks.
+constexpr int kBmTiles = kScatterBlockSamples / 16;
+constexpr int kBmSlots = 32;
+constexpr int kBmMaxTiles = kBmTiles * kBmSlots;  // 1024 tiles per work item
+constexpr int kBmLevels = 16;                     // the compiled MLP inputs have at most 32 features
+struct DyMaxLds {
+    uint32_t v[kBmSlots][kBmLevels];
+};
+
+__device__ __forceinline__ void dymax_clear(DyMaxLds& bm)
+{
+    for (int i = threadIdx.x; i < kBmSlots * kBmLevels; i += blockDim.x) (&bm.v[0][0])[i] = 0u;
+}
+
+// Lanes (q, j) of a wave hold dy of sample j of `tile` for levels lv and
+// lv + 1 (features 2 lv .. 2 lv + 3); `ok`: the sample exists and lv < L.
+// Called by every lane of the wave.
+__device__ __forceinline__ void dymax_note(DyMaxLds& bm, int64_t tile, int64_t tile_begin, int lv, floatx4 g, bool ok,
+                                           int j, bool& bad)
+{
+    float m0 = ok ? fmaxf(fabsf(g[0]), fabsf(g[1])) : 0.0f;
+    float m1 = ok ? fmaxf(fabsf(g[2]), fabsf(g[3])) : 0.0f;
+    bad |= ok && !(isfinite(g[0]) && isfinite(g[1]) && isfinite(g[2]) && isfinite(g[3]));
+    m0 = fmaxf(m0, dpp_f32<0x101>(m0));
+    m1 = fmaxf(m1, dpp_f32<0x101>(m1));
+    m0 = fmaxf(m0, dpp_f32<0x102>(m0));
+    m1 = fmaxf(m1, dpp_f32<0x102>(m1));
+    m0 = fmaxf(m0, dpp_f32<0x104>(m0));
+    m1 = fmaxf(m1, dpp_f32<0x104>(m1));
+    m0 = fmaxf(m0, dpp_f32<0x108>(m0));
+    m1 = fmaxf(m1, dpp_f32<0x108>(m1));
+    if (j == 0 && ok) {
+        const int slot = (int)((tile - tile_begin) / kBmTiles);
+        atomicMax(&bm.v[slot][lv], __float_as_uint(m0));
+        atomicMax(&bm.v[slot][lv + 1], __float_as_uint(m1));
+    }
+}
+
+// After a barrier: the work item's block maxima to block_max ([L][n_blocks]
+// of the object) and the non-finite flag.
+__device__ __forceinline__ void dymax_flush(const DyMaxLds& bm, float* __restrict__ block_max, int64_t n_blocks,
+                                            int n_levels, int64_t tile_begin, int64_t tile_end)
+{
+    const int64_t b0 = tile_begin / kBmTiles;
+    const int n_slots = (int)((tile_end - tile_begin + kBmTiles - 1) / kBmTiles);
+    for (int i = threadIdx.x; i < n_slots * n_levels; i += blockDim.x) {
+        const int slot = i / n_levels, l = i % n_levels;
+        if (b0 + slot < n_blocks) block_max[(int64_t)l * n_blocks + b0 + slot] = __uint_as_float(bm.v[slot][l]);
+    }
+}
+
 
 // Per-block LDS and launch parameters of the backward kernels.
 constexpr int kBwdWaves = 8;      // waves per block

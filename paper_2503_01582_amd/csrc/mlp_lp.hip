@@ -330,10 +330,13 @@ __device__ __forceinline__ void accumulate_dw_lp(const float* __restrict__ sD, c
 
 // Backward over tiles tile0, tile0 + step, ... < end of one object whose
 // fragments are at the start of smem_lp; called by every thread of the block.
+// bm (or null): also note the maxima of |dy| of the work item starting at tile
+// tile_begin; bad: set on a non-finite dy.
 template <int IN, int W, int D, class P>
 __device__ __forceinline__ void mlp_bwd_tiles_lp(unsigned char* __restrict__ smem_lp, const float2* __restrict__ y,
                                  const float4* __restrict__ dout, int64_t n_s, float2* __restrict__ dy,
-                                 float* __restrict__ dst, int64_t tile0, int64_t end, int64_t step)
+                                 float* __restrict__ dst, int64_t tile0, int64_t end, int64_t step,
+                                 DyMaxLds* bm = nullptr, int64_t tile_begin = 0, bool* bad = nullptr)
 {
     using N = NetLp<IN, W, D>;
     using B = BwdLdsLp<IN, W, D>;
@@ -442,6 +445,7 @@ __device__ __forceinline__ void mlp_bwd_tiles_lp(unsigned char* __restrict__ sme
                 dy[(int64_t)(f >> 1) * n_s + s] = make_float2(acc[0], acc[1]);
                 dy[(int64_t)((f >> 1) + 1) * n_s + s] = make_float2(acc[2], acc[3]);
             }
+            if (bm) dymax_note(*bm, tile, tile_begin, f >> 1, acc, valid && f < IN, j, *bad);
         }
     }
 
@@ -482,16 +486,25 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_bwd_lp_batch(const MlpWo
                                                                      const float2* __restrict__ y,
                                                                      const float4* __restrict__ dout,
                                                                      float2* __restrict__ dy,
-                                                                     float* __restrict__ partial, int64_t slot_stride)
+                                                                     float* __restrict__ partial, int64_t slot_stride,
+                                                                     float* __restrict__ block_max,
+                                                                     int32_t* __restrict__ nonfinite)
 {
     using N = NetLp<IN, W, D>;
+    static_assert(IN / 2 <= kBmLevels, "levels");
     extern __shared__ __align__(16) unsigned char smem_lp[];
+    __shared__ DyMaxLds bm;
     const MlpWork wk = work[blockIdx.x];
+    dymax_clear(bm);
     load_fragments_lp<IN, W, D, P>(params + wk.w_off, reinterpret_cast<typename P::vec*>(smem_lp), N::N_ALL);
     __syncthreads();
+    bool bad = false;
     mlp_bwd_tiles_lp<IN, W, D, P>(smem_lp, y + wk.y_off / 2, dout + wk.s_off, wk.n_s, dy + wk.y_off / 2,
                                   partial + (int64_t)blockIdx.x * slot_stride, wk.tile_begin + (threadIdx.x >> 6),
-                                  wk.tile_end, kBwdWaves);
+                                  wk.tile_end, kBwdWaves, &bm, wk.tile_begin, &bad);
+    if (bad && nonfinite) *nonfinite = 1;
+    __syncthreads();
+    dymax_flush(bm, block_max + wk.bmax_off, wk.n_sblocks, IN / 2, wk.tile_begin, wk.tile_end);
 }
 
 // ---------------------------------------------------------------- 128 wide
@@ -508,7 +521,8 @@ template <int IN, int W, int D, class P>
 __device__ __forceinline__ void mlp_chain_bwd_tiles_lp(const typename P::vec* __restrict__ bfrag, const float4* __restrict__ sc,
                                        const float4* __restrict__ dout, const typename P::vec* __restrict__ act16,
                                        typename P::vec* __restrict__ dlt16, int64_t n_s, float2* __restrict__ dy,
-                                       int64_t tile0, int64_t end, int64_t step)
+                                       int64_t tile0, int64_t end, int64_t step, DyMaxLds* bm = nullptr,
+                                       int64_t tile_begin = 0, bool* bad = nullptr)
 {
     using N = NetLp<IN, W, D>;
     constexpr int BO = 0, BH = N::BH - N::N_FWD, B1 = N::B1 - N::N_FWD;
@@ -578,6 +592,7 @@ __device__ __forceinline__ void mlp_chain_bwd_tiles_lp(const typename P::vec* __
                 dy[(int64_t)(f >> 1) * n_s + s] = make_float2(gy[to][0], gy[to][1]);
                 dy[(int64_t)((f >> 1) + 1) * n_s + s] = make_float2(gy[to][2], gy[to][3]);
             }
+            if (bm) dymax_note(*bm, tile, tile_begin, f >> 1, gy[to], valid && f < IN, j, *bad);
         }
     }
 }
@@ -828,18 +843,27 @@ __global__ __launch_bounds__(256) void k_mlp_chain_bwd_lp_batch(const MlpWork* _
                                                                 const float* __restrict__ params,
                                                                 const float4* __restrict__ sc,
                                                                 const float4* __restrict__ dout,
-                                                                float* __restrict__ act, float2* __restrict__ dy)
+                                                                float* __restrict__ act, float2* __restrict__ dy,
+                                                                float* __restrict__ block_max,
+                                                                int32_t* __restrict__ nonfinite)
 {
     using N = NetLp<IN, W, D>;
+    static_assert(IN / 2 <= kBmLevels, "levels");
     extern __shared__ __align__(16) unsigned char smem_b[];
+    __shared__ DyMaxLds bm;
     typename P::vec* frag = reinterpret_cast<typename P::vec*>(smem_b);
     const MlpWork wk = work[blockIdx.x];
+    dymax_clear(bm);
     load_fragments_lp<IN, W, D, P>(params + wk.w_off, frag, N::N_ALL - N::N_FWD, N::N_FWD);
     __syncthreads();
     typename P::vec* a16 = reinterpret_cast<typename P::vec*>(act + wk.a_off);
+    bool bad = false;
     mlp_chain_bwd_tiles_lp<IN, W, D, P>(frag, sc + wk.s_off, dout + wk.s_off, a16, a16 + (int64_t)D * wk.n_s * W / 4,
                                         wk.n_s, dy + wk.y_off / 2, wk.tile_begin + (threadIdx.x >> 6), wk.tile_end,
-                                        blockDim.x / 64);
+                                        blockDim.x / 64, &bm, wk.tile_begin, &bad);
+    if (bad && nonfinite) *nonfinite = 1;
+    __syncthreads();
+    dymax_flush(bm, block_max + wk.bmax_off, wk.n_sblocks, IN / 2, wk.tile_begin, wk.tile_end);
 }
 
 template <int IN, int W, int D, class P>
@@ -961,14 +985,15 @@ hipError_t fwd_lp_batch(const MlpWork* work, int n_blocks, const float* params, 
 
 template <int IN, int W, int D, class P>
 hipError_t bwd_lp_batch(const MlpWork* work, int n_blocks, const float* params, const float* y, const float* dout,
-                        const float* sc, float* dy, float* partial, int64_t slot_stride, float* act, hipStream_t s)
+                        const float* sc, float* dy, float* partial, int64_t slot_stride, float* act, float* block_max,
+                        int32_t* nonfinite, hipStream_t s)
 {
     if constexpr (W >= kWideWidth) {
         const size_t lds = chain_lds_lp<IN, W, D, P>();
         hipError_t e = set_lds_lp(k_mlp_chain_bwd_lp_batch<IN, W, D, P>, lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_mlp_chain_bwd_lp_batch<IN, W, D, P>), dim3((uint32_t)n_blocks), dim3(256), lds, s, work,
-                           params, (const float4*)sc, (const float4*)dout, act, (float2*)dy);
+                           params, (const float4*)sc, (const float4*)dout, act, (float2*)dy, block_max, nonfinite);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         const size_t dwl = dw_lds_bytes_lp<IN, W, D>();
         if ((e = set_lds_lp(k_mlp_dw_lp_batch<IN, W, D, P>, dwl)) != hipSuccess) return e;
@@ -981,7 +1006,8 @@ hipError_t bwd_lp_batch(const MlpWork* work, int n_blocks, const float* params, 
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(kern, dim3((uint32_t)n_blocks), dim3(64 * kBwdWaves), lds, s, work, params,
-                           (const float2*)y, (const float4*)dout, (float2*)dy, partial, slot_stride);
+                           (const float2*)y, (const float4*)dout, (float2*)dy, partial, slot_stride, block_max,
+                           nonfinite);
         return hipGetLastError();
     }
 }
@@ -1044,11 +1070,12 @@ hipError_t fwd_batch_dispatch(const MlpShape& m, const MlpWork* work, int n_bloc
 template <class P>
 hipError_t bwd_batch_dispatch(const MlpShape& m, const MlpWork* work, int n_blocks, const float* params,
                               const float* y, const float* dout, const float* sc, float* dy, float* partial,
-                              int64_t slot_stride, float* act, hipStream_t s)
+                              int64_t slot_stride, float* act, float* block_max, int32_t* nonfinite, hipStream_t s)
 {
-#define X(I, Wd, Dp)                                        \
-    if (m.in_dim == I && m.width == Wd && m.hidden == Dp) \
-        return bwd_lp_batch<I, Wd, Dp, P>(work, n_blocks, params, y, dout, sc, dy, partial, slot_stride, act, s);
+#define X(I, Wd, Dp)                                                                                     \
+    if (m.in_dim == I && m.width == Wd && m.hidden == Dp)                                              \
+        return bwd_lp_batch<I, Wd, Dp, P>(work, n_blocks, params, y, dout, sc, dy, partial, slot_stride, act, \
+                                          block_max, nonfinite, s);
     PRENOM_FOR_EACH_MLP_LP(X)
 #undef X
     return hipErrorInvalidValue;
@@ -1085,13 +1112,16 @@ hipError_t launch_mlp_fwd_lp_batch(const MlpShape& m, const MlpWork* work, int n
 
 hipError_t launch_mlp_bwd_lp_batch(const MlpShape& m, const MlpWork* work, int n_blocks, const float* params,
                                    const float* y, const float* dout, const float* sc, float* dy, float* partial,
-                                   int64_t slot_stride, float* act, hipStream_t s)
+                                   int64_t slot_stride, float* act, float* block_max, int32_t* nonfinite,
+                                   hipStream_t s)
 {
     if (n_blocks == 0) return hipSuccess;
     if (m.dtype == PRENOM_BF16)
-        return bwd_batch_dispatch<Bf16Op>(m, work, n_blocks, params, y, dout, sc, dy, partial, slot_stride, act, s);
+        return bwd_batch_dispatch<Bf16Op>(m, work, n_blocks, params, y, dout, sc, dy, partial, slot_stride, act,
+                                          block_max, nonfinite, s);
     if (m.dtype == PRENOM_F16)
-        return bwd_batch_dispatch<F16Op>(m, work, n_blocks, params, y, dout, sc, dy, partial, slot_stride, act, s);
+        return bwd_batch_dispatch<F16Op>(m, work, n_blocks, params, y, dout, sc, dy, partial, slot_stride, act,
+                                         block_max, nonfinite, s);
     return hipErrorInvalidValue;
 }
 

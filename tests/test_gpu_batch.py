@@ -193,7 +193,7 @@ def test_batch_equals_single_object_calls():
     geo = oracle_geometry(objs, b)
     loss = LossSpec(lambda_d=0.1)
     tiles = [dict(in_dim=o.arch.in_dim, width=o.arch.width, hidden=o.arch.hidden, dtype="fp32", fwd_tiles=12,
-                  bwd_tiles=40) for o in objs]
+                  bwd_tiles=96) for o in objs]
     for tl in (None, tiles):
         run = BatchRun(objs, params, b, geo, loss, tiles=tl)
         got = run.fwd()
