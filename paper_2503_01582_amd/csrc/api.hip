@@ -585,6 +585,7 @@ prenom_status prenom_render_bwd(const prenom_model* model, const prenom_render_c
         sa.fwd_counts = 1;  // render_fwd (or the recompute above) wrote the tile histograms
         sa.merge_runs = 1;
         sa.chunk_min_bits = 21;  // one pass over one object: items of 2^21 records keep the CUs busy
+        sa.compact = a->table_dtype == PRENOM_F16;
         for (int ph = 0; ph < kScatterPhases; ++ph)
             PRENOM_LAUNCH(ph == 0 ? "k_scatter_dymax" : kScatterPhaseNames[ph], s, launch_scatter_phase(sa, ph, s));
     }

@@ -60,7 +60,7 @@ struct Plan {
     int64_t n_rays = 0, n_params = 0, n_mlp_total = 0, n_tiles = 0, n_items = 0, records = 0;
     int64_t y_floats = 0, partial_floats = 0, counts = 0, bmax = 0, act_floats = 0;
     int32_t n_levels_total = 0, tiles_max = 1;
-    bool any_f16_table = false;
+    bool any_f16_table = false, all_f16_table = true;
     // workspace offsets (bytes)
     size_t o_dev, o_sc, o_sc_pass, o_red, o_fwd, o_bwd;
     size_t y, sc_out, dout, dy, ray_state, ray_loss, partial, act, cnt, offs, block_max, level_max, tile_exp, tile_total,
@@ -154,6 +154,7 @@ prenom_status build_plan(const prenom_batch* b, int32_t S, Plan& p)
         d.prior = o.prior;
         for (int k = 0; k < 12; ++k) d.A[k] = (double)o.world_to_obj[k];
         p.any_f16_table = p.any_f16_table || a->table_dtype == PRENOM_F16;
+        p.all_f16_table = p.all_f16_table && a->table_dtype == PRENOM_F16;
 
         ScatterObj& so = p.sc[i];
         so = scatter_obj(d.grid, n_s);
@@ -375,6 +376,7 @@ ScatterArgs scatter_args(const Plan& p, const ScatterGroup& g, void* ws, const f
     sa.fwd_counts = 1;  // fwd_features (render_fwd, or the recompute in render_bwd) wrote the histograms
     sa.merge_runs = 1;
     sa.chunk_min_bits = 18;  // a pass of a few objects needs smaller items to fill the CUs
+    sa.compact = p.all_f16_table;
     return sa;
 }
 

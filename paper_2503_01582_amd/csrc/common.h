@@ -342,7 +342,7 @@ struct ScatterArgs {
     uint64_t* tile_start;   // [n_tiles + 1]
     uint64_t* chunk_start;  // [n_tiles + 2]: chunk bases, their total, the chunk size's log2
     unsigned long long* work_counter;
-    uint64_t* recs;         // [records] packed records (scatter.hip: row, shared exponent, two mantissas)
+    uint64_t* recs;         // [records] packed records (scatter.hip: row, shared exponent, two mantissas); 8 bytes each
     int64_t n_records;      // length of recs
     int32_t* nonfinite;     // set to 1 when a dy entry is not finite (loss scaling), or null
     // 1: counts were written by the training forward (TileHist); the first
@@ -359,6 +359,9 @@ struct ScatterArgs {
     // by several workgroups whose FP32 partials meet in atomics, in an order
     // that can change the last bits; 21 keeps most tiles to one item.
     int32_t chunk_min_bits;
+    // 1: compact records (15-bit mantissas, 48 bits: 32-bit words at recs,
+    // then n_records 16-bit words), for FP16 tables; 0: 64-bit records.
+    int32_t compact;
 };
 // The scatter runs as kScatterPhases dependent kernels, launched in order
 // (phase 0 .. kScatterPhases - 1): count (or, with fwd_counts, the block

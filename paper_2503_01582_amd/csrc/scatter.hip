@@ -63,13 +63,19 @@ constexpr int kChunkMinBits = 18, kChunkMaxBits = 21;
 constexpr uint64_t kChunksPerBlock = 4;
 
 // ---------------------------------------------------------------- records
-// One 64-bit word per record: bits 0-12 the row within the tile, bits 13-19
-// an exponent offset r, bits 20-41 and 42-63 the two's-complement mantissas
-// qx, qy; the record's value is (qx, qy) * 2^(E - r - 21), E being the
-// level's record exponent.  A record whose larger feature lies below
-// 2^(E - 128) (r beyond 7 bits) is dropped.
+// A record holds the row within the tile (bits 0-12), an exponent offset r
+// (EB bits) and the two's-complement mantissas qx, qy (MB bits each); its
+// value is (qx, qy) * 2^(E - r - (MB - 1)), E being the level's record
+// exponent, and a record whose larger feature lies below 2^(E - 2^EB - 1) (r
+// beyond EB bits) is dropped.  Two formats:
+//   full:    EB = 7, MB = 22, one 64-bit word (21 significant bits);
+//   compact: EB = 5, MB = 15, 48 bits kept as a 32-bit word (bits 0-31) in
+//            one array and a 16-bit word (bits 32-47) in another (14
+//            significant bits), for FP16 tables.
 constexpr int kRecExpBits = 7;
 constexpr int kRecMantBits = 22;
+constexpr int kRecExpBitsC = 5;
+constexpr int kRecMantBitsC = 15;
 
 // Record exponent E of a level whose largest |dy| is lm: a record sums at most
 // 8 contributions w dy with 0 <= w <= 1, so |record| <= 8 lm < 2^(E - 1).
@@ -80,6 +86,7 @@ __device__ __forceinline__ int level_rec_exp(float lm)
     return e + 4;
 }
 
+template <int EB, int MB>
 __device__ __forceinline__ uint64_t encode_record(float2 v, int E, uint32_t row)
 {
     const float m = fmaxf(fabsf(v.x), fabsf(v.y));
@@ -87,28 +94,39 @@ __device__ __forceinline__ uint64_t encode_record(float2 v, int E, uint32_t row)
     if (m > 0.0f) {
         int k = 0;
         frexpf(m, &k);  // 2^(k-1) <= m < 2^k
-        float rx = rintf(ldexpf(v.x, 21 - k)), ry = rintf(ldexpf(v.y, 21 - k));
-        if (fmaxf(fabsf(rx), fabsf(ry)) >= 2097152.0f) {  // the larger one rounded up to 2^21
+        float rx = rintf(ldexpf(v.x, MB - 1 - k)), ry = rintf(ldexpf(v.y, MB - 1 - k));
+        if (fmaxf(fabsf(rx), fabsf(ry)) >= (float)(1u << (MB - 1))) {  // the larger one rounded up to 2^(MB-1)
             ++k;
-            rx = rintf(ldexpf(v.x, 21 - k));
-            ry = rintf(ldexpf(v.y, 21 - k));
+            rx = rintf(ldexpf(v.x, MB - 1 - k));
+            ry = rintf(ldexpf(v.y, MB - 1 - k));
         }
         const int r = E - k;
-        constexpr uint32_t kMant = (1u << kRecMantBits) - 1u;
-        if (r >= 0 && r < (1 << kRecExpBits))
-            rec |= (uint64_t)r << kTileBits | (uint64_t)((uint32_t)(int32_t)rx & kMant) << (kTileBits + kRecExpBits) |
-                   (uint64_t)((uint32_t)(int32_t)ry & kMant) << (kTileBits + kRecExpBits + kRecMantBits);
+        constexpr uint32_t kMant = (1u << MB) - 1u;
+        if (r >= 0 && r < (1 << EB))
+            rec |= (uint64_t)r << kTileBits | (uint64_t)((uint32_t)(int32_t)rx & kMant) << (kTileBits + EB) |
+                   (uint64_t)((uint32_t)(int32_t)ry & kMant) << (kTileBits + EB + MB);
     }
     return rec;
 }
 
-// q * 2^sh rounded to an integer (halves upward), for |q| <= 2^21, sh <= 33.
+// Fields of record word w (format EB, MB): row key, exponent offset, mantissas.
+template <int EB, int MB>
+__device__ __forceinline__ void decode_record(uint64_t w, uint32_t& key, int& r, long long& qx, long long& qy)
+{
+    key = (uint32_t)w & (kTileRows - 1);
+    r = (int)((w >> kTileBits) & ((1u << EB) - 1u));
+    qx = (long long)(w << (64 - kTileBits - EB - MB)) >> (64 - MB);
+    qy = (long long)(w << (64 - kTileBits - EB - 2 * MB)) >> (64 - MB);
+}
+
+// q * 2^sh rounded to an integer (halves upward), for |q| <= 2^21, sh <= 37.
 __device__ __forceinline__ long long scale_mantissa(long long q, int sh)
 {
     if (sh >= 0) return q * (1ll << min(sh, 40));  // (the clamp only matters for non-finite gradients)
     const int d = -sh;
     return d > 62 ? 0ll : (q + (1ll << (d - 1))) >> d;
 }
+static_assert(kTileBits + kRecExpBitsC + 2 * kRecMantBitsC == 48, "compact record fields fill 48 bits");
 static_assert(kTileBits + kRecExpBits + 2 * kRecMantBits == 64, "record fields fill one word");
 
 
@@ -555,7 +573,8 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
             if (!((heads >> e) & 1u)) continue;
             const uint32_t tt = c.row[e] >> kTileBits;
             const uint32_t p = seg[tt] + rank[e];
-            s_rec[p] = encode_record(val[e], E, c.row[e] & (kTileRows - 1));
+            s_rec[p] = a.compact ? encode_record<kRecExpBitsC, kRecMantBitsC>(val[e], E, c.row[e] & (kTileRows - 1))
+                                 : encode_record<kRecExpBits, kRecMantBits>(val[e], E, c.row[e] & (kTileRows - 1));
             s_tile[p] = (TileT)tt;
         }
     }
@@ -580,14 +599,26 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
         for (int k = 0; k < kHalf; ++k) {
             const uint32_t p = threadIdx.x + (h + k) * kPlaceThreads;
             const uint64_t dst = gbase[min(tt[k], (uint32_t)nt - 1u)] + p;
-            if (p < total && dst < (uint64_t)a.n_records) a.recs[dst] = rec[k];
+            if (p < total && dst < (uint64_t)a.n_records) {
+                if (a.compact) {
+                    reinterpret_cast<uint32_t*>(a.recs)[dst] = (uint32_t)rec[k];
+                    reinterpret_cast<uint16_t*>(reinterpret_cast<uint32_t*>(a.recs) + a.n_records)[dst] =
+                        (uint16_t)(rec[k] >> 32);
+                } else {
+                    a.recs[dst] = rec[k];
+                }
+            }
         }
     }
 }
 
-template <bool kMany>
+template <bool kMany, bool kCompact>
 __global__ __launch_bounds__(kReduceThreads) void k_scatter_reduce(ScatterArgs a)
 {
+    constexpr int EB = kCompact ? kRecExpBitsC : kRecExpBits, MB = kCompact ? kRecMantBitsC : kRecMantBits;
+    // a run's words: four 16-byte loads of 64-bit records, or two of 32-bit
+    // low words and one of 16-bit high words
+    constexpr int kLoads = kCompact ? 3 : kRun / 2;
     __shared__ unsigned long long acc[2 * kTileRows];  // fixed point: feature 0 rows, then feature 1 rows
     __shared__ int64_t s_chunk;
     const uint64_t n_chunks = a.chunk_start[a.n_tiles];
@@ -619,9 +650,9 @@ __global__ __launch_bounds__(kReduceThreads) void k_scatter_reduce(ScatterArgs a
         const uint64_t r_end = min(r_begin + ((uint64_t)1 << cb), a.tile_start[tile + 1]);
         const bool owner = (a.chunk_start[tile + 1] - a.chunk_start[tile]) == 1;
         const int ex = a.tile_exp[tile];
-        // a record (qx, qy, r) is worth (qx, qy) 2^(E - r - 21); in fixed point
-        // at 2^ex that is (qx, qy) 2^(sh0 - r)
-        const int sh0 = level_rec_exp(a.level_max[o.lev_off + l]) - 21 + ex;
+        // a record (qx, qy, r) is worth (qx, qy) 2^(E - r - (MB - 1)); in fixed
+        // point at 2^ex that is (qx, qy) 2^(sh0 - r)
+        const int sh0 = level_rec_exp(a.level_max[o.lev_off + l]) - (MB - 1) + ex;
         for (int i = threadIdx.x; i < n_rows; i += kReduceThreads) {
             acc[i] = 0ull;
             acc[kTileRows + i] = 0ull;
@@ -636,14 +667,22 @@ __global__ __launch_bounds__(kReduceThreads) void k_scatter_reduce(ScatterArgs a
         // LDS atomic per row and run is issued instead of one per record.
         const uint64_t q_begin = r_begin / kRun, q_end = (r_end + kRun - 1) / kRun;
         for (uint64_t q0 = q_begin + threadIdx.x; q0 < q_end; q0 += (uint64_t)kReduceThreads * kRunsPerThread) {
-            uint4 rw[kRunsPerThread][kRun / 2];
+            uint4 rw[kRunsPerThread][kLoads];
 #pragma unroll
             for (int u = 0; u < kRunsPerThread; ++u) {
                 const uint64_t q = q0 + (uint64_t)u * kReduceThreads;
                 const uint64_t qc = q < q_end ? q : q_begin;
-                const uint4* rp = reinterpret_cast<const uint4*>(a.recs + qc * kRun);
+                if constexpr (kCompact) {
+                    const uint32_t* lo = reinterpret_cast<const uint32_t*>(a.recs);
+                    const uint16_t* hi = reinterpret_cast<const uint16_t*>(lo + a.n_records);
+                    rw[u][0] = reinterpret_cast<const uint4*>(lo + qc * kRun)[0];
+                    rw[u][1] = reinterpret_cast<const uint4*>(lo + qc * kRun)[1];
+                    rw[u][2] = reinterpret_cast<const uint4*>(hi + qc * kRun)[0];
+                } else {
+                    const uint4* rp = reinterpret_cast<const uint4*>(a.recs + qc * kRun);
 #pragma unroll
-                for (int i = 0; i < kRun / 2; ++i) rw[u][i] = rp[i];
+                    for (int i = 0; i < kRun / 2; ++i) rw[u][i] = rp[i];
+                }
             }
 #pragma unroll
             for (int u = 0; u < kRunsPerThread; ++u) {
@@ -653,13 +692,21 @@ __global__ __launch_bounds__(kReduceThreads) void k_scatter_reduce(ScatterArgs a
                 long long sx[kRun], sy[kRun];
 #pragma unroll
                 for (int i = 0; i < kRun; ++i) {
-                    const uint32_t lo = (i & 1) ? rw[u][i >> 1].z : rw[u][i >> 1].x;
-                    const uint32_t hi = (i & 1) ? rw[u][i >> 1].w : rw[u][i >> 1].y;
-                    const uint64_t w = (uint64_t)hi << 32 | lo;
-                    key[i] = lo & (kTileRows - 1);
-                    const int sh = sh0 - (int)((lo >> kTileBits) & ((1u << kRecExpBits) - 1u));
-                    const long long qx = (long long)(w << (64 - kTileBits - kRecExpBits - kRecMantBits)) >> (64 - kRecMantBits);
-                    const long long qy = (long long)w >> (64 - kRecMantBits);
+                    uint32_t lo, hi;
+                    if constexpr (kCompact) {
+                        const uint4& l4 = rw[u][i >> 2];
+                        lo = (i & 3) == 0 ? l4.x : (i & 3) == 1 ? l4.y : (i & 3) == 2 ? l4.z : l4.w;
+                        const uint4& h4 = rw[u][2];
+                        const uint32_t hw = (i >> 1) == 0 ? h4.x : (i >> 1) == 1 ? h4.y : (i >> 1) == 2 ? h4.z : h4.w;
+                        hi = (i & 1) ? hw >> 16 : hw & 0xffffu;
+                    } else {
+                        lo = (i & 1) ? rw[u][i >> 1].z : rw[u][i >> 1].x;
+                        hi = (i & 1) ? rw[u][i >> 1].w : rw[u][i >> 1].y;
+                    }
+                    int r;
+                    long long qx, qy;
+                    decode_record<EB, MB>((uint64_t)hi << 32 | lo, key[i], r, qx, qy);
+                    const int sh = sh0 - r;
                     const bool ok = q < q_end && rec0 + i >= r_begin && rec0 + i < r_end;
                     sx[i] = ok ? scale_mantissa(qx, sh) : 0ll;
                     sy[i] = ok ? scale_mantissa(qy, sh) : 0ll;
@@ -737,7 +784,12 @@ hipError_t scatter_phase_impl(const ScatterArgs& a, int phase, hipStream_t s)
             break;
         }
         case 5:
-            hipLaunchKernelGGL(k_scatter_reduce<kMany>, dim3((uint32_t)a.reduce_blocks), dim3(kReduceThreads), 0, s, a);
+            if (a.compact)
+                hipLaunchKernelGGL((k_scatter_reduce<kMany, true>), dim3((uint32_t)a.reduce_blocks),
+                                   dim3(kReduceThreads), 0, s, a);
+            else
+                hipLaunchKernelGGL((k_scatter_reduce<kMany, false>), dim3((uint32_t)a.reduce_blocks),
+                                   dim3(kReduceThreads), 0, s, a);
             break;
         default:
             return hipErrorInvalidValue;
