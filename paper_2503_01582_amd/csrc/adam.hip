@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kAdamBlock) void k_to_f16(const float* __restrict__
 int64_t stream_blocks(int64_t n4)
 {
     int64_t blocks = (n4 + kAdamBlock - 1) / kAdamBlock;
-    return blocks < 1 ? 1 : (blocks > 8192 ? 8192 : blocks);
+    return blocks < 1 ? 1 : (blocks > (1 << 20) ? (1 << 20) : blocks);
 }
 
 }  // namespace
