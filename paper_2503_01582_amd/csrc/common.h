@@ -401,9 +401,11 @@ constexpr int kWideWidth = 128;
 inline int64_t mlp_act_floats(const MlpShape& m, int64_t n_s)
 {
     if (m.width < kWideWidth) return 0;
-    // FP32: activations and deltas; 16-bit: both in the MFMA type, plus the ReLU mask words
+    // FP32: activations and deltas; 16-bit: both in the MFMA type (whole 16-sample
+    // tiles), plus the ReLU mask words
+    const int64_t n_sp = (n_s + 15) / 16 * 16;
     return m.dtype == PRENOM_F32 ? 2 * (int64_t)m.hidden * n_s * m.width
-                                 : (int64_t)m.hidden * n_s * (m.width + m.width / 32);
+                                 : (int64_t)m.hidden * n_sp * (m.width + m.width / 32);
 }
 int mlp_bwd_waves(int64_t n_samples);  // partial-gradient slots (one per block) the bwd writes
 // act: activation/delta buffer of mlp_act_floats floats (128-wide MLPs; else unused)

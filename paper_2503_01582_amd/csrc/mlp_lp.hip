@@ -89,12 +89,28 @@ __device__ __forceinline__ floatx4 mask_by_bits(floatx4 g, uint32_t m, int to)
 }
 
 // Layout of the 128-wide MLP's activation buffer (mlp_act_floats floats):
-// activations [D][n_s][W] and deltas [D][n_s][W] in the MFMA type, then the
-// ReLU mask words [D][n_s][4].
+// the activations, then the deltas, of every hidden layer in the MFMA type,
+// each in the accumulator layout of its 16-sample tiles (for layer k, tile
+// t, neuron tile to: 64 groups of 4 values, group 16 q + j holding neurons
+// 16 to + 4 q .. + 3 of sample 16 t + j, so one wave's store of a neuron tile
+// is 512 contiguous bytes); then the ReLU mask words [D][n_s][4].
+template <int W>
+__device__ __forceinline__ int64_t wide_vec(int k, int64_t n_s, int64_t s, int to, int q)
+{
+    const int64_t n_t = (n_s + 15) >> 4;
+    return (((int64_t)k * n_t + (s >> 4)) * (W / 16) + to) * 64 + q * 16 + (s & 15);
+}
+
+template <int W, int D, class P>
+__device__ __forceinline__ typename P::vec* wide_deltas(typename P::vec* a16, int64_t n_s)
+{
+    return a16 + (int64_t)D * ((n_s + 15) >> 4) * 4 * W;
+}
+
 template <int W, int D, class P>
 __device__ __forceinline__ uint32_t* wide_masks(typename P::vec* a16, int64_t n_s)
 {
-    return reinterpret_cast<uint32_t*>(a16 + (int64_t)2 * D * n_s * W / 4);
+    return reinterpret_cast<uint32_t*>(a16 + (int64_t)2 * D * ((n_s + 15) >> 4) * 4 * W);
 }
 
 template <int IN, int W, int D>
@@ -264,7 +280,7 @@ __device__ __forceinline__ void mlp_fwd_tiles_lp(const typename P::vec* __restri
 #pragma unroll
             for (int k = 0; k < D; ++k) {
 #pragma unroll
-                for (int to = 0; to < N::OT; ++to) a16[(((int64_t)k * n_s + s) * W + 16 * to + 4 * q) / 4] = pack<P>(hs[k][to]);
+                for (int to = 0; to < N::OT; ++to) a16[wide_vec<W>(k, n_s, s, to, q)] = pack<P>(hs[k][to]);
                 masks[((int64_t)k * n_s + s) * 4 + q] = relu_mask_bits(hs[k], N::OT);
             }
         }
@@ -516,7 +532,7 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_bwd_lp_batch(const MlpWo
 // the 4 waves splitting the output rows.
 constexpr int kWideWavesLp = 4;
 
-// act16 / dlt16: [D][n_s][W] 16-bit values, indexed in groups of 4 (P::vec).
+// act16 / dlt16: the activations and deltas in the layout of wide_vec.
 template <int IN, int W, int D, class P>
 __device__ __forceinline__ void mlp_chain_bwd_tiles_lp(const typename P::vec* __restrict__ bfrag, const float4* __restrict__ sc,
                                        const float4* __restrict__ dout, const typename P::vec* __restrict__ act16,
@@ -556,7 +572,7 @@ __device__ __forceinline__ void mlp_chain_bwd_tiles_lp(const typename P::vec* __
         const floatx4 dO = {g.x * v.x, g.y * v.y * (1.0f - v.y), g.z * v.z * (1.0f - v.z), g.w * v.w * (1.0f - v.w)};
         const typename P::vec dOp = pack<P>(dO);
         floatx4 delta[N::OT];
-        auto vi = [&](int k, int to) { return (((int64_t)k * n_s + s) * W + 16 * to + 4 * q) / 4; };
+        auto vi = [&](int k, int to) { return wide_vec<W>(k, n_s, s, to, q); };
         auto mask_of = [&](int k) { return mc[k]; };
         uint32_t mk = mask_of(D - 1);
 #pragma unroll
@@ -638,7 +654,7 @@ __device__ __forceinline__ uint2 bits(typename P::vec v)
 // Staging of samples [s0, min(s0 + kDwChunk, s_end)) (zeros past the end),
 // in two halves so the next chunk's global loads overlap the current chunk's
 // MFMAs: dw_load_lp reads a thread's share into registers, dw_store_lp
-// writes it to LDS.  act16 / dlt16: [D][n_s][W] 16-bit rows; y: level-major
+// writes it to LDS.  act16 / dlt16: as laid out by wide_vec; y: level-major
 // [L][n_s][2].  256 threads.
 template <int W, int D>
 struct DwRegsLp {
@@ -665,11 +681,18 @@ __device__ __forceinline__ void dw_load_lp(DwRegsLp<W, D>& R, const float* __res
         const int arr = i / (D * Rg::SG * Rg::V), rem = i % (D * Rg::SG * Rg::V);
         const int k = rem / (Rg::SG * Rg::V), r2 = rem % (Rg::SG * Rg::V), sg = r2 / Rg::V, c = r2 % Rg::V;
         const typename P::vec* src = arr == 0 ? dlt16 : act16;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t s = s0 + 4 * sg + r;
-            R.ad[u][r] = i < Rg::N_AD && s < s_end ? bits<P>(src[((int64_t)k * n_s + s) * Rg::V + c]) : make_uint2(0u, 0u);
+        // the 4 samples of the group are consecutive in one tile: two 16-byte loads
+        const int64_t sb = s0 + 4 * sg;
+        uint4 w0 = make_uint4(0u, 0u, 0u, 0u), w1 = w0;
+        if (i < Rg::N_AD && sb < s_end) {
+            const uint4* p = reinterpret_cast<const uint4*>(src + wide_vec<W>(k, n_s, sb, c >> 2, c & 3));
+            w0 = p[0];
+            w1 = p[1];
         }
+        R.ad[u][0] = sb < s_end ? make_uint2(w0.x, w0.y) : make_uint2(0u, 0u);
+        R.ad[u][1] = sb + 1 < s_end ? make_uint2(w0.z, w0.w) : make_uint2(0u, 0u);
+        R.ad[u][2] = sb + 2 < s_end ? make_uint2(w1.x, w1.y) : make_uint2(0u, 0u);
+        R.ad[u][3] = sb + 3 < s_end ? make_uint2(w1.z, w1.w) : make_uint2(0u, 0u);
     }
     {
         const int l = threadIdx.x / Rg::SG, sg = threadIdx.x % Rg::SG;
@@ -834,7 +857,7 @@ __global__ __launch_bounds__(256) void k_mlp_chain_bwd_lp(const float* __restric
     __syncthreads();
     const int64_t wave0 = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
     typename P::vec* a16 = reinterpret_cast<typename P::vec*>(act);
-    mlp_chain_bwd_tiles_lp<IN, W, D, P>(frag, sc, dout, a16, a16 + (int64_t)D * n_s * W / 4, n_s, dy, wave0,
+    mlp_chain_bwd_tiles_lp<IN, W, D, P>(frag, sc, dout, a16, wide_deltas<W, D, P>(a16, n_s), n_s, dy, wave0,
                                         (n_s + 15) / 16, (int64_t)gridDim.x * (blockDim.x / 64));
 }
 
@@ -858,7 +881,7 @@ __global__ __launch_bounds__(256) void k_mlp_chain_bwd_lp_batch(const MlpWork* _
     __syncthreads();
     typename P::vec* a16 = reinterpret_cast<typename P::vec*>(act + wk.a_off);
     bool bad = false;
-    mlp_chain_bwd_tiles_lp<IN, W, D, P>(frag, sc + wk.s_off, dout + wk.s_off, a16, a16 + (int64_t)D * wk.n_s * W / 4,
+    mlp_chain_bwd_tiles_lp<IN, W, D, P>(frag, sc + wk.s_off, dout + wk.s_off, a16, wide_deltas<W, D, P>(a16, wk.n_s),
                                         wk.n_s, dy + wk.y_off / 2, wk.tile_begin + (threadIdx.x >> 6), wk.tile_end,
                                         blockDim.x / 64, &bm, wk.tile_begin, &bad);
     if (bad && nonfinite) *nonfinite = 1;
@@ -878,7 +901,7 @@ __global__ __launch_bounds__(64 * kWideWavesLp) void k_mlp_dw_lp(const float* __
     const int64_t b = (int64_t)blockIdx.x * tiles_per_block * 16;
     const int64_t e = min(b + tiles_per_block * 16, n_s);
     const typename P::vec* a16 = reinterpret_cast<const typename P::vec*>(act);
-    mlp_dw_range_lp<IN, W, D, P>(dw_lds, y, sc, dout, a16, a16 + (int64_t)D * n_s * W / 4, n_s, b, e,
+    mlp_dw_range_lp<IN, W, D, P>(dw_lds, y, sc, dout, a16, wide_deltas<W, D, P>(const_cast<typename P::vec*>(a16), n_s), n_s, b, e,
                                  partial + (int64_t)blockIdx.x * N::N_PARAMS);
 }
 
@@ -895,7 +918,7 @@ __global__ __launch_bounds__(64 * kWideWavesLp) void k_mlp_dw_lp_batch(const Mlp
     const int64_t b = wk.tile_begin * 16, e = min(wk.tile_end * 16, wk.n_s);
     const typename P::vec* a16 = reinterpret_cast<const typename P::vec*>(act + wk.a_off);
     mlp_dw_range_lp<IN, W, D, P>(dw_lds, y + wk.y_off, sc + wk.s_off, dout + wk.s_off, a16,
-                                 a16 + (int64_t)D * wk.n_s * W / 4, wk.n_s, b, e,
+                                 wide_deltas<W, D, P>(const_cast<typename P::vec*>(a16), wk.n_s), wk.n_s, b, e,
                                  partial + (int64_t)blockIdx.x * slot_stride);
 }
 

@@ -36,7 +36,7 @@ import oracle as orc
 from parity_util import MAX_KINK_SHARE, rel_errors, relu_stable_rays
 from synth.arch import ARCH_LARGE
 from synth.params import init_params
-from synth.workloads import LossSpec, prior_batch, prior_world
+from synth.workloads import LossSpec, SampleSpec, prior_batch, prior_world, uniform_xi
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -76,17 +76,29 @@ def test_reduced_precision_against_oracle(mlp_dtype, table_dtype):
 
 @pytest.mark.parametrize("hidden,mlp_dtype", [(1, "bf16"), (2, "bf16"), (2, "fp16")])
 def test_reduced_precision_wide_mlp(hidden, mlp_dtype):
-    """The 128-wide MLP (forward storing 16-bit activations; backward fusing
-    the delta chain with the weight gradient chunk by chunk) on a ragged ray
-    count that leaves a partial chunk."""
+    """The 128-wide MLP (forward storing 16-bit activations and ReLU mask
+    bits; a delta chain and a weight-gradient kernel) on a ragged ray count
+    that leaves a partial chunk."""
     print(f"test_reduced_precision_wide_mlp[hidden={hidden}, {mlp_dtype}]", flush=True)
     arch = dataclasses.replace(ARCH_LARGE, width=128, hidden=hidden, mlp_dtype=mlp_dtype, table_dtype="fp16")
     run_case(arch, 777)
 
 
-def run_case(arch, n_rays):
+def test_reduced_precision_wide_mlp_ragged_samples():
+    """The 128-wide 16-bit MLP with 7 + 17 samples per ray: the sample count
+    (333 x 24) is not a multiple of the 16-sample tile, so the last tile of
+    the stored activations and deltas is partial."""
+    print("test_reduced_precision_wide_mlp_ragged_samples", flush=True)
+    arch = dataclasses.replace(ARCH_LARGE, width=128, hidden=2, mlp_dtype="bf16", table_dtype="fp16")
+    run_case(arch, 333, spec=SampleSpec(n_coarse=7, n_fine=17, include_coarse=True, uniform_only=False))
+
+
+def run_case(arch, n_rays, spec=None):
     from paper_2503_01582_amd import api
     b = prior_batch(world(), n_rays, step=31, loss=LossSpec(lambda_d=0.1))
+    if spec is not None:
+        b.xi = uniform_xi(np.random.default_rng(8), n_rays, spec.n_fine)
+        b.sample = spec
     params = init_params(arch, 5)
     params[:arch.n_table_params] = np.random.default_rng(6).uniform(
         -0.3, 0.3, arch.n_table_params).astype(np.float32)
