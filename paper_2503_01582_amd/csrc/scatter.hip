@@ -94,12 +94,11 @@ __device__ __forceinline__ uint64_t encode_record(float2 v, int E, uint32_t row)
     if (m > 0.0f) {
         int k = 0;
         frexpf(m, &k);  // 2^(k-1) <= m < 2^k
-        float rx = rintf(ldexpf(v.x, MB - 1 - k)), ry = rintf(ldexpf(v.y, MB - 1 - k));
-        if (fmaxf(fabsf(rx), fabsf(ry)) >= (float)(1u << (MB - 1))) {  // the larger one rounded up to 2^(MB-1)
-            ++k;
-            rx = rintf(ldexpf(v.x, MB - 1 - k));
-            ry = rintf(ldexpf(v.y, MB - 1 - k));
-        }
+        // the larger one can round up to 2^(MB-1), one past the field: it is
+        // held at 2^(MB-1) - 1 (an error of one unit in its last place)
+        constexpr float kMax = (float)((1u << (MB - 1)) - 1u);
+        const float rx = fminf(fmaxf(rintf(ldexpf(v.x, MB - 1 - k)), -kMax), kMax);
+        const float ry = fminf(fmaxf(rintf(ldexpf(v.y, MB - 1 - k)), -kMax), kMax);
         const int r = E - k;
         constexpr uint32_t kMant = (1u << MB) - 1u;
         if (r >= 0 && r < (1 << EB))
