@@ -529,8 +529,9 @@ __global__ __launch_bounds__(64 * kBwdWaves) void k_mlp_bwd_lp_batch(const MlpWo
 // kernel with only the transposed fragments writes every layer's delta and
 // dy; a weight-gradient kernel contracts deltas with activations over the
 // block's samples (operands rounded to the MFMA type, FP32 accumulation),
-// the 4 waves splitting the output rows.
+// the waves splitting the output rows.
 constexpr int kWideWavesLp = 4;
+constexpr int kDwThreadsLp = 64 * kWideWavesLp;
 
 // act16 / dlt16: the activations and deltas in the layout of wide_vec.
 template <int IN, int W, int D, class P>
@@ -655,13 +656,13 @@ __device__ __forceinline__ uint2 bits(typename P::vec v)
 // in two halves so the next chunk's global loads overlap the current chunk's
 // MFMAs: dw_load_lp reads a thread's share into registers, dw_store_lp
 // writes it to LDS.  act16 / dlt16: as laid out by wide_vec; y: level-major
-// [L][n_s][2].  256 threads.
+// [L][n_s][2].  kDwThreadsLp threads.
 template <int W, int D>
 struct DwRegsLp {
     static constexpr int SG = kDwChunk / 4;              // 4-sample groups per chunk
     static constexpr int V = W / 4;                      // 4-neuron groups per row
     static constexpr int N_AD = 2 * D * SG * V;          // 4 x 4 blocks of deltas and activations
-    static constexpr int PER = (N_AD + 255) / 256;
+    static constexpr int PER = (N_AD + kDwThreadsLp - 1) / kDwThreadsLp;
     uint2 ad[PER][4];  // rows r = 0..3 (samples) of each block
     float2 yv[4];      // features 2l, 2l + 1 of 4 samples (threads < 16 SG)
     float4 g, v;       // head adjoint inputs of one sample (threads < kDwChunk)
@@ -677,7 +678,7 @@ __device__ __forceinline__ void dw_load_lp(DwRegsLp<W, D>& R, const float* __res
     using Rg = DwRegsLp<W, D>;
 #pragma unroll
     for (int u = 0; u < Rg::PER; ++u) {
-        const int i = threadIdx.x + 256 * u;
+        const int i = threadIdx.x + kDwThreadsLp * u;
         const int arr = i / (D * Rg::SG * Rg::V), rem = i % (D * Rg::SG * Rg::V);
         const int k = rem / (Rg::SG * Rg::V), r2 = rem % (Rg::SG * Rg::V), sg = r2 / Rg::V, c = r2 % Rg::V;
         const typename P::vec* src = arr == 0 ? dlt16 : act16;
@@ -720,7 +721,7 @@ __device__ __forceinline__ void dw_store_lp(uint16_t* __restrict__ lds, const Dw
     // activations and deltas: one 4 x 4 block (4 samples x 4 neurons) per item
 #pragma unroll
     for (int u = 0; u < Rg::PER; ++u) {
-        const int i = threadIdx.x + 256 * u;
+        const int i = threadIdx.x + kDwThreadsLp * u;
         if (i < Rg::N_AD) {
             const int arr = i / (D * Rg::SG * Rg::V), rem = i % (D * Rg::SG * Rg::V);
             const int k = rem / (Rg::SG * Rg::V), r2 = rem % (Rg::SG * Rg::V), sg = r2 / Rg::V, c = r2 % Rg::V;
@@ -781,7 +782,7 @@ __device__ __forceinline__ void mlp_dw_range_lp(uint16_t* __restrict__ lds, cons
     auto op = [&](int base, int row, int k0) {
         return __builtin_bit_cast(typename P::vec, *reinterpret_cast<const uint2*>(lds + base + row * kDwRowLp + k0));
     };
-    static_assert(64 * kWideWavesLp == 256, "staging assumes 256 threads");
+    static_assert(kDwThreadsLp >= 16 * (kDwChunk / 4) && kDwThreadsLp >= kDwChunk, "staging threads");
     DwRegsLp<W, D> R;
     if (s_begin < s_end) dw_load_lp<IN, W, D, P>(R, y, sc, dout, act16, dlt16, n_s, s_begin, s_end);
     for (int64_t c0 = s_begin; c0 < s_end; c0 += kDwChunk) {
