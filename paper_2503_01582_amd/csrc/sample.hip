@@ -1,18 +1,19 @@
 // Prior-based probabilistic ray sampling (Sec. III-B "Probabilistic Ray
 // Sampling", Eq. (4)-(6) and the escape rule).
 //
-// One wavefront per ray.  The whole decision chain (object-frame transform,
-// slab test, coarse midpoints, trilinear prior lookup, prefix sums of
-// sigma_i * delta_i, the expm1 ratio that forms the CDF, the comparison with
-// u_k) is evaluated in FP64 with contraction disabled, so the sampled bins do
-// not hinge on FP32 rounding.  The lanes share the work of one ray:
+// One group of kRayLanes lanes per ray, four rays per wavefront.  The whole
+// decision chain (object-frame transform, slab test, coarse midpoints,
+// trilinear prior lookup, prefix sums of sigma_i * delta_i, the expm1 ratio
+// that forms the CDF, the comparison with u_k) is evaluated in FP64 with
+// contraction disabled, so the sampled bins do not hinge on FP32 rounding.
+// The lanes of a group share the work of one ray:
 //
-//   * the N_c coarse bins' sigma_i * delta_i, one bin per lane (prior lookups
-//     in parallel), kept in LDS;
+//   * the N_c coarse bins' sigma_i * delta_i, bins spread over the lanes
+//     (prior lookups in parallel), kept in LDS;
 //   * the CDF value at the end of each bin, each lane summing the bins before
 //     its own in bin order (the same FP64 additions, in the same order, as a
 //     single sequential pass);
-//   * the draws u_k, one per lane: the bin of draw k is the first bin whose
+//   * the draws u_k, spread over the lanes: the bin of draw k is the first bin whose
 //     CDF end reaches u_k, found by binary search when the CDF ends do not
 //     decrease (always, for a non-negative prior); otherwise one lane walks
 //     the bins for all draws in order;
@@ -27,6 +28,8 @@
 namespace prenom {
 namespace {
 
+constexpr int kRayLanes = 16;                    // lanes per ray
+constexpr int kRaysPerBlock = 64 / kRayLanes;    // rays per wavefront (one wavefront per block)
 
 struct RayFrame {
     double o[3], d[3];
@@ -70,13 +73,17 @@ __device__ __forceinline__ int midpoints_upto(const RayFrame& r, int Nc, double 
     return lo;
 }
 
-// One ray, by one wavefront (blockDim.x == 64).  A, prior and R are the ray's
-// object's pose and prior (per object in a batch); everything else comes from
-// `a`.
+// One ray, by the kRayLanes lanes of one group of the wavefront (lane: the
+// lane within the group; every lane of the group takes the same path, and
+// shuffles stay inside the group).  A, prior and R are the ray's object's
+// pose and prior (per object in a batch); everything else comes from `a`;
+// lds is the group's own region.
 __device__ void sample_ray(const SampleArgs& a, const double* A_obj, const float* prior, int R, bool use_prior,
                            int64_t ray, double* lds)
 {
-    const int lane = threadIdx.x;
+    constexpr int G = kRayLanes;
+    const int lane = threadIdx.x % G;
+    const uint64_t group_mask = ((1ull << G) - 1ull) << (threadIdx.x / G * G % 64);
     const int Nc = a.n_coarse, Nr = a.n_fine;
     const int S = Nr + (a.include_coarse ? Nc : 0);
     double* tau = lds;
@@ -124,11 +131,11 @@ __device__ void sample_ray(const SampleArgs& a, const double* A_obj, const float
     int32_t* br = a.bins + (int64_t)Nr * ray;
     const float* xr = a.xi + (int64_t)Nr * ray;
     if (!hit) {
-        for (int j = lane; j < S; j += 64) {
+        for (int j = lane; j < S; j += G) {
             tr[j] = 0.0f;
             dtr[j] = 0.0f;
         }
-        for (int k = lane; k < Nr; k += 64) br[k] = -1;
+        for (int k = lane; k < Nr; k += G) br[k] = -1;
         if (lane == 0) a.flags[ray] = PRENOM_FLAG_MISS;
         return;
     }
@@ -137,7 +144,7 @@ __device__ void sample_ray(const SampleArgs& a, const double* A_obj, const float
 
     // coarse bins: sigma_i delta_i, then the total mass (bin order)
     if (use_prior)
-        for (int i = lane; i < Nc; i += 64) tau[i] = coarse_tau(prior, R, r, i);
+        for (int i = lane; i < Nc; i += G) tau[i] = coarse_tau(prior, R, r, i);
     __syncthreads();
     bool escaped = false;
     double total_S = 0.0;
@@ -153,7 +160,7 @@ __device__ void sample_ray(const SampleArgs& a, const double* A_obj, const float
     const double den = expm1(-total_S);
     bool ascending = true;
     if (cdf_draws) {
-        for (int b = lane; b < Nc; b += 64) {
+        for (int b = lane; b < Nc; b += G) {
             double Sb = 0.0;
             for (int i = 0; i <= b; ++i) Sb = Sb + tau[i];
             cdf[b] = (b + 1 == Nc) ? 1.0 : expm1(-Sb) / den;
@@ -162,12 +169,13 @@ __device__ void sample_ray(const SampleArgs& a, const double* A_obj, const float
         // Searching each draw's bin on its own equals the walk when the CDF
         // ends below the last bin do not decrease and the draws u_k do not
         // either (both hold for a non-negative prior and xi in [0, 1]).
-        for (int b = lane; b + 2 < Nc; b += 64)
+        for (int b = lane; b + 2 < Nc; b += G)
             if (!(cdf[b] <= cdf[b + 1])) ascending = false;
-        for (int k = lane; k + 1 < Nr; k += 64)
+        for (int k = lane; k + 1 < Nr; k += G)
             if (!(((double)k + (double)xr[k]) / (double)Nr <= ((double)(k + 1) + (double)xr[k + 1]) / (double)Nr))
                 ascending = false;
-        ascending = __syncthreads_and(ascending);
+        ascending = (__ballot(!ascending) & group_mask) == 0;  // over the group's lanes
+        __syncthreads();
         if (!ascending && lane == 0) {  // sequential walk over the draws, in order
             int bb = 0;
             for (int k = 0; k < Nr; ++k) {
@@ -180,7 +188,7 @@ __device__ void sample_ray(const SampleArgs& a, const double* A_obj, const float
     }
 
     // draws: inverse CDF within the bin (Eq. (6)), or uniform in [tn, tf]
-    for (int k = lane; k < Nr; k += 64) {
+    for (int k = lane; k < Nr; k += G) {
         const double u = ((double)k + (double)xr[k]) / (double)Nr;
         double tk;
         int bk = -1;
@@ -212,22 +220,22 @@ __device__ void sample_ray(const SampleArgs& a, const double* A_obj, const float
 
     // ranks: midpoints emitted before draw k = max over k' <= k of the counts
     if (a.include_coarse) {
-        int carry = 0;  // running maximum, 64 draws at a time
-        for (int k0 = 0; k0 < Nr; k0 += 64) {
+        int carry = 0;  // running maximum, G draws at a time
+        for (int k0 = 0; k0 < Nr; k0 += G) {
             const int k = k0 + lane;
             int v = k < Nr ? run[k] : 0;
 #pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const int up = __shfl_up(v, d);
+            for (int d = 1; d < G; d <<= 1) {
+                const int up = __shfl_up(v, d, G);
                 if (lane >= d) v = v > up ? v : up;
             }
             v = v > carry ? v : carry;
             if (k < Nr) run[k] = v;
-            carry = __shfl(v, 63);
+            carry = __shfl(v, G - 1, G);
         }
         __syncthreads();
-        for (int k = lane; k < Nr; k += 64) out[k + run[k]] = draws[k];
-        for (int i = lane; i < Nc; i += 64) {
+        for (int k = lane; k < Nr; k += G) out[k + run[k]] = draws[k];
+        for (int i = lane; i < Nc; i += G) {
             int lo = 0, hi = Nr;  // draws before midpoint i: first k with run[k] > i
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
@@ -239,10 +247,10 @@ __device__ void sample_ray(const SampleArgs& a, const double* A_obj, const float
             out[i + lo] = r.tn + ((double)i + 0.5) * r.delta;
         }
     } else {
-        for (int k = lane; k < Nr; k += 64) out[k] = draws[k];
+        for (int k = lane; k < Nr; k += G) out[k] = draws[k];
     }
     __syncthreads();
-    for (int j = lane; j < S; j += 64) {
+    for (int j = lane; j < S; j += G) {
         const double tv = out[j];
         const double next = j + 1 < S ? out[j + 1] : r.tf;
         tr[j] = (float)tv;
@@ -250,10 +258,19 @@ __device__ void sample_ray(const SampleArgs& a, const double* A_obj, const float
     }
 }
 
+// LDS of one ray, in doubles (the regions of a block's rays follow each other).
+__device__ __forceinline__ size_t ray_lds_doubles(const SampleArgs& a)
+{
+    return sample_lds_bytes(a.n_coarse, a.n_fine, a.n_fine + (a.include_coarse ? a.n_coarse : 0)) / sizeof(double);
+}
+
 __global__ __launch_bounds__(64) void k_sample(SampleArgs a)
 {
     extern __shared__ double lds[];
-    sample_ray(a, a.A, a.prior, a.R, a.use_prior != 0, blockIdx.x, lds);
+    const int g = threadIdx.x / kRayLanes;
+    const int64_t ray = (int64_t)blockIdx.x * kRaysPerBlock + g;
+    if (ray >= a.n) return;  // the whole group
+    sample_ray(a, a.A, a.prior, a.R, a.use_prior != 0, ray, lds + g * ray_lds_doubles(a));
 }
 
 // All rays of a batch: the ray's object (last with ray_begin <= ray) supplies
@@ -261,32 +278,37 @@ __global__ __launch_bounds__(64) void k_sample(SampleArgs a)
 __global__ __launch_bounds__(64) void k_sample_batch(SampleArgs a, const ObjDev* __restrict__ objs, int n_obj)
 {
     extern __shared__ double lds[];
-    const int64_t ray = blockIdx.x;
+    const int g = threadIdx.x / kRayLanes;
+    const int64_t ray = (int64_t)blockIdx.x * kRaysPerBlock + g;
+    if (ray >= a.n) return;  // the whole group
     const ObjDev& o = objs[find_object(objs, n_obj, ray)];
-    sample_ray(a, o.A, o.prior, o.prior_res, a.use_prior != 0 && o.prior != nullptr, ray, lds);
+    sample_ray(a, o.A, o.prior, o.prior_res, a.use_prior != 0 && o.prior != nullptr, ray,
+               lds + g * ray_lds_doubles(a));
 }
 
 size_t sample_lds(const SampleArgs& a)
 {
-    return sample_lds_bytes(a.n_coarse, a.n_fine, a.n_fine + (a.include_coarse ? a.n_coarse : 0));
+    return kRaysPerBlock * sample_lds_bytes(a.n_coarse, a.n_fine, a.n_fine + (a.include_coarse ? a.n_coarse : 0));
 }
 
 }  // namespace
 
-// One block (one wavefront) per ray: at most 2^32 - 1 rays per launch.
+// One block (one wavefront) per kRaysPerBlock rays.
 hipError_t launch_sample_batch(const SampleArgs& a, const ObjDev* objs, int n_obj, hipStream_t s)
 {
     if (a.n == 0) return hipSuccess;
-    if (a.n > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_sample_batch, dim3((uint32_t)a.n), dim3(64), sample_lds(a), s, a, objs, n_obj);
+    const int64_t blocks = (a.n + kRaysPerBlock - 1) / kRaysPerBlock;
+    if (blocks > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sample_batch, dim3((uint32_t)blocks), dim3(64), sample_lds(a), s, a, objs, n_obj);
     return hipGetLastError();
 }
 
 hipError_t launch_sample(const SampleArgs& a, hipStream_t s)
 {
     if (a.n == 0) return hipSuccess;
-    if (a.n > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_sample, dim3((uint32_t)a.n), dim3(64), sample_lds(a), s, a);
+    const int64_t blocks = (a.n + kRaysPerBlock - 1) / kRaysPerBlock;
+    if (blocks > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sample, dim3((uint32_t)blocks), dim3(64), sample_lds(a), s, a);
     return hipGetLastError();
 }
 
