@@ -156,6 +156,53 @@ __device__ __forceinline__ float dpp_f32(float v)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, 0xf, 0xf, true));
 }
 
+// Tile histogram of the wave's records on a level of at most 16 tiles, for
+// counting only (no ranks): bit e of `heads` marks corner e as a record.  Each
+// lane counts its records per tile in the 4-bit fields of a 64-bit word (at
+// most 8 per tile), the fields are widened to bytes and summed over each row
+// of 16 lanes by four DPP additions (mirror, half mirror, two quad swaps:
+// every lane ends with the row's sums, at most 128 per tile), and lane i of
+// each row adds the row's count of tile i.  About 90 instructions per wave,
+// against about 35 per corner for wave_aggregated_add.  Every lane of the wave
+// must call it (lanes without records pass heads = 0).
+__device__ __forceinline__ void wave_count_tiles16(uint32_t* hist, const uint32_t row[8], uint32_t heads, int nt)
+{
+    uint64_t p = 0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const uint32_t t = row[e] >> kTileBits;  // < 16 for every row of the level
+        p += (uint64_t)((heads >> e) & 1u) << ((4u * t) & 63u);
+    }
+    const uint32_t lo = (uint32_t)p, hi = (uint32_t)(p >> 32);
+    // v[k]: tile b sits in byte (b >> 1) & 3 of v[(b & 1) * 2 + (b >> 3)]
+    uint32_t v[4] = {lo & 0x0f0f0f0fu, hi & 0x0f0f0f0fu, (lo >> 4) & 0x0f0f0f0fu, (hi >> 4) & 0x0f0f0f0fu};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] += dpp_u32<0x140>(v[k]);  // row_mirror: lane i + lane 15 - i
+        v[k] += dpp_u32<0x141>(v[k]);  // row_half_mirror
+        v[k] += dpp_u32<0x1b>(v[k]);   // quad_perm [3, 2, 1, 0]
+        v[k] += dpp_u32<0xb1>(v[k]);   // quad_perm [1, 0, 3, 2]
+    }
+    const uint32_t b = threadIdx.x & 15u;
+    const uint32_t k = (b & 1u) * 2u + (b >> 3);
+    const uint32_t w = k == 0 ? v[0] : k == 1 ? v[1] : k == 2 ? v[2] : v[3];
+    const uint32_t cnt = (w >> (8u * ((b >> 1) & 3u))) & 0xffu;
+    if ((int)b < nt && cnt != 0u) atomicAdd(&hist[b], cnt);
+}
+
+// Adds the lane's records (bit e of heads: corner e) to a block's LDS tile
+// histogram of a level of nt tiles.  Every lane of the wave must call it.
+__device__ __forceinline__ void count_records(uint32_t* hist, const Corners& c, uint32_t heads, int nt)
+{
+    if (nt <= 16) {
+        wave_count_tiles16(hist, c.row, heads, nt);
+        return;
+    }
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+        if ((heads >> e) & 1u) atomicAdd(&hist[c.row[e] >> kTileBits], 1u);
+}
+
 // Merging repeated corners.  Consecutive samples of a ray often share a cell
 // on the coarser levels, so the same corner row repeats on neighbouring
 // lanes; such a run becomes one record (the sum of its contributions).  Runs

@@ -186,16 +186,8 @@ __global__ __launch_bounds__(kScatterBlockSamples) void k_encode_samples_hist(Gr
     if (has) {
         const Row* lt = table + ((int64_t)l << g.log2_table);
         y[(int64_t)l * n_s + s] = gather_blend(lt, g, l, c);
-        if (nt <= kAggregateTiles) {
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-                if ((heads >> e) & 1u) wave_aggregated_add(hist, c.row[e] >> kTileBits);
-        } else {
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-                if ((heads >> e) & 1u) atomicAdd(&hist[c.row[e] >> kTileBits], 1u);
-        }
     }
+    count_records(hist, c, heads, nt);
     __syncthreads();
     uint32_t* out = h.counts + (int64_t)h.tile_base[l] * h.n_blocks + bx;
     for (int i = threadIdx.x; i < nt; i += kScatterBlockSamples) out[(int64_t)i * h.n_blocks] = hist[i];
@@ -250,16 +242,8 @@ __global__ __launch_bounds__(kScatterBlockSamples) void k_encode_batch_hist(cons
         else
             v = gather_blend_rows(reinterpret_cast<const float2*>(params + o.param_off) + row0, c);
         y[o.y_off / 2 + (int64_t)l * n_s + s] = v;
-        if (nt <= kAggregateTiles) {
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-                if ((heads >> e) & 1u) wave_aggregated_add(hist, c.row[e] >> kTileBits);
-        } else {
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-                if ((heads >> e) & 1u) atomicAdd(&hist[c.row[e] >> kTileBits], 1u);
-        }
     }
+    count_records(hist, c, heads, nt);
     __syncthreads();
     uint32_t* out = counts + so.count_off + (int64_t)so.tile_base[l] * so.n_blocks + bx;
     for (int i = threadIdx.x; i < nt; i += kScatterBlockSamples) out[(int64_t)i * so.n_blocks] = hist[i];

@@ -241,18 +241,8 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_count(ScatterArgs a)
         has = s < o.n_s && load_contrib(a, o, l, s, d, c);
     }
     if (a.nonfinite && s < o.n_s && !(isfinite(d.x) && isfinite(d.y))) a.nonfinite[0] = 1;
-    if (has) {
-        m = fmaxf(fabsf(d.x), fabsf(d.y));
-        if (nt <= kAggregateTiles) {
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-                if ((heads >> e) & 1u) wave_aggregated_add(hist, c.row[e] >> kTileBits);
-        } else {
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-                if ((heads >> e) & 1u) atomicAdd(&hist[c.row[e] >> kTileBits], 1u);
-        }
-    }
+    if (has) m = fmaxf(fabsf(d.x), fabsf(d.y));
+    count_records(hist, c, has ? heads : 0u, nt);
 #pragma unroll
     for (int dd = 32; dd >= 1; dd >>= 1) m = fmaxf(m, __shfl_xor(m, dd));
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
