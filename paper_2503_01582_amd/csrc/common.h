@@ -101,9 +101,13 @@ constexpr int kTileBits = 13;
 constexpr int kTileRows = 1 << kTileBits;
 constexpr int kMaxTilesPerLevel = 1 << (24 - kTileBits);  // T <= 2^24
 constexpr int kScatterBlockSamples = 512;
-// Levels with at most this many tiles have most lanes of a wave in the same
-// tile; their histogram atomics are combined per wave first.
-constexpr int kAggregateTiles = 16;
+// Place combines the rank atomics of a wave per tile first on levels of at
+// most this many tiles, where most lanes of a wave share a tile.  With more
+// tiles the leader rounds cost more vector instructions than the LDS
+// serialisation of same-address atomics they save, dense levels included
+// (48-object place on gfx950: 17.2 ms aggregating up to 16 tiles, 16.3 ms
+// up to 4 hashed or 16 dense, 15.7 ms up to 2).
+constexpr int kAggregateTiles = 2;
 
 // Adds 1 to hist[tile] for every active lane and returns the lane's rank
 // among the additions to that tile.  Lanes of the wave that share the tile of

@@ -49,8 +49,6 @@ namespace prenom {
 namespace {
 
 constexpr int kPlaceThreads = kScatterBlockSamples;
-// Hashed levels of at most this many tiles still aggregate their rank atomics.
-constexpr int kHashedAggregateTiles = 4;
 constexpr int kSamplesPerBlock = kPlaceThreads;  // one sample per thread
 constexpr int kRecordsPerBlock = kSamplesPerBlock * 8;
 constexpr int kScanThreads = 1024;
@@ -520,12 +518,8 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_place(ScatterArgs a)
         for (int e = 0; e < 8; ++e) val[e] = make_float2(c.w[e] * d.x, c.w[e] * d.y);
     }
     uint32_t rank[8];
-    // Lanes of a wave share tiles on dense levels (consecutive rows) and when
-    // a level has few tiles; on the hashed levels of a larger table the rows
-    // are spread at random and the aggregation rounds would find few lanes.
-    const bool aggregate = nt <= kHashedAggregateTiles || (nt <= kAggregateTiles && ((o.grid.dense_mask >> l) & 1u));
     if (has) {
-        if (aggregate) {
+        if (nt <= kAggregateTiles) {
 #pragma unroll
             for (int e = 0; e < 8; ++e)
                 if ((heads >> e) & 1u) rank[e] = wave_aggregated_add(hist, c.row[e] >> kTileBits);
