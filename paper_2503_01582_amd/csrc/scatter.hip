@@ -230,7 +230,7 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_count(ScatterArgs a)
     float m = 0.0f;
     const int64_t s = (int64_t)bx * kSamplesPerBlock + threadIdx.x;
     float2 d;
-    Corners c;
+    Corners c{};  // lanes past the samples take part in the wave's count with no records
     bool has;
     uint32_t heads = 0xffu;
     if (a.merge_runs) {  // every sample, runs of a repeated corner as one record
