@@ -272,17 +272,31 @@ __global__ __launch_bounds__(1024) void k_loss_finalize(const double* __restrict
     }
 }
 
-__global__ __launch_bounds__(256) void k_loss_objects(const ObjDev* __restrict__ objs,
-                                                      const double* __restrict__ ray_loss, float* loss)
+// One block per object (a batch has few objects, so each block takes 16
+// waves and keeps four loads in flight per thread); the sums run in a fixed
+// order.
+constexpr int kLossObjThreads = 1024;
+__global__ __launch_bounds__(kLossObjThreads) void k_loss_objects(const ObjDev* __restrict__ objs,
+                                                                  const double* __restrict__ ray_loss, float* loss)
 {
-    __shared__ double red[4];
+    __shared__ double red[kLossObjThreads / 64];
     const ObjDev& o = objs[blockIdx.x];
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < o.n_rays; i += 256) s += ray_loss[o.ray_begin + i];
-    s = wave_sum_d(s);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    const double* rl = ray_loss + o.ray_begin;
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t i = threadIdx.x;
+    for (; i + 3 * kLossObjThreads < o.n_rays; i += 4 * kLossObjThreads) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s[u] += rl[i + u * kLossObjThreads];
+    }
+    for (; i < o.n_rays; i += kLossObjThreads) s[0] += rl[i];
+    double t = wave_sum_d((s[0] + s[1]) + (s[2] + s[3]));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
     __syncthreads();
-    if (threadIdx.x == 0) loss[blockIdx.x] = (float)((red[0] + red[1]) + (red[2] + red[3]));
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int w = 0; w < kLossObjThreads / 64; ++w) tot += red[w];
+        loss[blockIdx.x] = (float)tot;
+    }
 }
 
 __global__ __launch_bounds__(64 * kWaves) void k_composite_bwd(CompositeArgs a)
@@ -413,7 +427,7 @@ hipError_t launch_loss_finalize(const double* partial, int n_blocks, float* loss
 hipError_t launch_loss_objects(const ObjDev* objs, int n_obj, const double* ray_loss, float* loss, hipStream_t s)
 {
     if (n_obj == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_loss_objects, dim3((uint32_t)n_obj), dim3(256), 0, s, objs, ray_loss, loss);
+    hipLaunchKernelGGL(k_loss_objects, dim3((uint32_t)n_obj), dim3(kLossObjThreads), 0, s, objs, ray_loss, loss);
     return hipGetLastError();
 }
 
