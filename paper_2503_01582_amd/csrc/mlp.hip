@@ -475,10 +475,17 @@ __device__ __forceinline__ void reduce_slots(const float* __restrict__ src, int6
                                              bool active, float* __restrict__ dst, double (*part)[kRedParams])
 {
     const int i = threadIdx.x % kRedParams, grp = threadIdx.x / kRedParams;
-    double acc = 0.0;
-    if (active)
-        for (int64_t sl = grp; sl < n_slots; sl += kRedGroups) acc += (double)src[sl * stride];
-    part[grp][i] = acc;
+    // four slots in flight per thread, summed in a fixed order
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (active) {
+        int64_t sl = grp;
+        for (; sl + 3 * kRedGroups < n_slots; sl += 4 * kRedGroups) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] += (double)src[(sl + u * kRedGroups) * stride];
+        }
+        for (; sl < n_slots; sl += kRedGroups) acc[0] += (double)src[sl * stride];
+    }
+    part[grp][i] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
     __syncthreads();
     if (grp == 0 && active) {
         double sum = 0.0;
