@@ -319,21 +319,28 @@ __global__ __launch_bounds__(kPlaceThreads) void k_scatter_dymax(ScatterArgs a)
     }
 }
 
+// One workgroup per (object, level) of the pass; a pass has few of them, so
+// each takes 16 waves (a maximum does not depend on the order).
+constexpr int kLevelMaxThreads = 1024;
 template <bool kMany>
-__global__ __launch_bounds__(256) void k_scatter_level_max(ScatterArgs a)
+__global__ __launch_bounds__(kLevelMaxThreads) void k_scatter_level_max(ScatterArgs a)
 {
-    __shared__ float red[4];
+    __shared__ float red[kLevelMaxThreads / 64];
     const int pair = blockIdx.x;
     const ScatterObj& o = sobj<kMany>(a, obj_of_level<kMany>(a, pair));
     const int l = pair - o.lev_off;
     const float* bm = a.block_max + o.bmax_off + (int64_t)l * o.n_blocks;
     float m = 0.0f;
-    for (int b = threadIdx.x; b < o.n_blocks; b += 256) m = fmaxf(m, bm[b]);
+    for (int b = threadIdx.x; b < o.n_blocks; b += kLevelMaxThreads) m = fmaxf(m, bm[b]);
 #pragma unroll
     for (int dd = 32; dd >= 1; dd >>= 1) m = fmaxf(m, __shfl_xor(m, dd));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
     __syncthreads();
-    if (threadIdx.x == 0) a.level_max[pair] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    if (threadIdx.x == 0) {
+        float r = 0.0f;
+        for (int w = 0; w < kLevelMaxThreads / 64; ++w) r = fmaxf(r, red[w]);
+        a.level_max[pair] = r;
+    }
 }
 
 // Inclusive prefix sum over the 64 lanes of a wave.
@@ -748,7 +755,8 @@ hipError_t scatter_phase_impl(const ScatterArgs& a, int phase, hipStream_t s)
                 hipLaunchKernelGGL(k_scatter_count<kMany>, dim3((uint32_t)a.n_items), dim3(kPlaceThreads), 0, s, a);
             break;
         case 1:
-            hipLaunchKernelGGL(k_scatter_level_max<kMany>, dim3((uint32_t)a.n_levels_total), dim3(256), 0, s, a);
+            hipLaunchKernelGGL(k_scatter_level_max<kMany>, dim3((uint32_t)a.n_levels_total), dim3(kLevelMaxThreads), 0, s,
+                               a);
             break;
         case 2:
             hipLaunchKernelGGL(k_scatter_scan_blocks<kMany>, dim3((uint32_t)a.n_tiles), dim3(kScanThreads), 0, s, a);
